@@ -1,0 +1,315 @@
+"""Oracle for the Gribov-copy enumerator -- TEST INFRASTRUCTURE ONLY.
+
+Plain double-precision CPU reference.  Only ``tests/``, the smoke check and
+the benchmark's CPU-baseline leg may import this module; the product path
+never does, and the two share no code.
+
+The per-start relaxation, the functional and the integer key run in
+``gribov_oracle.c`` (plain C, compiled without floating-point contraction).
+This module adds, in numpy:
+
+* the Faddeev-Popov operator M_FP, the Hessian of eq. (3) in theta
+  (Sec. I, lattice Landau gauge paragraph), assembled densely as
+  B^T diag(cos a) B from the link-site incidence matrix B, and its spectrum by
+  LAPACK (numpy.linalg.eigvalsh);
+* the first-Gribov-region test (abstract; Sec. I: minima, i.e. M_FP positive
+  semidefinite with only the constant zero mode);
+* the copy table: distinct minima keyed by the integer key, with hit counts,
+  the lowest start id reaching each, and the paper's own count of distinct
+  values of x at resolution 1e-8 (Sec. III, last paragraphs).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "gribov_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+CONVERGED, NONCONVERGED, BADNUM = 1, 2, 3
+FLAG_IN_REGION, FLAG_SINGULAR, FLAG_SADDLE, FLAG_COLLISION = 1, 2, 4, 8
+LAMBDA_TOL = 1e-6
+
+RECORD_DTYPE = np.dtype([
+    ("status", np.int32), ("sweeps32", np.int32), ("sweeps64", np.int32), ("n_elems", np.int32),
+    ("F", np.float64), ("x", np.float64), ("D", np.float64), ("cut_margin", np.float64),
+    ("key_hi", np.uint64), ("key_lo", np.uint64), ("paper_X", np.uint32), ("key_overflow", np.int32),
+])
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double), ("eps32", ctypes.c_double), ("eps64", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("stop_norm", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("max_sweeps", ctypes.c_int64), ("start_seed", ctypes.c_uint64),
+                ("orbit_index", ctypes.c_uint64)]
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle (gcc, -O2, OpenMP, no FP contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off",
+                               "-fno-fast-math", "-fPIC", "-shared", SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.POINTER
+        L.oracle_philox4x64_10.argtypes = [P(ctypes.c_uint64), P(ctypes.c_uint64), P(ctypes.c_uint64)]
+        L.oracle_mix64.argtypes = [ctypes.c_uint64]
+        L.oracle_mix64.restype = ctypes.c_uint64
+        L.oracle_start_angles.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                          ctypes.c_int64, P(ctypes.c_double)]
+        L.oracle_key_length.argtypes = [ctypes.c_int, P(ctypes.c_int)]
+        L.oracle_key_length.restype = ctypes.c_int64
+        L.oracle_solve.argtypes = [ctypes.c_int, P(ctypes.c_int), P(ctypes.c_double), P(ctypes.c_uint64),
+                                   ctypes.c_int64, P(_Params), P(ctypes.c_double), ctypes.c_int,
+                                   ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int32)]
+        L.oracle_observe.argtypes = [ctypes.c_int, P(ctypes.c_int), P(ctypes.c_double), P(ctypes.c_double),
+                                     ctypes.c_void_p, P(ctypes.c_int32), P(ctypes.c_double), P(ctypes.c_double)]
+        L.oracle_colouring.argtypes = [ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int32)]
+        L.oracle_neighbours.argtypes = [ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int32), P(ctypes.c_int32)]
+        assert L.oracle_record_size() == RECORD_DTYPE.itemsize
+        assert L.oracle_params_size() == ctypes.sizeof(_Params)
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if a is not None else None
+
+
+def _ext(extent):
+    e = np.zeros(4, dtype=np.int32)
+    e[:len(extent)] = extent
+    return e, e.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def volume(extent) -> int:
+    return int(np.prod(extent))
+
+
+# --------------------------------------------------------------------------
+# Small primitives (exposed for pinning against published values)
+# --------------------------------------------------------------------------
+
+def philox(ctr, key):
+    c = (ctypes.c_uint64 * 4)(*[int(x) for x in ctr])
+    k = (ctypes.c_uint64 * 2)(*[int(x) for x in key])
+    o = (ctypes.c_uint64 * 4)()
+    lib().oracle_philox4x64_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def mix64(z: int) -> int:
+    return int(lib().oracle_mix64(ctypes.c_uint64(z & ((1 << 64) - 1))))
+
+
+def start_angles(start_seed: int, start_id: int, orbit_index: int, V: int) -> np.ndarray:
+    out = np.empty(V, dtype=np.float64)
+    lib().oracle_start_angles(start_seed, start_id, orbit_index, V, _dp(out))
+    return out
+
+
+def colouring(extent):
+    e, ep = _ext(extent)
+    col = np.empty(volume(extent), dtype=np.int32)
+    K = lib().oracle_colouring(len(extent), ep, col.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return K, col
+
+
+def neighbours(extent):
+    e, ep = _ext(extent)
+    d, V = len(extent), volume(extent)
+    fwd = np.empty((d, V), dtype=np.int32)
+    bwd = np.empty((d, V), dtype=np.int32)
+    P = ctypes.POINTER(ctypes.c_int32)
+    rc = lib().oracle_neighbours(d, ep, fwd.ctypes.data_as(P), bwd.ctypes.data_as(P))
+    assert rc == 0
+    return fwd, bwd
+
+
+def key_length(extent) -> int:
+    e, ep = _ext(extent)
+    return int(lib().oracle_key_length(len(extent), ep))
+
+
+# --------------------------------------------------------------------------
+# Relaxation (C) -- eqs. (4)-(5) in the convention of eq. (3)
+# --------------------------------------------------------------------------
+
+@dataclass
+class SolveParams:
+    omega: float = 1.0
+    precision: str = "fp64"        # "fp64" or "mixed"
+    eps32: float = 1e-6
+    eps64: float = 1e-14
+    stop_norm: str = "mean_sq"     # or "max_abs" (the paper's rule)
+    check_every: int = 1
+    max_sweeps: int = 100_000
+    start_seed: int = 0
+    orbit_index: int = 0
+
+    def c(self) -> _Params:
+        return _Params(self.omega, self.eps32, self.eps64, 1 if self.precision == "mixed" else 0,
+                       1 if self.stop_norm == "max_abs" else 0, self.check_every, 0,
+                       self.max_sweeps, self.start_seed, self.orbit_index)
+
+
+def solve(extent, phi, start_ids, params: SolveParams, theta_init=None, threads: int = 0,
+          want_state: bool = False, want_payload: bool = False):
+    """Relax the listed starts.  Returns (records, g or None, payload or None).
+
+    g has shape (n, V, 2) (final Re, Im of g_i); payload (n, m) int32."""
+    e, ep = _ext(extent)
+    d, V = len(extent), volume(extent)
+    phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(d, V)
+    ids = np.ascontiguousarray(start_ids, dtype=np.uint64)
+    n = ids.size
+    rec = np.zeros(n, dtype=RECORD_DTYPE)
+    g = np.empty((n, V, 2), dtype=np.float64) if want_state else None
+    m = key_length(extent)
+    pay = np.empty((n, m), dtype=np.int32) if want_payload else None
+    th = None
+    if theta_init is not None:
+        th = np.ascontiguousarray(theta_init, dtype=np.float64).reshape(n, V)
+    prm = params.c()
+    rc = lib().oracle_solve(d, ep, _dp(phi), ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), n,
+                            ctypes.byref(prm), _dp(th), threads, rec.ctypes.data_as(ctypes.c_void_p),
+                            _dp(g), pay.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if pay is not None else None)
+    if rc != 0:
+        raise ValueError("oracle_solve: unsupported lattice %r (rc=%d)" % (tuple(extent), rc))
+    return rec, g, pay
+
+
+def observe(extent, phi, theta):
+    """Functional, key and link data of the state g = exp(i theta) (no relaxation)."""
+    e, ep = _ext(extent)
+    d, V = len(extent), volume(extent)
+    phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(d, V)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    rec = np.zeros(1, dtype=RECORD_DTYPE)
+    m = key_length(extent)
+    pay = np.empty(m, dtype=np.int32)
+    a = np.empty((d, V), dtype=np.float64)
+    w = np.empty((d, V), dtype=np.float64)
+    rc = lib().oracle_observe(d, ep, _dp(phi), _dp(theta), rec.ctypes.data_as(ctypes.c_void_p),
+                              pay.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(a), _dp(w))
+    assert rc == 0
+    return rec[0], pay, a, w
+
+
+def theta_of(g) -> np.ndarray:
+    """theta_i = arg g_i for a state of shape (V, 2)."""
+    return np.arctan2(g[:, 1], g[:, 0])
+
+
+# --------------------------------------------------------------------------
+# Faddeev-Popov operator (Hessian of eq. (3)) and the first Gribov region
+# --------------------------------------------------------------------------
+
+def incidence(extent) -> np.ndarray:
+    """B[l, site]: a_l = phi_l + theta_{i+mu} - theta_i, so dA_l/dtheta = +1 at
+    the forward end and -1 at the base (rows l = mu*V + i)."""
+    d, V = len(extent), volume(extent)
+    fwd, _ = neighbours(extent)
+    B = np.zeros((d * V, V), dtype=np.float64)
+    for mu in range(d):
+        for i in range(V):
+            l = mu * V + i
+            B[l, i] -= 1.0
+            B[l, fwd[mu, i]] += 1.0
+    return B
+
+
+def fp_operator(extent, w) -> np.ndarray:
+    """M_FP = B^T diag(w) B with w_l = cos a_l (the Hessian of eq. (3))."""
+    B = incidence(extent)
+    w = np.asarray(w, dtype=np.float64).reshape(-1)
+    return B.T @ (w[:, None] * B)
+
+
+def fp_spectrum(extent, w):
+    """(lambda_zero, lambda2, lambda_max).
+
+    M always annihilates the constant vector.  lambda2 is the lowest
+    eigenvalue of M on the complement of the constant vector, computed
+    densely as the lowest eigenvalue of M + sigma 11^T/V with sigma above
+    every eigenvalue of M (|lambda| <= 4d by Gershgorin).  lambda_zero is the
+    eigenvalue of M nearest to zero, for the zero-mode check."""
+    d, V = len(extent), volume(extent)
+    M = fp_operator(extent, w)
+    ev = np.linalg.eigvalsh(M)
+    sigma = 4.0 * d + 1.0
+    ev_shift = np.linalg.eigvalsh(M + sigma / V * np.ones((V, V)))
+    lam0 = ev[np.argmin(np.abs(ev))]
+    return float(lam0), float(ev_shift[0]), float(ev[-1])
+
+
+def region_flags(lam2: float, tol: float = LAMBDA_TOL) -> int:
+    if lam2 > tol:
+        return FLAG_IN_REGION
+    if lam2 < -tol:
+        return FLAG_SADDLE
+    return FLAG_SINGULAR
+
+
+# --------------------------------------------------------------------------
+# Enumeration of one orbit: per-start solves + copy table
+# --------------------------------------------------------------------------
+
+def enumerate_copies(extent, phi, start_ids, params: SolveParams, threads: int = 0,
+                     with_lambda: bool = True):
+    """Run the listed starts and build the copy table.
+
+    Returns dict with 'records' (per start), 'table' {(key_hi, key_lo): entry},
+    'paper_count' (distinct trunc(x*1e8) over converged starts)."""
+    ids = np.ascontiguousarray(start_ids, dtype=np.uint64)
+    rec, g, _ = solve(extent, phi, ids, params, threads=threads, want_state=with_lambda)
+    table = {}
+    for s in range(ids.size):
+        r = rec[s]
+        if r["status"] != CONVERGED:
+            continue
+        k = (int(r["key_hi"]), int(r["key_lo"]))
+        sid = int(ids[s])
+        e = table.get(k)
+        if e is None:
+            table[k] = dict(hits=1, first_start=sid, first_index=s, F=float(r["F"]),
+                            F_min=float(r["F"]), F_max=float(r["F"]))
+        else:
+            e["hits"] += 1
+            e["F_min"] = min(e["F_min"], float(r["F"]))
+            e["F_max"] = max(e["F_max"], float(r["F"]))
+            if sid < e["first_start"]:
+                e["first_start"], e["first_index"], e["F"] = sid, s, float(r["F"])
+    V = volume(extent)
+    for k, e in table.items():
+        flags = 0
+        if with_lambda:
+            gs = g[e["first_index"]]
+            _, _, _, w = observe(extent, phi, theta_of(gs))
+            lam0, lam2, lmax = fp_spectrum(extent, w)
+            e["lambda2"], e["lambda_zero"], e["lambda_max"] = lam2, lam0, lmax
+            flags |= region_flags(lam2)
+        if (e["F_max"] - e["F_min"]) / V > 1e-9:
+            flags |= FLAG_COLLISION
+        e["flags"] = flags
+        e["x"] = e["F"] / (len(extent) * V)
+    conv = rec["status"] == CONVERGED
+    paper_count = int(np.unique(rec["paper_X"][conv]).size)
+    return dict(records=rec, table=table, paper_count=paper_count, state=g)

@@ -1,0 +1,464 @@
+"""Pins of the oracle against facts fixed outside it.
+
+Every check here compares the oracle with something it does not compute
+itself: published generator outputs, numpy's Philox, formulas written out
+independently from eq. (3) (gradient, Hessian by finite differences), closed
+forms (1D ring, constant-field orbits), brute-force enumeration of all
+stationary points (eq. (2)), and the orbit averages printed in Tab. I and
+Tab. III.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import gribov_inputs as GI
+from oracle import bruteforce as BF
+from oracle import oracle as O
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+TWO_PI = 2.0 * math.pi
+
+
+def _gold_lines(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+
+
+# --------------------------------------------------------------------------
+# Random numbers (Sec. III: Philox-initialised random starts)
+# --------------------------------------------------------------------------
+
+def test_philox_known_answers():
+    for row in _gold_lines("philox4x64_10_kat.txt"):
+        v = [int(x, 16) for x in row]
+        assert O.philox(v[0:4], v[4:6]) == v[6:10]
+
+
+@pytest.mark.parametrize("ctr,key", [((0, 0, 0, 0), (0, 0)), ((5, 9, 3, 0x53), (17, 1)),
+                                     ((2**64 - 1, 4, 0, 0), (1, 2)), ((123456789, 2**63, 7, 11), (2**64 - 5, 0))])
+def test_philox_matches_numpy(ctr, key):
+    raw = GI._philox_blocks(key[0], key[1], ctr, 1)
+    assert O.philox(ctr, key) == [int(x) for x in raw]
+
+
+def test_splitmix_published_outputs():
+    state = 0
+    for row in _gold_lines("splitmix64.txt"):
+        state = (state + 0x9E3779B97F4A7C15) % (1 << 64)
+        assert O.mix64(state) == int(row[0], 16)
+
+
+def test_start_angles_follow_counter_map():
+    V = 37
+    th = O.start_angles(11, 5, 3, V)
+    raw = np.concatenate([GI._philox_blocks(11, 1, (b, 5, 3, 0x53), 1) for b in range((V + 3) // 4)])[:V]
+    assert np.array_equal(th, GI.uniform_angle(raw))
+    assert np.all(th >= -math.pi) and np.all(th < math.pi)
+
+
+def test_angle_map_endpoints():
+    # r = 0 maps exactly to -pi; the largest draw stays below pi.
+    assert GI.uniform_angle(np.array([0], dtype=np.uint64))[0] == -math.pi
+    top = GI.uniform_angle(np.array([2**64 - 1], dtype=np.uint64))[0]
+    assert top < math.pi
+
+
+# --------------------------------------------------------------------------
+# Geometry: periodic boundaries (Sec. I) and the checkerboard (Sec. III)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("extent,K", [((4, 4), 2), ((2, 2), 2), ((3, 3), 3), ((5, 5), 5), ((4, 6, 8), 2),
+                                      ((3, 6), 3), ((6, 6, 6, 6), 2), ((7,), 7), ((8,), 2), ((9, 3), 3)])
+def test_colouring_is_proper(extent, K):
+    k, col = O.colouring(extent)
+    assert k == K
+    fwd, bwd = O.neighbours(extent)
+    for mu in range(len(extent)):
+        assert np.all(col != col[fwd[mu]])
+        assert np.all(col != col[bwd[mu]])
+    assert set(np.unique(col)) == set(range(K))
+
+
+def test_no_colouring_for_coprime_odd_extents():
+    k, _ = O.colouring((3, 5))
+    assert k == 0
+    with pytest.raises(ValueError):
+        O.solve((3, 5), np.zeros((2, 15)), [0], O.SolveParams())
+
+
+def test_neighbours_periodic():
+    extent = (3, 4, 2)
+    fwd, bwd = O.neighbours(extent)
+    V = 24
+    for mu in range(3):
+        assert np.array_equal(bwd[mu][fwd[mu]], np.arange(V))
+        # walking N_mu steps returns to the start
+        i = np.arange(V)
+        for _ in range(extent[mu]):
+            i = fwd[mu][i]
+        assert np.array_equal(i, np.arange(V))
+    # site index convention: x0 fastest
+    assert fwd[0][0] == 1 and fwd[1][0] == 3 and fwd[2][0] == 12 and bwd[0][0] == 2
+
+
+# --------------------------------------------------------------------------
+# Functional, gradient and Hessian written out from eq. (3)
+# --------------------------------------------------------------------------
+
+def _eq3_F(extent, phi, theta):
+    land = BF.Landscape(extent, phi)
+    return land.F(theta), land.grad(theta), land
+
+
+@pytest.mark.parametrize("extent", [(4, 4), (2, 3, 4), (2, 2, 2, 2), (6,), (2, 2)])
+def test_functional_and_divergence_match_eq3(extent):
+    phi = GI.orbit_angles(extent, 3, 1)
+    V = int(np.prod(extent))
+    theta = O.start_angles(9, 2, 0, V)
+    rec, _, a, w = O.observe(extent, phi, theta)
+    F, grad, land = _eq3_F(extent, phi, theta)
+    assert abs(rec["F"] - F) < 1e-12 * len(extent) * V
+    # the oracle's stopping norm is the mean square of the divergence = -grad
+    assert abs(rec["D"] - np.mean(grad ** 2)) < 1e-12 * max(1.0, np.mean(grad ** 2))
+    # link weights and angles are those of the transformed links
+    al = land.link_angles(theta).reshape(len(extent), V)
+    assert np.allclose(np.cos(al), w, atol=1e-13)
+    assert np.allclose(np.angle(np.exp(1j * al)), a, atol=1e-12)
+
+
+def test_gradient_is_derivative_of_functional():
+    extent = (3, 4)
+    phi = GI.orbit_angles(extent, 5, 0)
+    V = 12
+    theta = O.start_angles(1, 1, 1, V)
+    land = BF.Landscape(extent, phi)
+    g = land.grad(theta)
+    h = 1e-6
+    for j in range(V):
+        e = np.zeros(V)
+        e[j] = h
+        fd = (land.F(theta + e) - land.F(theta - e)) / (2 * h)
+        assert abs(fd - g[j]) < 1e-8
+
+
+@pytest.mark.parametrize("extent", [(3, 4), (2, 2), (2, 2, 3)])
+def test_fp_operator_is_hessian(extent):
+    """M_FP = B^T diag(cos a) B against central second differences of eq. (3)."""
+    phi = GI.orbit_angles(extent, 2, 4)
+    V = int(np.prod(extent))
+    theta = O.start_angles(3, 3, 3, V)
+    _, _, _, w = O.observe(extent, phi, theta)
+    M = O.fp_operator(extent, w)
+    land = BF.Landscape(extent, phi)
+    h = 1e-4
+    H = np.zeros((V, V))
+    for j in range(V):
+        for k in range(V):
+            ej = np.zeros(V); ej[j] = h
+            ek = np.zeros(V); ek[k] = h
+            H[j, k] = (land.F(theta + ej + ek) - land.F(theta + ej - ek)
+                       - land.F(theta - ej + ek) + land.F(theta - ej - ek)) / (4 * h * h)
+    assert np.max(np.abs(H - M)) < 1e-6
+    assert np.max(np.abs(M @ np.ones(V))) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Converged copies: stationarity, gauge invariance, region, x <= 1
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("extent,omega", [((4, 4), 1.7), ((2, 2, 2), 1.0), ((4, 4, 4, 4), 1.7), ((6, 6), 1.0), ((3, 3), 1.7)])
+def test_converged_states_are_stationary_minima(extent, omega):
+    phi = GI.orbit_angles(extent, 0, 2)
+    d, V = len(extent), int(np.prod(extent))
+    rec, g, pay = O.solve(extent, phi, np.arange(12), O.SolveParams(omega=omega), want_state=True, want_payload=True)
+    assert np.all(rec["status"] == O.CONVERGED)
+    land = BF.Landscape(extent, phi)
+    for s in range(12):
+        th = O.theta_of(g[s])
+        grad = land.grad(th)
+        assert np.mean(grad ** 2) < 1.01e-14
+        assert abs(land.F(th) - rec["F"][s]) < 1e-10 * d * V
+        # gauge invariance: plaquettes and Polyakov loops of the transformed
+        # links equal those of phi modulo 2 pi
+        _, pay2, a, w = O.observe(extent, phi, th)
+        assert np.array_equal(pay2, pay[s])
+        fwd, _ = O.neighbours(extent)
+        for mu in range(d):
+            for nu in range(mu + 1, d):
+                A = a[mu] + a[nu][fwd[mu]] - a[mu][fwd[nu]] - a[nu]
+                P = phi[mu] + phi[nu][fwd[mu]] - phi[mu][fwd[nu]] - phi[nu]
+                r = (A - P) / TWO_PI
+                assert np.max(np.abs(r - np.rint(r))) < 1e-12
+            i = np.arange(V)
+            sa = np.zeros(V); sp = np.zeros(V)
+            for _ in range(extent[mu]):
+                sa += a[mu][i]; sp += phi[mu][i]
+                i = fwd[mu][i]
+            r = (sa - sp) / TWO_PI
+            assert np.max(np.abs(r - np.rint(r))) < 1e-12
+        lam0, lam2, lmax = O.fp_spectrum(extent, w)
+        assert abs(lam0) < 1e-10
+        assert lam2 > 0 and lmax <= 4 * d
+        assert 0.0 <= rec["x"][s] <= 1.0
+
+
+def test_key_invariant_under_global_phase_and_2pi_shifts():
+    extent = (4, 4, 4)
+    phi = GI.orbit_angles(extent, 0, 0)
+    rec, g, pay = O.solve(extent, phi, [7], O.SolveParams(omega=1.7), want_state=True, want_payload=True)
+    th = O.theta_of(g[0])
+    r0, p0, _, _ = O.observe(extent, phi, th)
+    r1, p1, _, _ = O.observe(extent, phi, th + 0.731)
+    shifts = TWO_PI * np.random.default_rng(0).integers(-2, 3, th.size)
+    r2, p2, _, _ = O.observe(extent, phi, th + shifts)
+    assert (r0["key_hi"], r0["key_lo"]) == (r1["key_hi"], r1["key_lo"]) == (r2["key_hi"], r2["key_lo"])
+    assert np.array_equal(p0, p1) and np.array_equal(p0, p2)
+    assert abs(r0["F"] - r1["F"]) < 1e-11
+
+
+def test_plaquette_numbers_close_on_every_cube():
+    """The wrap numbers are the curl of the link wrap integers, so their oriented
+    sum over the six faces of every elementary cube vanishes exactly."""
+    extent = (4, 4, 4, 4)
+    d, V = 4, 256
+    phi = GI.orbit_angles(extent, 0, 0)
+    rec, g, pay = O.solve(extent, phi, np.arange(6), O.SolveParams(omega=1.7), want_payload=True)
+    fwd, _ = O.neighbours(extent)
+    planes = [(mu, nu) for mu in range(d) for nu in range(mu + 1, d)]
+    for s in range(6):
+        n = {pl: pay[s][k * V:(k + 1) * V] for k, pl in enumerate(planes)}
+        assert np.any(np.concatenate(list(n.values())) != 0)
+        for mu, nu, rho in [(0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)]:
+            x = np.arange(V)
+            tot = (n[(nu, rho)][fwd[mu][x]] - n[(nu, rho)][x]
+                   - n[(mu, rho)][fwd[nu][x]] + n[(mu, rho)][x]
+                   + n[(mu, nu)][fwd[rho][x]] - n[(mu, nu)][x])
+            assert np.all(tot == 0)
+
+
+def test_distinct_minima_have_distinct_keys_and_no_collision():
+    extent = (4, 4, 4, 4)
+    phi = GI.orbit_angles(extent, 0, 0)
+    res = O.enumerate_copies(extent, phi, np.arange(300), O.SolveParams(omega=1.0), with_lambda=False)
+    Fs = sorted(e["F"] for e in res["table"].values())
+    assert len(res["table"]) > 250
+    for e in res["table"].values():
+        assert not (e["flags"] & O.FLAG_COLLISION)
+    # distinct keys never share a functional value to 1e-9
+    assert np.min(np.diff(Fs)) > 1e-9
+
+
+# --------------------------------------------------------------------------
+# Closed forms
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,seed", [(6, 0), (7, 1), (8, 2), (9, 3)])
+def test_1d_ring_closed_form(N, seed):
+    """1D ring: minima are uniform, a = (Phi + 2 pi k)/N with cos a > 0 (Phi the
+    unwrapped sum of the link angles); F_k = N (1 - cos a_k); the line winding
+    of the copy is k; lambda2 = 2 cos a_k (1 - cos(2 pi/N))."""
+    phi = GI.orbit_angles((N,), seed, 0)
+    Phi = float(np.sum(phi[0]))
+    ks = [k for k in range(-N, N + 1) if abs(Phi + TWO_PI * k) < N * math.pi / 2]
+    res = O.enumerate_copies((N,), phi, np.arange(4000), O.SolveParams(omega=1.0))
+    got = sorted((e["F"], e) for e in res["table"].values())
+    assert len(got) == len(ks)
+    rec, _, pay = O.solve((N,), phi, [e["first_start"] for _, e in got], O.SolveParams(), want_payload=True)
+    expect = {}
+    for k in ks:
+        a = (Phi + TWO_PI * k) / N
+        expect[k] = (N * (1 - math.cos(a)), 2 * math.cos(a) * (1 - math.cos(TWO_PI / N)))
+    for (F, e), p in zip(got, pay):
+        k = int(p[0])
+        assert k in expect
+        assert abs(F - expect[k][0]) < 1e-10
+        # the stopped state is off the exact minimum by |delta a| <~ sqrt(V eps)/lambda2,
+        # which moves lambda2 to first order (dlambda2/da <= 4 here)
+        tol = 4.0 * math.sqrt(N * 1e-14) / expect[k][1]
+        assert abs(e["lambda2"] - expect[k][1]) < tol
+
+
+@pytest.mark.parametrize("extent,c,k", [((8, 8), (0.3, -1.1), (1, 0)), ((6, 6, 6), (0.0, 0.0, 0.0), (0, 1, -1)),
+                                        ((4, 6), (2.9, -0.2), (-2, 1)), ((6, 4, 4, 4), (0.1, 0.2, -0.3, 0.4), (1, 0, 0, 0))])
+def test_twisted_states_of_constant_orbits(extent, c, k):
+    """phi_{i,mu} = c_mu: theta_x = sum_mu 2 pi k_mu x_mu / N_mu is stationary with
+    uniform a_mu = c_mu + 2 pi k_mu / N_mu; when every cos a_mu > 0 it is a
+    minimum with lambda2 = min_mu 2 cos a_mu (1 - cos(2 pi / N_mu)) and line
+    winding k_mu (when c_mu + 2 pi k_mu/N_mu stays in (-pi, pi])."""
+    d = len(extent)
+    V = int(np.prod(extent))
+    phi = GI.constant_orbit(extent, c)
+    coords = np.array(np.unravel_index(np.arange(V), extent[::-1]))[::-1]
+    theta = sum(TWO_PI * k[mu] * coords[mu] / extent[mu] for mu in range(d))
+    am = [c[mu] + TWO_PI * k[mu] / extent[mu] for mu in range(d)]
+    assert all(math.cos(x) > 0 and -math.pi < x <= math.pi for x in am)
+    rec, pay, a, w = O.observe(extent, phi, theta)
+    F_exact = V * sum(1 - math.cos(x) for x in am)
+    assert abs(rec["F"] - F_exact) < 1e-10
+    assert rec["D"] < 1e-26
+    lam0, lam2, _ = O.fp_spectrum(extent, w)
+    lam_exact = min(2 * math.cos(am[mu]) * (1 - math.cos(TWO_PI / extent[mu])) for mu in range(d))
+    assert abs(lam2 - lam_exact) < 1e-10 and abs(lam0) < 1e-10
+    n_pl = d * (d - 1) // 2 * V
+    assert np.all(pay[:n_pl] == 0)
+    lines = pay[n_pl:]
+    off = 0
+    for mu in range(d):
+        nl = V // extent[mu]
+        assert np.all(lines[off:off + nl] == k[mu])
+        off += nl
+    # relaxation started exactly there stays there (one sweep, same F)
+    r2, _, _ = O.solve(extent, phi, [0], O.SolveParams(omega=1.0), theta_init=theta[None, :])
+    assert r2["sweeps64"][0] == 1 and abs(r2["F"][0] - F_exact) < 1e-10
+    assert (r2["key_hi"][0], r2["key_lo"][0]) == (rec["key_hi"], rec["key_lo"])
+
+
+def test_cold_orbit_global_minimum():
+    extent = (6, 6)
+    phi = GI.cold_orbit(extent)
+    res = O.enumerate_copies(extent, phi, np.arange(200), O.SolveParams(omega=1.7))
+    best = min(res["table"].values(), key=lambda e: e["F"])
+    assert best["F"] < 1e-12
+    assert abs(best["lambda2"] - 2 * (1 - math.cos(TWO_PI / 6))) < 1e-9
+
+
+# --------------------------------------------------------------------------
+# Brute force: all stationary points of tiny lattices, eq. (2)
+# --------------------------------------------------------------------------
+
+def _min_keys_from_points(extent, phi, pts):
+    keys = set()
+    for p in pts:
+        if p["index"] == 0:
+            r, _, _, _ = O.observe(extent, phi, p["theta"])
+            keys.add((int(r["key_hi"]), int(r["key_lo"])))
+    return keys
+
+
+@pytest.mark.parametrize("orbit", [0, 1, 2])
+def test_bruteforce_2x2(orbit):
+    extent = (2, 2)
+    phi = GI.orbit_angles(extent, 0, orbit)
+    pts = BF.stationary_points(extent, phi, BF.grid_starts(4, 14))
+    idx = np.bincount([p["index"] for p in pts], minlength=4)
+    assert list(idx) == [1, 3, 3, 1]            # Betti numbers of T^3
+    assert BF.euler_sum(pts) == 0               # eq. (2): chi(S^1)^3 = 0
+    res = O.enumerate_copies(extent, phi, np.arange(500), O.SolveParams(omega=1.7))
+    assert set(res["table"]) == _min_keys_from_points(extent, phi, pts)
+
+
+def test_bruteforce_3x3_saturation():
+    """3x3 needs three colours.  Newton from 20000 random points finds a set
+    whose Morse-index sum vanishes (eq. (2)); its minima equal the copies found
+    by relaxation, and the relaxation set stops growing early."""
+    extent = (3, 3)
+    phi = GI.orbit_angles(extent, 0, 2)
+    pts = BF.stationary_points(extent, phi, BF.random_starts(9, 20000))
+    assert BF.euler_sum(pts) == 0
+    bf = _min_keys_from_points(extent, phi, pts)
+    assert len(bf) == 3
+    res = O.enumerate_copies(extent, phi, np.arange(20000), O.SolveParams(omega=1.0), with_lambda=False)
+    assert set(res["table"]) == bf
+    assert max(e["first_start"] for e in res["table"].values()) < 2000
+
+
+# --------------------------------------------------------------------------
+# Orbit statistics printed in the paper (Tab. I and Tab. III)
+# --------------------------------------------------------------------------
+
+def _paper_rows():
+    rows = {}
+    for ext, tab, n, mean, sd in _gold_lines("paper_tables.txt"):
+        rows[(tuple(int(x) for x in ext.split("x")), tab)] = (int(n), float(mean), float(sd))
+    return rows
+
+
+@pytest.mark.parametrize("extent,n_orbits,n_starts", [((2, 2), 100, 2000), ((4, 4), 100, 8000),
+                                                      ((2, 2, 2), 100, 2000), ((2, 2, 2, 2), 100, 4000),
+                                                      ((4, 4, 4), 30, 3000)])
+def test_orbit_statistics_match_tables(extent, n_orbits, n_starts):
+    """Fresh beta = 0 orbits (the paper's are not published) must reproduce the
+    printed orbit averages within three combined standard errors: the count of
+    distinct minima (Tab. I; a lower bound that our smaller sample may only
+    undercut) and x at the global minimum (Tab. III).  Plain relaxation, as in
+    the paper."""
+    rows = _paper_rows()
+    cnt, gmin = [], []
+    for oi in range(n_orbits):
+        phi = GI.orbit_angles(extent, 7, oi)
+        r = O.enumerate_copies(extent, phi, np.arange(n_starts), O.SolveParams(omega=1.0), with_lambda=False)
+        cnt.append(len(r["table"]))
+        gmin.append(min(e["x"] for e in r["table"].values()))
+    cnt, gmin = np.array(cnt, float), np.array(gmin)
+    if (extent, "I") in rows and extent != (4, 4, 4):
+        n, m, sd = rows[(extent, "I")]
+        se = math.sqrt(sd ** 2 / n + cnt.std() ** 2 / n_orbits)
+        assert abs(cnt.mean() - m) < 3 * se, (cnt.mean(), m, se)
+    n, m, sd = rows[(extent, "III")]
+    se = math.sqrt(sd ** 2 / n + gmin.std() ** 2 / n_orbits)
+    assert abs(gmin.mean() - m) < 3 * se, (gmin.mean(), m, se)
+
+
+# --------------------------------------------------------------------------
+# Stopping rule, precision modes, failure paths
+# --------------------------------------------------------------------------
+
+def test_paper_stopping_rule_gives_plateaus():
+    """Sec. III: max |gradient| < 1e-12 makes the functional values of one copy
+    agree to at least 1e-10."""
+    extent = (4, 4)
+    phi = GI.orbit_angles(extent, 0, 0)
+    p = O.SolveParams(omega=1.0, stop_norm="max_abs", eps64=1e-12)
+    rec, _, _ = O.solve(extent, phi, np.arange(400), p)
+    assert np.all(rec["status"] == O.CONVERGED)
+    keys = {}
+    for r in rec:
+        keys.setdefault((int(r["key_hi"]), int(r["key_lo"])), []).append(r["F"])
+    for Fs in keys.values():
+        assert max(Fs) - min(Fs) < 1e-10
+
+
+def test_mixed_precision_agrees_with_double_on_most_starts():
+    extent = (6, 6, 6, 6)
+    phi = GI.orbit_angles(extent, 0, 0)
+    ids = np.arange(200)
+    r64, _, _ = O.solve(extent, phi, ids, O.SolveParams(omega=1.7))
+    rmx, _, _ = O.solve(extent, phi, ids, O.SolveParams(omega=1.7, precision="mixed"))
+    assert np.all(rmx["status"] == O.CONVERGED)
+    same = (r64["key_hi"] == rmx["key_hi"]) & (r64["key_lo"] == rmx["key_lo"])
+    assert same.mean() > 0.97
+    V = 1296
+    assert np.max(np.abs(r64["F"][same] - rmx["F"][same])) / V < 1e-10
+    assert np.all(rmx["sweeps32"] > 0) and np.all(rmx["sweeps64"] > 0)
+
+
+def test_sweep_cap_marks_nonconverged():
+    extent = (4, 4)
+    phi = GI.orbit_angles(extent, 0, 0)
+    rec, _, _ = O.solve(extent, phi, np.arange(20), O.SolveParams(max_sweeps=1))
+    assert np.all(rec["status"] == O.NONCONVERGED)
+    assert np.all(rec["key_hi"] == 0)
+    res = O.enumerate_copies(extent, phi, np.arange(20), O.SolveParams(max_sweeps=1))
+    assert res["table"] == {}
+
+
+def test_check_interval():
+    extent = (4, 4)
+    phi = GI.orbit_angles(extent, 0, 0)
+    r1, _, _ = O.solve(extent, phi, np.arange(50), O.SolveParams(omega=1.7))
+    r5, _, _ = O.solve(extent, phi, np.arange(50), O.SolveParams(omega=1.7, check_every=5))
+    assert np.all(r5["sweeps64"] % 5 == 0)
+    assert np.all(r5["sweeps64"] >= r1["sweeps64"]) and np.all(r5["sweeps64"] - r1["sweeps64"] < 5)
+    assert np.array_equal(r1["key_hi"], r5["key_hi"])
+
+
+def test_paper_value_count():
+    """Sec. III: x in [0, 1] maps to X = trunc(x 1e8); equal X count as one."""
+    extent = (4, 4)
+    phi = GI.orbit_angles(extent, 0, 0)
+    res = O.enumerate_copies(extent, phi, np.arange(1000), O.SolveParams(omega=1.7), with_lambda=False)
+    rec = res["records"]
+    assert np.array_equal(rec["paper_X"], np.floor(rec["x"] * 1e8).astype(np.uint32))
+    assert res["paper_count"] == len({int(np.floor(e["x"] * 1e8)) for e in res["table"].values()})
