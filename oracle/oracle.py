@@ -15,7 +15,8 @@ This module adds, in numpy:
 * the first-Gribov-region test (abstract; Sec. I: minima, i.e. M_FP positive
   semidefinite with only the constant zero mode);
 * the copy table: distinct minima keyed by the integer key, with hit counts,
-  the lowest start id reaching each, and the paper's own count of distinct
+  the lowest start id reaching each, its representative start (lowest id at the
+  lowest functional value of the class), and the paper's own count of distinct
   values of x at resolution 1e-8 (Sec. III, last paragraphs).
 """
 from __future__ import annotations
@@ -272,44 +273,53 @@ def region_flags(lam2: float, tol: float = LAMBDA_TOL) -> int:
 # Enumeration of one orbit: per-start solves + copy table
 # --------------------------------------------------------------------------
 
+F_SPREAD_PER_SITE = 1e-9
+
+
 def enumerate_copies(extent, phi, start_ids, params: SolveParams, threads: int = 0,
-                     with_lambda: bool = True):
+                     with_lambda: bool = True, lambda_keys=None):
     """Run the listed starts and build the copy table.
 
+    A key can be reached by starts that stopped at different stationary
+    points of the same wrap class: relaxation may halt next to a saddle when
+    the divergence is already below the threshold there.  Copies are minima
+    (first Gribov region), so a copy is represented by the lowest start id
+    among its hits whose F lies within 1e-9 per site of the lowest F reaching
+    the key; F and lambda2 are that start's.  first_start is the lowest id
+    over all hits; a spread of F above 1e-9 per site sets FLAG_COLLISION.
+
+    lambda_keys: None (all copies) or a set of keys whose lambda2 is wanted.
     Returns dict with 'records' (per start), 'table' {(key_hi, key_lo): entry},
     'paper_count' (distinct trunc(x*1e8) over converged starts)."""
     ids = np.ascontiguousarray(start_ids, dtype=np.uint64)
     rec, g, _ = solve(extent, phi, ids, params, threads=threads, want_state=with_lambda)
-    table = {}
+    V = volume(extent)
+    hits = {}
     for s in range(ids.size):
         r = rec[s]
         if r["status"] != CONVERGED:
             continue
-        k = (int(r["key_hi"]), int(r["key_lo"]))
-        sid = int(ids[s])
-        e = table.get(k)
-        if e is None:
-            table[k] = dict(hits=1, first_start=sid, first_index=s, F=float(r["F"]),
-                            F_min=float(r["F"]), F_max=float(r["F"]))
-        else:
-            e["hits"] += 1
-            e["F_min"] = min(e["F_min"], float(r["F"]))
-            e["F_max"] = max(e["F_max"], float(r["F"]))
-            if sid < e["first_start"]:
-                e["first_start"], e["first_index"], e["F"] = sid, s, float(r["F"])
-    V = volume(extent)
-    for k, e in table.items():
+        hits.setdefault((int(r["key_hi"]), int(r["key_lo"])), []).append(s)
+    table = {}
+    for k, idx in hits.items():
+        Fs = np.array([rec["F"][s] for s in idx])
+        sids = np.array([int(ids[s]) for s in idx], dtype=np.uint64)
+        F_min, F_max = float(Fs.min()), float(Fs.max())
+        near = Fs - F_min <= F_SPREAD_PER_SITE * V
+        rep = idx[int(np.argmin(np.where(near, sids, np.iinfo(np.uint64).max)))]
+        e = dict(hits=len(idx), first_start=int(sids.min()), rep_start=int(ids[rep]), rep_index=rep,
+                 F=float(rec["F"][rep]), F_min=F_min, F_max=F_max)
         flags = 0
-        if with_lambda:
-            gs = g[e["first_index"]]
-            _, _, _, w = observe(extent, phi, theta_of(gs))
+        if with_lambda and (lambda_keys is None or k in lambda_keys):
+            _, _, _, w = observe(extent, phi, theta_of(g[rep]))
             lam0, lam2, lmax = fp_spectrum(extent, w)
             e["lambda2"], e["lambda_zero"], e["lambda_max"] = lam2, lam0, lmax
             flags |= region_flags(lam2)
-        if (e["F_max"] - e["F_min"]) / V > 1e-9:
+        if (F_max - F_min) / V > F_SPREAD_PER_SITE:
             flags |= FLAG_COLLISION
         e["flags"] = flags
         e["x"] = e["F"] / (len(extent) * V)
+        table[k] = e
     conv = rec["status"] == CONVERGED
     paper_count = int(np.unique(rec["paper_X"][conv]).size)
     return dict(records=rec, table=table, paper_count=paper_count, state=g)

@@ -462,3 +462,30 @@ def test_paper_value_count():
     rec = res["records"]
     assert np.array_equal(rec["paper_X"], np.floor(rec["x"] * 1e8).astype(np.uint32))
     assert res["paper_count"] == len({int(np.floor(e["x"] * 1e8)) for e in res["table"].values()})
+
+
+def test_saddle_stop_is_not_the_representative():
+    """Relaxation can halt next to a saddle once the divergence is already
+    below the threshold there.  On this orbit start 44981 stops at a point with
+    a negative FP eigenvalue whose wrap class is that of a genuine minimum
+    reached by seven other starts; run on to a far tighter threshold it rolls
+    into that minimum.  The table keeps the minimum as the copy and flags the
+    spread of F."""
+    extent = (4, 4, 4, 4)
+    V = 256
+    phi = GI.orbit_angles(extent, 0, 0)
+    ids = [4312, 5626, 8731, 13891, 44981, 81734, 89184, 96034]
+    rec, g, _ = O.solve(extent, phi, ids, O.SolveParams(omega=1.0), want_state=True)
+    assert len({(int(r["key_hi"]), int(r["key_lo"])) for r in rec}) == 1
+    lam = []
+    for s in range(len(ids)):
+        _, _, _, w = O.observe(extent, phi, O.theta_of(g[s]))
+        lam.append(O.fp_spectrum(extent, w)[1])
+    assert lam[4] < -1e-3 and all(l > 1e-3 for k, l in enumerate(lam) if k != 4)
+    assert rec["F"][4] - rec["F"].min() > 1e-9 * V
+    deep, _, _ = O.solve(extent, phi, [44981], O.SolveParams(omega=1.0, eps64=1e-26))
+    assert abs(deep["F"][0] - np.delete(rec["F"], 4).min()) < 1e-9
+    res = O.enumerate_copies(extent, phi, ids, O.SolveParams(omega=1.0))
+    (e,) = res["table"].values()
+    assert e["hits"] == 8 and e["first_start"] == 4312 and e["rep_start"] == 4312
+    assert e["flags"] & O.FLAG_COLLISION and e["flags"] & O.FLAG_IN_REGION
