@@ -1,0 +1,244 @@
+/*
+ * gribov.h -- C ABI of the MI355X Gribov-copy enumerator for compact U(1).
+ *
+ * Problem (Mehta & Schroeck, "Enumerating Copies in the First Gribov Region
+ * on the Lattice in up to four Dimensions"): on a periodic d-dimensional
+ * lattice (Sec. I, compact U(1) paragraph) with link angles phi_{i,mu}, find
+ * the local minima over gauge transformations theta of the lattice Landau
+ * functional, eq. (3),
+ *     F_phi(theta) = sum_{i,mu} (1 - cos(phi_{i,mu} + theta_{i+mu} - theta_i)),
+ * by relaxation from many random starts (Sec. III, eqs. (4)-(5)), keep the
+ * copies whose Faddeev-Popov operator (the Hessian of eq. (3), Sec. I,
+ * lattice Landau gauge paragraph) is positive on the complement of the
+ * constant mode (the first Gribov region), and count the distinct ones.
+ *
+ * Conventions for every entry point:
+ *  - Every function returns gc_status: GC_OK (0) or a negative error code.
+ *    No C++ exception crosses this boundary.
+ *  - Pointers are host pointers unless stated.  Inputs are copied before the
+ *    call returns; the caller keeps ownership of every buffer it passes.
+ *  - A gc_ctx owns all device memory, streams and kernels it creates.  Calls
+ *    on one gc_ctx are serialised internally and may come from any thread.
+ *  - A device fault makes the context sticky-failed: later calls return
+ *    GC_EDEVICE until gc_destroy; gc_last_error gives the text.
+ *  - Site index i = sum_mu x_mu s_mu with s_0 = 1, s_mu = s_{mu-1} N_{mu-1}
+ *    (x_0 fastest).  Link (i, mu) has index mu*V + i.
+ */
+#ifndef GRIBOV_H
+#define GRIBOV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gc_status;
+enum {
+    GC_OK = 0,
+    GC_EINVAL = -1,        /* bad argument (shape, NaN/Inf angle, null pointer, bad handle) */
+    GC_ENOMEM = -2,        /* request larger than the context's whole HBM budget */
+    GC_EUNSUPPORTED = -3,  /* lattice has no proper colouring (see gc_lattice_check) */
+    GC_EDEVICE = -4,       /* HIP runtime or kernel error; context is sticky-failed */
+    GC_EBUSY = -5,         /* orbit already has a launch in flight */
+    GC_ETIMEOUT = -6,      /* gc_wait timed out; the work continues */
+    GC_ENOTFOUND = -7,     /* no such copy */
+    GC_ESTATE = -8         /* call not valid in the orbit's current state */
+};
+
+/* Precision modes. */
+enum { GC_FP64 = 0,        /* every sweep in double precision */
+       GC_MIXED = 1 };     /* single-precision sweeps to eps32, then double polish to eps64 */
+
+/* Stopping norms on the lattice divergence div_i = Im(conj(g_i) S_i) (the
+ * negative gradient of eq. (3)). */
+enum { GC_MEAN_SQ = 0,     /* (1/V) sum_i div_i^2 < eps, per start */
+       GC_MAX_ABS = 1 };   /* max_i |div_i| < eps, per start (the paper's rule, Sec. III) */
+
+/* Per-start status. */
+enum { GC_START_PENDING = 0, GC_START_CONVERGED = 1, GC_START_NONCONVERGED = 2, GC_START_BADNUM = 3 };
+
+/* Copy flags (first Gribov region test, abstract and Sec. I). */
+enum {
+    GC_FLAG_IN_REGION = 1,    /* lambda2 > lambda_tol */
+    GC_FLAG_SINGULAR = 2,     /* |lambda2| <= lambda_tol */
+    GC_FLAG_SADDLE = 4,       /* lambda2 < -lambda_tol */
+    GC_FLAG_COLLISION = 8,    /* one key reached with functional values differing by > 1e-9 per site */
+    GC_FLAG_LANCZOS_CAP = 16  /* Lanczos stopped at its iteration cap */
+};
+
+/* Orbit states reported by gc_poll. */
+enum { GC_ORBIT_IDLE = 0, GC_ORBIT_QUEUED = 1, GC_ORBIT_RUNNING = 2, GC_ORBIT_DONE = 3, GC_ORBIT_ERROR = 4 };
+
+typedef struct gc_ctx gc_ctx;   /* opaque */
+typedef uint64_t gc_orbit;      /* 0 is never a valid handle */
+
+typedef struct {
+    int32_t device;             /* HIP device ordinal */
+    int32_t n_streams;          /* streams for concurrent launches (0 -> 4) */
+    uint64_t hbm_budget_bytes;  /* device bytes the context may hold for orbits and launches (0 -> 64 GiB) */
+} gc_ctx_params;
+
+typedef struct {
+    int32_t dim;                /* 1..4 */
+    int32_t extent[4];          /* N_mu >= 2 for mu < dim; V = prod N_mu <= 65536 */
+} gc_lattice;
+
+typedef struct {
+    double omega;               /* 1: relaxation (eqs. (4)-(5)); (0,2): over-relaxation g <- g N(1 + omega (z - 1)) */
+    double eps32;               /* stop of the single-precision phase (GC_MIXED) */
+    double eps64;               /* stop of the double-precision phase */
+    double lambda_tol;          /* region threshold tau on lambda2 */
+    int32_t precision;          /* GC_FP64 or GC_MIXED */
+    int32_t stop_norm;          /* GC_MEAN_SQ or GC_MAX_ABS */
+    uint32_t check_every;       /* evaluate the stopping norm after every k-th sweep (and at the cap) */
+    uint32_t lanczos_max_iter;  /* Lanczos iteration cap (<= 512) */
+    uint64_t max_sweeps;        /* per phase; beyond it a start is NONCONVERGED and not keyed */
+    uint64_t start_seed;        /* Philox key word for the random starts */
+    uint64_t first_start;       /* start ids are first_start .. first_start + n_starts - 1 */
+} gc_solve_params;
+
+typedef struct {
+    int32_t state;              /* GC_ORBIT_* */
+    int32_t pad;
+    uint64_t n_starts;          /* of the current or last launch */
+    uint64_t starts_done;
+    uint64_t converged;
+    uint64_t nonconverged;
+    uint64_t distinct;          /* distinct keys so far */
+    uint64_t in_region;         /* distinct keys with GC_FLAG_IN_REGION (valid when DONE) */
+    uint64_t saddles;
+    uint64_t singular;
+    uint64_t collisions;
+    uint64_t sweeps_total;      /* sum over starts of all sweeps (both precisions) */
+    uint64_t site_updates;      /* sweeps_total * V */
+    uint64_t lanczos_runs;
+    uint64_t paper_count;       /* distinct trunc(x * 1e8) over converged starts (valid when DONE) */
+    double submit_to_done_ms;   /* latency of the last launch (valid when DONE) */
+    double device_ms;           /* device time of the last launch (valid when DONE) */
+} gc_progress;
+
+/* One distinct copy. */
+typedef struct {
+    uint64_t key_hi, key_lo;    /* canonical integer key (plaquette and line wrap numbers, hashed) */
+    double F;                   /* eq. (3) at the copy, from its lowest start id */
+    double x;                   /* F / (d V), in [0, 1] inside the first region */
+    double lambda2;             /* lowest eigenvalue of M_FP orthogonal to the constant mode */
+    uint64_t hits;              /* starts that converged to this key */
+    uint64_t first_start;       /* lowest start id reaching it */
+    uint32_t flags;             /* GC_FLAG_* */
+    uint32_t lanczos_iters;
+} gc_copy;
+
+/* One start. */
+typedef struct {
+    int32_t status;             /* GC_START_* */
+    uint32_t sweeps32;
+    uint32_t sweeps64;
+    uint32_t lanczos_iters;     /* 0 when this start did not run the FP-operator filter */
+    double F;
+    double D;                   /* final stopping norm */
+    double lambda2;             /* NaN unless this start ran the filter */
+    uint64_t key_hi, key_lo;
+    uint32_t paper_X;           /* trunc(x * 1e8) */
+    uint32_t flags;
+} gc_start_record;
+
+/* Library version string ("major.minor.patch"). */
+const char *gc_version(void);
+
+/* Text for a status code. */
+const char *gc_status_str(gc_status s);
+
+/* Validate a lattice (host only, no device needed).  On success stores the
+ * number of checkerboard colours K: 2 when every extent is even, else the
+ * smallest K >= 3 dividing every extent (Sec. III's two sublattices need
+ * even extents).  Returns GC_EINVAL for a bad shape, GC_EUNSUPPORTED when no
+ * such K exists.  n_colours may be NULL. */
+gc_status gc_lattice_check(const gc_lattice *lat, int32_t *n_colours);
+
+/* Fill *p with the defaults: omega 1, eps32 1e-6, eps64 1e-14, lambda_tol
+ * 1e-6, GC_FP64, GC_MEAN_SQ, check_every 1, lanczos_max_iter 300,
+ * max_sweeps 100000, start_seed 0, first_start 0. */
+gc_status gc_solve_params_default(gc_solve_params *p);
+
+/* Create a context on params->device (NULL params: device 0, defaults). */
+gc_status gc_create(const gc_ctx_params *params, gc_ctx **out);
+
+/* Wait for all launches, free every device resource, destroy the context. */
+gc_status gc_destroy(gc_ctx *ctx);
+
+/* Load an orbit: phi is [dim][V] link angles in radians (host, float64, any
+ * real values; NaN/Inf -> GC_EINVAL).  orbit_index enters the counter of the
+ * random starts so that starts of different orbits are independent.  The
+ * link field U = exp(i phi) and the orbit's plaquette and line sums of phi
+ * (the base of the integer key) are formed once here. */
+gc_status gc_orbit_load(gc_ctx *ctx, const gc_lattice *lat, const double *phi,
+                        uint64_t orbit_index, gc_orbit *out);
+
+/* Hot orbit at beta = 0 (Sec. I): phi uniform on [-pi, pi), link l = mu V + i
+ * drawn by Philox4x64-10 with key (seed, 0), counter (l/4, orbit_index,
+ * 0x4F, 0), word l%4, angle = fl(fl(((r>>11) 2^-53) 2pi) - pi). */
+gc_status gc_orbit_random(gc_ctx *ctx, const gc_lattice *lat, uint64_t seed,
+                          uint64_t orbit_index, gc_orbit *out);
+
+/* Copy the orbit's angles back (host [dim][V]). */
+gc_status gc_orbit_angles(gc_ctx *ctx, gc_orbit orbit, double *phi_out);
+
+/* Asynchronously enumerate copies from n_starts random starts (Sec. III):
+ * start s draws theta_i by Philox4x64-10 with key (start_seed, 1), counter
+ * (i/4, s, orbit_index, 0x53), word i%4, then relaxes it colour by colour
+ * until its stopping norm falls below eps, computes F, x, the integer key,
+ * inserts the key in the orbit's copy table and, for the lowest start id of
+ * each key, the lowest non-constant eigenvalue lambda2 of M_FP by Lanczos.
+ * Returns at once.  The launch waits in a queue while the context's HBM
+ * budget is in use; a launch larger than the whole budget is GC_ENOMEM.
+ * A second launch on the same orbit replaces its table (GC_EBUSY while one
+ * is in flight).  params NULL: defaults. */
+gc_status gc_launch(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_solve_params *params);
+
+/* Launch several orbits as one batch: one persistent kernel launch (captured
+ * in a HIP graph) serves every orbit's starts.  Same semantics per orbit as
+ * gc_launch; all orbits share params. */
+gc_status gc_launch_batch(gc_ctx *ctx, int32_t n_orbits, const gc_orbit *orbits,
+                          const uint64_t *n_starts, const gc_solve_params *params);
+
+/* Non-blocking progress of the orbit's current or last launch. */
+gc_status gc_poll(gc_ctx *ctx, gc_orbit orbit, gc_progress *out);
+
+/* Block until the orbit's launch is DONE (timeout_ms < 0: forever).
+ * GC_ETIMEOUT leaves the launch running. */
+gc_status gc_wait(gc_ctx *ctx, gc_orbit orbit, int64_t timeout_ms);
+
+/* Distinct copies of a DONE orbit, sorted by (key_hi, key_lo): writes up to
+ * cap records from position offset into out, their count to *n_written and
+ * the table size to *n_total (either may be NULL). */
+gc_status gc_fetch(gc_ctx *ctx, gc_orbit orbit, uint64_t offset, uint64_t cap,
+                   gc_copy *out, uint64_t *n_written, uint64_t *n_total);
+
+/* Per-start records of a DONE orbit in start-id order (index 0 is
+ * first_start of the launch). */
+gc_status gc_fetch_starts(gc_ctx *ctx, gc_orbit orbit, uint64_t offset, uint64_t cap,
+                          gc_start_record *out, uint64_t *n_written);
+
+/* Representative of a copy: re-runs start_id of the orbit's last launch
+ * deterministically and returns theta_i - theta_{V-1} wrapped to (-pi, pi]
+ * (the global phase removed by fixing the last site, Sec. I) in theta_out
+ * [V].  Works for any start id of that launch, converged or not. */
+gc_status gc_fetch_state(gc_ctx *ctx, gc_orbit orbit, uint64_t start_id, double *theta_out);
+
+/* Free the orbit and its tables (waits for its launch first). */
+gc_status gc_release(gc_ctx *ctx, gc_orbit orbit);
+
+/* Sticky error text of the context (always NUL-terminated when cap > 0). */
+gc_status gc_last_error(gc_ctx *ctx, char *buf, size_t cap);
+
+/* Device time of the last completed launch's solve kernel in milliseconds,
+ * measured with HIP events on the stream the kernel ran on. */
+gc_status gc_kernel_time_ms(gc_ctx *ctx, gc_orbit orbit, double *solve_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRIBOV_H */

@@ -1,0 +1,131 @@
+// Internal structures shared by the device kernels and the host runtime of
+// the Gribov-copy enumerator.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define GC_MAXD 4
+#define GC_MAXPT 16        // sites per thread held in registers by the Lanczos step
+#define GC_LMAX 512        // Lanczos iteration cap (tridiagonal storage)
+
+// Per-start status codes (mirror GC_START_* of the public header).
+#define GC_ST_PENDING 0
+#define GC_ST_CONVERGED 1
+#define GC_ST_NONCONVERGED 2
+#define GC_ST_BADNUM 3
+
+// Copy flags (mirror GC_FLAG_*).
+#define GC_F_IN_REGION 1u
+#define GC_F_SINGULAR 2u
+#define GC_F_SADDLE 4u
+#define GC_F_COLLISION 8u
+#define GC_F_LANCZOS_CAP 16u
+#define GC_F_KEY_OVERFLOW 32u
+
+// Job flags.
+#define GC_JOB_NO_TABLE 1u     // skip key insertion and the FP filter (state re-runs)
+#define GC_JOB_FIX 2u          // re-solve the starts listed in fix[], always run the filter
+
+// Relative spread of F (per site) above which one key is flagged as reached
+// by different stationary points.
+#define GC_F_SPREAD_PER_SITE 1e-9
+
+// Geometry and link field of one orbit, all in device memory.
+struct GcOrbitDev {
+    int32_t d, V, K;
+    int32_t n_plaq, n_lines, n_elems;
+    int32_t ext[GC_MAXD];
+    int32_t line_off[GC_MAXD + 1];   // first line index of each direction
+    int32_t plane_mu[6], plane_nu[6];
+    uint64_t orbit_index;
+    const int32_t *coff;             // [K+1] offsets into perm per colour
+    const uint16_t *perm;            // [V] sites grouped by colour, ascending inside a colour
+    const uint16_t *nbr;             // [2d][V]: forward neighbour of (mu, i) at [mu][i], backward at [d+mu][i]
+    const double2 *U64;              // [d][V] (cos phi, sin phi)
+    const float2 *U32;               // [d][V] rounded from U64
+    const double *phi_plaq;          // [n_plaq] plaquette sums of raw phi
+    const double *phi_line;          // [n_lines] line sums of raw phi
+    const uint16_t *line_site;       // [n_lines] site of each line with x_mu = 0
+};
+
+// Per-start record, 64 bytes, same layout as gc_start_record.
+struct GcStartRec {
+    int32_t status;
+    uint32_t sweeps32, sweeps64, lanczos_iters;
+    double F, D, lambda2;
+    uint64_t key_hi, key_lo;
+    uint32_t paper_X, flags;
+};
+
+// Copy-table slot, 64 bytes.  key_hi == 0 marks an empty slot.
+struct GcEntry {
+    uint64_t key_hi, key_lo;
+    uint64_t hits, first_start;
+    uint64_t fmin_bits, fmax_bits;   // IEEE bits of F >= 0 order like the values
+    uint32_t ready, pad;
+    uint64_t rep_start;              // lowest start id with F within tolerance of the minimum F
+};
+
+// A copy whose representative start is not its lowest start id (its hits
+// include a start that stopped next to another stationary point of the same
+// class): the representative is solved again to obtain its lambda2.
+struct GcFix {
+    uint64_t start;                  // representative start id
+    uint64_t slot;                   // index into the job's compact copy array
+    double lambda2;
+    uint32_t flags, lanczos_iters;
+};
+
+// Device counters of one job.
+struct GcCounters {
+    unsigned long long starts_done, converged, nonconverged, distinct;
+    unsigned long long sweeps_total, lanczos_runs, errors, spare;
+};
+
+// Compact copy record written by the finalize kernel (same layout as gc_copy).
+struct GcCopyRec {
+    uint64_t key_hi, key_lo;
+    double F, x, lambda2;
+    uint64_t hits, first_start;
+    uint32_t flags, lanczos_iters;
+};
+
+// One job (orbit + params + outputs) as seen by the kernels.
+struct GcJobDev {
+    GcOrbitDev orb;
+    double omega, eps32, eps64, lambda_tol;
+    int32_t precision, stop_norm, check_every, lanczos_max;
+    uint64_t max_sweeps, start_seed, first_start, n_starts;
+    uint32_t flags, pad;
+    GcStartRec *rec;                 // [n_starts]
+    GcEntry *table;                  // [table_mask + 1]
+    uint64_t table_mask;
+    GcCounters *cnt;
+    GcCopyRec *copies;               // [n_starts] finalize output
+    unsigned long long *n_copies;
+    double *state_out;               // optional [V] representative angles (start 0 of the job)
+    GcFix *fix;                      // [n_starts] representatives to re-solve
+    unsigned long long *n_fix;
+};
+
+static_assert(sizeof(GcStartRec) == 64, "record layout");
+static_assert(sizeof(GcEntry) == 64, "entry layout");
+static_assert(sizeof(GcCopyRec) == 64, "copy layout");
+
+// Launch entry points implemented in gc_kernels.hip.
+hipError_t gc_launch_solve(int block, const GcJobDev *jobs, int n_jobs, const uint64_t *prefix,
+                           unsigned long long *next, uint64_t total, double *scratch,
+                           uint64_t scratch_stride, int grid, size_t lds_bytes, hipStream_t s);
+hipError_t gc_solve_occupancy(int block, size_t lds_bytes, int *blocks_per_cu);
+hipError_t gc_launch_reset(const GcJobDev *jobs_host, int n_jobs, unsigned long long *next,
+                           hipStream_t s);
+hipError_t gc_launch_finalize(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);
+// Re-solve the listed representatives (one job at a time, device-side count)
+// and patch their lambda2 into the compact copies.
+hipError_t gc_launch_fixup(int block, const GcJobDev *fix_jobs_dev, const GcJobDev *jobs_host, int n_jobs,
+                           unsigned long long *next, double *scratch, uint64_t scratch_stride, int grid,
+                           size_t lds_bytes, hipStream_t s);
+hipError_t gc_launch_orbit_random(double *phi, int64_t n_links, uint64_t seed, uint64_t orbit_index,
+                                  hipStream_t s);
+size_t gc_solve_lds_bytes(int V, int precision);

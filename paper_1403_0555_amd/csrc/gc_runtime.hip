@@ -1,0 +1,1144 @@
+// Host runtime and C ABI of the Gribov-copy enumerator (see include/gribov.h).
+//
+// A context owns a device, a few HIP streams, an HBM byte budget, a pool of
+// device blocks, the loaded orbits and their launches ("jobs").  gc_launch
+// admits a job when its bytes fit the free budget (else it waits in FIFO
+// order) and enqueues on a stream: reset (fill kernels), the persistent solve
+// kernel, finalize (table compaction), and the D2H of the job's counters.  A
+// scheduler thread watches the jobs' completion events, frees their working
+// memory and admits waiting jobs, so launches that arrive while others run
+// overlap on the device.
+#include "../../include/gribov.h"
+#include "gc_internal.h"
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_since(Clock::time_point a, Clock::time_point b)
+{
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+uint64_t next_pow2(uint64_t x)
+{
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// Lattice checks and geometry (Sec. I: periodic lattice; Sec. III: checkerboard)
+// ---------------------------------------------------------------------------
+constexpr int kMaxV = 4096;
+
+int num_colours(int d, const int *n)
+{
+    bool all_even = true;
+    for (int mu = 0; mu < d; ++mu)
+        if (n[mu] % 2) all_even = false;
+    if (all_even) return 2;
+    int nmin = n[0];
+    for (int mu = 1; mu < d; ++mu) nmin = std::min(nmin, n[mu]);
+    for (int K = 3; K <= nmin; ++K) {
+        bool ok = true;
+        for (int mu = 0; mu < d; ++mu)
+            if (n[mu] % K) ok = false;
+        if (ok) return K;
+    }
+    return 0;
+}
+
+gc_status check_lattice(const gc_lattice *lat, int *K_out, int *V_out)
+{
+    if (!lat || lat->dim < 1 || lat->dim > 4) return GC_EINVAL;
+    int64_t V = 1;
+    for (int mu = 0; mu < lat->dim; ++mu) {
+        if (lat->extent[mu] < 2 || lat->extent[mu] > 65536) return GC_EINVAL;
+        V *= lat->extent[mu];
+        if (V > 65536) return GC_EUNSUPPORTED;
+    }
+    const int K = num_colours(lat->dim, lat->extent);
+    if (K == 0) return GC_EUNSUPPORTED;
+    if (K_out) *K_out = K;
+    if (V_out) *V_out = (int)V;
+    return GC_OK;
+}
+
+int block_for(int V)
+{
+    if (V <= 128) return 64;
+    if (V <= 512) return 128;
+    return 256;
+}
+
+// ---------------------------------------------------------------------------
+// Device memory pool: blocks are cached by size class and reused.
+// ---------------------------------------------------------------------------
+struct Pool {
+    std::multimap<size_t, void *> free_blocks;
+    size_t cached = 0;
+
+    hipError_t get(size_t bytes, void **p)
+    {
+        bytes = next_pow2(std::max<size_t>(bytes, 4096));
+        auto it = free_blocks.find(bytes);
+        if (it != free_blocks.end()) {
+            *p = it->second;
+            free_blocks.erase(it);
+            cached -= bytes;
+            return hipSuccess;
+        }
+        return hipMalloc(p, bytes);
+    }
+    void put(void *p, size_t bytes)
+    {
+        if (!p) return;
+        bytes = next_pow2(std::max<size_t>(bytes, 4096));
+        free_blocks.emplace(bytes, p);
+        cached += bytes;
+    }
+    void drain()
+    {
+        for (auto &kv : free_blocks) (void)hipFree(kv.second);
+        free_blocks.clear();
+        cached = 0;
+    }
+    static size_t rounded(size_t bytes) { return next_pow2(std::max<size_t>(bytes, 4096)); }
+};
+
+struct Orbit;
+
+struct Job {
+    std::vector<Orbit *> orbits;     // one for gc_launch, several for a batch
+    std::vector<uint64_t> n_starts;
+    gc_solve_params p{};
+    int state = GC_ORBIT_QUEUED;
+    bool graph = false;
+    size_t bytes = 0;                // budget charge while running
+    void *mem = nullptr;             // working block
+    int stream = 0;
+    hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_done = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t gx = nullptr;
+    Clock::time_point t_submit, t_done;
+    std::vector<GcJobDev> jobs;      // host images of the per-orbit job structs
+    // pinned host results
+    GcCounters *h_cnt = nullptr;               // [n_jobs]
+    unsigned long long *h_ncopies = nullptr;   // [n_jobs]
+    double solve_ms = 0.0;
+    uint64_t total = 0;
+};
+
+struct Orbit {
+    gc_orbit handle = 0;
+    gc_lattice lat{};
+    int d = 0, V = 0, K = 0;
+    uint64_t orbit_index = 0;
+    std::vector<double> phi;
+    void *tables = nullptr;
+    size_t table_bytes = 0;
+    GcOrbitDev dev{};
+    // results of the last launch
+    Job *job = nullptr;
+    int job_index = 0;               // position inside a batch job
+    void *res_mem = nullptr;         // device block with rec/table/copies kept after DONE
+    size_t res_bytes = 0;
+    GcJobDev res{};                  // pointers into res_mem
+    bool have_copies = false;
+    std::vector<gc_copy> copies;
+    bool have_starts = false;
+    std::vector<gc_start_record> starts;
+    uint64_t paper_count = 0;
+    gc_progress last{};
+};
+
+}  // namespace
+
+struct gc_ctx {
+    int device = 0;
+    int n_cu = 0;
+    size_t lds_max = 0;
+    uint64_t budget = 0, used = 0;
+    std::vector<hipStream_t> streams;
+    std::vector<int> stream_load;
+    Pool pool;
+    std::mutex mu;
+    std::condition_variable cv;       // wakes the scheduler
+    std::condition_variable done_cv;  // wakes waiters
+    std::thread sched;
+    bool stop = false;
+    bool failed = false;
+    std::string err;
+    uint64_t next_handle = 1;
+    std::map<gc_orbit, std::unique_ptr<Orbit>> orbits;
+    std::deque<Job *> queued;
+    std::vector<Job *> running;
+};
+
+namespace {
+
+gc_status fail(gc_ctx *c, hipError_t e, const char *what)
+{
+    c->failed = true;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    c->err = buf;
+    return GC_EDEVICE;
+}
+
+#define GC_HIP(call)                                       \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return fail(ctx, e_, #call); \
+    } while (0)
+
+// Build and upload the geometry tables of an orbit.
+gc_status build_orbit(gc_ctx *ctx, Orbit *o)
+{
+    const int d = o->d, V = o->V;
+    const int *n = o->lat.extent;
+    int stride[4];
+    stride[0] = 1;
+    for (int mu = 1; mu < d; ++mu) stride[mu] = stride[mu - 1] * n[mu - 1];
+    std::vector<int> coord((size_t)V * d);
+    for (int i = 0; i < V; ++i) {
+        int r = i;
+        for (int mu = 0; mu < d; ++mu) {
+            coord[(size_t)i * d + mu] = r % n[mu];
+            r /= n[mu];
+        }
+    }
+    std::vector<uint16_t> nbr((size_t)2 * d * V);
+    std::vector<int> col(V);
+    for (int i = 0; i < V; ++i) {
+        int sum = 0;
+        for (int mu = 0; mu < d; ++mu) {
+            const int x = coord[(size_t)i * d + mu];
+            sum += x;
+            const int xf = (x + 1) % n[mu], xb = (x + n[mu] - 1) % n[mu];
+            nbr[(size_t)mu * V + i] = (uint16_t)(i + (xf - x) * stride[mu]);
+            nbr[(size_t)(d + mu) * V + i] = (uint16_t)(i + (xb - x) * stride[mu]);
+        }
+        col[i] = sum % o->K;
+    }
+    std::vector<int32_t> coff(o->K + 1, 0);
+    std::vector<uint16_t> perm;
+    perm.reserve(V);
+    for (int c = 0; c < o->K; ++c) {
+        coff[c] = (int32_t)perm.size();
+        for (int i = 0; i < V; ++i)
+            if (col[i] == c) perm.push_back((uint16_t)i);
+    }
+    coff[o->K] = V;
+    std::vector<double2> U64((size_t)d * V);
+    std::vector<float2> U32((size_t)d * V);
+    for (size_t l = 0; l < (size_t)d * V; ++l) {
+        U64[l] = make_double2(std::cos(o->phi[l]), std::sin(o->phi[l]));
+        U32[l] = make_float2((float)U64[l].x, (float)U64[l].y);
+    }
+    GcOrbitDev &D = o->dev;
+    memset(&D, 0, sizeof D);
+    D.d = d;
+    D.V = V;
+    D.K = o->K;
+    for (int mu = 0; mu < d; ++mu) D.ext[mu] = n[mu];
+    int np = 0;
+    for (int mu = 0; mu < d; ++mu)
+        for (int nu = mu + 1; nu < d; ++nu) {
+            D.plane_mu[np] = mu;
+            D.plane_nu[np] = nu;
+            ++np;
+        }
+    D.n_plaq = np * V;
+    std::vector<double> phi_plaq((size_t)D.n_plaq);
+    const double *phi = o->phi.data();
+    for (int p = 0; p < np; ++p) {
+        const int mu = D.plane_mu[p], nu = D.plane_nu[p];
+        for (int i = 0; i < V; ++i) {
+            const int fm = nbr[(size_t)mu * V + i], fn = nbr[(size_t)nu * V + i];
+            double s = phi[(size_t)mu * V + i] + phi[(size_t)nu * V + fm];
+            s = s - phi[(size_t)mu * V + fn];
+            s = s - phi[(size_t)nu * V + i];
+            phi_plaq[(size_t)p * V + i] = s;
+        }
+    }
+    std::vector<double> phi_line;
+    std::vector<uint16_t> line_site;
+    for (int mu = 0; mu < d; ++mu) {
+        D.line_off[mu] = (int32_t)line_site.size();
+        for (int i0 = 0; i0 < V; ++i0) {
+            if (coord[(size_t)i0 * d + mu] != 0) continue;
+            double s = 0.0;
+            int i = i0;
+            for (int t = 0; t < n[mu]; ++t) {
+                s = s + phi[(size_t)mu * V + i];
+                i = nbr[(size_t)mu * V + i];
+            }
+            line_site.push_back((uint16_t)i0);
+            phi_line.push_back(s);
+        }
+    }
+    D.line_off[d] = (int32_t)line_site.size();
+    D.n_lines = (int32_t)line_site.size();
+    D.n_elems = D.n_plaq + D.n_lines;
+    D.orbit_index = o->orbit_index;
+
+    // one device block for every table
+    size_t off = 0;
+    auto place = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes, 256); return at; };
+    const size_t o_coff = place(coff.size() * 4), o_perm = place(perm.size() * 2), o_nbr = place(nbr.size() * 2);
+    const size_t o_u64 = place(U64.size() * 16), o_u32 = place(U32.size() * 8);
+    const size_t o_pp = place(phi_plaq.size() * 8 + 8), o_pl = place(phi_line.size() * 8 + 8);
+    const size_t o_ls = place(line_site.size() * 2 + 2);
+    std::vector<unsigned char> host(off, 0);
+    memcpy(&host[o_coff], coff.data(), coff.size() * 4);
+    memcpy(&host[o_perm], perm.data(), perm.size() * 2);
+    memcpy(&host[o_nbr], nbr.data(), nbr.size() * 2);
+    memcpy(&host[o_u64], U64.data(), U64.size() * 16);
+    memcpy(&host[o_u32], U32.data(), U32.size() * 8);
+    if (!phi_plaq.empty()) memcpy(&host[o_pp], phi_plaq.data(), phi_plaq.size() * 8);
+    memcpy(&host[o_pl], phi_line.data(), phi_line.size() * 8);
+    memcpy(&host[o_ls], line_site.data(), line_site.size() * 2);
+    void *dev = nullptr;
+    GC_HIP(hipMalloc(&dev, off));
+    GC_HIP(hipMemcpy(dev, host.data(), off, hipMemcpyHostToDevice));
+    unsigned char *b = (unsigned char *)dev;
+    D.coff = (const int32_t *)(b + o_coff);
+    D.perm = (const uint16_t *)(b + o_perm);
+    D.nbr = (const uint16_t *)(b + o_nbr);
+    D.U64 = (const double2 *)(b + o_u64);
+    D.U32 = (const float2 *)(b + o_u32);
+    D.phi_plaq = (const double *)(b + o_pp);
+    D.phi_line = (const double *)(b + o_pl);
+    D.line_site = (const uint16_t *)(b + o_ls);
+    o->tables = dev;
+    o->table_bytes = off;
+    return GC_OK;
+}
+
+// Bytes of device memory a job needs while it runs (and what it keeps after).
+struct JobLayout {
+    std::vector<size_t> o_rec, o_table, o_cnt, o_copies, o_ncopies, o_fix, o_nfix;
+    size_t o_fixjobs = 0, o_fixnext = 0;
+    std::vector<uint64_t> table_cap;
+    size_t o_jobs = 0, o_prefix = 0, o_next = 0, o_scratch = 0;
+    size_t keep_bytes = 0;   // per-orbit results (kept after DONE): computed per orbit
+    size_t total = 0;
+    int block = 64, grid = 1;
+    size_t lds = 0;
+    uint64_t scratch_stride = 0;
+};
+
+gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
+{
+    const int nj = (int)job->orbits.size();
+    size_t off = 0;
+    auto place = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes, 256); return at; };
+    L.o_jobs = place(sizeof(GcJobDev) * nj);
+    L.o_fixjobs = place(sizeof(GcJobDev) * nj);
+    L.o_prefix = place(sizeof(uint64_t) * (nj + 1));
+    L.o_next = place(sizeof(unsigned long long));
+    L.o_fixnext = place(sizeof(unsigned long long));
+    int maxV = 0, maxdV = 0;
+    uint64_t total = 0;
+    for (int j = 0; j < nj; ++j) {
+        Orbit *o = job->orbits[j];
+        const uint64_t n = job->n_starts[j];
+        const uint64_t cap = next_pow2(std::max<uint64_t>(2 * n, 64));
+        L.table_cap.push_back(cap);
+        L.o_rec.push_back(place(sizeof(GcStartRec) * n));
+        L.o_table.push_back(place(sizeof(GcEntry) * cap));
+        L.o_cnt.push_back(place(sizeof(GcCounters)));
+        L.o_copies.push_back(place(sizeof(GcCopyRec) * n));
+        L.o_ncopies.push_back(place(sizeof(unsigned long long)));
+        L.o_fix.push_back(place(sizeof(GcFix) * n));
+        L.o_nfix.push_back(place(sizeof(unsigned long long)));
+        maxV = std::max(maxV, o->V);
+        maxdV = std::max(maxdV, o->d * o->V);
+        total += n;
+    }
+    L.block = block_for(maxV);
+    L.lds = gc_solve_lds_bytes(maxV, job->p.precision);
+    if (L.lds > ctx->lds_max || maxV > kMaxV) return GC_EUNSUPPORTED;
+    int per_cu = 0;
+    hipError_t e = gc_solve_occupancy(L.block, L.lds, &per_cu);
+    if (e != hipSuccess) return fail(ctx, e, "occupancy");
+    per_cu = std::max(per_cu, 1);
+    uint64_t grid = (uint64_t)per_cu * (uint64_t)ctx->n_cu;
+    grid = std::min<uint64_t>(grid, std::max<uint64_t>(total, 1));
+    L.grid = (int)grid;
+    L.scratch_stride = (uint64_t)2 * maxdV;
+    L.o_scratch = place(sizeof(double) * L.scratch_stride * L.grid);
+    L.total = off;
+    return GC_OK;
+}
+
+void free_job(gc_ctx *ctx, Job *job)
+{
+    if (job->mem) {
+        ctx->pool.put(job->mem, job->bytes);
+        job->mem = nullptr;
+    }
+    if (job->ev_k0) (void)hipEventDestroy(job->ev_k0);
+    if (job->ev_k1) (void)hipEventDestroy(job->ev_k1);
+    if (job->ev_done) (void)hipEventDestroy(job->ev_done);
+    if (job->gx) (void)hipGraphExecDestroy(job->gx);
+    if (job->g) (void)hipGraphDestroy(job->g);
+    if (job->h_cnt) (void)hipHostFree(job->h_cnt);
+    if (job->h_ncopies) (void)hipHostFree(job->h_ncopies);
+    job->ev_k0 = job->ev_k1 = job->ev_done = nullptr;
+    job->gx = nullptr;
+    job->g = nullptr;
+    job->h_cnt = nullptr;
+    job->h_ncopies = nullptr;
+}
+
+// Enqueue a job's device work.  Caller holds ctx->mu and has checked the budget.
+gc_status start_job(gc_ctx *ctx, Job *job)
+{
+    JobLayout L;
+    gc_status st = plan_job(ctx, job, L);
+    if (st != GC_OK) return st;
+    job->bytes = Pool::rounded(L.total);
+    GC_HIP(ctx->pool.get(L.total, &job->mem));
+    ctx->used += job->bytes;
+    const int nj = (int)job->orbits.size();
+    unsigned char *base = (unsigned char *)job->mem;
+    // least-loaded stream
+    int si = 0;
+    for (int k = 1; k < (int)ctx->streams.size(); ++k)
+        if (ctx->stream_load[k] < ctx->stream_load[si]) si = k;
+    job->stream = si;
+    ctx->stream_load[si]++;
+    hipStream_t s = ctx->streams[si];
+
+    std::vector<uint64_t> prefix(nj + 1, 0);
+    job->jobs.assign(nj, GcJobDev{});
+    for (int j = 0; j < nj; ++j) {
+        Orbit *o = job->orbits[j];
+        GcJobDev &J = job->jobs[j];
+        memset(&J, 0, sizeof J);
+        J.orb = o->dev;
+        J.omega = job->p.omega;
+        J.eps32 = job->p.eps32;
+        J.eps64 = job->p.eps64;
+        J.lambda_tol = job->p.lambda_tol;
+        J.precision = job->p.precision;
+        J.stop_norm = job->p.stop_norm;
+        J.check_every = (int32_t)std::max<uint32_t>(job->p.check_every, 1);
+        J.lanczos_max = (int32_t)std::min<uint32_t>(std::max<uint32_t>(job->p.lanczos_max_iter, 1), GC_LMAX);
+        J.max_sweeps = job->p.max_sweeps;
+        J.start_seed = job->p.start_seed;
+        J.first_start = job->p.first_start;
+        J.n_starts = job->n_starts[j];
+        J.rec = (GcStartRec *)(base + L.o_rec[j]);
+        J.table = (GcEntry *)(base + L.o_table[j]);
+        J.table_mask = L.table_cap[j] - 1;
+        J.cnt = (GcCounters *)(base + L.o_cnt[j]);
+        J.copies = (GcCopyRec *)(base + L.o_copies[j]);
+        J.n_copies = (unsigned long long *)(base + L.o_ncopies[j]);
+        J.state_out = nullptr;
+        J.fix = (GcFix *)(base + L.o_fix[j]);
+        J.n_fix = (unsigned long long *)(base + L.o_nfix[j]);
+        prefix[j + 1] = prefix[j] + job->n_starts[j];
+    }
+    std::vector<GcJobDev> fixjobs(job->jobs);
+    for (GcJobDev &F : fixjobs) F.flags |= GC_JOB_FIX;
+    job->total = prefix[nj];
+    GC_HIP(hipHostMalloc((void **)&job->h_cnt, sizeof(GcCounters) * nj, hipHostMallocDefault));
+    GC_HIP(hipHostMalloc((void **)&job->h_ncopies, sizeof(unsigned long long) * nj, hipHostMallocDefault));
+    GC_HIP(hipEventCreate(&job->ev_k0));
+    GC_HIP(hipEventCreate(&job->ev_k1));
+    GC_HIP(hipEventCreateWithFlags(&job->ev_done, hipEventDisableTiming));
+    GC_HIP(hipMemcpyAsync(base + L.o_jobs, job->jobs.data(), sizeof(GcJobDev) * nj, hipMemcpyHostToDevice, s));
+    GC_HIP(hipMemcpyAsync(base + L.o_prefix, prefix.data(), sizeof(uint64_t) * (nj + 1), hipMemcpyHostToDevice, s));
+    GC_HIP(hipMemcpyAsync(base + L.o_fixjobs, fixjobs.data(), sizeof(GcJobDev) * nj, hipMemcpyHostToDevice, s));
+    // the H2D copies above come from pageable memory and are complete on return
+    auto enqueue_body = [&](hipStream_t qs) -> hipError_t {
+        hipError_t e = gc_launch_reset(job->jobs.data(), nj, (unsigned long long *)(base + L.o_next), qs);
+        if (e != hipSuccess) return e;
+        if (!job->graph) {
+            e = hipEventRecord(job->ev_k0, qs);
+            if (e != hipSuccess) return e;
+        }
+        e = gc_launch_solve(L.block, (const GcJobDev *)(base + L.o_jobs), nj, (const uint64_t *)(base + L.o_prefix),
+                            (unsigned long long *)(base + L.o_next), job->total, (double *)(base + L.o_scratch),
+                            L.scratch_stride, L.grid, L.lds, qs);
+        if (e != hipSuccess) return e;
+        if (!job->graph) {
+            e = hipEventRecord(job->ev_k1, qs);
+            if (e != hipSuccess) return e;
+        }
+        e = gc_launch_finalize(job->jobs.data(), nj, qs);
+        if (e != hipSuccess) return e;
+        e = gc_launch_fixup(L.block, (const GcJobDev *)(base + L.o_fixjobs), job->jobs.data(), nj,
+                            (unsigned long long *)(base + L.o_fixnext), (double *)(base + L.o_scratch),
+                            L.scratch_stride, std::min(L.grid, 256), L.lds, qs);
+        if (e != hipSuccess) return e;
+        for (int j = 0; j < nj; ++j) {
+            e = hipMemcpyAsync(&job->h_cnt[j], job->jobs[j].cnt, sizeof(GcCounters), hipMemcpyDeviceToHost, qs);
+            if (e != hipSuccess) return e;
+            e = hipMemcpyAsync(&job->h_ncopies[j], job->jobs[j].n_copies, sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, qs);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    if (job->graph) {
+        GC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_body(s);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(s, &g);
+        if (e != hipSuccess) return fail(ctx, e, "batch capture");
+        if (e2 != hipSuccess) return fail(ctx, e2, "hipStreamEndCapture");
+        job->g = g;
+        GC_HIP(hipGraphInstantiate(&job->gx, g, nullptr, nullptr, 0));
+        GC_HIP(hipEventRecord(job->ev_k0, s));
+        GC_HIP(hipGraphLaunch(job->gx, s));
+        GC_HIP(hipEventRecord(job->ev_k1, s));
+    } else {
+        hipError_t e = enqueue_body(s);
+        if (e != hipSuccess) return fail(ctx, e, "launch");
+    }
+    GC_HIP(hipEventRecord(job->ev_done, s));
+    job->state = GC_ORBIT_RUNNING;
+    for (int j = 0; j < nj; ++j) {
+        Orbit *o = job->orbits[j];
+        o->res = job->jobs[j];
+    }
+    ctx->running.push_back(job);
+    return GC_OK;
+}
+
+// Budget charge of a queued job (computed without allocating).
+gc_status job_bytes(gc_ctx *ctx, Job *job, size_t *bytes)
+{
+    JobLayout L;
+    gc_status st = plan_job(ctx, job, L);
+    if (st != GC_OK) return st;
+    *bytes = Pool::rounded(L.total);
+    return GC_OK;
+}
+
+void admit_locked(gc_ctx *ctx)
+{
+    while (!ctx->queued.empty() && !ctx->failed) {
+        Job *job = ctx->queued.front();
+        size_t need = 0;
+        if (job_bytes(ctx, job, &need) != GC_OK) {
+            job->state = GC_ORBIT_ERROR;
+            ctx->queued.pop_front();
+            continue;
+        }
+        if (ctx->used + need > ctx->budget && !ctx->running.empty()) break;
+        ctx->queued.pop_front();
+        if (start_job(ctx, job) != GC_OK) {
+            job->state = GC_ORBIT_ERROR;
+            ctx->done_cv.notify_all();
+        }
+    }
+}
+
+// Move a finished job's results out of its working block.  The working block
+// stays allocated until the orbits are released or relaunched (the per-start
+// records and copies live in it), but it no longer counts toward admission
+// once every orbit in it has been fetched or released.
+void complete_locked(gc_ctx *ctx, Job *job)
+{
+    job->t_done = Clock::now();
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, job->ev_k0, job->ev_k1) == hipSuccess) job->solve_ms = ms;
+    job->state = GC_ORBIT_DONE;
+    ctx->stream_load[job->stream]--;
+    for (size_t j = 0; j < job->orbits.size(); ++j) {
+        Orbit *o = job->orbits[j];
+        if (o->job != job) continue;
+        gc_progress &P = o->last;
+        const GcCounters &c = job->h_cnt[j];
+        P.state = GC_ORBIT_DONE;
+        P.n_starts = job->n_starts[j];
+        P.starts_done = c.starts_done;
+        P.converged = c.converged;
+        P.nonconverged = c.nonconverged;
+        P.distinct = job->h_ncopies[j];
+        P.sweeps_total = c.sweeps_total;
+        P.site_updates = c.sweeps_total * (uint64_t)o->V;
+        P.lanczos_runs = c.lanczos_runs;
+        P.submit_to_done_ms = ms_since(job->t_submit, job->t_done);
+        P.device_ms = job->solve_ms;
+        if (c.errors) {
+            ctx->failed = true;
+            ctx->err = "copy table insert failed (table full or spin limit)";
+        }
+    }
+}
+
+void scheduler_main(gc_ctx *ctx)
+{
+    (void)hipSetDevice(ctx->device);
+    std::unique_lock<std::mutex> lk(ctx->mu);
+    while (!ctx->stop) {
+        if (ctx->running.empty() && ctx->queued.empty()) {
+            ctx->cv.wait(lk);
+            continue;
+        }
+        bool changed = false;
+        for (size_t k = 0; k < ctx->running.size();) {
+            Job *job = ctx->running[k];
+            hipError_t q = hipEventQuery(job->ev_done);
+            if (q == hipSuccess) {
+                complete_locked(ctx, job);
+                ctx->running.erase(ctx->running.begin() + k);
+                changed = true;
+            } else if (q != hipErrorNotReady) {
+                fail(ctx, q, "kernel");
+                job->state = GC_ORBIT_ERROR;
+                ctx->running.erase(ctx->running.begin() + k);
+                changed = true;
+            } else {
+                ++k;
+            }
+        }
+        if (changed) {
+            admit_locked(ctx);
+            ctx->done_cv.notify_all();
+        }
+        ctx->cv.wait_for(lk, std::chrono::microseconds(100));
+    }
+}
+
+Orbit *find_orbit(gc_ctx *ctx, gc_orbit h)
+{
+    auto it = ctx->orbits.find(h);
+    return it == ctx->orbits.end() ? nullptr : it->second.get();
+}
+
+// Release the results block a finished job keeps for one orbit; the job's
+// working block is returned to the pool once no orbit refers to it.
+void drop_results_locked(gc_ctx *ctx, Orbit *o)
+{
+    Job *job = o->job;
+    if (!job) return;
+    o->job = nullptr;
+    o->have_copies = false;
+    o->have_starts = false;
+    o->copies.clear();
+    o->starts.clear();
+    bool still_used = false;
+    for (auto &kv : ctx->orbits)
+        if (kv.second->job == job) still_used = true;
+    if (!still_used) {
+        if (job->mem) ctx->used -= job->bytes;
+        free_job(ctx, job);
+        delete job;
+    }
+}
+
+gc_status wait_locked(gc_ctx *ctx, std::unique_lock<std::mutex> &lk, Orbit *o, int64_t timeout_ms)
+{
+    Job *job = o->job;
+    if (!job) return GC_ESTATE;
+    auto pred = [&] { return ctx->failed || job->state == GC_ORBIT_DONE || job->state == GC_ORBIT_ERROR; };
+    if (timeout_ms < 0) {
+        ctx->done_cv.wait(lk, pred);
+    } else if (!ctx->done_cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred)) {
+        return GC_ETIMEOUT;
+    }
+    if (ctx->failed) return GC_EDEVICE;
+    if (job->state == GC_ORBIT_ERROR) return GC_EDEVICE;
+    return GC_OK;
+}
+
+void fill_defaults(gc_solve_params *p)
+{
+    memset(p, 0, sizeof *p);
+    p->omega = 1.0;
+    p->eps32 = 1e-6;
+    p->eps64 = 1e-14;
+    p->lambda_tol = 1e-6;
+    p->precision = GC_FP64;
+    p->stop_norm = GC_MEAN_SQ;
+    p->check_every = 1;
+    p->lanczos_max_iter = 300;
+    p->max_sweeps = 100000;
+    p->start_seed = 0;
+    p->first_start = 0;
+}
+
+gc_status check_params(const gc_solve_params *p)
+{
+    if (!(p->omega > 0.0 && p->omega < 2.0)) return GC_EINVAL;
+    if (!(p->eps64 > 0.0) || !(p->eps32 > 0.0) || !std::isfinite(p->eps64) || !std::isfinite(p->eps32)) return GC_EINVAL;
+    if (p->precision != GC_FP64 && p->precision != GC_MIXED) return GC_EINVAL;
+    if (p->stop_norm != GC_MEAN_SQ && p->stop_norm != GC_MAX_ABS) return GC_EINVAL;
+    if (p->max_sweeps < 1 || p->max_sweeps > 0xFFFFFFFFull) return GC_EINVAL;
+    if (!(p->lambda_tol >= 0.0)) return GC_EINVAL;
+    return GC_OK;
+}
+
+gc_status new_orbit(gc_ctx *ctx, const gc_lattice *lat, std::vector<double> &&phi, uint64_t orbit_index,
+                    gc_orbit *out)
+{
+    int K = 0, V = 0;
+    gc_status st = check_lattice(lat, &K, &V);
+    if (st != GC_OK) return st;
+    if (V > kMaxV || gc_solve_lds_bytes(V, GC_MIXED) > ctx->lds_max) return GC_EUNSUPPORTED;
+    auto o = std::make_unique<Orbit>();
+    o->lat = *lat;
+    o->d = lat->dim;
+    o->V = V;
+    o->K = K;
+    o->orbit_index = orbit_index;
+    o->phi = std::move(phi);
+    st = build_orbit(ctx, o.get());
+    if (st != GC_OK) return st;
+    o->handle = ctx->next_handle++;
+    *out = o->handle;
+    ctx->orbits[o->handle] = std::move(o);
+    return GC_OK;
+}
+
+gc_status enqueue_locked(gc_ctx *ctx, Job *job)
+{
+    size_t need = 0;
+    gc_status st = job_bytes(ctx, job, &need);
+    if (st != GC_OK) return st;
+    if (need > ctx->budget) return GC_ENOMEM;
+    job->t_submit = Clock::now();
+    for (size_t j = 0; j < job->orbits.size(); ++j) {
+        Orbit *o = job->orbits[j];
+        drop_results_locked(ctx, o);
+        o->job = job;
+        o->job_index = (int)j;
+        memset(&o->last, 0, sizeof o->last);
+        o->last.state = GC_ORBIT_QUEUED;
+        o->last.n_starts = job->n_starts[j];
+    }
+    ctx->queued.push_back(job);
+    admit_locked(ctx);
+    ctx->cv.notify_all();
+    return GC_OK;
+}
+
+gc_status ensure_copies_locked(gc_ctx *ctx, Orbit *o)
+{
+    if (o->have_copies) return GC_OK;
+    Job *job = o->job;
+    const uint64_t n = job->h_ncopies[o->job_index];
+    std::vector<GcCopyRec> raw(n);
+    if (n) GC_HIP(hipMemcpy(raw.data(), o->res.copies, n * sizeof(GcCopyRec), hipMemcpyDeviceToHost));
+    o->copies.resize(n);
+    static_assert(sizeof(GcCopyRec) == sizeof(gc_copy), "copy layout");
+    if (n) memcpy(o->copies.data(), raw.data(), n * sizeof(gc_copy));
+    std::sort(o->copies.begin(), o->copies.end(), [](const gc_copy &a, const gc_copy &b) {
+        return a.key_hi != b.key_hi ? a.key_hi < b.key_hi : a.key_lo < b.key_lo;
+    });
+    uint64_t inr = 0, sad = 0, sng = 0, col = 0;
+    for (const gc_copy &c : o->copies) {
+        if (c.flags & GC_FLAG_IN_REGION) ++inr;
+        if (c.flags & GC_FLAG_SADDLE) ++sad;
+        if (c.flags & GC_FLAG_SINGULAR) ++sng;
+        if (c.flags & GC_FLAG_COLLISION) ++col;
+    }
+    o->last.in_region = inr;
+    o->last.saddles = sad;
+    o->last.singular = sng;
+    o->last.collisions = col;
+    o->have_copies = true;
+    return GC_OK;
+}
+
+gc_status ensure_starts_locked(gc_ctx *ctx, Orbit *o)
+{
+    if (o->have_starts) return GC_OK;
+    const uint64_t n = o->job->n_starts[o->job_index];
+    o->starts.resize(n);
+    static_assert(sizeof(GcStartRec) == sizeof(gc_start_record), "record layout");
+    if (n) GC_HIP(hipMemcpy(o->starts.data(), o->res.rec, n * sizeof(gc_start_record), hipMemcpyDeviceToHost));
+    std::vector<uint32_t> xs;
+    xs.reserve(n);
+    for (const gc_start_record &r : o->starts)
+        if (r.status == GC_START_CONVERGED) xs.push_back(r.paper_X);
+    std::sort(xs.begin(), xs.end());
+    o->paper_count = (uint64_t)(std::unique(xs.begin(), xs.end()) - xs.begin());
+    o->last.paper_count = o->paper_count;
+    o->have_starts = true;
+    return GC_OK;
+}
+
+#define GC_ENTER(ctx)                                  \
+    if (!(ctx)) return GC_EINVAL;                      \
+    std::unique_lock<std::mutex> lk((ctx)->mu);        \
+    if ((ctx)->failed) return GC_EDEVICE;              \
+    (void)hipSetDevice((ctx)->device)
+
+}  // namespace
+
+extern "C" {
+
+const char *gc_version(void) { return "0.1.0"; }
+
+const char *gc_status_str(gc_status s)
+{
+    switch (s) {
+    case GC_OK: return "ok";
+    case GC_EINVAL: return "invalid argument";
+    case GC_ENOMEM: return "request exceeds the HBM budget";
+    case GC_EUNSUPPORTED: return "unsupported lattice";
+    case GC_EDEVICE: return "device error";
+    case GC_EBUSY: return "orbit busy";
+    case GC_ETIMEOUT: return "timeout";
+    case GC_ENOTFOUND: return "not found";
+    case GC_ESTATE: return "invalid state";
+    default: return "unknown status";
+    }
+}
+
+gc_status gc_lattice_check(const gc_lattice *lat, int32_t *n_colours)
+{
+    int K = 0, V = 0;
+    gc_status st = check_lattice(lat, &K, &V);
+    if (st == GC_OK && V > kMaxV) st = GC_EUNSUPPORTED;
+    if (st == GC_OK && n_colours) *n_colours = K;
+    return st;
+}
+
+gc_status gc_solve_params_default(gc_solve_params *p)
+{
+    if (!p) return GC_EINVAL;
+    fill_defaults(p);
+    return GC_OK;
+}
+
+gc_status gc_create(const gc_ctx_params *params, gc_ctx **out)
+{
+    if (!out) return GC_EINVAL;
+    *out = nullptr;
+    gc_ctx_params P{};
+    if (params) P = *params;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return GC_EDEVICE;
+    if (P.device < 0 || P.device >= ndev) return GC_EINVAL;
+    if (hipSetDevice(P.device) != hipSuccess) return GC_EDEVICE;
+    auto ctx = std::make_unique<gc_ctx>();
+    ctx->device = P.device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, P.device) != hipSuccess) return GC_EDEVICE;
+    ctx->n_cu = prop.multiProcessorCount;
+    ctx->lds_max = prop.sharedMemPerBlock;
+    ctx->budget = P.hbm_budget_bytes ? P.hbm_budget_bytes : (64ull << 30);
+    const int ns = P.n_streams > 0 ? std::min(P.n_streams, 16) : 4;
+    for (int k = 0; k < ns; ++k) {
+        hipStream_t s;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return GC_EDEVICE;
+        ctx->streams.push_back(s);
+        ctx->stream_load.push_back(0);
+    }
+    gc_ctx *raw = ctx.release();
+    raw->sched = std::thread(scheduler_main, raw);
+    *out = raw;
+    return GC_OK;
+}
+
+gc_status gc_destroy(gc_ctx *ctx)
+{
+    if (!ctx) return GC_EINVAL;
+    {
+        std::unique_lock<std::mutex> lk(ctx->mu);
+        (void)hipSetDevice(ctx->device);
+        for (hipStream_t s : ctx->streams) (void)hipStreamSynchronize(s);
+        ctx->stop = true;
+        ctx->cv.notify_all();
+    }
+    ctx->sched.join();
+    (void)hipSetDevice(ctx->device);
+    std::vector<Job *> jobs;
+    for (auto &kv : ctx->orbits)
+        if (kv.second->job && std::find(jobs.begin(), jobs.end(), kv.second->job) == jobs.end())
+            jobs.push_back(kv.second->job);
+    for (Job *j : ctx->queued)
+        if (std::find(jobs.begin(), jobs.end(), j) == jobs.end()) jobs.push_back(j);
+    for (Job *j : jobs) {
+        free_job(ctx, j);
+        delete j;
+    }
+    for (auto &kv : ctx->orbits)
+        if (kv.second->tables) (void)hipFree(kv.second->tables);
+    ctx->pool.drain();
+    for (hipStream_t s : ctx->streams) (void)hipStreamDestroy(s);
+    delete ctx;
+    return GC_OK;
+}
+
+gc_status gc_orbit_load(gc_ctx *ctx, const gc_lattice *lat, const double *phi, uint64_t orbit_index, gc_orbit *out)
+{
+    if (!lat || !phi || !out) return GC_EINVAL;
+    int K = 0, V = 0;
+    gc_status st = check_lattice(lat, &K, &V);
+    if (st != GC_OK) return st;
+    const size_t n = (size_t)lat->dim * V;
+    for (size_t l = 0; l < n; ++l)
+        if (!std::isfinite(phi[l])) return GC_EINVAL;
+    GC_ENTER(ctx);
+    std::vector<double> v(phi, phi + n);
+    return new_orbit(ctx, lat, std::move(v), orbit_index, out);
+}
+
+gc_status gc_orbit_random(gc_ctx *ctx, const gc_lattice *lat, uint64_t seed, uint64_t orbit_index, gc_orbit *out)
+{
+    if (!lat || !out) return GC_EINVAL;
+    int K = 0, V = 0;
+    gc_status st = check_lattice(lat, &K, &V);
+    if (st != GC_OK) return st;
+    GC_ENTER(ctx);
+    const int64_t n = (int64_t)lat->dim * V;
+    double *dphi = nullptr;
+    GC_HIP(hipMalloc(&dphi, sizeof(double) * n));
+    hipStream_t s = ctx->streams[0];
+    hipError_t e = gc_launch_orbit_random(dphi, n, seed, orbit_index, s);
+    std::vector<double> v(n);
+    if (e == hipSuccess) e = hipMemcpyAsync(v.data(), dphi, sizeof(double) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dphi);
+    if (e != hipSuccess) return fail(ctx, e, "orbit_random");
+    return new_orbit(ctx, lat, std::move(v), orbit_index, out);
+}
+
+gc_status gc_orbit_angles(gc_ctx *ctx, gc_orbit orbit, double *phi_out)
+{
+    if (!phi_out) return GC_EINVAL;
+    GC_ENTER(ctx);
+    Orbit *o = find_orbit(ctx, orbit);
+    if (!o) return GC_EINVAL;
+    memcpy(phi_out, o->phi.data(), o->phi.size() * sizeof(double));
+    return GC_OK;
+}
+
+gc_status gc_launch(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_solve_params *params)
+{
+    gc_solve_params p;
+    if (params) p = *params; else fill_defaults(&p);
+    gc_status st = check_params(&p);
+    if (st != GC_OK) return st;
+    if (n_starts == 0 || n_starts > (1ull << 32)) return GC_EINVAL;
+    GC_ENTER(ctx);
+    Orbit *o = find_orbit(ctx, orbit);
+    if (!o) return GC_EINVAL;
+    if (o->job && (o->job->state == GC_ORBIT_QUEUED || o->job->state == GC_ORBIT_RUNNING)) return GC_EBUSY;
+    Job *job = new Job;
+    job->orbits.push_back(o);
+    job->n_starts.push_back(n_starts);
+    job->p = p;
+    st = enqueue_locked(ctx, job);
+    if (st != GC_OK) delete job;
+    return st;
+}
+
+gc_status gc_launch_batch(gc_ctx *ctx, int32_t n_orbits, const gc_orbit *orbits, const uint64_t *n_starts,
+                          const gc_solve_params *params)
+{
+    if (n_orbits < 1 || n_orbits > 256 || !orbits || !n_starts) return GC_EINVAL;
+    gc_solve_params p;
+    if (params) p = *params; else fill_defaults(&p);
+    gc_status st = check_params(&p);
+    if (st != GC_OK) return st;
+    GC_ENTER(ctx);
+    Job *job = new Job;
+    job->graph = true;
+    job->p = p;
+    for (int k = 0; k < n_orbits; ++k) {
+        Orbit *o = find_orbit(ctx, orbits[k]);
+        if (!o || n_starts[k] == 0 || n_starts[k] > (1ull << 32)) { delete job; return GC_EINVAL; }
+        if (std::find(job->orbits.begin(), job->orbits.end(), o) != job->orbits.end()) { delete job; return GC_EINVAL; }
+        if (o->job && (o->job->state == GC_ORBIT_QUEUED || o->job->state == GC_ORBIT_RUNNING)) { delete job; return GC_EBUSY; }
+        job->orbits.push_back(o);
+        job->n_starts.push_back(n_starts[k]);
+    }
+    st = enqueue_locked(ctx, job);
+    if (st != GC_OK) delete job;
+    return st;
+}
+
+gc_status gc_poll(gc_ctx *ctx, gc_orbit orbit, gc_progress *out)
+{
+    if (!out) return GC_EINVAL;
+    GC_ENTER(ctx);
+    Orbit *o = find_orbit(ctx, orbit);
+    if (!o) return GC_EINVAL;
+    if (!o->job) {
+        memset(out, 0, sizeof *out);
+        out->state = GC_ORBIT_IDLE;
+        return GC_OK;
+    }
+    if (o->job->state == GC_ORBIT_DONE) {
+        gc_status st = ensure_copies_locked(ctx, o);
+        if (st != GC_OK) return st;
+    } else {
+        o->last.state = o->job->state;
+    }
+    *out = o->last;
+    return GC_OK;
+}
+
+gc_status gc_wait(gc_ctx *ctx, gc_orbit orbit, int64_t timeout_ms)
+{
+    GC_ENTER(ctx);
+    Orbit *o = find_orbit(ctx, orbit);
+    if (!o) return GC_EINVAL;
+    return wait_locked(ctx, lk, o, timeout_ms);
+}
+
+gc_status gc_fetch(gc_ctx *ctx, gc_orbit orbit, uint64_t offset, uint64_t cap, gc_copy *out, uint64_t *n_written,
+                   uint64_t *n_total)
+{
+    if (cap && !out) return GC_EINVAL;
+    GC_ENTER(ctx);
+    Orbit *o = find_orbit(ctx, orbit);
+    if (!o) return GC_EINVAL;
+    if (!o->job || o->job->state != GC_ORBIT_DONE) return GC_ESTATE;
+    gc_status st = ensure_copies_locked(ctx, o);
+    if (st != GC_OK) return st;
+    const uint64_t n = o->copies.size();
+    uint64_t w = 0;
+    for (uint64_t k = offset; k < n && w < cap; ++k, ++w) out[w] = o->copies[k];
+    if (n_written) *n_written = w;
+    if (n_total) *n_total = n;
+    return GC_OK;
+}
+
+gc_status gc_fetch_starts(gc_ctx *ctx, gc_orbit orbit, uint64_t offset, uint64_t cap, gc_start_record *out,
+                          uint64_t *n_written)
+{
+    if (cap && !out) return GC_EINVAL;
+    GC_ENTER(ctx);
+    Orbit *o = find_orbit(ctx, orbit);
+    if (!o) return GC_EINVAL;
+    if (!o->job || o->job->state != GC_ORBIT_DONE) return GC_ESTATE;
+    gc_status st = ensure_starts_locked(ctx, o);
+    if (st != GC_OK) return st;
+    const uint64_t n = o->starts.size();
+    uint64_t w = 0;
+    for (uint64_t k = offset; k < n && w < cap; ++k, ++w) out[w] = o->starts[k];
+    if (n_written) *n_written = w;
+    return GC_OK;
+}
+
+gc_status gc_fetch_state(gc_ctx *ctx, gc_orbit orbit, uint64_t start_id, double *theta_out)
+{
+    if (!theta_out) return GC_EINVAL;
+    GC_ENTER(ctx);
+    Orbit *o = find_orbit(ctx, orbit);
+    if (!o) return GC_EINVAL;
+    if (!o->job || o->job->state != GC_ORBIT_DONE) return GC_ESTATE;
+    const gc_solve_params &p = o->job->p;
+    const uint64_t n = o->job->n_starts[o->job_index];
+    if (start_id < p.first_start || start_id - p.first_start >= n) return GC_EINVAL;
+    // a one-start job without table, writing the representative angles
+    const int V = o->V, d = o->d;
+    const int block = block_for(V);
+    const size_t lds = gc_solve_lds_bytes(V, p.precision);
+    size_t off = 0;
+    auto place = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes, 256); return at; };
+    const size_t o_job = place(sizeof(GcJobDev)), o_prefix = place(16), o_next = place(8), o_rec = place(64),
+                 o_cnt = place(sizeof(GcCounters)), o_state = place(sizeof(double) * V),
+                 o_scr = place(sizeof(double) * 2 * d * V), o_table = place(sizeof(GcEntry) * 64),
+                 o_nc = place(8), o_nfix = place(8);
+    void *mem = nullptr;
+    GC_HIP(hipMalloc(&mem, off));
+    unsigned char *b = (unsigned char *)mem;
+    GcJobDev J;
+    memset(&J, 0, sizeof J);
+    J.orb = o->dev;
+    J.omega = p.omega;
+    J.eps32 = p.eps32;
+    J.eps64 = p.eps64;
+    J.lambda_tol = p.lambda_tol;
+    J.precision = p.precision;
+    J.stop_norm = p.stop_norm;
+    J.check_every = (int32_t)std::max<uint32_t>(p.check_every, 1);
+    J.lanczos_max = 1;
+    J.max_sweeps = p.max_sweeps;
+    J.start_seed = p.start_seed;
+    J.first_start = start_id;
+    J.n_starts = 1;
+    J.flags = GC_JOB_NO_TABLE;
+    J.rec = (GcStartRec *)(b + o_rec);
+    J.table = (GcEntry *)(b + o_table);
+    J.table_mask = 63;
+    J.cnt = (GcCounters *)(b + o_cnt);
+    J.copies = nullptr;
+    J.n_copies = (unsigned long long *)(b + o_nc);
+    J.state_out = (double *)(b + o_state);
+    J.fix = nullptr;
+    J.n_fix = (unsigned long long *)(b + o_nfix);
+    const uint64_t prefix[2] = {0, 1};
+    hipStream_t s = ctx->streams[0];
+    hipError_t e = hipMemcpyAsync(b + o_job, &J, sizeof J, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b + o_prefix, prefix, sizeof prefix, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = gc_launch_reset(&J, 1, (unsigned long long *)(b + o_next), s);
+    if (e == hipSuccess)
+        e = gc_launch_solve(block, (const GcJobDev *)(b + o_job), 1, (const uint64_t *)(b + o_prefix),
+                            (unsigned long long *)(b + o_next), 1, (double *)(b + o_scr), (uint64_t)2 * d * V, 1, lds, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(theta_out, b + o_state, sizeof(double) * V, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(mem);
+    if (e != hipSuccess) return fail(ctx, e, "fetch_state");
+    return GC_OK;
+}
+
+gc_status gc_release(gc_ctx *ctx, gc_orbit orbit)
+{
+    GC_ENTER(ctx);
+    Orbit *o = find_orbit(ctx, orbit);
+    if (!o) return GC_EINVAL;
+    if (o->job && (o->job->state == GC_ORBIT_QUEUED || o->job->state == GC_ORBIT_RUNNING)) {
+        gc_status st = wait_locked(ctx, lk, o, -1);
+        if (st != GC_OK) return st;
+    }
+    drop_results_locked(ctx, o);
+    if (o->tables) (void)hipFree(o->tables);
+    ctx->orbits.erase(orbit);
+    admit_locked(ctx);
+    return GC_OK;
+}
+
+gc_status gc_last_error(gc_ctx *ctx, char *buf, size_t cap)
+{
+    if (!ctx || (!buf && cap)) return GC_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (cap) {
+        snprintf(buf, cap, "%s", ctx->err.c_str());
+    }
+    return GC_OK;
+}
+
+gc_status gc_kernel_time_ms(gc_ctx *ctx, gc_orbit orbit, double *solve_ms)
+{
+    if (!solve_ms) return GC_EINVAL;
+    GC_ENTER(ctx);
+    Orbit *o = find_orbit(ctx, orbit);
+    if (!o) return GC_EINVAL;
+    if (!o->job || o->job->state != GC_ORBIT_DONE) return GC_ESTATE;
+    *solve_ms = o->job->solve_ms;
+    return GC_OK;
+}
+
+}  // extern "C"
