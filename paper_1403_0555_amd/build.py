@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgribov.so")
-SOURCES = ["gc_kernels.hip", "gc_runtime.hip"]
+SOURCES = ["gc_relax_wg.hip", "gc_wave.hip", "gc_post.hip", "gc_runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1,0 +1,176 @@
+// Device helpers shared by the enumerator's kernels.
+#pragma once
+
+#include "gc_internal.h"
+
+#include <math.h>
+
+namespace gc {
+
+constexpr double kPi = 3.14159265358979311599796346854;
+constexpr double kTwoPi = 6.28318530717958623199592693709;
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 64x64 -> 128-bit products, key bumped by the Weyl constants each round.
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+        const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+}
+
+// Uniform angle in [-pi, pi): fl(fl(u 2pi) - pi), u = (r >> 11) 2^-53, with
+// contraction off so that the product is rounded before the subtraction.
+__device__ __forceinline__ double angle_of(uint64_t r)
+{
+#pragma clang fp contract(off)
+    const double u = (double)(r >> 11) * 0x1.0p-53;
+    const double t = u * kTwoPi;
+    return t - kPi;
+}
+
+// SplitMix64 output function (Steele, Lea, Flood 2014).
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// Random start angle of site i of start sid (Philox block i/4, word i%4).
+__device__ __forceinline__ void start_block(uint64_t start_seed, uint64_t sid, uint64_t orbit_index, uint64_t b,
+                                            uint64_t out[4])
+{
+    out[0] = b;
+    out[1] = sid;
+    out[2] = orbit_index;
+    out[3] = 0x53ULL;
+    philox4x64_10(out, start_seed, 1ULL);
+}
+
+// Wavefront-level ordering of LDS traffic: every lane's earlier LDS writes
+// are visible to every lane's later reads (LDS instructions of one wave
+// execute in order; this keeps the compiler from reordering them).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cross-lane ordering of global-memory traffic inside one wavefront.
+__device__ __forceinline__ void wave_sync_global()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Butterfly reductions over the 64 lanes; every lane ends with the same value
+// and the association order depends only on the lane count.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ int wave_min_int(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// A zero the optimiser cannot see through.  Indexing per-site tables with it
+// inside a loop keeps them from being hoisted into registers.
+__device__ __forceinline__ int opaque_zero()
+{
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    return z;
+}
+
+template <typename R> struct cx;
+template <> struct cx<float> { using T = float2; };
+template <> struct cx<double> { using T = double2; };
+
+__device__ __forceinline__ float rsq(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
+
+// Local maximisation of eqs. (4)-(5) in the eq. (3) convention: from the
+// staple S, g <- S/|S| (omega = 1) or the over-relaxed
+// g <- g N(1 + omega (z - 1)), z = conj(g) S/|S|, N(w) = w/|w|.  |S| = 0
+// leaves g unchanged.
+template <typename R>
+__device__ __forceinline__ typename cx<R>::T local_update(typename cx<R>::T g0, typename cx<R>::T s, R omega,
+                                                          bool relax)
+{
+    using C = typename cx<R>::T;
+    const R n2 = s.x * s.x + s.y * s.y;
+    if (n2 == (R)0) return g0;
+    const R r = rsq(n2);
+    const R hx = s.x * r, hy = s.y * r;
+    C g;
+    if (relax) {
+        g.x = hx;
+        g.y = hy;
+    } else {
+        const R zx = g0.x * hx + g0.y * hy;
+        const R zy = g0.x * hy - g0.y * hx;
+        R wx = (R)1 + omega * (zx - (R)1);
+        R wy = omega * zy;
+        const R rw = rsq(wx * wx + wy * wy);
+        wx *= rw;
+        wy *= rw;
+        g.x = g0.x * wx - g0.y * wy;
+        g.y = g0.x * wy + g0.y * wx;
+    }
+    return g;
+}
+
+// Per-start bookkeeping shared by the relax kernels (one lane calls).
+__device__ __forceinline__ void record_relax(const GcJobDev &J, uint64_t local, int status, uint64_t sw32,
+                                             uint64_t sw64, double D)
+{
+    GcStartRec r = {};
+    r.status = status;
+    r.sweeps32 = (uint32_t)sw32;
+    r.sweeps64 = (uint32_t)sw64;
+    r.D = D;
+    r.lambda2 = NAN;
+    J.rec[local] = r;
+    atomicAdd(&J.cnt->starts_done, 1ULL);
+    atomicAdd(status == GC_ST_CONVERGED ? &J.cnt->converged : &J.cnt->nonconverged, 1ULL);
+    atomicAdd(&J.cnt->sweeps_total, (unsigned long long)(sw32 + sw64));
+}
+
+}  // namespace gc

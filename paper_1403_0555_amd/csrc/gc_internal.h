@@ -24,8 +24,7 @@
 #define GC_F_KEY_OVERFLOW 32u
 
 // Job flags.
-#define GC_JOB_NO_TABLE 1u     // skip key insertion and the FP filter (state re-runs)
-#define GC_JOB_FIX 2u          // re-solve the starts listed in fix[], always run the filter
+#define GC_JOB_FIX 2u          // post-process the representatives listed in fix[], always run the filter
 
 // Relative spread of F (per site) above which one key is flagged as reached
 // by different stationary points.
@@ -69,7 +68,7 @@ struct GcEntry {
 
 // A copy whose representative start is not its lowest start id (its hits
 // include a start that stopped next to another stationary point of the same
-// class): the representative is solved again to obtain its lambda2.
+// class): the representative's stored state is filtered afterwards.
 struct GcFix {
     uint64_t start;                  // representative start id
     uint64_t slot;                   // index into the job's compact copy array
@@ -104,8 +103,8 @@ struct GcJobDev {
     GcCounters *cnt;
     GcCopyRec *copies;               // [n_starts] finalize output
     unsigned long long *n_copies;
-    double *state_out;               // optional [V] representative angles (start 0 of the job)
-    GcFix *fix;                      // [n_starts] representatives to re-solve
+    double2 *states;                 // [n_starts][V] final g of every start, natural site order
+    GcFix *fix;                      // [n_starts] representatives to filter
     unsigned long long *n_fix;
 };
 
@@ -113,19 +112,24 @@ static_assert(sizeof(GcStartRec) == 64, "record layout");
 static_assert(sizeof(GcEntry) == 64, "entry layout");
 static_assert(sizeof(GcCopyRec) == 64, "copy layout");
 
-// Launch entry points implemented in gc_kernels.hip.
-hipError_t gc_launch_solve(int block, const GcJobDev *jobs, int n_jobs, const uint64_t *prefix,
-                           unsigned long long *next, uint64_t total, double *scratch,
-                           uint64_t scratch_stride, int grid, size_t lds_bytes, hipStream_t s);
-hipError_t gc_solve_occupancy(int block, size_t lds_bytes, int *blocks_per_cu);
-hipError_t gc_launch_reset(const GcJobDev *jobs_host, int n_jobs, unsigned long long *next,
-                           hipStream_t s);
-hipError_t gc_launch_finalize(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);
-// Re-solve the listed representatives (one job at a time, device-side count)
-// and patch their lambda2 into the compact copies.
-hipError_t gc_launch_fixup(int block, const GcJobDev *fix_jobs_dev, const GcJobDev *jobs_host, int n_jobs,
-                           unsigned long long *next, double *scratch, uint64_t scratch_stride, int grid,
-                           size_t lds_bytes, hipStream_t s);
-hipError_t gc_launch_orbit_random(double *phi, int64_t n_links, uint64_t seed, uint64_t orbit_index,
-                                  hipStream_t s);
-size_t gc_solve_lds_bytes(int V, int precision);
+// Relax kernel, one workgroup per start (any colouring).
+size_t gc_relax_wg_lds_bytes(int V);
+hipError_t gc_relax_wg_occupancy(int block, size_t lds_bytes, int *blocks_per_cu);
+hipError_t gc_launch_relax_wg(int block, const GcJobDev *jobs, int n_jobs, const uint64_t *prefix,
+                              unsigned long long *next, uint64_t total, int grid, size_t lds_bytes, hipStream_t s);
+
+// Post kernel, one wavefront per start: functional, key, table insertion and
+// the FP-operator filter.  total_dev (device count) overrides total.
+size_t gc_post_lds_bytes(int V);
+uint64_t gc_post_scratch_doubles(int d, int V);
+hipError_t gc_post_occupancy(size_t lds_bytes, int *blocks_per_cu);
+hipError_t gc_launch_post(const GcJobDev *jobs, int n_jobs, const uint64_t *prefix, unsigned long long *next,
+                          uint64_t total, const unsigned long long *total_dev, double *scratch, uint64_t stride,
+                          int grid, size_t lds_bytes, hipStream_t s);
+
+// Table and bookkeeping kernels.
+hipError_t gc_launch_reset(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);
+hipError_t gc_launch_finalize(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);   // representatives + compaction
+hipError_t gc_launch_patch(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);      // fix-up results -> copies
+hipError_t gc_launch_orbit_random(double *phi, int64_t n_links, uint64_t seed, uint64_t orbit_index, hipStream_t s);
+hipError_t gc_launch_zero_u64(unsigned long long *p, int n, hipStream_t s);

@@ -10,6 +10,7 @@
 // overlap on the device.
 #include "../../include/gribov.h"
 #include "gc_internal.h"
+#include "gc_wave.h"
 
 #include <algorithm>
 #include <atomic>
@@ -156,6 +157,8 @@ struct Orbit {
     void *tables = nullptr;
     size_t table_bytes = 0;
     GcOrbitDev dev{};
+    GcWaveOrbit wdev{};              // colour-split tables (K == 2 only)
+    void *wave_tables = nullptr;
     // results of the last launch
     Job *job = nullptr;
     int job_index = 0;               // position inside a batch job
@@ -331,20 +334,83 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
     D.line_site = (const uint16_t *)(b + o_ls);
     o->tables = dev;
     o->table_bytes = off;
+    memset(&o->wdev, 0, sizeof o->wdev);
+    if (o->K == 2) {
+        // colour-split tables: (c, h) with c the colour, h = i >> 1
+        const int half = V / 2;
+        std::vector<uint16_t> loc(V);
+        std::vector<int> site((size_t)2 * half, -1);
+        for (int i = 0; i < V; ++i) {
+            loc[i] = (uint16_t)(col[i] * half + (i >> 1));
+            site[(size_t)col[i] * half + (i >> 1)] = i;
+        }
+        std::vector<uint16_t> nb((size_t)2 * half * 8, 0);
+        std::vector<double2> c64((size_t)2 * 2 * d * half);
+        std::vector<float2> c32((size_t)2 * 2 * d * half);
+        for (int c = 0; c < 2; ++c)
+            for (int h = 0; h < half; ++h) {
+                const int i = site[(size_t)c * half + h];
+                for (int k = 0; k < 2 * d; ++k) {
+                    const int mu = k < d ? k : k - d;
+                    const int nsite = k < d ? nbr[(size_t)mu * V + i] : nbr[(size_t)(d + mu) * V + i];
+                    nb[((size_t)c * half + h) * 8 + k] = (uint16_t)(nsite >> 1);
+                    double2 u;
+                    if (k < d) {
+                        u = U64[(size_t)mu * V + i];
+                    } else {
+                        u = U64[(size_t)mu * V + nsite];
+                        u.y = -u.y;
+                    }
+                    c64[((size_t)c * 2 * d + k) * half + h] = u;
+                    c32[((size_t)c * 2 * d + k) * half + h] = make_float2((float)u.x, (float)u.y);
+                }
+            }
+        size_t woff = 0;
+        auto wplace = [&](size_t bytes) { size_t at = woff; woff = align_up(woff + bytes, 256); return at; };
+        const size_t w_loc = wplace(loc.size() * 2), w_nb = wplace(nb.size() * 2), w_c64 = wplace(c64.size() * 16),
+                     w_c32 = wplace(c32.size() * 8);
+        std::vector<unsigned char> wh(woff, 0);
+        memcpy(&wh[w_loc], loc.data(), loc.size() * 2);
+        memcpy(&wh[w_nb], nb.data(), nb.size() * 2);
+        memcpy(&wh[w_c64], c64.data(), c64.size() * 16);
+        memcpy(&wh[w_c32], c32.data(), c32.size() * 8);
+        void *wdevmem = nullptr;
+        GC_HIP(hipMalloc(&wdevmem, woff));
+        GC_HIP(hipMemcpy(wdevmem, wh.data(), woff, hipMemcpyHostToDevice));
+        unsigned char *wb = (unsigned char *)wdevmem;
+        o->wdev.half = half;
+        o->wdev.loc = (const uint16_t *)(wb + w_loc);
+        o->wdev.nb = (const uint4 *)(wb + w_nb);
+        o->wdev.coef64 = (const double2 *)(wb + w_c64);
+        o->wdev.coef32 = (const float2 *)(wb + w_c32);
+        o->wave_tables = wdevmem;
+    }
     return GC_OK;
 }
 
-// Bytes of device memory a job needs while it runs (and what it keeps after).
-struct JobLayout {
-    std::vector<size_t> o_rec, o_table, o_cnt, o_copies, o_ncopies, o_fix, o_nfix;
-    size_t o_fixjobs = 0, o_fixnext = 0;
-    std::vector<uint64_t> table_cap;
-    size_t o_jobs = 0, o_prefix = 0, o_next = 0, o_scratch = 0;
-    size_t keep_bytes = 0;   // per-orbit results (kept after DONE): computed per orbit
-    size_t total = 0;
-    int block = 64, grid = 1;
+// Relax launch groups: orbits with odd extents use the workgroup-per-start
+// kernel; orbits with even extents the wavefront-per-start kernel, one launch
+// per dimension (that kernel is specialised on d).
+struct Group {
+    bool wave = false;
+    int d = 0;
+    std::vector<int> jobs;           // indices into Job::orbits
+    int block = 64, grid = 1, ns = 1, coef_lds = 0;
     size_t lds = 0;
-    uint64_t scratch_stride = 0;
+    size_t o_jobs = 0, o_worbs = 0, o_next = 0, o_prefix = 0, o_bounce = 0;
+    uint64_t total = 0;
+};
+
+// Device memory of one job.
+struct JobLayout {
+    std::vector<size_t> o_rec, o_table, o_cnt, o_copies, o_ncopies, o_fix, o_nfix, o_states;
+    std::vector<uint64_t> table_cap;
+    std::vector<Group> groups;
+    size_t o_jobs = 0, o_fixjobs = 0, o_prefix = 0, o_next = 0, o_fixnext = 0, o_scratch = 0;
+    size_t total = 0;
+    int post_grid = 1;
+    size_t post_lds = 0;
+    uint64_t post_stride = 0;
 };
 
 gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
@@ -357,11 +423,12 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
     L.o_prefix = place(sizeof(uint64_t) * (nj + 1));
     L.o_next = place(sizeof(unsigned long long));
     L.o_fixnext = place(sizeof(unsigned long long));
-    int maxV = 0, maxdV = 0;
+    int maxV = 0, maxd = 0;
     uint64_t total = 0;
     for (int j = 0; j < nj; ++j) {
         Orbit *o = job->orbits[j];
         const uint64_t n = job->n_starts[j];
+        if (o->V > kMaxV) return GC_EUNSUPPORTED;
         const uint64_t cap = next_pow2(std::max<uint64_t>(2 * n, 64));
         L.table_cap.push_back(cap);
         L.o_rec.push_back(place(sizeof(GcStartRec) * n));
@@ -371,22 +438,71 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         L.o_ncopies.push_back(place(sizeof(unsigned long long)));
         L.o_fix.push_back(place(sizeof(GcFix) * n));
         L.o_nfix.push_back(place(sizeof(unsigned long long)));
+        L.o_states.push_back(place(sizeof(double2) * n * (uint64_t)o->V));
         maxV = std::max(maxV, o->V);
-        maxdV = std::max(maxdV, o->d * o->V);
+        maxd = std::max(maxd, o->d);
         total += n;
+        const bool wave = (o->K == 2);
+        const int gd = wave ? o->d : 0;
+        Group *g = nullptr;
+        for (Group &x : L.groups)
+            if (x.wave == wave && x.d == gd) g = &x;
+        if (!g) {
+            L.groups.push_back(Group{});
+            g = &L.groups.back();
+            g->wave = wave;
+            g->d = gd;
+        }
+        g->jobs.push_back(j);
+        g->total += n;
     }
-    L.block = block_for(maxV);
-    L.lds = gc_solve_lds_bytes(maxV, job->p.precision);
-    if (L.lds > ctx->lds_max || maxV > kMaxV) return GC_EUNSUPPORTED;
+    const bool mixed = job->p.precision == GC_MIXED;
+    for (Group &g : L.groups) {
+        int gV = 0;
+        for (int j : g.jobs) gV = std::max(gV, job->orbits[j]->V);
+        int per_cu = 0;
+        if (g.wave) {
+            g.ns = (gV / 2 + 63) / 64;
+            g.block = 64 * GC_WAVES;
+            size_t coef_bytes = 0;
+            for (int j : g.jobs) {
+                const Orbit *o = job->orbits[j];
+                coef_bytes = std::max(coef_bytes, (size_t)2 * o->d * o->V * (mixed ? 24 : 16));
+            }
+            const size_t states = (size_t)GC_WAVES * 16 * gV;
+            g.coef_lds = (coef_bytes + states <= 64 * 1024) ? 1 : 0;
+            g.lds = states + (g.coef_lds ? coef_bytes : 0);
+            if (g.lds > ctx->lds_max) return GC_EUNSUPPORTED;
+            hipError_t e = gc_wave_occupancy(g.d, g.ns, g.lds, &per_cu);
+            if (e != hipSuccess) return fail(ctx, e, "occupancy");
+        } else {
+            g.block = block_for(gV);
+            g.lds = gc_relax_wg_lds_bytes(gV);
+            if (g.lds > ctx->lds_max) return GC_EUNSUPPORTED;
+            hipError_t e = gc_relax_wg_occupancy(g.block, g.lds, &per_cu);
+            if (e != hipSuccess) return fail(ctx, e, "occupancy");
+        }
+        per_cu = std::max(per_cu, 1);
+        const uint64_t per_wg = g.wave ? GC_WAVES : 1;
+        uint64_t grid = (uint64_t)per_cu * (uint64_t)ctx->n_cu;
+        grid = std::min<uint64_t>(grid, std::max<uint64_t>((g.total + per_wg - 1) / per_wg, 1));
+        g.grid = (int)grid;
+        g.o_jobs = place(sizeof(GcJobDev) * g.jobs.size());
+        g.o_worbs = place(sizeof(GcWaveOrbit) * g.jobs.size());
+        g.o_next = place(sizeof(unsigned long long) * g.jobs.size());
+        g.o_prefix = place(sizeof(uint64_t) * (g.jobs.size() + 1));
+        g.o_bounce = g.wave ? place(sizeof(float2) * (size_t)gV * per_wg * g.grid) : 0;
+    }
+    // post pass: one wavefront per start over every job
+    L.post_lds = gc_post_lds_bytes(maxV);
+    if (L.post_lds > ctx->lds_max) return GC_EUNSUPPORTED;
     int per_cu = 0;
-    hipError_t e = gc_solve_occupancy(L.block, L.lds, &per_cu);
+    hipError_t e = gc_post_occupancy(L.post_lds, &per_cu);
     if (e != hipSuccess) return fail(ctx, e, "occupancy");
     per_cu = std::max(per_cu, 1);
-    uint64_t grid = (uint64_t)per_cu * (uint64_t)ctx->n_cu;
-    grid = std::min<uint64_t>(grid, std::max<uint64_t>(total, 1));
-    L.grid = (int)grid;
-    L.scratch_stride = (uint64_t)2 * maxdV;
-    L.o_scratch = place(sizeof(double) * L.scratch_stride * L.grid);
+    L.post_grid = (int)std::min<uint64_t>((uint64_t)per_cu * ctx->n_cu, std::max<uint64_t>(total, 1));
+    L.post_stride = gc_post_scratch_doubles(maxd, maxV);
+    L.o_scratch = place(sizeof(double) * L.post_stride * L.post_grid);
     L.total = off;
     return GC_OK;
 }
@@ -422,16 +538,15 @@ gc_status start_job(gc_ctx *ctx, Job *job)
     ctx->used += job->bytes;
     const int nj = (int)job->orbits.size();
     unsigned char *base = (unsigned char *)job->mem;
-    // least-loaded stream
-    int si = 0;
+    int si = 0;   // least-loaded stream
     for (int k = 1; k < (int)ctx->streams.size(); ++k)
         if (ctx->stream_load[k] < ctx->stream_load[si]) si = k;
     job->stream = si;
     ctx->stream_load[si]++;
     hipStream_t s = ctx->streams[si];
 
-    std::vector<uint64_t> prefix(nj + 1, 0);
     job->jobs.assign(nj, GcJobDev{});
+    std::vector<uint64_t> prefix(1, 0);
     for (int j = 0; j < nj; ++j) {
         Orbit *o = job->orbits[j];
         GcJobDev &J = job->jobs[j];
@@ -455,43 +570,80 @@ gc_status start_job(gc_ctx *ctx, Job *job)
         J.cnt = (GcCounters *)(base + L.o_cnt[j]);
         J.copies = (GcCopyRec *)(base + L.o_copies[j]);
         J.n_copies = (unsigned long long *)(base + L.o_ncopies[j]);
-        J.state_out = nullptr;
+        J.states = (double2 *)(base + L.o_states[j]);
         J.fix = (GcFix *)(base + L.o_fix[j]);
         J.n_fix = (unsigned long long *)(base + L.o_nfix[j]);
-        prefix[j + 1] = prefix[j] + job->n_starts[j];
+        prefix.push_back(prefix.back() + job->n_starts[j]);
     }
+    job->total = prefix.back();
     std::vector<GcJobDev> fixjobs(job->jobs);
     for (GcJobDev &F : fixjobs) F.flags |= GC_JOB_FIX;
-    job->total = prefix[nj];
     GC_HIP(hipHostMalloc((void **)&job->h_cnt, sizeof(GcCounters) * nj, hipHostMallocDefault));
     GC_HIP(hipHostMalloc((void **)&job->h_ncopies, sizeof(unsigned long long) * nj, hipHostMallocDefault));
     GC_HIP(hipEventCreate(&job->ev_k0));
     GC_HIP(hipEventCreate(&job->ev_k1));
     GC_HIP(hipEventCreateWithFlags(&job->ev_done, hipEventDisableTiming));
     GC_HIP(hipMemcpyAsync(base + L.o_jobs, job->jobs.data(), sizeof(GcJobDev) * nj, hipMemcpyHostToDevice, s));
-    GC_HIP(hipMemcpyAsync(base + L.o_prefix, prefix.data(), sizeof(uint64_t) * (nj + 1), hipMemcpyHostToDevice, s));
     GC_HIP(hipMemcpyAsync(base + L.o_fixjobs, fixjobs.data(), sizeof(GcJobDev) * nj, hipMemcpyHostToDevice, s));
-    // the H2D copies above come from pageable memory and are complete on return
+    GC_HIP(hipMemcpyAsync(base + L.o_prefix, prefix.data(), sizeof(uint64_t) * prefix.size(), hipMemcpyHostToDevice, s));
+    for (const Group &g : L.groups) {
+        std::vector<GcJobDev> gj;
+        std::vector<GcWaveOrbit> gw;
+        std::vector<uint64_t> gp(1, 0);
+        for (int j : g.jobs) {
+            gj.push_back(job->jobs[j]);
+            gw.push_back(job->orbits[j]->wdev);
+            gp.push_back(gp.back() + job->n_starts[j]);
+        }
+        GC_HIP(hipMemcpyAsync(base + g.o_jobs, gj.data(), sizeof(GcJobDev) * gj.size(), hipMemcpyHostToDevice, s));
+        GC_HIP(hipMemcpyAsync(base + g.o_worbs, gw.data(), sizeof(GcWaveOrbit) * gw.size(), hipMemcpyHostToDevice, s));
+        GC_HIP(hipMemcpyAsync(base + g.o_prefix, gp.data(), sizeof(uint64_t) * gp.size(), hipMemcpyHostToDevice, s));
+    }
+    GC_HIP(hipStreamSynchronize(s));
+    double *scratch = (double *)(base + L.o_scratch);
     auto enqueue_body = [&](hipStream_t qs) -> hipError_t {
-        hipError_t e = gc_launch_reset(job->jobs.data(), nj, (unsigned long long *)(base + L.o_next), qs);
+        hipError_t e = gc_launch_reset(job->jobs.data(), nj, qs);
         if (e != hipSuccess) return e;
+        e = gc_launch_zero_u64((unsigned long long *)(base + L.o_next), 1, qs);
+        if (e != hipSuccess) return e;
+        for (const Group &g : L.groups) {
+            e = gc_launch_zero_u64((unsigned long long *)(base + g.o_next), (int)g.jobs.size(), qs);
+            if (e != hipSuccess) return e;
+        }
         if (!job->graph) {
             e = hipEventRecord(job->ev_k0, qs);
             if (e != hipSuccess) return e;
         }
-        e = gc_launch_solve(L.block, (const GcJobDev *)(base + L.o_jobs), nj, (const uint64_t *)(base + L.o_prefix),
-                            (unsigned long long *)(base + L.o_next), job->total, (double *)(base + L.o_scratch),
-                            L.scratch_stride, L.grid, L.lds, qs);
-        if (e != hipSuccess) return e;
+        for (const Group &g : L.groups) {
+            if (g.wave)
+                e = gc_launch_wave(g.d, g.ns, (const GcJobDev *)(base + g.o_jobs), (const GcWaveOrbit *)(base + g.o_worbs),
+                                   (int)g.jobs.size(), (unsigned long long *)(base + g.o_next), g.coef_lds,
+                                   (float2 *)(base + g.o_bounce), g.grid, g.lds, qs);
+            else
+                e = gc_launch_relax_wg(g.block, (const GcJobDev *)(base + g.o_jobs), (int)g.jobs.size(),
+                                       (const uint64_t *)(base + g.o_prefix), (unsigned long long *)(base + g.o_next),
+                                       g.total, g.grid, g.lds, qs);
+            if (e != hipSuccess) return e;
+        }
         if (!job->graph) {
             e = hipEventRecord(job->ev_k1, qs);
             if (e != hipSuccess) return e;
         }
+        e = gc_launch_post((const GcJobDev *)(base + L.o_jobs), nj, (const uint64_t *)(base + L.o_prefix),
+                           (unsigned long long *)(base + L.o_next), job->total, nullptr, scratch, L.post_stride,
+                           L.post_grid, L.post_lds, qs);
+        if (e != hipSuccess) return e;
         e = gc_launch_finalize(job->jobs.data(), nj, qs);
         if (e != hipSuccess) return e;
-        e = gc_launch_fixup(L.block, (const GcJobDev *)(base + L.o_fixjobs), job->jobs.data(), nj,
-                            (unsigned long long *)(base + L.o_fixnext), (double *)(base + L.o_scratch),
-                            L.scratch_stride, std::min(L.grid, 256), L.lds, qs);
+        for (int j = 0; j < nj; ++j) {
+            e = gc_launch_zero_u64((unsigned long long *)(base + L.o_fixnext), 1, qs);
+            if (e != hipSuccess) return e;
+            e = gc_launch_post((const GcJobDev *)(base + L.o_fixjobs) + j, 1, nullptr,
+                               (unsigned long long *)(base + L.o_fixnext), 0, job->jobs[j].n_fix, scratch,
+                               L.post_stride, std::min(L.post_grid, 64), L.post_lds, qs);
+            if (e != hipSuccess) return e;
+        }
+        e = gc_launch_patch(job->jobs.data(), nj, qs);
         if (e != hipSuccess) return e;
         for (int j = 0; j < nj; ++j) {
             e = hipMemcpyAsync(&job->h_cnt[j], job->jobs[j].cnt, sizeof(GcCounters), hipMemcpyDeviceToHost, qs);
@@ -520,10 +672,7 @@ gc_status start_job(gc_ctx *ctx, Job *job)
     }
     GC_HIP(hipEventRecord(job->ev_done, s));
     job->state = GC_ORBIT_RUNNING;
-    for (int j = 0; j < nj; ++j) {
-        Orbit *o = job->orbits[j];
-        o->res = job->jobs[j];
-    }
+    for (int j = 0; j < nj; ++j) job->orbits[j]->res = job->jobs[j];
     ctx->running.push_back(job);
     return GC_OK;
 }
@@ -700,7 +849,7 @@ gc_status new_orbit(gc_ctx *ctx, const gc_lattice *lat, std::vector<double> &&ph
     int K = 0, V = 0;
     gc_status st = check_lattice(lat, &K, &V);
     if (st != GC_OK) return st;
-    if (V > kMaxV || gc_solve_lds_bytes(V, GC_MIXED) > ctx->lds_max) return GC_EUNSUPPORTED;
+    if (V > kMaxV || gc_relax_wg_lds_bytes(V) > ctx->lds_max) return GC_EUNSUPPORTED;
     auto o = std::make_unique<Orbit>();
     o->lat = *lat;
     o->d = lat->dim;
@@ -880,8 +1029,10 @@ gc_status gc_destroy(gc_ctx *ctx)
         free_job(ctx, j);
         delete j;
     }
-    for (auto &kv : ctx->orbits)
+    for (auto &kv : ctx->orbits) {
         if (kv.second->tables) (void)hipFree(kv.second->tables);
+        if (kv.second->wave_tables) (void)hipFree(kv.second->wave_tables);
+    }
     ctx->pool.drain();
     for (hipStream_t s : ctx->streams) (void)hipStreamDestroy(s);
     delete ctx;
@@ -1051,56 +1202,17 @@ gc_status gc_fetch_state(gc_ctx *ctx, gc_orbit orbit, uint64_t start_id, double 
     const gc_solve_params &p = o->job->p;
     const uint64_t n = o->job->n_starts[o->job_index];
     if (start_id < p.first_start || start_id - p.first_start >= n) return GC_EINVAL;
-    // a one-start job without table, writing the representative angles
-    const int V = o->V, d = o->d;
-    const int block = block_for(V);
-    const size_t lds = gc_solve_lds_bytes(V, p.precision);
-    size_t off = 0;
-    auto place = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes, 256); return at; };
-    const size_t o_job = place(sizeof(GcJobDev)), o_prefix = place(16), o_next = place(8), o_rec = place(64),
-                 o_cnt = place(sizeof(GcCounters)), o_state = place(sizeof(double) * V),
-                 o_scr = place(sizeof(double) * 2 * d * V), o_table = place(sizeof(GcEntry) * 64),
-                 o_nc = place(8), o_nfix = place(8);
-    void *mem = nullptr;
-    GC_HIP(hipMalloc(&mem, off));
-    unsigned char *b = (unsigned char *)mem;
-    GcJobDev J;
-    memset(&J, 0, sizeof J);
-    J.orb = o->dev;
-    J.omega = p.omega;
-    J.eps32 = p.eps32;
-    J.eps64 = p.eps64;
-    J.lambda_tol = p.lambda_tol;
-    J.precision = p.precision;
-    J.stop_norm = p.stop_norm;
-    J.check_every = (int32_t)std::max<uint32_t>(p.check_every, 1);
-    J.lanczos_max = 1;
-    J.max_sweeps = p.max_sweeps;
-    J.start_seed = p.start_seed;
-    J.first_start = start_id;
-    J.n_starts = 1;
-    J.flags = GC_JOB_NO_TABLE;
-    J.rec = (GcStartRec *)(b + o_rec);
-    J.table = (GcEntry *)(b + o_table);
-    J.table_mask = 63;
-    J.cnt = (GcCounters *)(b + o_cnt);
-    J.copies = nullptr;
-    J.n_copies = (unsigned long long *)(b + o_nc);
-    J.state_out = (double *)(b + o_state);
-    J.fix = nullptr;
-    J.n_fix = (unsigned long long *)(b + o_nfix);
-    const uint64_t prefix[2] = {0, 1};
-    hipStream_t s = ctx->streams[0];
-    hipError_t e = hipMemcpyAsync(b + o_job, &J, sizeof J, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(b + o_prefix, prefix, sizeof prefix, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = gc_launch_reset(&J, 1, (unsigned long long *)(b + o_next), s);
-    if (e == hipSuccess)
-        e = gc_launch_solve(block, (const GcJobDev *)(b + o_job), 1, (const uint64_t *)(b + o_prefix),
-                            (unsigned long long *)(b + o_next), 1, (double *)(b + o_scr), (uint64_t)2 * d * V, 1, lds, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(theta_out, b + o_state, sizeof(double) * V, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(mem);
-    if (e != hipSuccess) return fail(ctx, e, "fetch_state");
+    const int V = o->V;
+    std::vector<double2> g(V);
+    GC_HIP(hipMemcpy(g.data(), o->res.states + (start_id - p.first_start) * (uint64_t)V, sizeof(double2) * V,
+                     hipMemcpyDeviceToHost));
+    // theta_i - theta_{V-1} = arg(g_i conj(g_{V-1})), exactly 0 at the last site
+    const double2 gl = g[V - 1];
+    for (int i = 0; i < V; ++i) {
+        const double im = g[i].y * gl.x - g[i].x * gl.y;
+        const double re = g[i].x * gl.x + g[i].y * gl.y;
+        theta_out[i] = std::atan2(im, re);
+    }
     return GC_OK;
 }
 
@@ -1115,6 +1227,7 @@ gc_status gc_release(gc_ctx *ctx, gc_orbit orbit)
     }
     drop_results_locked(ctx, o);
     if (o->tables) (void)hipFree(o->tables);
+    if (o->wave_tables) (void)hipFree(o->wave_tables);
     ctx->orbits.erase(orbit);
     admit_locked(ctx);
     return GC_OK;
