@@ -59,12 +59,123 @@ def cpu_baseline(w: GI.Workload, phi, n_sample: int):
             "site_updates_per_s": upd / dt}
 
 
+def run_batch(gc, args):
+    """Uneven multi-orbit batch: every orbit's starts in one graph-captured launch."""
+    reqs = GI.uneven_batch(32)
+    params = gc.SolveParams(omega=1.7, precision=args.precision)
+    ctx = gc.Context(0)
+    hs = []
+    for r in reqs:
+        hs.append(ctx.gc_orbit_load(r["extent"], GI.orbit_angles(r["extent"], r["seed"], r["orbit_index"]),
+                                    r["orbit_index"]))
+    ns = [r["n_starts"] for r in reqs]
+    V = [int(np.prod(r["extent"])) for r in reqs]
+
+    def step():
+        ctx.gc_launch_batch(hs, ns, params)
+        for h in hs:
+            if ctx.gc_wait(h, 600_000) != gc.GC_OK:
+                raise RuntimeError("batch timed out")
+        inreg = upd = dist = 0
+        for h in hs:
+            c = ctx.gc_fetch(h)
+            inreg += int(c["hits"][(c["flags"] & gc.GC_FLAG_IN_REGION) != 0].sum())
+            dist += len(c)
+            upd += int(ctx.gc_poll(h)["site_updates"])
+        return inreg, upd, dist
+
+    for _ in range(args.warmup):
+        step()
+    t0 = time.perf_counter()
+    tot = [0, 0, 0]
+    for k in range(args.steps):
+        r = step()
+        tot = [a + b for a, b in zip(tot, r)]
+        print("batch step %d done" % k, file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    ctx.close()
+    return {
+        "metric": "converged Gribov copies/s", "value": tot[0] / wall, "unit": "copies/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": "uneven_batch_32_orbits", "orbits": len(reqs), "starts": int(sum(ns)),
+                   "site_range": [min(V), max(V)], "omega": 1.7, "precision": args.precision},
+        "site_updates_per_s": tot[1] / wall, "distinct_copies_per_s": tot[2] / wall,
+    }
+
+
+def run_serve(gc, args):
+    """Serving stream: Poisson-arriving orbit requests, HBM-budget admission,
+    continuous batching on the device; p50/p99 latency from submission to the
+    orbit's final table."""
+    import threading
+    probe = GI.poisson_requests(args.requests, 1.0, seed=1)
+    # capacity estimate: starts/s measured on a short warmup request mix
+    params = gc.SolveParams(omega=1.7, precision=args.precision)
+    ctx = gc.Context(0, hbm_budget_bytes=int(args.budget_gb * (1 << 30)))
+    work = sum(r["n_starts"] * int(np.prod(r["extent"])) for r in probe)
+    t0 = time.perf_counter()
+    for r in probe[:8]:
+        h = ctx.gc_orbit_load(r["extent"], GI.orbit_angles(r["extent"], r["seed"], r["orbit_index"]), r["orbit_index"])
+        ctx.gc_launch(h, r["n_starts"], params)
+        ctx.gc_wait(h)
+        ctx.gc_release(h)
+    cap_sites = sum(r["n_starts"] * int(np.prod(r["extent"])) for r in probe[:8]) / (time.perf_counter() - t0)
+    rate = args.load * cap_sites / (work / len(probe))
+    reqs = GI.poisson_requests(args.requests, rate, seed=1)
+    lat, results = [], []
+    lock = threading.Lock()
+    handles = []
+    t_start = time.perf_counter()
+    for r in reqs:
+        now = time.perf_counter() - t_start
+        if r["t_arrive"] > now:
+            time.sleep(r["t_arrive"] - now)
+        h = ctx.gc_orbit_load(r["extent"], GI.orbit_angles(r["extent"], r["seed"], r["orbit_index"]), r["orbit_index"])
+        ctx.gc_launch(h, r["n_starts"], params)
+        handles.append(h)
+        # release finished orbits as we go (frees their HBM for admission)
+        done = []
+        for hh in handles:
+            if ctx.gc_poll(hh)["state"] == gc.GC_ORBIT_DONE:
+                done.append(hh)
+        for hh in done:
+            p = ctx.gc_poll(hh)
+            c = ctx.gc_fetch(hh)
+            results.append((p, c))
+            ctx.gc_release(hh)
+            handles.remove(hh)
+    for hh in handles:
+        ctx.gc_wait(hh)
+        results.append((ctx.gc_poll(hh), ctx.gc_fetch(hh)))
+        ctx.gc_release(hh)
+    wall = time.perf_counter() - t_start
+    ctx.close()
+    lat = [p["submit_to_done_ms"] for p, _ in results]
+    inreg = sum(int(c["hits"][(c["flags"] & gc.GC_FLAG_IN_REGION) != 0].sum()) for _, c in results)
+    upd = sum(int(p["site_updates"]) for p, _ in results)
+    return {
+        "metric": "converged Gribov copies/s", "value": inreg / wall, "unit": "copies/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": "serving_poisson", "requests": len(reqs), "offered_load": args.load,
+                   "rate_per_s": rate, "budget_gb": args.budget_gb, "omega": 1.7, "precision": args.precision},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "site_updates_per_s": upd / wall,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="u1_4d_4x4x4x4_relax", choices=sorted(GI.WORKLOADS))
+    ap.add_argument("--workload", default="u1_4d_4x4x4x4_relax", choices=sorted(GI.WORKLOADS) + ["batch", "serve"])
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"], help="batch/serve modes")
+    ap.add_argument("--requests", type=int, default=300, help="serve mode")
+    ap.add_argument("--load", type=float, default=0.8, help="serve mode: offered load / capacity")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve mode")
     ap.add_argument("--starts", type=int, default=0, help="override the workload's start count")
     ap.add_argument("--cpu-sample", type=int, default=2000)
     ap.add_argument("--no-cpu", action="store_true")
@@ -76,6 +187,11 @@ def main():
         sys.exit(2)
 
     import paper_1403_0555_amd as gc
+
+    if args.workload in ("batch", "serve"):
+        out = run_batch(gc, args) if args.workload == "batch" else run_serve(gc, args)
+        print(json.dumps(out), flush=True)
+        return
 
     w = GI.WORKLOADS[args.workload]
     n = args.starts or w.n_starts

@@ -82,7 +82,7 @@ typedef struct {
 
 typedef struct {
     int32_t dim;                /* 1..4 */
-    int32_t extent[4];          /* N_mu >= 2 for mu < dim; V = prod N_mu <= 65536 */
+    int32_t extent[4];          /* N_mu >= 2 for mu < dim; V = prod N_mu <= 4096 (a start's state is held on chip) */
 } gc_lattice;
 
 typedef struct {
@@ -122,9 +122,10 @@ typedef struct {
 /* One distinct copy. */
 typedef struct {
     uint64_t key_hi, key_lo;    /* canonical integer key (plaquette and line wrap numbers, hashed) */
-    double F;                   /* eq. (3) at the copy, from its lowest start id */
+    double F;                   /* eq. (3) at the copy's representative: the lowest start id whose F is
+                                   within 1e-9 per site of the lowest F reaching the key */
     double x;                   /* F / (d V), in [0, 1] inside the first region */
-    double lambda2;             /* lowest eigenvalue of M_FP orthogonal to the constant mode */
+    double lambda2;             /* lowest eigenvalue of M_FP orthogonal to the constant mode, at the representative */
     uint64_t hits;              /* starts that converged to this key */
     uint64_t first_start;       /* lowest start id reaching it */
     uint32_t flags;             /* GC_FLAG_* */
@@ -136,13 +137,13 @@ typedef struct {
     int32_t status;             /* GC_START_* */
     uint32_t sweeps32;
     uint32_t sweeps64;
-    uint32_t lanczos_iters;     /* 0 when this start did not run the FP-operator filter */
+    uint32_t lanczos_iters;     /* 0 unless this start is the representative of its copy */
     double F;
     double D;                   /* final stopping norm */
-    double lambda2;             /* NaN unless this start ran the filter */
+    double lambda2;             /* the copy's lambda2 at its representative start, NaN at every other start */
     uint64_t key_hi, key_lo;
     uint32_t paper_X;           /* trunc(x * 1e8) */
-    uint32_t flags;
+    uint32_t flags;             /* GC_FLAG_KEY_OVERFLOW; the lambda2 flags only at a representative */
 } gc_start_record;
 
 /* Library version string ("major.minor.patch"). */
@@ -222,10 +223,10 @@ gc_status gc_fetch(gc_ctx *ctx, gc_orbit orbit, uint64_t offset, uint64_t cap,
 gc_status gc_fetch_starts(gc_ctx *ctx, gc_orbit orbit, uint64_t offset, uint64_t cap,
                           gc_start_record *out, uint64_t *n_written);
 
-/* Representative of a copy: re-runs start_id of the orbit's last launch
- * deterministically and returns theta_i - theta_{V-1} wrapped to (-pi, pi]
- * (the global phase removed by fixing the last site, Sec. I) in theta_out
- * [V].  Works for any start id of that launch, converged or not. */
+/* Final state of one start of the orbit's last (DONE) launch: writes
+ * theta_i - theta_{V-1} wrapped to (-pi, pi] (the global phase removed by
+ * fixing the last site, Sec. I) to theta_out [V].  Any start id of that
+ * launch, converged or not. */
 gc_status gc_fetch_state(gc_ctx *ctx, gc_orbit orbit, uint64_t start_id, double *theta_out);
 
 /* Free the orbit and its tables (waits for its launch first). */
@@ -233,6 +234,15 @@ gc_status gc_release(gc_ctx *ctx, gc_orbit orbit);
 
 /* Sticky error text of the context (always NUL-terminated when cap > 0). */
 gc_status gc_last_error(gc_ctx *ctx, char *buf, size_t cap);
+
+/* HBM bytes a gc_launch of n_starts on this orbit would be charged against
+ * the context's budget (what admission compares with the free budget). */
+gc_status gc_launch_bytes(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_solve_params *params,
+                          uint64_t *bytes);
+
+/* The context's HBM budget, the bytes charged by launches that still hold
+ * memory, and the number of launches waiting for admission (any may be NULL). */
+gc_status gc_memory_info(gc_ctx *ctx, uint64_t *budget, uint64_t *in_use, uint64_t *queued);
 
 /* Device time of the last completed launch's solve kernel in milliseconds,
  * measured with HIP events on the stream the kernel ran on. */

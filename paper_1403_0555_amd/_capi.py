@@ -26,7 +26,8 @@ EXPORTED_SYMBOLS = [
     "gc_version", "gc_status_str", "gc_lattice_check", "gc_solve_params_default",
     "gc_create", "gc_destroy", "gc_orbit_load", "gc_orbit_random", "gc_orbit_angles",
     "gc_launch", "gc_launch_batch", "gc_poll", "gc_wait", "gc_fetch", "gc_fetch_starts",
-    "gc_fetch_state", "gc_release", "gc_last_error", "gc_kernel_time_ms",
+    "gc_fetch_state", "gc_release", "gc_last_error", "gc_kernel_time_ms", "gc_launch_bytes",
+    "gc_memory_info",
 ]
 
 
@@ -109,6 +110,8 @@ def lib():
         "gc_release": ([vp, u64], i32),
         "gc_last_error": ([vp, ctypes.c_char_p, ctypes.c_size_t], i32),
         "gc_kernel_time_ms": ([vp, u64, P(ctypes.c_double)], i32),
+        "gc_launch_bytes": ([vp, u64, u64, P(gc_solve_params), P(u64)], i32),
+        "gc_memory_info": ([vp, P(u64), P(u64), P(u64)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -292,6 +295,19 @@ class Context:
         v = ctypes.c_double()
         self._check(self._L.gc_kernel_time_ms(self._h, orbit, ctypes.byref(v)), "gc_kernel_time_ms")
         return v.value
+
+    def gc_launch_bytes(self, orbit: int, n_starts: int, params: SolveParams | None = None) -> int:
+        p = (params or SolveParams()).c()
+        b = ctypes.c_uint64()
+        self._check(self._L.gc_launch_bytes(self._h, orbit, n_starts, ctypes.byref(p), ctypes.byref(b)),
+                    "gc_launch_bytes")
+        return b.value
+
+    def gc_memory_info(self) -> dict:
+        b, u, q = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(self._L.gc_memory_info(self._h, ctypes.byref(b), ctypes.byref(u), ctypes.byref(q)),
+                    "gc_memory_info")
+        return {"budget": b.value, "in_use": u.value, "queued": q.value}
 
     def gc_last_error(self) -> str:
         buf = ctypes.create_string_buffer(512)

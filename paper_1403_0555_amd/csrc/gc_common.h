@@ -110,6 +110,17 @@ __device__ __forceinline__ int wave_min_int(int v)
     return v;
 }
 
+// Values known to be equal on every lane (broadcast through LDS or a
+// shuffle): reading lane 0 puts them in scalar registers, so that whatever is
+// indexed by them (job descriptors, start records) is loaded once per wave.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uniform(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // A zero the optimiser cannot see through.  Indexing per-site tables with it
 // inside a loop keeps them from being hoisted into registers.
 __device__ __forceinline__ int opaque_zero()
@@ -119,28 +130,40 @@ __device__ __forceinline__ int opaque_zero()
     return z;
 }
 
+// Address-space views: LDS (3) and global (1) pointers make the compiler emit
+// ds_* or global_* instructions instead of generic flat accesses.
+template <typename T> using lds_ptr = __attribute__((address_space(3))) T *;
+template <typename T> using glb_ptr = __attribute__((address_space(1))) T *;
+template <typename T> __device__ __forceinline__ glb_ptr<T> as_global(T *p) { return (glb_ptr<T>)p; }
+template <typename T> __device__ __forceinline__ lds_ptr<T> as_lds(T *p) { return (lds_ptr<T>)p; }
+
+// Complex numbers as clang vector types: builtin, so they load and store
+// through any address space.
+typedef float flt2 __attribute__((ext_vector_type(2)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
 template <typename R> struct cx;
-template <> struct cx<float> { using T = float2; };
-template <> struct cx<double> { using T = double2; };
+template <> struct cx<float> { using T = flt2; };
+template <> struct cx<double> { using T = dbl2; };
 
 __device__ __forceinline__ float rsq(float x) { return rsqrtf(x); }
 __device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
 
 // Local maximisation of eqs. (4)-(5) in the eq. (3) convention: from the
-// staple S, g <- S/|S| (omega = 1) or the over-relaxed
+// staple S, g <- S/|S| (RELAX, omega = 1) or the over-relaxed
 // g <- g N(1 + omega (z - 1)), z = conj(g) S/|S|, N(w) = w/|w|.  |S| = 0
-// leaves g unchanged.
-template <typename R>
-__device__ __forceinline__ typename cx<R>::T local_update(typename cx<R>::T g0, typename cx<R>::T s, R omega,
-                                                          bool relax)
+// leaves g unchanged.  Written without branches so that the compiler can
+// schedule a whole colour pass as one block.
+template <bool RELAX, typename R>
+__device__ __forceinline__ typename cx<R>::T local_update(typename cx<R>::T g0, typename cx<R>::T s, R omega)
 {
     using C = typename cx<R>::T;
     const R n2 = s.x * s.x + s.y * s.y;
-    if (n2 == (R)0) return g0;
-    const R r = rsq(n2);
+    const bool ok = n2 > (R)0;
+    const R r = rsq(ok ? n2 : (R)1);
     const R hx = s.x * r, hy = s.y * r;
     C g;
-    if (relax) {
+    if (RELAX) {
         g.x = hx;
         g.y = hy;
     } else {
@@ -154,6 +177,8 @@ __device__ __forceinline__ typename cx<R>::T local_update(typename cx<R>::T g0, 
         g.x = g0.x * wx - g0.y * wy;
         g.y = g0.x * wy + g0.y * wx;
     }
+    g.x = ok ? g.x : g0.x;
+    g.y = ok ? g.y : g0.y;
     return g;
 }
 

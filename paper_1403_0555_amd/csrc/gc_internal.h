@@ -118,14 +118,17 @@ hipError_t gc_relax_wg_occupancy(int block, size_t lds_bytes, int *blocks_per_cu
 hipError_t gc_launch_relax_wg(int block, const GcJobDev *jobs, int n_jobs, const uint64_t *prefix,
                               unsigned long long *next, uint64_t total, int grid, size_t lds_bytes, hipStream_t s);
 
-// Post kernel, one wavefront per start: functional, key, table insertion and
+// Post kernel, one workgroup per start: functional, key, table insertion and
 // the FP-operator filter.  total_dev (device count) overrides total.
-size_t gc_post_lds_bytes(int V);
-uint64_t gc_post_scratch_doubles(int d, int V);
-hipError_t gc_post_occupancy(size_t lds_bytes, int *blocks_per_cu);
-hipError_t gc_launch_post(const GcJobDev *jobs, int n_jobs, const uint64_t *prefix, unsigned long long *next,
-                          uint64_t total, const unsigned long long *total_dev, double *scratch, uint64_t stride,
-                          int grid, size_t lds_bytes, hipStream_t s);
+// Workgroup shape for V sites: block threads, sp sites per thread, link
+// weights in registers (wreg) or in a global buffer of d V doubles per
+// workgroup (wbuf, wstride doubles apart).
+size_t gc_post_lds_bytes(int d, int V);
+void gc_post_shape(int V, int *block, int *sites_per_thread, int *wreg);
+hipError_t gc_post_occupancy(int block, int sp, int wreg, size_t lds_bytes, int *blocks_per_cu);
+hipError_t gc_launch_post(int block, int sp, int wreg, const GcJobDev *jobs, int n_jobs, const uint64_t *prefix,
+                          unsigned long long *next, uint64_t total, const unsigned long long *total_dev,
+                          double *wbuf, uint64_t wstride, int grid, size_t lds_bytes, hipStream_t s);
 
 // Table and bookkeeping kernels.
 hipError_t gc_launch_reset(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);

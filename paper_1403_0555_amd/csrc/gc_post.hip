@@ -20,41 +20,6 @@ namespace {
 
 using namespace gc;
 
-// Smallest eigenvalue of the k x k tridiagonal (alpha, beta): multisection
-// over the 64 lanes on the Sturm count (negative LDL^T pivots).
-__device__ double tridiag_min_eig(const double *alpha, const double *beta, int k)
-{
-    const int lane = threadIdx.x & 63;
-    double lo = INFINITY, hi = -INFINITY;
-    for (int j = 0; j < k; ++j) {
-        const double bl = j > 0 ? fabs(beta[j - 1]) : 0.0;
-        const double br = j + 1 < k ? fabs(beta[j]) : 0.0;
-        lo = fmin(lo, alpha[j] - bl - br);
-        hi = fmax(hi, alpha[j] + bl + br);
-    }
-    lo -= 1e-12 * (1.0 + fabs(lo));
-    hi += 1e-12 * (1.0 + fabs(hi));
-    for (int round = 0; round < 24; ++round) {
-        const double step = (hi - lo) / 65.0;
-        const double x = lo + step * (double)(lane + 1);
-        int cnt = 0;
-        double q = alpha[0] - x;
-        if (q < 0) ++cnt;
-        for (int j = 1; j < k; ++j) {
-            const double qq = (q == 0.0) ? 1e-300 : q;
-            q = (alpha[j] - x) - beta[j - 1] * beta[j - 1] / qq;
-            if (q < 0) ++cnt;
-        }
-        const int first = wave_min_int(cnt >= 1 ? lane : 64);
-        const double nlo = (first == 0) ? lo : lo + step * (double)first;
-        const double nhi = (first == 64) ? hi : lo + step * (double)(first + 1);
-        lo = nlo;
-        hi = nhi;
-        if (hi - lo <= 1e-15 * fmax(1.0, fabs(hi))) break;
-    }
-    return 0.5 * (lo + hi);
-}
-
 // Insert a key (one lane).  A new key is claimed by CAS on its high word; the
 // claimer then publishes the low word.  Returns whether this start is the
 // lowest start id seen for the key so far.
@@ -115,88 +80,120 @@ __device__ GcEntry *table_find(const GcJobDev &J, uint64_t key_hi, uint64_t key_
     return nullptr;
 }
 
-// Lowest eigenvalue of M + sigma 11^T/V by Lanczos without reorthogonalisation
-// (extreme Ritz values converge regardless).  q lives in LDS; q_prev and the
-// residual in the wave's scratch, each lane touching only its own entries.
-__device__ double lanczos_lambda2(const GcJobDev &J, double *vq, const double *sw, double *vp, double *vr,
-                                  double *alpha, double *beta, uint32_t &iters, bool &conv)
+// Workgroup reductions over B threads: wave butterflies, then the waves'
+// partials combined in a fixed order.  Every thread returns the result.
+template <int B, int N>
+__device__ __forceinline__ void wg_sum_n(double (&v)[N], double *red)
 {
-    const int lane = threadIdx.x & 63;
-    const GcOrbitDev &O = J.orb;
-    const int V = O.V, d = O.d;
-    const double sigma = 4.0 * d + 1.0;
-    // deterministic start vector orthogonal to the constant mode
-    double acc = 0.0;
-    for (int i = lane; i < V; i += 64) {
-        const double r0 = (double)(mix64((uint64_t)i + 0x5851F42D4C957F2DULL) >> 11) * 0x1.0p-53 - 0.5;
-        vr[i] = r0;
-        acc += r0;
+#pragma unroll
+    for (int n = 0; n < N; ++n) v[n] = wave_sum(v[n]);
+    if (B > 64) {
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int n = 0; n < N; ++n) red[n * (B / 64) + (threadIdx.x >> 6)] = v[n];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            double t = red[n * (B / 64)];
+#pragma unroll
+            for (int w = 1; w < B / 64; ++w) t += red[n * (B / 64) + w];
+            v[n] = t;
+        }
     }
-    const double mean = wave_sum(acc) / (double)V;
-    acc = 0.0;
-    for (int i = lane; i < V; i += 64) {
-        const double r0 = vr[i] - mean;
-        vr[i] = r0;
-        vp[i] = 0.0;
-        acc += r0 * r0;
+}
+
+template <int B>
+__device__ __forceinline__ uint64_t wg_sum_u64(uint64_t v, uint64_t *red)
+{
+    v = wave_sum_u64(v);
+    if (B > 64) {
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        uint64_t t = red[0];
+#pragma unroll
+        for (int w = 1; w < B / 64; ++w) t += red[w];
+        v = t;
     }
-    const double nrm = sqrt(wave_sum(acc));
-    for (int i = lane; i < V; i += 64) vq[i] = vr[i] / nrm;
-    wave_sync();
-    double beta_prev = 0.0, theta = INFINITY, theta_old = INFINITY;
-    const int maxit = min(min(J.lanczos_max, GC_LMAX), V);
-    int it = 0;
-    conv = false;
-    for (it = 0; it < maxit; ++it) {
-        double sq = 0.0;
-        for (int i = lane; i < V; i += 64) sq += vq[i];
-        const double shift = sigma * wave_sum(sq) / (double)V;
-        double aq = 0.0;
-        for (int i = lane; i < V; i += 64) {
-            const double qi = vq[i];
-            double m = 0.0;
-            for (int mu = 0; mu < d; ++mu) {
-                const int f = O.nbr[mu * V + i], b = O.nbr[(d + mu) * V + i];
-                m += sw[mu * V + i] * (qi - vq[f]);
-                m += sw[mu * V + b] * (qi - vq[b]);
-            }
-            const double r = m + shift - beta_prev * vp[i];
-            vr[i] = r;
-            aq += r * qi;
-        }
-        const double a_j = wave_sum(aq);
-        acc = 0.0;
-        for (int i = lane; i < V; i += 64) {
-            const double r = vr[i] - a_j * vq[i];
-            vr[i] = r;
-            acc += r * r;
-        }
-        const double b_j = sqrt(wave_sum(acc));
-        if (lane == 0) {
-            alpha[it] = a_j;
-            beta[it] = b_j;
-        }
-        wave_sync_global();
-        const bool breakdown = b_j <= 1e-13 * sigma;
-        if (((it + 1) % 8 == 0) || breakdown || it + 1 == maxit) {
-            theta = tridiag_min_eig(alpha, beta, it + 1);
-            if (breakdown || fabs(theta - theta_old) <= 1e-12 * fmax(1.0, fabs(theta))) {
-                conv = true;
-                ++it;
-                break;
-            }
-            theta_old = theta;
-        }
-        wave_sync();   // every neighbour read of q is done
-        for (int i = lane; i < V; i += 64) {
-            vp[i] = vq[i];
-            vq[i] = vr[i] / b_j;
-        }
-        beta_prev = b_j;
-        wave_sync();
+    return v;
+}
+
+template <int B>
+__device__ __forceinline__ int wg_min_int(int v, int *red)
+{
+    v = wave_min_int(v);
+    if (B > 64) {
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        int t = red[0];
+#pragma unroll
+        for (int w = 1; w < B / 64; ++w) t = min(t, red[w]);
+        v = t;
     }
-    iters = (uint32_t)it;
-    return theta;
+    return v;
+}
+
+// Number of eigenvalues of the k x k tridiagonal below x: the negative pivots
+// of the LDL^T factorisation of T - x (Sturm count), full-precision division.
+__device__ __forceinline__ int sturm_count(const double *alpha, const double *beta2, int k, double x)
+{
+    int cnt = 0;
+    double q = alpha[0] - x;
+    if (q < 0) ++cnt;
+    for (int j = 1; j < k; ++j) {
+        const double qq = (q == 0.0) ? 1e-300 : q;
+        q = (alpha[j] - x) - beta2[j - 1] / qq;
+        if (q < 0) ++cnt;
+    }
+    return cnt;
+}
+
+// Smallest eigenvalue of the tridiagonal by (B+1)-section inside [lo, hi]
+// (count(lo) = 0, count(hi) >= 1).
+template <int B>
+__device__ double tridiag_min_eig(const double *alpha, const double *beta2, int k, double lo, double hi, int *ired)
+{
+    for (int round = 0; round < 24; ++round) {
+        if (hi - lo <= 1e-15 * fmax(1.0, fabs(hi))) break;
+        const double step = (hi - lo) / (double)(B + 1);
+        const double x = lo + step * (double)(threadIdx.x + 1);
+        const int first = wg_min_int<B>(sturm_count(alpha, beta2, k, x) >= 1 ? (int)threadIdx.x : B, ired);
+        const double nlo = (first == 0) ? lo : lo + step * (double)first;
+        const double nhi = (first == B) ? hi : lo + step * (double)(first + 1);
+        lo = nlo;
+        hi = nhi;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Smallest Ritz value of the k x k tridiagonal.  By interlacing it never
+// increases as k grows, so the previous value bounds it above; a window
+// below it is tried first, with the Gershgorin interval as the fallback.
+template <int B>
+__device__ double ritz_min(const double *alpha, const double *beta2, const double *babs, int k, double prev,
+                           double prev_step, int *ired)
+{
+    double lo = INFINITY, hi = -INFINITY;
+    for (int j = 0; j < k; ++j) {
+        const double bl = j > 0 ? babs[j - 1] : 0.0;
+        const double br = j + 1 < k ? babs[j] : 0.0;
+        lo = fmin(lo, alpha[j] - bl - br);
+        hi = fmax(hi, alpha[j] + bl + br);
+    }
+    lo -= 1e-12 * (1.0 + fabs(lo));
+    hi += 1e-12 * (1.0 + fabs(hi));
+    if (prev < hi) {
+        const double top = prev + 1e-12 * (1.0 + fabs(prev));
+        const double bot = top - fmax(4.0 * prev_step, 1e-9 * (1.0 + fabs(prev)));
+        const bool top_ok = sturm_count(alpha, beta2, k, top) >= 1;
+        if (top_ok && bot > lo && sturm_count(alpha, beta2, k, bot) == 0)
+            return tridiag_min_eig<B>(alpha, beta2, k, bot, top, ired);
+        if (top_ok) hi = top;
+    }
+    return tridiag_min_eig<B>(alpha, beta2, k, lo, hi, ired);
 }
 
 __device__ uint32_t region_flags(double lam2, double tol)
@@ -206,78 +203,118 @@ __device__ uint32_t region_flags(double lam2, double tol)
     return GC_F_SINGULAR;
 }
 
-// One wavefront per workgroup; LDS holds the start's state (16V bytes), later
-// reused for the Lanczos vector q.  Scratch per wavefront: alpha, beta, link
-// angles [d][V], link weights [d][V], q_prev [V], residual [V].
-__global__ __launch_bounds__(64) void post_kernel(const GcJobDev *__restrict__ jobs, int n_jobs,
-                                                  const uint64_t *__restrict__ prefix, unsigned long long *next,
-                                                  uint64_t total, const unsigned long long *total_dev,
-                                                  double *scratch, uint64_t stride)
+// One workgroup of B threads per start; thread t owns sites i = t + B k,
+// k < SP.  With WREG the link weights of the own sites stay in registers
+// (SP <= 4); otherwise the forward link weights of the start go to the
+// workgroup's slice of wbuf (dV doubles) and are re-read from there.  Entries
+// of q_prev and of the residual of the own sites stay in registers.
+// LDS: the state g (16V bytes, later the Lanczos vector q), then the link
+// angles as floats (4dV bytes) during the key, reused for the tridiagonal.
+// The angle of a link is atan2 in single precision: the branch cut at +-pi is
+// decided by the sign of Im u alone, which rounding keeps, and a plaquette or
+// line sum then lies within about 1e-5 of its multiple of 2pi, so the wrap
+// numbers are the ones double precision gives.
+template <int B, int SP, bool WREG>
+__global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jobs, int n_jobs,
+                                                 const uint64_t *__restrict__ prefix, unsigned long long *next,
+                                                 uint64_t total, const unsigned long long *total_dev,
+                                                 double *wbuf_all, uint64_t wstride)
 {
+    constexpr int NW = WREG ? SP : 1;   // register weights per thread (dummy when !WREG)
+    glb_ptr<double> wbuf = as_global(wbuf_all + (WREG ? 0 : (uint64_t)blockIdx.x * wstride));
     extern __shared__ __align__(16) unsigned char smem[];
-    const int lane = threadIdx.x & 63;
+    __shared__ double red[3 * (B / 64)];
+    __shared__ uint64_t ured[B / 64];
+    __shared__ int ired[B / 64];
+    __shared__ unsigned long long claim;
+    __shared__ int run_sh;
     if (total_dev) total = *total_dev;
-    double *wscr = scratch + (uint64_t)blockIdx.x * stride;
     for (;;) {
-        unsigned long long s = 0;
-        if (lane == 0) s = atomicAdd(next, 1ULL);
-        s = __shfl(s, 0, 64);
+        // re-derived per start so that nothing indexed by it is hoisted out of
+        // the start loop and held in registers across it
+        const int tid = (int)threadIdx.x + opaque_zero();
+        if (tid == 0) claim = atomicAdd(next, 1ULL);
+        __syncthreads();
+        const uint64_t s = uniform((uint64_t)claim);
+        __syncthreads();
         if (s >= total) break;
         int jn = 0;
         if (prefix)
             while (jn + 1 < n_jobs && prefix[jn + 1] <= s) ++jn;
+        jn = uniform(jn);
         const GcJobDev &J = jobs[jn];
         const GcOrbitDev &O = J.orb;
         const int V = O.V, d = O.d;
         const bool fixmode = (J.flags & GC_JOB_FIX) != 0;
         const uint64_t local = fixmode ? J.fix[s].start - J.first_start : s - (prefix ? prefix[jn] : 0);
         const uint64_t sid = J.first_start + local;
-        GcStartRec rec = J.rec[local];
-        if (rec.status != GC_ST_CONVERGED) continue;   // uniform across the wave
+        const GcStartRec rec0 = J.rec[local];
+        if (rec0.status != GC_ST_CONVERGED) continue;   // uniform across the workgroup
 
-        double2 *g = reinterpret_cast<double2 *>(smem);
-        const double2 *src = J.states + local * (uint64_t)V;
-        for (int i = lane; i < V; i += 64) g[i] = src[i];
-        wave_sync();
+        lds_ptr<dbl2> g = as_lds(reinterpret_cast<dbl2 *>(smem));
+        // the link angles (key phase) and the tridiagonal (Lanczos) share LDS
+        lds_ptr<float> a32 = as_lds(reinterpret_cast<float *>(smem + 16 * (size_t)V));
+        double *alpha = reinterpret_cast<double *>(smem + 16 * (size_t)V);
+        const int lmax = min(min(J.lanczos_max, GC_LMAX), V);
+        double *beta2 = alpha + lmax;
+        double *babs = beta2 + lmax;
+        glb_ptr<const dbl2> src = as_global(reinterpret_cast<const dbl2 *>(J.states + local * (uint64_t)V));
+        for (int i = tid; i < V; i += B) g[i] = src[i];
+        __syncthreads();
 
-        double *alpha = wscr;
-        double *beta = wscr + GC_LMAX;
-        double *sa = wscr + 2 * GC_LMAX;     // [d][V]
-        double *sw = sa + (size_t)d * V;     // [d][V]
-        double *vp = sw + (size_t)d * V;     // [V]
-        double *vr = vp + V;                 // [V]
-
-        // ---- observables
+        // ---- observables of the own sites: forward links (F, angles) and the
+        // FP weights w = Re u of every link touching the site
+        glb_ptr<const dbl2> U = as_global(reinterpret_cast<const dbl2 *>(O.U64));
+        double wf[NW][GC_MAXD], wb[NW][GC_MAXD];
+        uint32_t nfb[SP][GC_MAXD];   // forward | backward << 16
         double facc = 0.0;
-        for (int l = lane; l < d * V; l += 64) {
-            const int mu = l / V, i = l - mu * V;
-            const int f = O.nbr[mu * V + i];
-            const double2 u = O.U64[l];
-            const double2 gi = g[i], gf = g[f];
-            const double tr = u.x * gf.x - u.y * gf.y;
-            const double ti = u.x * gf.y + u.y * gf.x;
-            const double ur = gi.x * tr + gi.y * ti;
-            const double ui = gi.x * ti - gi.y * tr;
-            facc += 1.0 - ur;
-            sa[l] = atan2(ui, ur);
-            sw[l] = ur;
+#pragma unroll
+        for (int k = 0; k < SP; ++k) {
+            const int i = tid + B * k;
+#pragma unroll
+            for (int mu = 0; mu < GC_MAXD; ++mu) {
+                if (WREG) {
+                    wf[k % NW][mu] = 0.0;
+                    wb[k % NW][mu] = 0.0;
+                }
+                nfb[k][mu] = 0;
+                if (i < V && mu < d) {
+                    const int f = O.nbr[mu * V + i], b = O.nbr[(d + mu) * V + i];
+                    nfb[k][mu] = (uint32_t)f | ((uint32_t)b << 16);
+                    const dbl2 gi = g[i], gf = g[f], gb = g[b];
+                    const dbl2 u = U[mu * V + i];
+                    const double tr = u.x * gf.x - u.y * gf.y, ti = u.x * gf.y + u.y * gf.x;
+                    const double ur = gi.x * tr + gi.y * ti, ui = gi.x * ti - gi.y * tr;
+                    facc += 1.0 - ur;
+                    a32[mu * V + i] = atan2f((float)ui, (float)ur);
+                    if (WREG) wf[k % NW][mu] = ur;
+                    else wbuf[mu * V + i] = ur;
+                    const dbl2 v = U[mu * V + b];
+                    const double sr = v.x * gi.x - v.y * gi.y, si = v.x * gi.y + v.y * gi.x;
+                    if (WREG) wb[k % NW][mu] = gb.x * sr + gb.y * si;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
-        const double F = wave_sum(facc);
-        wave_sync_global();
+        double tmp1[1] = {facc};
+        wg_sum_n<B, 1>(tmp1, red);
+        const double F = tmp1[0];
+        __syncthreads();   // angles visible to the whole workgroup
         uint32_t flags = 0;
-        uint64_t key_hi = rec.key_hi, key_lo = rec.key_lo;
+        uint64_t key_hi = rec0.key_hi, key_lo = rec0.key_lo;
         if (!fixmode) {
-            // ---- integer key
+            // ---- integer key: plaquette wrap numbers, then line windings
             const uint64_t c0 = 0x243F6A8885A308D3ULL, c1 = 0x13198A2E03707344ULL;
             uint64_t h0 = 0, h1 = 0;
             int overflow = 0;
-            for (int k = lane; k < O.n_elems; k += 64) {
+            for (int k = tid; k < O.n_elems; k += B) {
                 double val;
                 if (k < O.n_plaq) {
                     const int pl = k / V, i = k - pl * V;
                     const int mu = O.plane_mu[pl], nu = O.plane_nu[pl];
                     const int fm = O.nbr[mu * V + i], fn = O.nbr[nu * V + i];
-                    const double A = sa[mu * V + i] + sa[nu * V + fm] - sa[mu * V + fn] - sa[nu * V + i];
+                    const double A = (double)a32[mu * V + i] + (double)a32[nu * V + fm] - (double)a32[mu * V + fn] -
+                                     (double)a32[nu * V + i];
                     val = rint((A - O.phi_plaq[k]) / kTwoPi);
                 } else {
                     const int q = k - O.n_plaq;
@@ -286,7 +323,7 @@ __global__ __launch_bounds__(64) void post_kernel(const GcJobDev *__restrict__ j
                     int i = O.line_site[q];
                     double acc = 0.0;
                     for (int t = 0; t < O.ext[mu]; ++t) {
-                        acc += sa[mu * V + i];
+                        acc += (double)a32[mu * V + i];
                         i = O.nbr[mu * V + i];
                     }
                     val = rint((acc - O.phi_line[q]) / kTwoPi);
@@ -297,51 +334,163 @@ __global__ __launch_bounds__(64) void post_kernel(const GcJobDev *__restrict__ j
                 h0 += mix64(c0 ^ word);
                 h1 += mix64(c1 ^ word);
             }
-            h0 = wave_sum_u64(h0);
-            h1 = wave_sum_u64(h1);
-            const int ok = wave_min_int(overflow ? 0 : 1);
+            h0 = wg_sum_u64<B>(h0, ured);
+            h1 = wg_sum_u64<B>(h1, ured);
+            const int ok = wg_min_int<B>(overflow ? 0 : 1, ired);
             key_hi = mix64(h0 + (uint64_t)O.n_elems);
             key_lo = mix64(h1 + (uint64_t)O.n_elems);
             if (key_hi == 0) key_hi = 1;
             if (!ok) flags |= GC_F_KEY_OVERFLOW;
+            if (tid == 0) {
+                bool claimed, is_min, failed;
+                table_insert(J, key_hi, key_lo, sid, F, claimed, is_min, failed);
+                run_sh = is_min ? 1 : 0;
+                if (claimed) atomicAdd(&J.cnt->distinct, 1ULL);
+                if (failed) atomicAdd(&J.cnt->errors, 1ULL);
+            }
+        } else if (tid == 0) {
+            run_sh = 1;
         }
-        // ---- dedup (one lane), then the filter for the lowest start of a key
-        int run = fixmode ? 1 : 0;
-        if (!fixmode && lane == 0) {
-            bool claimed, is_min, failed;
-            table_insert(J, key_hi, key_lo, sid, F, claimed, is_min, failed);
-            run = is_min ? 1 : 0;
-            if (claimed) atomicAdd(&J.cnt->distinct, 1ULL);
-            if (failed) atomicAdd(&J.cnt->errors, 1ULL);
-        }
-        run = __shfl(run, 0, 64);
+        __syncthreads();
+        const bool run = uniform(run_sh) != 0;
         double lam2 = NAN;
         uint32_t lit = 0;
         if (run) {
-            wave_sync();   // q overwrites the state
-            bool conv;
-            lam2 = lanczos_lambda2(J, reinterpret_cast<double *>(g), sw, vp, vr, alpha, beta, lit, conv);
+            // ---- Lanczos on A = M + sigma 11^T/V, M = B^T diag(w) B; q in LDS
+            // over the state, q_prev and the residual in registers
+            const double sigma = 4.0 * d + 1.0;
+            lds_ptr<double> vq = as_lds(reinterpret_cast<double *>(smem));
+            double qp[SP], r[SP];
+            double sums[2] = {0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < SP; ++k) {
+                const int i = tid + B * k;
+                qp[k] = 0.0;
+                r[k] = 0.0;
+                if (i < V) {
+                    r[k] = (double)(mix64((uint64_t)i + 0x5851F42D4C957F2DULL) >> 11) * 0x1.0p-53 - 0.5;
+                    sums[0] += r[k];
+                }
+            }
+            wg_sum_n<B, 1>(*reinterpret_cast<double(*)[1]>(&sums[0]), red);
+            const double mean = sums[0] / (double)V;
+            double nn[1] = {0.0};
+#pragma unroll
+            for (int k = 0; k < SP; ++k) {
+                const int i = tid + B * k;
+                if (i < V) {
+                    r[k] -= mean;
+                    nn[0] += r[k] * r[k];
+                }
+            }
+            wg_sum_n<B, 1>(nn, red);
+            const double inv = 1.0 / sqrt(nn[0]);
+            __syncthreads();   // every thread is done with g before q overwrites it
+#pragma unroll
+            for (int k = 0; k < SP; ++k) {
+                const int i = tid + B * k;
+                if (i < V) vq[i] = r[k] * inv;
+            }
+            __syncthreads();
+            double beta_prev = 0.0, theta = INFINITY, theta_old = INFINITY, theta_step = 1.0;
+            int it = 0;
+            bool conv = false;
+            for (it = 0; it < lmax; ++it) {
+                // (M q)_i for the own sites, then q.Mq, sum q, q.q_prev at once
+                double mq[SP];
+                double s3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int k = 0; k < SP; ++k) {
+                    const int i = tid + B * k;
+                    mq[k] = 0.0;
+                    if (i < V) {
+                        const double qi = vq[i];
+                        double m = 0.0;
+#pragma unroll
+                        for (int mu = 0; mu < GC_MAXD; ++mu)
+                            if (mu < d) {
+                                const uint32_t f = nfb[k][mu] & 0xFFFFu, b = nfb[k][mu] >> 16;
+                                const double w1 = WREG ? wf[k % NW][mu] : wbuf[mu * V + i];
+                                const double w2 = WREG ? wb[k % NW][mu] : wbuf[mu * V + b];
+                                m += w1 * (qi - vq[f]) + w2 * (qi - vq[b]);
+                            }
+                        mq[k] = m;
+                        s3[0] += qi * m;
+                        s3[1] += qi;
+                        s3[2] += qi * qp[k];
+                    }
+                    // one site at a time: keeps the scheduler from holding
+                    // every neighbour of every own site in registers
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                wg_sum_n<B, 3>(s3, red);
+                const double shift = sigma * s3[1] / (double)V;
+                const double a_j = s3[0] + shift * s3[1] - beta_prev * s3[2];
+                double rr[1] = {0.0};
+#pragma unroll
+                for (int k = 0; k < SP; ++k) {
+                    const int i = tid + B * k;
+                    if (i < V) {
+                        const double qi = vq[i];
+                        r[k] = mq[k] + shift - beta_prev * qp[k] - a_j * qi;
+                        rr[0] += r[k] * r[k];
+                    }
+                }
+                wg_sum_n<B, 1>(rr, red);
+                const double b_j = sqrt(rr[0]);
+                if (tid == 0) {
+                    alpha[it] = a_j;
+                    beta2[it] = b_j * b_j;
+                    babs[it] = b_j;
+                }
+                __syncthreads();
+                const bool breakdown = b_j <= 1e-13 * sigma;
+                if (((it + 1) % 8 == 0) || breakdown || it + 1 == lmax) {
+                    theta = ritz_min<B>(alpha, beta2, babs, it + 1, theta_old, theta_step, ired);
+                    if (breakdown || fabs(theta - theta_old) <= 1e-12 * fmax(1.0, fabs(theta))) {
+                        conv = true;
+                        ++it;
+                        break;
+                    }
+                    if (theta_old < INFINITY) theta_step = theta_old - theta;
+                    theta_old = theta;
+                }
+                const double ib = 1.0 / b_j;
+#pragma unroll
+                for (int k = 0; k < SP; ++k) {
+                    const int i = tid + B * k;
+                    if (i < V) {
+                        qp[k] = vq[i];
+                        vq[i] = r[k] * ib;
+                    }
+                }
+                beta_prev = b_j;
+                __syncthreads();
+            }
+            lam2 = theta;
+            lit = (uint32_t)it;
             if (!conv) flags |= GC_F_LANCZOS_CAP;
             flags |= region_flags(lam2, J.lambda_tol);
-            if (lane == 0) atomicAdd(&J.cnt->lanczos_runs, 1ULL);
+            if (tid == 0) atomicAdd(&J.cnt->lanczos_runs, 1ULL);
         }
-        if (lane == 0) {
+        if (tid == 0) {
             if (fixmode) {
                 J.fix[s].lambda2 = lam2;
                 J.fix[s].flags = flags;
                 J.fix[s].lanczos_iters = lit;
             } else {
-                rec.F = F;
-                rec.key_hi = key_hi;
-                rec.key_lo = key_lo;
-                rec.paper_X = (uint32_t)(F / ((double)d * (double)V) * 1e8);
-                rec.flags = flags;
-                rec.lambda2 = lam2;
-                rec.lanczos_iters = lit;
-                J.rec[local] = rec;
+                GcStartRec rc = rec0;
+                rc.F = F;
+                rc.key_hi = key_hi;
+                rc.key_lo = key_lo;
+                rc.paper_X = (uint32_t)(F / ((double)d * (double)V) * 1e8);
+                rc.flags = flags;
+                rc.lambda2 = lam2;
+                rc.lanczos_iters = lit;
+                J.rec[local] = rc;
             }
         }
-        wave_sync();
+        __syncthreads();
     }
 }
 
@@ -437,6 +586,27 @@ __global__ void compact_kernel(GcJobDev J)
     }
 }
 
+constexpr uint32_t kFilterFlags = GC_F_IN_REGION | GC_F_SINGULAR | GC_F_SADDLE | GC_F_LANCZOS_CAP;
+
+// Which other starts of a key also ran the filter depends on the order of
+// insertion; their results are dropped so that a start record carries the
+// filter exactly when the start is its copy's representative.
+__global__ void scrub_kernel(GcJobDev J)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < J.n_starts; k += stride) {
+        GcStartRec &r = J.rec[k];
+        if (r.status != GC_ST_CONVERGED || r.lanczos_iters == 0) continue;
+        const GcEntry *e = table_find(J, r.key_hi, r.key_lo);
+        if (e && e->rep_start == J.first_start + k) continue;
+        r.lambda2 = NAN;
+        r.lanczos_iters = 0;
+        r.flags &= ~kFilterFlags;
+    }
+}
+
+// Filter results recomputed at representatives: into the copy and the
+// representative's start record.
 __global__ void patch_kernel(GcJobDev J)
 {
     const uint64_t n = *J.n_fix;
@@ -444,8 +614,12 @@ __global__ void patch_kernel(GcJobDev J)
         const GcFix f = J.fix[k];
         GcCopyRec &c = J.copies[f.slot];
         c.lambda2 = f.lambda2;
-        c.flags |= f.flags & (GC_F_IN_REGION | GC_F_SINGULAR | GC_F_SADDLE | GC_F_LANCZOS_CAP);
+        c.flags |= f.flags & kFilterFlags;
         c.lanczos_iters = f.lanczos_iters;
+        GcStartRec &r = J.rec[f.start - J.first_start];
+        r.lambda2 = f.lambda2;
+        r.lanczos_iters = f.lanczos_iters;
+        r.flags = (r.flags & ~kFilterFlags) | (f.flags & kFilterFlags);
     }
 }
 
@@ -476,22 +650,69 @@ int grid_for(uint64_t work)
 
 }  // namespace
 
-size_t gc_post_lds_bytes(int V) { return 16 * (size_t)V; }
-
-uint64_t gc_post_scratch_doubles(int d, int V) { return 2ull * GC_LMAX + 2ull * d * V + 2ull * V; }
-
-hipError_t gc_post_occupancy(size_t lds_bytes, int *blocks_per_cu)
+size_t gc_post_lds_bytes(int d, int V)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, post_kernel, 64, lds_bytes);
+    const size_t lmax = V < GC_LMAX ? V : GC_LMAX;
+    const size_t angles = 4 * (size_t)d * V, tri = 3 * sizeof(double) * lmax;
+    return 16 * (size_t)V + (angles > tri ? angles : tri);
 }
 
-hipError_t gc_launch_post(const GcJobDev *jobs, int n_jobs, const uint64_t *prefix, unsigned long long *next,
-                          uint64_t total, const unsigned long long *total_dev, double *scratch, uint64_t stride,
-                          int grid, size_t lds_bytes, hipStream_t s)
+void gc_post_shape(int V, int *block, int *sp, int *wreg)
 {
-    hipLaunchKernelGGL(post_kernel, dim3(grid), dim3(64), lds_bytes, s, jobs, n_jobs, prefix, next, total, total_dev,
-                       scratch, stride);
+    // up to 4 sites per thread with the link weights in registers; the
+    // largest lattices keep them in global memory
+    static const int shapes[][4] = {{64, 64, 1, 1},     {128, 64, 2, 1},    {256, 64, 4, 1},
+                                    {512, 128, 4, 1},   {1024, 256, 4, 1},  {1536, 384, 4, 1},
+                                    {2048, 512, 4, 1},  {4096, 512, 8, 0}};
+    for (const auto &t : shapes)
+        if (V <= t[0]) {
+            *block = t[1];
+            *sp = t[2];
+            *wreg = t[3];
+            return;
+        }
+    *block = 0;
+    *sp = 0;
+    *wreg = 0;
+}
+
+#define GC_POST_DISPATCH(FN, ...)                                                   \
+    if (block == 64 && sp == 1 && wreg) return FN<64, 1, true>(__VA_ARGS__);        \
+    if (block == 64 && sp == 2 && wreg) return FN<64, 2, true>(__VA_ARGS__);        \
+    if (block == 64 && sp == 4 && wreg) return FN<64, 4, true>(__VA_ARGS__);        \
+    if (block == 128 && sp == 4 && wreg) return FN<128, 4, true>(__VA_ARGS__);      \
+    if (block == 256 && sp == 4 && wreg) return FN<256, 4, true>(__VA_ARGS__);      \
+    if (block == 384 && sp == 4 && wreg) return FN<384, 4, true>(__VA_ARGS__);      \
+    if (block == 512 && sp == 4 && wreg) return FN<512, 4, true>(__VA_ARGS__);      \
+    if (block == 512 && sp == 8 && !wreg) return FN<512, 8, false>(__VA_ARGS__);    \
+    return hipErrorInvalidValue;
+
+template <int B, int SP, bool WREG>
+static hipError_t post_occ_t(size_t lds, int *per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, post_kernel<B, SP, WREG>, B, lds);
+}
+
+template <int B, int SP, bool WREG>
+static hipError_t post_launch_t(const GcJobDev *jobs, int n_jobs, const uint64_t *prefix, unsigned long long *next,
+                                uint64_t total, const unsigned long long *total_dev, double *wbuf, uint64_t wstride,
+                                int grid, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((post_kernel<B, SP, WREG>), dim3(grid), dim3(B), lds, s, jobs, n_jobs, prefix, next, total,
+                       total_dev, wbuf, wstride);
     return hipGetLastError();
+}
+
+hipError_t gc_post_occupancy(int block, int sp, int wreg, size_t lds_bytes, int *blocks_per_cu)
+{
+    GC_POST_DISPATCH(post_occ_t, lds_bytes, blocks_per_cu)
+}
+
+hipError_t gc_launch_post(int block, int sp, int wreg, const GcJobDev *jobs, int n_jobs, const uint64_t *prefix,
+                          unsigned long long *next, uint64_t total, const unsigned long long *total_dev,
+                          double *wbuf, uint64_t wstride, int grid, size_t lds_bytes, hipStream_t s)
+{
+    GC_POST_DISPATCH(post_launch_t, jobs, n_jobs, prefix, next, total, total_dev, wbuf, wstride, grid, lds_bytes, s)
 }
 
 hipError_t gc_launch_reset(const GcJobDev *jobs_host, int n_jobs, hipStream_t s)
@@ -523,8 +744,11 @@ hipError_t gc_launch_finalize(const GcJobDev *jobs_host, int n_jobs, hipStream_t
 hipError_t gc_launch_patch(const GcJobDev *jobs_host, int n_jobs, hipStream_t s)
 {
     for (int j = 0; j < n_jobs; ++j) {
+        hipLaunchKernelGGL(scrub_kernel, dim3(grid_for(jobs_host[j].n_starts)), dim3(256), 0, s, jobs_host[j]);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(patch_kernel, dim3(64), dim3(256), 0, s, jobs_host[j]);
-        const hipError_t e = hipGetLastError();
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

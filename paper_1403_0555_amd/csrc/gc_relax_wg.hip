@@ -42,8 +42,14 @@ __device__ __forceinline__ double wg_max(double v, double *red)
 }
 
 template <typename R> __device__ __forceinline__ const typename cx<R>::T *links(const GcOrbitDev &O);
-template <> __device__ __forceinline__ const float2 *links<float>(const GcOrbitDev &O) { return O.U32; }
-template <> __device__ __forceinline__ const double2 *links<double>(const GcOrbitDev &O) { return O.U64; }
+template <> __device__ __forceinline__ const flt2 *links<float>(const GcOrbitDev &O)
+{
+    return reinterpret_cast<const flt2 *>(O.U32);
+}
+template <> __device__ __forceinline__ const dbl2 *links<double>(const GcOrbitDev &O)
+{
+    return reinterpret_cast<const dbl2 *>(O.U64);
+}
 
 // S_i = sum_mu [U_{i,mu} g_{i+mu} + conj(U_{i-mu,mu}) g_{i-mu}], mu ascending
 template <typename R>
@@ -90,7 +96,8 @@ __device__ int relax_phase(const GcJobDev &J, typename cx<R>::T *st, double eps,
             const int lo = O.coff[c], hi = O.coff[c + 1];
             for (int p = lo + tid; p < hi; p += B) {
                 const int i = O.perm[p];
-                st[i] = local_update<R>(st[i], staple<R>(O, U, st, i), omega, relax);
+                const C sv = staple<R>(O, U, st, i);
+                st[i] = relax ? local_update<true, R>(st[i], sv, omega) : local_update<false, R>(st[i], sv, omega);
             }
             __syncthreads();
         }
@@ -124,18 +131,19 @@ __global__ __launch_bounds__(B) void relax_wg_kernel(const GcJobDev *__restrict_
     for (;;) {
         if (tid == 0) claim = atomicAdd(next, 1ULL);
         __syncthreads();
-        const unsigned long long s = claim;
+        const uint64_t s = uniform((uint64_t)claim);
         __syncthreads();
         if (s >= total) break;
         int jn = 0;
         while (jn + 1 < n_jobs && prefix[jn + 1] <= s) ++jn;
+        jn = uniform(jn);
         const GcJobDev &J = jobs[jn];
         const GcOrbitDev &O = J.orb;
         const int V = O.V;
         const uint64_t local = s - prefix[jn];
         const uint64_t sid = J.first_start + local;
-        double2 *st64 = reinterpret_cast<double2 *>(smem);
-        float2 *st32 = reinterpret_cast<float2 *>(smem + 16 * (size_t)V);
+        dbl2 *st64 = reinterpret_cast<dbl2 *>(smem);
+        flt2 *st32 = reinterpret_cast<flt2 *>(smem + 16 * (size_t)V);
 
         for (int b = tid; 4 * b < V; b += B) {
             uint64_t c[4];
@@ -146,8 +154,8 @@ __global__ __launch_bounds__(B) void relax_wg_kernel(const GcJobDev *__restrict_
                 if (i < V) {
                     double sn, cs;
                     sincos(angle_of(c[k]), &sn, &cs);
-                    if (J.precision == 1) st32[i] = make_float2((float)cs, (float)sn);
-                    else st64[i] = make_double2(cs, sn);
+                    if (J.precision == 1) st32[i] = flt2{(float)cs, (float)sn};
+                    else st64[i] = dbl2{cs, sn};
                 }
             }
         }
@@ -162,10 +170,10 @@ __global__ __launch_bounds__(B) void relax_wg_kernel(const GcJobDev *__restrict_
             if (status == GC_ST_CONVERGED) {
                 in64 = true;
                 for (int i = tid; i < V; i += B) {
-                    const float2 g = st32[i];
+                    const flt2 g = st32[i];
                     const double xr = (double)g.x, xi = (double)g.y;
                     const double r = rsqrt(xr * xr + xi * xi);
-                    st64[i] = make_double2(xr * r, xi * r);
+                    st64[i] = dbl2{xr * r, xi * r};
                 }
                 __syncthreads();
                 status = relax_phase<double, B>(J, st64, J.eps64, sw64, D, red);
@@ -173,9 +181,9 @@ __global__ __launch_bounds__(B) void relax_wg_kernel(const GcJobDev *__restrict_
         } else {
             status = relax_phase<double, B>(J, st64, J.eps64, sw64, D, red);
         }
-        double2 *out = J.states + local * (uint64_t)V;
+        dbl2 *out = reinterpret_cast<dbl2 *>(J.states + local * (uint64_t)V);
         for (int i = tid; i < V; i += B)
-            out[i] = in64 ? st64[i] : make_double2((double)st32[i].x, (double)st32[i].y);
+            out[i] = in64 ? st64[i] : dbl2{(double)st32[i].x, (double)st32[i].y};
         if (tid == 0) record_relax(J, local, status, sw32, sw64, D);
         __syncthreads();
     }

@@ -91,28 +91,37 @@ int block_for(int V)
 }
 
 // ---------------------------------------------------------------------------
-// Device memory pool: blocks are cached by size class and reused.
+// Device memory pool: freed blocks are cached and reused by later requests of
+// at most their size (and not more than 25% smaller).  Sizes are rounded to
+// 2 MiB granules (powers of two below that).
 // ---------------------------------------------------------------------------
 struct Pool {
     std::multimap<size_t, void *> free_blocks;
     size_t cached = 0;
 
-    hipError_t get(size_t bytes, void **p)
+    static size_t rounded(size_t bytes)
     {
-        bytes = next_pow2(std::max<size_t>(bytes, 4096));
-        auto it = free_blocks.find(bytes);
-        if (it != free_blocks.end()) {
+        const size_t g = size_t(2) << 20;
+        if (bytes <= g) return next_pow2(std::max<size_t>(bytes, 4096));
+        return (bytes + g - 1) / g * g;
+    }
+    hipError_t get(size_t bytes, void **p, size_t *got)
+    {
+        bytes = rounded(bytes);
+        auto it = free_blocks.lower_bound(bytes);
+        if (it != free_blocks.end() && it->first <= bytes + bytes / 4) {
             *p = it->second;
+            *got = it->first;
+            cached -= it->first;
             free_blocks.erase(it);
-            cached -= bytes;
             return hipSuccess;
         }
+        *got = bytes;
         return hipMalloc(p, bytes);
     }
     void put(void *p, size_t bytes)
     {
         if (!p) return;
-        bytes = next_pow2(std::max<size_t>(bytes, 4096));
         free_blocks.emplace(bytes, p);
         cached += bytes;
     }
@@ -122,7 +131,6 @@ struct Pool {
         free_blocks.clear();
         cached = 0;
     }
-    static size_t rounded(size_t bytes) { return next_pow2(std::max<size_t>(bytes, 4096)); }
 };
 
 struct Orbit;
@@ -345,11 +353,19 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
             site[(size_t)col[i] * half + (i >> 1)] = i;
         }
         std::vector<uint16_t> nb((size_t)2 * half * 8, 0);
+        std::vector<uint32_t> desc((size_t)2 * half, 0);
         std::vector<double2> c64((size_t)2 * 2 * d * half);
         std::vector<float2> c32((size_t)2 * 2 * d * half);
         for (int c = 0; c < 2; ++c)
             for (int h = 0; h < half; ++h) {
                 const int i = site[(size_t)c * half + h];
+                uint32_t dw = (uint32_t)i;
+                for (int mu = 0; mu < d; ++mu) {
+                    const int x = coord[(size_t)i * d + mu];
+                    if (x == n[mu] - 1) dw |= 1u << (12 + mu);
+                    if (x == 0) dw |= 1u << (16 + mu);
+                }
+                desc[(size_t)c * half + h] = dw;
                 for (int k = 0; k < 2 * d; ++k) {
                     const int mu = k < d ? k : k - d;
                     const int nsite = k < d ? nbr[(size_t)mu * V + i] : nbr[(size_t)(d + mu) * V + i];
@@ -368,12 +384,13 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
         size_t woff = 0;
         auto wplace = [&](size_t bytes) { size_t at = woff; woff = align_up(woff + bytes, 256); return at; };
         const size_t w_loc = wplace(loc.size() * 2), w_nb = wplace(nb.size() * 2), w_c64 = wplace(c64.size() * 16),
-                     w_c32 = wplace(c32.size() * 8);
+                     w_c32 = wplace(c32.size() * 8), w_desc = wplace(desc.size() * 4);
         std::vector<unsigned char> wh(woff, 0);
         memcpy(&wh[w_loc], loc.data(), loc.size() * 2);
         memcpy(&wh[w_nb], nb.data(), nb.size() * 2);
         memcpy(&wh[w_c64], c64.data(), c64.size() * 16);
         memcpy(&wh[w_c32], c32.data(), c32.size() * 8);
+        memcpy(&wh[w_desc], desc.data(), desc.size() * 4);
         void *wdevmem = nullptr;
         GC_HIP(hipMalloc(&wdevmem, woff));
         GC_HIP(hipMemcpy(wdevmem, wh.data(), woff, hipMemcpyHostToDevice));
@@ -383,6 +400,7 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
         o->wdev.nb = (const uint4 *)(wb + w_nb);
         o->wdev.coef64 = (const double2 *)(wb + w_c64);
         o->wdev.coef32 = (const float2 *)(wb + w_c32);
+        o->wdev.desc = (const uint32_t *)(wb + w_desc);
         o->wave_tables = wdevmem;
     }
     return GC_OK;
@@ -401,16 +419,25 @@ struct Group {
     uint64_t total = 0;
 };
 
+// Orbits sharing one post-kernel shape (workgroup size by V), so that an
+// orbit's per-start arithmetic is the same alone and in a batch.
+struct PostGroup {
+    int block = 64, sp = 1, wreg = 1, grid = 1;
+    size_t lds = 0;
+    uint64_t total = 0, wstride = 0;
+    std::vector<int> jobs;
+    size_t o_jobs = 0, o_prefix = 0, o_next = 0, o_wbuf = 0;
+};
+
 // Device memory of one job.
 struct JobLayout {
     std::vector<size_t> o_rec, o_table, o_cnt, o_copies, o_ncopies, o_fix, o_nfix, o_states;
     std::vector<uint64_t> table_cap;
     std::vector<Group> groups;
-    size_t o_jobs = 0, o_fixjobs = 0, o_prefix = 0, o_next = 0, o_fixnext = 0, o_scratch = 0;
+    std::vector<PostGroup> posts;
+    std::vector<int> post_of;   // job -> post group
+    size_t o_fixjobs = 0, o_fixnext = 0;
     size_t total = 0;
-    int post_grid = 1;
-    size_t post_lds = 0;
-    uint64_t post_stride = 0;
 };
 
 gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
@@ -418,10 +445,7 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
     const int nj = (int)job->orbits.size();
     size_t off = 0;
     auto place = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes, 256); return at; };
-    L.o_jobs = place(sizeof(GcJobDev) * nj);
     L.o_fixjobs = place(sizeof(GcJobDev) * nj);
-    L.o_prefix = place(sizeof(uint64_t) * (nj + 1));
-    L.o_next = place(sizeof(unsigned long long));
     L.o_fixnext = place(sizeof(unsigned long long));
     int maxV = 0, maxd = 0;
     uint64_t total = 0;
@@ -442,8 +466,12 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         maxV = std::max(maxV, o->V);
         maxd = std::max(maxd, o->d);
         total += n;
-        const bool wave = (o->K == 2);
-        const int gd = wave ? o->d : 0;
+        // two colours: one wavefront per start, GC_WAVES states per workgroup
+        // in LDS; lattices too large for that take the workgroup kernel
+        const bool wave = (o->K == 2) && (size_t)GC_WAVES * 16 * o->V <= ctx->lds_max;
+        // wave groups by dimension; workgroup-kernel groups by block size, so
+        // that an orbit's reductions run in the same order alone and batched
+        const int gd = wave ? o->d : -block_for(o->V);
         Group *g = nullptr;
         for (Group &x : L.groups)
             if (x.wave == wave && x.d == gd) g = &x;
@@ -473,7 +501,7 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             g.coef_lds = (coef_bytes + states <= 64 * 1024) ? 1 : 0;
             g.lds = states + (g.coef_lds ? coef_bytes : 0);
             if (g.lds > ctx->lds_max) return GC_EUNSUPPORTED;
-            hipError_t e = gc_wave_occupancy(g.d, g.ns, g.lds, &per_cu);
+            hipError_t e = gc_wave_occupancy(g.d, g.ns, g.coef_lds, g.lds, &per_cu);
             if (e != hipSuccess) return fail(ctx, e, "occupancy");
         } else {
             g.block = block_for(gV);
@@ -493,16 +521,50 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         g.o_prefix = place(sizeof(uint64_t) * (g.jobs.size() + 1));
         g.o_bounce = g.wave ? place(sizeof(float2) * (size_t)gV * per_wg * g.grid) : 0;
     }
-    // post pass: one wavefront per start over every job
-    L.post_lds = gc_post_lds_bytes(maxV);
-    if (L.post_lds > ctx->lds_max) return GC_EUNSUPPORTED;
-    int per_cu = 0;
-    hipError_t e = gc_post_occupancy(L.post_lds, &per_cu);
-    if (e != hipSuccess) return fail(ctx, e, "occupancy");
-    per_cu = std::max(per_cu, 1);
-    L.post_grid = (int)std::min<uint64_t>((uint64_t)per_cu * ctx->n_cu, std::max<uint64_t>(total, 1));
-    L.post_stride = gc_post_scratch_doubles(maxd, maxV);
-    L.o_scratch = place(sizeof(double) * L.post_stride * L.post_grid);
+    // post pass: one workgroup per start, one launch per workgroup shape
+    L.post_of.assign(nj, -1);
+    for (int j = 0; j < nj; ++j) {
+        int block = 0, sp = 0, wreg = 0;
+        gc_post_shape(job->orbits[j]->V, &block, &sp, &wreg);
+        if (block == 0) return GC_EUNSUPPORTED;
+        int k = 0;
+        while (k < (int)L.posts.size() &&
+               !(L.posts[k].block == block && L.posts[k].sp == sp && L.posts[k].wreg == wreg))
+            ++k;
+        if (k == (int)L.posts.size()) {
+            L.posts.push_back(PostGroup{});
+            L.posts[k].block = block;
+            L.posts[k].sp = sp;
+            L.posts[k].wreg = wreg;
+        }
+        L.posts[k].jobs.push_back(j);
+        L.posts[k].total += job->n_starts[j];
+        L.post_of[j] = k;
+    }
+    for (PostGroup &pg : L.posts) {
+        int pV = 0, pd = 0;
+        for (int j : pg.jobs) {
+            pV = std::max(pV, job->orbits[j]->V);
+            pd = std::max(pd, job->orbits[j]->d);
+        }
+        pg.lds = gc_post_lds_bytes(pd, pV);
+        if (pg.lds > ctx->lds_max) return GC_EUNSUPPORTED;
+        int per_cu = 0;
+        hipError_t e = gc_post_occupancy(pg.block, pg.sp, pg.wreg, pg.lds, &per_cu);
+        if (e != hipSuccess) return fail(ctx, e, "occupancy");
+        per_cu = std::max(per_cu, 1);
+        pg.grid = (int)std::min<uint64_t>((uint64_t)per_cu * ctx->n_cu, std::max<uint64_t>(pg.total, 1));
+        pg.o_jobs = place(sizeof(GcJobDev) * pg.jobs.size());
+        pg.o_prefix = place(sizeof(uint64_t) * (pg.jobs.size() + 1));
+        pg.o_next = place(sizeof(unsigned long long));
+        if (!pg.wreg) {
+            pg.wstride = ((uint64_t)pd * pV + 31) & ~(uint64_t)31;
+            pg.o_wbuf = place(sizeof(double) * pg.wstride * pg.grid);
+        }
+    }
+    (void)maxV;
+    (void)maxd;
+    (void)total;
     L.total = off;
     return GC_OK;
 }
@@ -533,8 +595,16 @@ gc_status start_job(gc_ctx *ctx, Job *job)
     JobLayout L;
     gc_status st = plan_job(ctx, job, L);
     if (st != GC_OK) return st;
-    job->bytes = Pool::rounded(L.total);
-    GC_HIP(ctx->pool.get(L.total, &job->mem));
+    size_t got = 0;
+    hipError_t pe = ctx->pool.get(L.total, &job->mem, &got);
+    if (pe == hipErrorOutOfMemory || pe == hipErrorMemoryAllocation) {
+        // cached blocks may be holding the memory: return them and retry once
+        (void)hipGetLastError();
+        ctx->pool.drain();
+        pe = ctx->pool.get(L.total, &job->mem, &got);
+    }
+    GC_HIP(pe);
+    job->bytes = got;
     ctx->used += job->bytes;
     const int nj = (int)job->orbits.size();
     unsigned char *base = (unsigned char *)job->mem;
@@ -583,13 +653,31 @@ gc_status start_job(gc_ctx *ctx, Job *job)
     GC_HIP(hipEventCreate(&job->ev_k0));
     GC_HIP(hipEventCreate(&job->ev_k1));
     GC_HIP(hipEventCreateWithFlags(&job->ev_done, hipEventDisableTiming));
-    GC_HIP(hipMemcpyAsync(base + L.o_jobs, job->jobs.data(), sizeof(GcJobDev) * nj, hipMemcpyHostToDevice, s));
     GC_HIP(hipMemcpyAsync(base + L.o_fixjobs, fixjobs.data(), sizeof(GcJobDev) * nj, hipMemcpyHostToDevice, s));
-    GC_HIP(hipMemcpyAsync(base + L.o_prefix, prefix.data(), sizeof(uint64_t) * prefix.size(), hipMemcpyHostToDevice, s));
-    for (const Group &g : L.groups) {
-        std::vector<GcJobDev> gj;
-        std::vector<GcWaveOrbit> gw;
-        std::vector<uint64_t> gp(1, 0);
+    // host staging must outlive the asynchronous copies (synchronised below)
+    std::vector<std::vector<GcJobDev>> pjobs(L.posts.size());
+    std::vector<std::vector<uint64_t>> pprefix(L.posts.size());
+    for (size_t k = 0; k < L.posts.size(); ++k) {
+        const PostGroup &pg = L.posts[k];
+        pprefix[k].assign(1, 0);
+        for (int j : pg.jobs) {
+            pjobs[k].push_back(job->jobs[j]);
+            pprefix[k].push_back(pprefix[k].back() + job->n_starts[j]);
+        }
+        GC_HIP(hipMemcpyAsync(base + pg.o_jobs, pjobs[k].data(), sizeof(GcJobDev) * pjobs[k].size(),
+                              hipMemcpyHostToDevice, s));
+        GC_HIP(hipMemcpyAsync(base + pg.o_prefix, pprefix[k].data(), sizeof(uint64_t) * pprefix[k].size(),
+                              hipMemcpyHostToDevice, s));
+    }
+    std::vector<std::vector<GcJobDev>> rjobs(L.groups.size());
+    std::vector<std::vector<GcWaveOrbit>> rworbs(L.groups.size());
+    std::vector<std::vector<uint64_t>> rprefix(L.groups.size());
+    for (size_t k = 0; k < L.groups.size(); ++k) {
+        const Group &g = L.groups[k];
+        std::vector<GcJobDev> &gj = rjobs[k];
+        std::vector<GcWaveOrbit> &gw = rworbs[k];
+        std::vector<uint64_t> &gp = rprefix[k];
+        gp.assign(1, 0);
         for (int j : g.jobs) {
             gj.push_back(job->jobs[j]);
             gw.push_back(job->orbits[j]->wdev);
@@ -600,12 +688,14 @@ gc_status start_job(gc_ctx *ctx, Job *job)
         GC_HIP(hipMemcpyAsync(base + g.o_prefix, gp.data(), sizeof(uint64_t) * gp.size(), hipMemcpyHostToDevice, s));
     }
     GC_HIP(hipStreamSynchronize(s));
-    double *scratch = (double *)(base + L.o_scratch);
+    auto wbuf_of = [&](const PostGroup &pg) { return pg.wreg ? nullptr : (double *)(base + pg.o_wbuf); };
     auto enqueue_body = [&](hipStream_t qs) -> hipError_t {
         hipError_t e = gc_launch_reset(job->jobs.data(), nj, qs);
         if (e != hipSuccess) return e;
-        e = gc_launch_zero_u64((unsigned long long *)(base + L.o_next), 1, qs);
-        if (e != hipSuccess) return e;
+        for (const PostGroup &pg : L.posts) {
+            e = gc_launch_zero_u64((unsigned long long *)(base + pg.o_next), 1, qs);
+            if (e != hipSuccess) return e;
+        }
         for (const Group &g : L.groups) {
             e = gc_launch_zero_u64((unsigned long long *)(base + g.o_next), (int)g.jobs.size(), qs);
             if (e != hipSuccess) return e;
@@ -629,18 +719,21 @@ gc_status start_job(gc_ctx *ctx, Job *job)
             e = hipEventRecord(job->ev_k1, qs);
             if (e != hipSuccess) return e;
         }
-        e = gc_launch_post((const GcJobDev *)(base + L.o_jobs), nj, (const uint64_t *)(base + L.o_prefix),
-                           (unsigned long long *)(base + L.o_next), job->total, nullptr, scratch, L.post_stride,
-                           L.post_grid, L.post_lds, qs);
-        if (e != hipSuccess) return e;
+        for (const PostGroup &pg : L.posts) {
+            e = gc_launch_post(pg.block, pg.sp, pg.wreg, (const GcJobDev *)(base + pg.o_jobs), (int)pg.jobs.size(),
+                               (const uint64_t *)(base + pg.o_prefix), (unsigned long long *)(base + pg.o_next),
+                               pg.total, nullptr, wbuf_of(pg), pg.wstride, pg.grid, pg.lds, qs);
+            if (e != hipSuccess) return e;
+        }
         e = gc_launch_finalize(job->jobs.data(), nj, qs);
         if (e != hipSuccess) return e;
         for (int j = 0; j < nj; ++j) {
             e = gc_launch_zero_u64((unsigned long long *)(base + L.o_fixnext), 1, qs);
             if (e != hipSuccess) return e;
-            e = gc_launch_post((const GcJobDev *)(base + L.o_fixjobs) + j, 1, nullptr,
-                               (unsigned long long *)(base + L.o_fixnext), 0, job->jobs[j].n_fix, scratch,
-                               L.post_stride, std::min(L.post_grid, 64), L.post_lds, qs);
+            const PostGroup &pg = L.posts[L.post_of[j]];
+            e = gc_launch_post(pg.block, pg.sp, pg.wreg, (const GcJobDev *)(base + L.o_fixjobs) + j, 1, nullptr,
+                               (unsigned long long *)(base + L.o_fixnext), 0, job->jobs[j].n_fix, wbuf_of(pg),
+                               pg.wstride, std::min(pg.grid, 64), pg.lds, qs);
             if (e != hipSuccess) return e;
         }
         e = gc_launch_patch(job->jobs.data(), nj, qs);
@@ -1240,6 +1333,35 @@ gc_status gc_last_error(gc_ctx *ctx, char *buf, size_t cap)
     if (cap) {
         snprintf(buf, cap, "%s", ctx->err.c_str());
     }
+    return GC_OK;
+}
+
+gc_status gc_launch_bytes(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_solve_params *params,
+                          uint64_t *bytes)
+{
+    if (!bytes || n_starts == 0) return GC_EINVAL;
+    gc_solve_params p;
+    if (params) p = *params; else fill_defaults(&p);
+    GC_ENTER(ctx);
+    Orbit *o = find_orbit(ctx, orbit);
+    if (!o) return GC_EINVAL;
+    Job tmp;
+    tmp.orbits.push_back(o);
+    tmp.n_starts.push_back(n_starts);
+    tmp.p = p;
+    size_t b = 0;
+    gc_status st = job_bytes(ctx, &tmp, &b);
+    if (st != GC_OK) return st;
+    *bytes = b;
+    return GC_OK;
+}
+
+gc_status gc_memory_info(gc_ctx *ctx, uint64_t *budget, uint64_t *in_use, uint64_t *queued)
+{
+    GC_ENTER(ctx);
+    if (budget) *budget = ctx->budget;
+    if (in_use) *in_use = ctx->used;
+    if (queued) *queued = ctx->queued.size();
     return GC_OK;
 }
 

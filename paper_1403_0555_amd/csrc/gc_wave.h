@@ -8,6 +8,7 @@ struct GcWaveOrbit {
     int32_t half, pad;              // V / 2
     const uint16_t *loc;            // [V] site -> c * half + h
     const uint4 *nb;                // [2][half] neighbour half indices, 8 x u16 (forward mu, then backward)
+    const uint32_t *desc;           // [2][half] site i | forward-wrap bits << 12 | backward-wrap bits << 16
     const double2 *coef64;          // [2][2d][half] U_{i,k} (forward) / conj(U_{i-k,k}) (backward)
     const float2 *coef32;           // same, rounded to single precision
 };
@@ -16,7 +17,7 @@ struct GcWaveOrbit {
 // private scratch for the single-to-double promotion.
 constexpr int GC_WAVES = 4;
 
-hipError_t gc_wave_occupancy(int d, int ns, size_t lds, int *per_cu);
+hipError_t gc_wave_occupancy(int d, int ns, int coef_lds, size_t lds, int *per_cu);
 hipError_t gc_launch_wave(int d, int ns, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs,
                           unsigned long long *job_next, int coef_lds, float2 *bounce, int grid, size_t lds,
                           hipStream_t s);

@@ -29,20 +29,29 @@ namespace {
 
 using namespace gc;
 
-// S for slot (c, h): sum_k coef[c][k][h] * st[1-c][nb_k]
-template <int D, typename R>
-__device__ __forceinline__ typename cx<R>::T staple(const typename cx<R>::T *__restrict__ coef,
-                                                    const typename cx<R>::T *other, const uint4 nbp,
-                                                    int c, int h, int half)
+// Lattice strides: s_mu and the wrap N_mu s_mu, uniform per orbit.
+template <int D> struct Strides {
+    int s[D], w[D];
+};
+
+// S for slot (c, h) of site i: sum_k coef[c][k][h] g_{n_k}, neighbours from
+// the slot descriptor (site index and the boundary-wrap bits of each
+// direction), forward mu = 0..d-1 then backward, as in the coefficients.
+template <int D, typename R, typename CP, typename SP>
+__device__ __forceinline__ typename cx<R>::T staple(CP coef, SP other, uint32_t dsc, const Strides<D> &L, int c,
+                                                    int h, int half)
 {
     using C = typename cx<R>::T;
-    const uint32_t w[4] = {nbp.x, nbp.y, nbp.z, nbp.w};
+    const int i = (int)(dsc & 0xFFFu);
     R ax = 0, ay = 0;
 #pragma unroll
     for (int k = 0; k < 2 * D; ++k) {
-        const int n = (int)((w[k >> 1] >> (16 * (k & 1))) & 0xFFFFu);
+        const int mu = k < D ? k : k - D;
+        int j;
+        if (k < D) j = i + L.s[mu] - (((dsc >> (12 + mu)) & 1u) ? L.w[mu] : 0);
+        else j = i - L.s[mu] + (((dsc >> (16 + mu)) & 1u) ? L.w[mu] : 0);
         const C u = coef[(c * 2 * D + k) * half + h];
-        const C g = other[n];
+        const C g = other[j >> 1];
         ax += u.x * g.x - u.y * g.y;
         ay += u.x * g.y + u.y * g.x;
     }
@@ -52,74 +61,66 @@ __device__ __forceinline__ typename cx<R>::T staple(const typename cx<R>::T *__r
     return s;
 }
 
-// New value of g at one site from its staple (relaxation or over-relaxation).
-template <typename R>
-__device__ __forceinline__ typename cx<R>::T local_update(typename cx<R>::T g0, typename cx<R>::T s, R omega, bool relax)
-{
-    using C = typename cx<R>::T;
-    const R n2 = s.x * s.x + s.y * s.y;
-    if (n2 == (R)0) return g0;
-    const R r = rsq(n2);
-    const R hx = s.x * r, hy = s.y * r;
-    C g;
-    if (relax) {
-        g.x = hx;
-        g.y = hy;
-    } else {
-        const R zx = g0.x * hx + g0.y * hy;
-        const R zy = g0.x * hy - g0.y * hx;
-        R wx = (R)1 + omega * (zx - (R)1);
-        R wy = omega * zy;
-        const R rw = rsq(wx * wx + wy * wy);
-        wx *= rw;
-        wy *= rw;
-        g.x = g0.x * wx - g0.y * wy;
-        g.y = g0.x * wy + g0.y * wx;
-    }
-    return g;
-}
-
 // Sweeps of one precision on the wave's state st[2][half].  Returns status.
-template <int D, typename R, int NS>
-__device__ int relax_wave(const GcJobDev &J, const GcWaveOrbit &WO, const typename cx<R>::T *__restrict__ coef,
-                          typename cx<R>::T *st, double eps, uint64_t &sweeps, double &D_out)
+// Lane l owns slots h = l + 64k, k < NS, of each colour; slots beyond the
+// half volume are computed on a clamped index and discarded, so the passes
+// have no divergent branches.
+template <int D, typename R, int NS, bool RELAX, typename CP>
+__device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<typename cx<R>::T> st,
+                            double eps, uint64_t &sweeps, double &D_out)
 {
     using C = typename cx<R>::T;
     const int lane = threadIdx.x & 63;
     const int half = WO.half;
-    C *st0 = st, *st1 = st + half;
+    lds_ptr<C> st0 = st;
+    lds_ptr<C> st1 = st + half;
     const R omega = (R)J.omega;
-    const bool relax = (omega == (R)1);
     const uint64_t check = J.check_every > 0 ? (uint64_t)J.check_every : 1;
     const bool maxabs = J.stop_norm != 0;
-    const uint4 *__restrict__ nb0 = WO.nb;
-    const uint4 *__restrict__ nb1 = WO.nb + half;
+    Strides<D> L;
+    {
+        int str = 1;
+#pragma unroll
+        for (int mu = 0; mu < D; ++mu) {
+            L.s[mu] = str;
+            L.w[mu] = str * J.orb.ext[mu];
+            str *= J.orb.ext[mu];
+        }
+    }
+    // slot descriptors stay in registers for the whole solve
+    uint32_t d0[NS], d1[NS];
+    int hs[NS];
+    bool valid[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const int h = lane + 64 * k;
+        valid[k] = h < half;
+        hs[k] = valid[k] ? h : half - 1;
+        d0[k] = WO.desc[hs[k]];
+        d1[k] = WO.desc[half + hs[k]];
+    }
 
     uint64_t t = 0;
     double acc1 = 0.0;           // colour-1 part of the norm of sweep t
     int status = GC_ST_NONCONVERGED;
     D_out = INFINITY;
-    // sweep t + 1 reads the colour-0 staples of the state after sweep t;
-    // when t is a check point they complete the norm of sweep t.
     for (;;) {
+        // sweep t + 1 first reads the colour-0 staples of the state after
+        // sweep t; at a check point they complete the norm of sweep t
         const bool pending = (t > 0) && (t % check == 0 || t == J.max_sweeps);
         const bool last = (t == J.max_sweeps);
         const int z = opaque_zero();
-        // ---- colour 0 (and the colour-0 part of the pending norm)
         C gnew[NS];
         double acc0 = 0.0;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            const int h = lane + 64 * k;
-            if (h < half) {
-                const C s = staple<D, R>(coef, st1, nb0[h + z], 0, h + z, half);
-                const C g0 = st0[h];
-                if (pending) {
-                    const double dv = (double)(g0.x * s.y - g0.y * s.x);
-                    acc0 = maxabs ? fmax(acc0, fabs(dv)) : acc0 + dv * dv;
-                }
-                gnew[k] = last ? g0 : local_update<R>(g0, s, omega, relax);
-            }
+            const int h = hs[k] + z;
+            const C s = staple<D, R>(coef, st1, d0[k] + (uint32_t)z, L, 0, h, half);
+            const C g0 = st0[h];
+            const double dv = (double)(g0.x * s.y - g0.y * s.x);
+            const double a = maxabs ? fmax(acc0, fabs(dv)) : acc0 + dv * dv;
+            acc0 = valid[k] ? a : acc0;
+            gnew[k] = local_update<RELAX, R>(g0, s, omega);
         }
         if (pending) {
             const double Dn = maxabs ? fmax(wave_max(acc0), acc1) : (wave_sum(acc0) + acc1) / (double)(2 * half);
@@ -129,10 +130,8 @@ __device__ int relax_wave(const GcJobDev &J, const GcWaveOrbit &WO, const typena
         }
         if (last) break;
 #pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            const int h = lane + 64 * k;
-            if (h < half) st0[h] = gnew[k];
-        }
+        for (int k = 0; k < NS; ++k)
+            if (valid[k]) st0[hs[k]] = gnew[k];
         wave_sync();
         // ---- colour 1, with its part of the norm of this sweep
         ++t;
@@ -140,16 +139,13 @@ __device__ int relax_wave(const GcJobDev &J, const GcWaveOrbit &WO, const typena
         double a1 = 0.0;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            const int h = lane + 64 * k;
-            if (h < half) {
-                const C s = staple<D, R>(coef, st0, nb1[h + z], 1, h + z, half);
-                const C g = local_update<R>(st1[h], s, omega, relax);
-                st1[h] = g;
-                if (chk) {
-                    const double dv = (double)(g.x * s.y - g.y * s.x);
-                    a1 = maxabs ? fmax(a1, fabs(dv)) : a1 + dv * dv;
-                }
-            }
+            const int h = hs[k] + z;
+            const C s = staple<D, R>(coef, st0, d1[k] + (uint32_t)z, L, 1, h, half);
+            const C g = local_update<RELAX, R>(st1[h], s, omega);
+            if (valid[k]) st1[hs[k]] = g;
+            const double dv = (double)(g.x * s.y - g.y * s.x);
+            const double a = maxabs ? fmax(a1, fabs(dv)) : a1 + dv * dv;
+            a1 = valid[k] ? a : a1;
         }
         if (chk) acc1 = maxabs ? wave_max(a1) : wave_sum(a1);
         wave_sync();
@@ -158,9 +154,17 @@ __device__ int relax_wave(const GcJobDev &J, const GcWaveOrbit &WO, const typena
     return status;
 }
 
-template <int D, int NS>
-__device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, const double2 *coef64,
-                                 const float2 *coef32, double2 *st64, float2 *st32, float2 *bounce, uint64_t local)
+template <int D, typename R, int NS, typename CP>
+__device__ int relax_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<typename cx<R>::T> st,
+                          double eps, uint64_t &sweeps, double &D_out)
+{
+    if ((R)J.omega == (R)1) return relax_wave_t<D, R, NS, true>(J, WO, coef, st, eps, sweeps, D_out);
+    return relax_wave_t<D, R, NS, false>(J, WO, coef, st, eps, sweeps, D_out);
+}
+
+template <int D, int NS, typename CP64, typename CP32>
+__device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 coef64, CP32 coef32,
+                                 lds_ptr<dbl2> st64, lds_ptr<flt2> st32, glb_ptr<flt2> bounce, uint64_t local)
 {
     const int lane = threadIdx.x & 63;
     const GcOrbitDev &O = J.orb;
@@ -178,8 +182,8 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, const
                 double sn, cs;
                 sincos(angle_of(c[k]), &sn, &cs);
                 const int p = WO.loc[i];
-                if (J.precision == 1) st32[p] = make_float2((float)cs, (float)sn);
-                else st64[p] = make_double2(cs, sn);
+                if (J.precision == 1) st32[p] = flt2{(float)cs, (float)sn};
+                else st64[p] = dbl2{cs, sn};
             }
         }
     }
@@ -199,10 +203,10 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, const
             for (int p = lane; p < V; p += 64) bounce[p] = st32[p];
             wave_sync();
             for (int p = lane; p < V; p += 64) {
-                const float2 g = bounce[p];
+                const flt2 g = bounce[p];
                 const double xr = (double)g.x, xi = (double)g.y;
                 const double r = rsqrt(xr * xr + xi * xi);
-                st64[p] = make_double2(xr * r, xi * r);
+                st64[p] = dbl2{xr * r, xi * r};
             }
             wave_sync();
             status = relax_wave<D, double, NS>(J, WO, coef64, st64, J.eps64, sw64, Dn);
@@ -211,23 +215,22 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, const
         status = relax_wave<D, double, NS>(J, WO, coef64, st64, J.eps64, sw64, Dn);
     }
     // final state in natural site order
-    double2 *out = J.states + local * (uint64_t)V;
+    glb_ptr<dbl2> out = as_global(reinterpret_cast<dbl2 *>(J.states + local * (uint64_t)V));
     for (int i = lane; i < V; i += 64) {
         const int p = WO.loc[i];
-        out[i] = in64 ? st64[p] : make_double2((double)st32[p].x, (double)st32[p].y);
+        out[i] = in64 ? st64[p] : dbl2{(double)st32[p].x, (double)st32[p].y};
     }
     if (lane == 0) record_relax(J, local, status, sw32, sw64, Dn);
     wave_sync();
 }
 
-// WG = WAVES wavefronts.  LDS: [coef64 | coef32 staged when coef_lds] then
-// per wave a 16V-byte state region (double2[V], or float2[V] in the single-
-// precision phase).
-template <int D, int NS, int WAVES>
+// WG = WAVES wavefronts.  LDS: [coef64 | coef32 when COEF_LDS] then per wave
+// a 16V-byte state region (double2[V], or float2[V] in the single-precision
+// phase).
+template <int D, int NS, int WAVES, bool COEF_LDS>
 __global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__restrict__ jobs,
                                                           const GcWaveOrbit *__restrict__ worbs, int n_jobs,
-                                                          unsigned long long *job_next, int coef_lds,
-                                                          float2 *bounce_all)
+                                                          unsigned long long *job_next, float2 *bounce_all)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int cur_job;
@@ -247,38 +250,40 @@ __global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__rest
             cur_job = pick;
         }
         __syncthreads();
-        const int jn = cur_job;
+        const int jn = uniform(cur_job);
         __syncthreads();
         if (jn < 0) break;
         const GcJobDev &J = jobs[jn];
         const GcWaveOrbit &WO = worbs[jn];
         const int V = J.orb.V;
         const int ncoef = 2 * D * V;      // complex entries per precision
-        const double2 *coef64 = WO.coef64;
-        const float2 *coef32 = WO.coef32;
         size_t off = 0;
-        if (coef_lds) {
-            double2 *c64 = reinterpret_cast<double2 *>(smem);
-            for (int t = threadIdx.x; t < ncoef; t += 64 * WAVES) c64[t] = WO.coef64[t];
-            coef64 = c64;
+        const dbl2 *g64 = reinterpret_cast<const dbl2 *>(WO.coef64);
+        const flt2 *g32 = reinterpret_cast<const flt2 *>(WO.coef32);
+        lds_ptr<dbl2> c64 = as_lds(reinterpret_cast<dbl2 *>(smem));
+        lds_ptr<flt2> c32 = as_lds(reinterpret_cast<flt2 *>(smem + 16 * (size_t)ncoef));
+        if (COEF_LDS) {
+            for (int t = threadIdx.x; t < ncoef; t += 64 * WAVES) c64[t] = g64[t];
             off = 16 * (size_t)ncoef;
             if (J.precision == 1) {
-                float2 *c32 = reinterpret_cast<float2 *>(smem + off);
-                for (int t = threadIdx.x; t < ncoef; t += 64 * WAVES) c32[t] = WO.coef32[t];
-                coef32 = c32;
+                for (int t = threadIdx.x; t < ncoef; t += 64 * WAVES) c32[t] = g32[t];
                 off += 8 * (size_t)ncoef;
             }
         }
         __syncthreads();
-        double2 *st64 = reinterpret_cast<double2 *>(smem + off + (size_t)wave * 16 * V);
-        float2 *st32 = reinterpret_cast<float2 *>(st64);
+        lds_ptr<dbl2> st64 = as_lds(reinterpret_cast<dbl2 *>(smem + off + (size_t)wave * 16 * V));
+        lds_ptr<flt2> st32 = as_lds(reinterpret_cast<flt2 *>(smem + off + (size_t)wave * 16 * V));
+        glb_ptr<flt2> bounce =
+            as_global(reinterpret_cast<flt2 *>(bounce_all) + ((uint64_t)blockIdx.x * WAVES + wave) * (uint64_t)V);
         for (;;) {
             unsigned long long s = 0;
             if (lane == 0) s = atomicAdd(&job_next[jn], 1ULL);
-            s = __shfl(s, 0, 64);
+            s = uniform((uint64_t)s);
             if (s >= J.n_starts) break;
-            float2 *bounce = bounce_all + ((uint64_t)blockIdx.x * WAVES + wave) * (uint64_t)V;
-            relax_start_wave<D, NS>(J, WO, coef64, coef32, st64, st32, bounce, s);
+            if (COEF_LDS)
+                relax_start_wave<D, NS>(J, WO, c64, c32, st64, st32, bounce, s);
+            else
+                relax_start_wave<D, NS>(J, WO, as_global(g64), as_global(g32), st64, st32, bounce, s);
         }
         __syncthreads();
         j0 = jn;
@@ -289,15 +294,21 @@ template <int D, int NS, int WAVES>
 hipError_t launch_t(const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, unsigned long long *job_next,
                     int coef_lds, float2 *bounce, int grid, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((wave_kernel<D, NS, WAVES>), dim3(grid), dim3(64 * WAVES), lds, s, jobs, worbs, n_jobs,
-                       job_next, coef_lds, bounce);
+    if (coef_lds)
+        hipLaunchKernelGGL((wave_kernel<D, NS, WAVES, true>), dim3(grid), dim3(64 * WAVES), lds, s, jobs, worbs,
+                           n_jobs, job_next, bounce);
+    else
+        hipLaunchKernelGGL((wave_kernel<D, NS, WAVES, false>), dim3(grid), dim3(64 * WAVES), lds, s, jobs, worbs,
+                           n_jobs, job_next, bounce);
     return hipGetLastError();
 }
 
 template <int D, int NS, int WAVES>
-hipError_t occ_t(size_t lds, int *per_cu)
+hipError_t occ_t(int coef_lds, size_t lds, int *per_cu)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, wave_kernel<D, NS, WAVES>, 64 * WAVES, lds);
+    if (coef_lds)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, wave_kernel<D, NS, WAVES, true>, 64 * WAVES, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, wave_kernel<D, NS, WAVES, false>, 64 * WAVES, lds);
 }
 
 }  // namespace
@@ -319,9 +330,9 @@ hipError_t occ_t(size_t lds, int *per_cu)
     default: return hipErrorInvalidValue;                                                      \
     }
 
-hipError_t gc_wave_occupancy(int d, int ns, size_t lds, int *per_cu)
+hipError_t gc_wave_occupancy(int d, int ns, int coef_lds, size_t lds, int *per_cu)
 {
-    GC_WAVE_DISPATCH(occ_t, lds, per_cu)
+    GC_WAVE_DISPATCH(occ_t, coef_lds, lds, per_cu)
 }
 
 hipError_t gc_launch_wave(int d, int ns, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs,

@@ -86,6 +86,25 @@ def compare_tables(extent, phi, copies, o_res, params, check_lambda=True):
             assert (int(c["flags"]) & 7) == (e["flags"] & 7)
 
 
+def check_start_filter(copies, starts, o_res, first_start=0):
+    """The filter's result sits in the start record of each copy's
+    representative (the same bits as the copy) and nowhere else."""
+    gk = {(int(c["key_hi"]), int(c["key_lo"])): c for c in copies}
+    reps = set()
+    for k, e in o_res["table"].items():
+        r = e["rep_start"] - first_start
+        reps.add(r)
+        c = gk[k]
+        assert starts["lambda2"][r] == c["lambda2"]
+        assert starts["lanczos_iters"][r] == c["lanczos_iters"]
+        assert (int(starts["flags"][r]) & 7) == (int(c["flags"]) & 7)
+    others = np.ones(len(starts), bool)
+    others[list(reps)] = False
+    assert np.all(np.isnan(starts["lambda2"][others]))
+    assert np.all(starts["lanczos_iters"][others] == 0)
+    assert np.all((starts["flags"][others] & 7) == 0)
+
+
 # ---------------------------------------------------------------------------
 
 def test_orbit_random_matches_input_generator(ctx):
@@ -104,6 +123,7 @@ def test_small_2d_workload_full_parity(ctx):
     o = O.enumerate_copies(extent, phi, np.arange(1000), oracle_params(p))
     compare_starts(extent, starts, o["records"])
     compare_tables(extent, phi, copies, o, p)
+    check_start_filter(copies, starts, o)
     assert prog["distinct"] == len(o["table"]) and prog["converged"] == 1000
     assert prog["in_region"] == len(o["table"])
     ctx.gc_release(h)
@@ -122,6 +142,7 @@ def test_small_2d_workload_full_parity(ctx):
     ((10, 10, 10), 1.7, 40),       # V = 1000: several site tiles and a ragged tail
     ((6, 6, 6, 6), 1.7, 24),
     ((8, 8, 8), 1.0, 20),
+    ((8, 8, 8, 8), 1.7, 3),        # V = 4096: the filter keeps link weights in global memory
 ])
 def test_parity_shapes(ctx, extent, omega, n):
     phi = GI.orbit_angles(extent, 1, 3)
@@ -130,6 +151,7 @@ def test_parity_shapes(ctx, extent, omega, n):
     o = O.enumerate_copies(extent, phi, np.arange(n), oracle_params(p, 3))
     compare_starts(extent, starts, o["records"])
     compare_tables(extent, phi, copies, o, p)
+    check_start_filter(copies, starts, o)
     ctx.gc_release(h)
 
 
@@ -143,6 +165,7 @@ def test_first_start_offset_and_seed(ctx):
     o = O.enumerate_copies(extent, phi, 123456789 + np.arange(100), op)
     compare_starts(extent, starts, o["records"])
     compare_tables(extent, phi, copies, o, p)
+    check_start_filter(copies, starts, o, first_start=123456789)
     ctx.gc_release(h)
 
 
