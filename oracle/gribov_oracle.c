@@ -449,7 +449,8 @@ static int or_payload(const or_lattice *L, const double *phi, const double *a, i
 
 /* 128-bit key: lane j sums mix64(c_j ^ (k << 8 | (uint8)e_k)) over payload
  * positions k (mod 2^64), then finalises with mix64(sum + length).  A zero
- * high word is mapped to 1 (zero marks an empty table slot). */
+ * word is mapped to 1 (zero marks an empty table slot in the high word and a
+ * slot whose low word is not yet written in the low word). */
 static void or_hash(const int32_t *e, int64_t m, uint64_t *hi, uint64_t *lo)
 {
     const uint64_t c0 = 0x243F6A8885A308D3ULL, c1 = 0x13198A2E03707344ULL;
@@ -462,6 +463,7 @@ static void or_hash(const int32_t *e, int64_t m, uint64_t *hi, uint64_t *lo)
     h0 = oracle_mix64(h0 + (uint64_t)m);
     h1 = oracle_mix64(h1 + (uint64_t)m);
     if (h0 == 0) h0 = 1;
+    if (h1 == 0) h1 = 1;
     *hi = h0;
     *lo = h1;
 }
