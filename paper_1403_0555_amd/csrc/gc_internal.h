@@ -62,7 +62,7 @@ struct GcEntry {
     uint64_t key_hi, key_lo;
     uint64_t hits, first_start;
     uint64_t fmin_bits, fmax_bits;   // IEEE bits of F >= 0 order like the values
-    uint32_t ready, pad;
+    uint32_t pad0, pad1;
     uint64_t rep_start;              // lowest start id with F within tolerance of the minimum F
 };
 
@@ -121,7 +121,7 @@ hipError_t gc_launch_relax_wg(int block, const GcJobDev *jobs, int n_jobs, const
 // Post kernel, one workgroup per start: functional, key, table insertion and
 // the FP-operator filter.  total_dev (device count) overrides total.
 // Workgroup shape for V sites: block threads, sp sites per thread, link
-// weights in registers (wreg) or in a global buffer of d V doubles per
+// weights in registers (wreg) or in a global buffer of (d + 3) V doubles per
 // workgroup (wbuf, wstride doubles apart).
 size_t gc_post_lds_bytes(int d, int V);
 void gc_post_shape(int V, int *block, int *sites_per_thread, int *wreg);

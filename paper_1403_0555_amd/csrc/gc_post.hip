@@ -21,8 +21,12 @@ namespace {
 using namespace gc;
 
 // Insert a key (one lane).  A new key is claimed by CAS on its high word; the
-// claimer then publishes the low word.  Returns whether this start is the
-// lowest start id seen for the key so far.
+// claimer then writes the low word, which is never zero, so zero means "not
+// written yet" to a start that finds the high word.  Only relaxed atomics are
+// used: an agent-scope acquire or release would write back or invalidate the
+// whole L2 of the XCD.  Nothing else is published through the entry before
+// the kernel ends (hits, ids and F bounds are atomics read by later kernels).
+// Returns whether this start is the lowest start id seen for the key so far.
 __device__ void table_insert(const GcJobDev &J, uint64_t key_hi, uint64_t key_lo, uint64_t sid, double F,
                              bool &claimed, bool &is_min, bool &failed)
 {
@@ -39,19 +43,18 @@ __device__ void table_insert(const GcJobDev &J, uint64_t key_hi, uint64_t key_lo
         bool match = false;
         if (old == 0ULL) {
             __hip_atomic_store(&e->key_lo, key_lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&e->ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             claimed = true;
             match = true;
         } else if (old == key_hi) {
             // the claimer writes key_lo right after its CAS; bounded wait
-            uint32_t rdy = 0;
+            uint64_t lo = 0;
             for (int spin = 0; spin < (1 << 22); ++spin) {
-                rdy = __hip_atomic_load(&e->ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                if (rdy) break;
+                lo = __hip_atomic_load(&e->key_lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (lo != 0) break;
                 __builtin_amdgcn_s_sleep(2);
             }
-            if (!rdy) return;
-            match = (__hip_atomic_load(&e->key_lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == key_lo);
+            if (lo == 0) return;
+            match = (lo == key_lo);
         }
         if (match) {
             atomicAdd((unsigned long long *)&e->hits, 1ULL);
@@ -136,25 +139,63 @@ __device__ __forceinline__ int wg_min_int(int v, int *red)
     return v;
 }
 
-// Number of eigenvalues of the k x k tridiagonal below x: the negative pivots
-// of the LDL^T factorisation of T - x (Sturm count), full-precision division.
-__device__ __forceinline__ int sturm_count(const double *alpha, const double *beta2, int k, double x)
+typedef __attribute__((address_space(3))) const double lds_cdouble;
+
+// Number of eigenvalues of the k x k tridiagonal below x: the sign changes
+// of the Sturm sequence p_0 = 1, p_j = det(T_j - x) = (alpha_j - x) p_{j-1}
+// - beta_{j-1}^2 p_{j-2}.  An exact zero is replaced by the smallest normal
+// number of the sign opposite to its predecessor (the usual convention for
+// a vanishing term; the next term then takes that sign too).  Division- and
+// branch-free: one dependent FMA and a select per step, sign changes counted
+// from the sign bits.  The diagonal and off-diagonal are fetched from LDS
+// eight rows ahead of the recurrence, and the pair (p_{j-1}, p_j) is rescaled
+// by a power of two after every eight rows, which keeps it in range and
+// leaves every sign unchanged.
+__device__ __forceinline__ double sturm_nonzero(double p, double prev)
 {
-    int cnt = 0;
-    double q = alpha[0] - x;
-    if (q < 0) ++cnt;
-    for (int j = 1; j < k; ++j) {
-        const double qq = (q == 0.0) ? 1e-300 : q;
-        q = (alpha[j] - x) - beta2[j - 1] / qq;
-        if (q < 0) ++cnt;
+    return (p == 0.0) ? -copysign(0x1.0p-1022, prev) : p;
+}
+
+__device__ __forceinline__ int sign_change(double a, double b)
+{
+    return (int)(((uint64_t)__double_as_longlong(a) ^ (uint64_t)__double_as_longlong(b)) >> 63);
+}
+
+__device__ __forceinline__ void sturm_step(double a, double b2, double x, double &p0, double &p1, int &cnt)
+{
+    const double p2 = sturm_nonzero(fma(a - x, p1, -b2 * p0), p1);
+    cnt += sign_change(p2, p1);
+    p0 = p1;
+    p1 = p2;
+}
+
+__device__ int sturm_count(lds_cdouble *alpha, lds_cdouble *beta2, int k, double x)
+{
+    double p0 = 1.0, p1 = sturm_nonzero(alpha[0] - x, 1.0);
+    int cnt = sign_change(p1, 1.0);
+    int j = 1;
+    for (; j + 8 <= k; j += 8) {
+        double a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a[u] = alpha[j + u];
+            b[u] = beta2[j + u - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sturm_step(a[u], b[u], x, p0, p1, cnt);
+        int e;
+        (void)frexp(p1, &e);
+        p0 = ldexp(p0, -e);
+        p1 = ldexp(p1, -e);
     }
+    for (; j < k; ++j) sturm_step(alpha[j], beta2[j - 1], x, p0, p1, cnt);
     return cnt;
 }
 
 // Smallest eigenvalue of the tridiagonal by (B+1)-section inside [lo, hi]
 // (count(lo) = 0, count(hi) >= 1).
 template <int B>
-__device__ double tridiag_min_eig(const double *alpha, const double *beta2, int k, double lo, double hi, int *ired)
+__device__ double tridiag_min_eig(lds_cdouble *alpha, lds_cdouble *beta2, int k, double lo, double hi, int *ired)
 {
     for (int round = 0; round < 24; ++round) {
         if (hi - lo <= 1e-15 * fmax(1.0, fabs(hi))) break;
@@ -169,22 +210,15 @@ __device__ double tridiag_min_eig(const double *alpha, const double *beta2, int 
     return 0.5 * (lo + hi);
 }
 
-// Smallest Ritz value of the k x k tridiagonal.  By interlacing it never
-// increases as k grows, so the previous value bounds it above; a window
-// below it is tried first, with the Gershgorin interval as the fallback.
+// Smallest Ritz value of the k x k tridiagonal, inside the Gershgorin
+// interval [glo, ghi].  By interlacing it never increases as k grows, so the
+// previous value bounds it above; a window below it is tried first.
 template <int B>
-__device__ double ritz_min(const double *alpha, const double *beta2, const double *babs, int k, double prev,
+__device__ double ritz_min(lds_cdouble *alpha, lds_cdouble *beta2, int k, double glo, double ghi, double prev,
                            double prev_step, int *ired)
 {
-    double lo = INFINITY, hi = -INFINITY;
-    for (int j = 0; j < k; ++j) {
-        const double bl = j > 0 ? babs[j - 1] : 0.0;
-        const double br = j + 1 < k ? babs[j] : 0.0;
-        lo = fmin(lo, alpha[j] - bl - br);
-        hi = fmax(hi, alpha[j] + bl + br);
-    }
-    lo -= 1e-12 * (1.0 + fabs(lo));
-    hi += 1e-12 * (1.0 + fabs(hi));
+    double lo = glo - 1e-12 * (1.0 + fabs(glo));
+    double hi = ghi + 1e-12 * (1.0 + fabs(ghi));
     if (prev < hi) {
         const double top = prev + 1e-12 * (1.0 + fabs(prev));
         const double bot = top - fmax(4.0 * prev_step, 1e-9 * (1.0 + fabs(prev)));
@@ -203,11 +237,26 @@ __device__ uint32_t region_flags(double lam2, double tol)
     return GC_F_SINGULAR;
 }
 
+// Values at a thread's own sites i = tid + B k: registers, or a strided
+// view of the workgroup's global slice.
+template <bool REG, int SP> struct OwnVec;
+template <int SP> struct OwnVec<true, SP> {
+    double v[SP];
+    __device__ __forceinline__ double get(int k) const { return v[k]; }
+    __device__ __forceinline__ void set(int k, double x) { v[k] = x; }
+};
+template <int SP> struct OwnVec<false, SP> {
+    glb_ptr<double> p;
+    int stride;
+    __device__ __forceinline__ double get(int k) const { return p[k * stride]; }
+    __device__ __forceinline__ void set(int k, double x) { p[k * stride] = x; }
+};
+
 // One workgroup of B threads per start; thread t owns sites i = t + B k,
-// k < SP.  With WREG the link weights of the own sites stay in registers
-// (SP <= 4); otherwise the forward link weights of the start go to the
-// workgroup's slice of wbuf (dV doubles) and are re-read from there.  Entries
-// of q_prev and of the residual of the own sites stay in registers.
+// k < SP.  With WREG the link weights, neighbour indices and the entries of
+// q_prev, the residual and M q of the own sites stay in registers (SP <= 4);
+// otherwise they live in the workgroup's slice of wbuf ((d + 3) V doubles:
+// forward link weights, then q_prev, residual and M q).
 // LDS: the state g (16V bytes, later the Lanczos vector q), then the link
 // angles as floats (4dV bytes) during the key, reused for the tridiagonal.
 // The angle of a link is atan2 in single precision: the branch cut at +-pi is
@@ -221,6 +270,7 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                                                  double *wbuf_all, uint64_t wstride)
 {
     constexpr int NW = WREG ? SP : 1;   // register weights per thread (dummy when !WREG)
+    constexpr int NN = WREG ? SP : 1;   // register neighbour words per thread
     glb_ptr<double> wbuf = as_global(wbuf_all + (WREG ? 0 : (uint64_t)blockIdx.x * wstride));
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[3 * (B / 64)];
@@ -254,10 +304,9 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
         lds_ptr<dbl2> g = as_lds(reinterpret_cast<dbl2 *>(smem));
         // the link angles (key phase) and the tridiagonal (Lanczos) share LDS
         lds_ptr<float> a32 = as_lds(reinterpret_cast<float *>(smem + 16 * (size_t)V));
-        double *alpha = reinterpret_cast<double *>(smem + 16 * (size_t)V);
+        lds_ptr<double> alpha = as_lds(reinterpret_cast<double *>(smem + 16 * (size_t)V));
         const int lmax = min(min(J.lanczos_max, GC_LMAX), V);
-        double *beta2 = alpha + lmax;
-        double *babs = beta2 + lmax;
+        lds_ptr<double> beta2 = alpha + lmax;
         glb_ptr<const dbl2> src = as_global(reinterpret_cast<const dbl2 *>(J.states + local * (uint64_t)V));
         for (int i = tid; i < V; i += B) g[i] = src[i];
         __syncthreads();
@@ -266,7 +315,7 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
         // FP weights w = Re u of every link touching the site
         glb_ptr<const dbl2> U = as_global(reinterpret_cast<const dbl2 *>(O.U64));
         double wf[NW][GC_MAXD], wb[NW][GC_MAXD];
-        uint32_t nfb[SP][GC_MAXD];   // forward | backward << 16
+        uint32_t nfb[NN][GC_MAXD];   // forward | backward << 16
         double facc = 0.0;
 #pragma unroll
         for (int k = 0; k < SP; ++k) {
@@ -277,10 +326,10 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                     wf[k % NW][mu] = 0.0;
                     wb[k % NW][mu] = 0.0;
                 }
-                nfb[k][mu] = 0;
+                if (WREG) nfb[k % NN][mu] = 0;
                 if (i < V && mu < d) {
                     const int f = O.nbr[mu * V + i], b = O.nbr[(d + mu) * V + i];
-                    nfb[k][mu] = (uint32_t)f | ((uint32_t)b << 16);
+                    if (WREG) nfb[k % NN][mu] = (uint32_t)f | ((uint32_t)b << 16);
                     const dbl2 gi = g[i], gf = g[f], gb = g[b];
                     const dbl2 u = U[mu * V + i];
                     const double tr = u.x * gf.x - u.y * gf.y, ti = u.x * gf.y + u.y * gf.x;
@@ -293,7 +342,6 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                     const double sr = v.x * gi.x - v.y * gi.y, si = v.x * gi.y + v.y * gi.x;
                     if (WREG) wb[k % NW][mu] = gb.x * sr + gb.y * si;
                 }
-                __builtin_amdgcn_sched_barrier(0);
             }
         }
         double tmp1[1] = {facc};
@@ -340,6 +388,7 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
             key_hi = mix64(h0 + (uint64_t)O.n_elems);
             key_lo = mix64(h1 + (uint64_t)O.n_elems);
             if (key_hi == 0) key_hi = 1;
+            if (key_lo == 0) key_lo = 1;
             if (!ok) flags |= GC_F_KEY_OVERFLOW;
             if (tid == 0) {
                 bool claimed, is_min, failed;
@@ -360,16 +409,22 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
             // over the state, q_prev and the residual in registers
             const double sigma = 4.0 * d + 1.0;
             lds_ptr<double> vq = as_lds(reinterpret_cast<double *>(smem));
-            double qp[SP], r[SP];
+            OwnVec<WREG, SP> qp, r, mq;
+            if constexpr (!WREG) {
+                qp.p = wbuf + (size_t)d * V + tid;
+                r.p = qp.p + V;
+                mq.p = r.p + V;
+                qp.stride = r.stride = mq.stride = B;
+            }
             double sums[2] = {0.0, 0.0};
 #pragma unroll
             for (int k = 0; k < SP; ++k) {
                 const int i = tid + B * k;
-                qp[k] = 0.0;
-                r[k] = 0.0;
                 if (i < V) {
-                    r[k] = (double)(mix64((uint64_t)i + 0x5851F42D4C957F2DULL) >> 11) * 0x1.0p-53 - 0.5;
-                    sums[0] += r[k];
+                    const double x = (double)(mix64((uint64_t)i + 0x5851F42D4C957F2DULL) >> 11) * 0x1.0p-53 - 0.5;
+                    qp.set(k, 0.0);
+                    r.set(k, x);
+                    sums[0] += x;
                 }
             }
             wg_sum_n<B, 1>(*reinterpret_cast<double(*)[1]>(&sums[0]), red);
@@ -379,8 +434,9 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
             for (int k = 0; k < SP; ++k) {
                 const int i = tid + B * k;
                 if (i < V) {
-                    r[k] -= mean;
-                    nn[0] += r[k] * r[k];
+                    const double x = r.get(k) - mean;
+                    r.set(k, x);
+                    nn[0] += x * x;
                 }
             }
             wg_sum_n<B, 1>(nn, red);
@@ -389,35 +445,47 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
 #pragma unroll
             for (int k = 0; k < SP; ++k) {
                 const int i = tid + B * k;
-                if (i < V) vq[i] = r[k] * inv;
+                if (i < V) vq[i] = r.get(k) * inv;
             }
             __syncthreads();
             double beta_prev = 0.0, theta = INFINITY, theta_old = INFINITY, theta_step = 1.0;
+            double rows_lo = INFINITY, rows_hi = -INFINITY;   // Gershgorin bounds of the complete rows
             int it = 0;
             bool conv = false;
             for (it = 0; it < lmax; ++it) {
+                // per-iteration copy of the thread index: the site addresses are
+                // recomputed each iteration instead of being held in registers
+                const int ti = tid + opaque_zero();
                 // (M q)_i for the own sites, then q.Mq, sum q, q.q_prev at once
-                double mq[SP];
                 double s3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
                 for (int k = 0; k < SP; ++k) {
-                    const int i = tid + B * k;
-                    mq[k] = 0.0;
+                    const int i = ti + B * k;
                     if (i < V) {
                         const double qi = vq[i];
                         double m = 0.0;
 #pragma unroll
                         for (int mu = 0; mu < GC_MAXD; ++mu)
                             if (mu < d) {
-                                const uint32_t f = nfb[k][mu] & 0xFFFFu, b = nfb[k][mu] >> 16;
-                                const double w1 = WREG ? wf[k % NW][mu] : wbuf[mu * V + i];
-                                const double w2 = WREG ? wb[k % NW][mu] : wbuf[mu * V + b];
+                                uint32_t f, b;
+                                double w1, w2;
+                                if constexpr (WREG) {
+                                    f = nfb[k % NN][mu] & 0xFFFFu;
+                                    b = nfb[k % NN][mu] >> 16;
+                                    w1 = wf[k % NW][mu];
+                                    w2 = wb[k % NW][mu];
+                                } else {
+                                    f = O.nbr[mu * V + i];
+                                    b = O.nbr[(d + mu) * V + i];
+                                    w1 = wbuf[mu * V + i];
+                                    w2 = wbuf[mu * V + b];
+                                }
                                 m += w1 * (qi - vq[f]) + w2 * (qi - vq[b]);
                             }
-                        mq[k] = m;
+                        mq.set(k, m);
                         s3[0] += qi * m;
                         s3[1] += qi;
-                        s3[2] += qi * qp[k];
+                        s3[2] += qi * qp.get(k);
                     }
                     // one site at a time: keeps the scheduler from holding
                     // every neighbour of every own site in registers
@@ -429,11 +497,12 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                 double rr[1] = {0.0};
 #pragma unroll
                 for (int k = 0; k < SP; ++k) {
-                    const int i = tid + B * k;
+                    const int i = ti + B * k;
                     if (i < V) {
                         const double qi = vq[i];
-                        r[k] = mq[k] + shift - beta_prev * qp[k] - a_j * qi;
-                        rr[0] += r[k] * r[k];
+                        const double x = mq.get(k) + shift - beta_prev * qp.get(k) - a_j * qi;
+                        r.set(k, x);
+                        rr[0] += x * x;
                     }
                 }
                 wg_sum_n<B, 1>(rr, red);
@@ -441,12 +510,12 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                 if (tid == 0) {
                     alpha[it] = a_j;
                     beta2[it] = b_j * b_j;
-                    babs[it] = b_j;
                 }
                 __syncthreads();
                 const bool breakdown = b_j <= 1e-13 * sigma;
                 if (((it + 1) % 8 == 0) || breakdown || it + 1 == lmax) {
-                    theta = ritz_min<B>(alpha, beta2, babs, it + 1, theta_old, theta_step, ired);
+                    theta = ritz_min<B>(alpha, beta2, it + 1, fmin(rows_lo, a_j - beta_prev),
+                                        fmax(rows_hi, a_j + beta_prev), theta_old, theta_step, ired);
                     if (breakdown || fabs(theta - theta_old) <= 1e-12 * fmax(1.0, fabs(theta))) {
                         conv = true;
                         ++it;
@@ -455,13 +524,16 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                     if (theta_old < INFINITY) theta_step = theta_old - theta;
                     theta_old = theta;
                 }
+                // row it of T now has both neighbours: into the Gershgorin bounds
+                rows_lo = fmin(rows_lo, a_j - beta_prev - b_j);
+                rows_hi = fmax(rows_hi, a_j + beta_prev + b_j);
                 const double ib = 1.0 / b_j;
 #pragma unroll
                 for (int k = 0; k < SP; ++k) {
-                    const int i = tid + B * k;
+                    const int i = ti + B * k;
                     if (i < V) {
-                        qp[k] = vq[i];
-                        vq[i] = r[k] * ib;
+                        qp.set(k, vq[i]);
+                        vq[i] = r.get(k) * ib;
                     }
                 }
                 beta_prev = b_j;
@@ -506,8 +578,8 @@ __global__ void reset_kernel(GcJobDev J)
         e.first_start = ~0ULL;
         e.fmin_bits = ~0ULL;
         e.fmax_bits = 0;
-        e.ready = 0;
-        e.pad = 0;
+        e.pad0 = 0;
+        e.pad1 = 0;
         e.rep_start = ~0ULL;
         J.table[t] = e;
     }
@@ -653,7 +725,7 @@ int grid_for(uint64_t work)
 size_t gc_post_lds_bytes(int d, int V)
 {
     const size_t lmax = V < GC_LMAX ? V : GC_LMAX;
-    const size_t angles = 4 * (size_t)d * V, tri = 3 * sizeof(double) * lmax;
+    const size_t angles = 4 * (size_t)d * V, tri = 2 * sizeof(double) * lmax;
     return 16 * (size_t)V + (angles > tri ? angles : tri);
 }
 
@@ -663,7 +735,7 @@ void gc_post_shape(int V, int *block, int *sp, int *wreg)
     // largest lattices keep them in global memory
     static const int shapes[][4] = {{64, 64, 1, 1},     {128, 64, 2, 1},    {256, 64, 4, 1},
                                     {512, 128, 4, 1},   {1024, 256, 4, 1},  {1536, 384, 4, 1},
-                                    {2048, 512, 4, 1},  {4096, 512, 8, 0}};
+                                    {4096, 512, 8, 0}};
     for (const auto &t : shapes)
         if (V <= t[0]) {
             *block = t[1];
@@ -683,7 +755,6 @@ void gc_post_shape(int V, int *block, int *sp, int *wreg)
     if (block == 128 && sp == 4 && wreg) return FN<128, 4, true>(__VA_ARGS__);      \
     if (block == 256 && sp == 4 && wreg) return FN<256, 4, true>(__VA_ARGS__);      \
     if (block == 384 && sp == 4 && wreg) return FN<384, 4, true>(__VA_ARGS__);      \
-    if (block == 512 && sp == 4 && wreg) return FN<512, 4, true>(__VA_ARGS__);      \
     if (block == 512 && sp == 8 && !wreg) return FN<512, 8, false>(__VA_ARGS__);    \
     return hipErrorInvalidValue;
 

@@ -558,7 +558,7 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         pg.o_prefix = place(sizeof(uint64_t) * (pg.jobs.size() + 1));
         pg.o_next = place(sizeof(unsigned long long));
         if (!pg.wreg) {
-            pg.wstride = ((uint64_t)pd * pV + 31) & ~(uint64_t)31;
+            pg.wstride = ((uint64_t)(pd + 3) * pV + 31) & ~(uint64_t)31;
             pg.o_wbuf = place(sizeof(double) * pg.wstride * pg.grid);
         }
     }
