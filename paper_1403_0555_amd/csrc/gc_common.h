@@ -141,6 +141,7 @@ template <typename T> __device__ __forceinline__ lds_ptr<T> as_lds(T *p) { retur
 // through any address space.
 typedef float flt2 __attribute__((ext_vector_type(2)));
 typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <typename R> struct cx;
 template <> struct cx<float> { using T = flt2; };

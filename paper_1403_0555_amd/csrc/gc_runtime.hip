@@ -13,6 +13,7 @@
 #include "gc_wave.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -187,6 +188,7 @@ struct gc_ctx {
     int device = 0;
     int n_cu = 0;
     size_t lds_max = 0;
+    int creg_override = -1;   // GC_WAVE_CREG: register-held coefficient colours (tuning)
     uint64_t budget = 0, used = 0;
     std::vector<hipStream_t> streams;
     std::vector<int> stream_load;
@@ -413,7 +415,7 @@ struct Group {
     bool wave = false;
     int d = 0;
     std::vector<int> jobs;           // indices into Job::orbits
-    int block = 64, grid = 1, ns = 1, coef_lds = 0;
+    int block = 64, grid = 1, ns = 1, coef_lds = 0, creg = 0;
     size_t lds = 0;
     size_t o_jobs = 0, o_worbs = 0, o_next = 0, o_prefix = 0, o_bounce = 0;
     uint64_t total = 0;
@@ -468,7 +470,7 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         total += n;
         // two colours: one wavefront per start, GC_WAVES states per workgroup
         // in LDS; lattices too large for that take the workgroup kernel
-        const bool wave = (o->K == 2) && (size_t)GC_WAVES * 16 * o->V <= ctx->lds_max;
+        const bool wave = (o->K == 2) && (size_t)(GC_WAVES + 1) * 16 * o->V <= ctx->lds_max;
         // wave groups by dimension; workgroup-kernel groups by block size, so
         // that an orbit's reductions run in the same order alone and batched
         const int gd = wave ? o->d : -block_for(o->V);
@@ -497,11 +499,13 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
                 const Orbit *o = job->orbits[j];
                 coef_bytes = std::max(coef_bytes, (size_t)2 * o->d * o->V * (mixed ? 24 : 16));
             }
-            const size_t states = (size_t)GC_WAVES * 16 * gV;
+            const size_t states = (size_t)GC_WAVES * 16 * gV + (g.ns <= 2 ? 16 * (size_t)gV : 0);   // + neighbour table
             g.coef_lds = (coef_bytes + states <= 64 * 1024) ? 1 : 0;
             g.lds = states + (g.coef_lds ? coef_bytes : 0);
             if (g.lds > ctx->lds_max) return GC_EUNSUPPORTED;
-            hipError_t e = gc_wave_occupancy(g.d, g.ns, g.coef_lds, g.lds, &per_cu);
+            g.creg = 0;
+            if (ctx->creg_override >= 0) g.creg = std::min(ctx->creg_override, gc_wave_creg_max(g.d, g.ns));
+            hipError_t e = gc_wave_occupancy(g.d, g.ns, g.coef_lds | (g.creg << 1), g.lds, &per_cu);
             if (e != hipSuccess) return fail(ctx, e, "occupancy");
         } else {
             g.block = block_for(gV);
@@ -707,7 +711,8 @@ gc_status start_job(gc_ctx *ctx, Job *job)
         for (const Group &g : L.groups) {
             if (g.wave)
                 e = gc_launch_wave(g.d, g.ns, (const GcJobDev *)(base + g.o_jobs), (const GcWaveOrbit *)(base + g.o_worbs),
-                                   (int)g.jobs.size(), (unsigned long long *)(base + g.o_next), g.coef_lds,
+                                   (int)g.jobs.size(), (unsigned long long *)(base + g.o_next),
+                                   g.coef_lds | (g.creg << 1),
                                    (float2 *)(base + g.o_bounce), g.grid, g.lds, qs);
             else
                 e = gc_launch_relax_wg(g.block, (const GcJobDev *)(base + g.o_jobs), (int)g.jobs.size(),
@@ -1086,6 +1091,7 @@ gc_status gc_create(const gc_ctx_params *params, gc_ctx **out)
     if (hipGetDeviceProperties(&prop, P.device) != hipSuccess) return GC_EDEVICE;
     ctx->n_cu = prop.multiProcessorCount;
     ctx->lds_max = prop.sharedMemPerBlock;
+    if (const char *v = getenv("GC_WAVE_CREG")) ctx->creg_override = atoi(v);
     ctx->budget = P.hbm_budget_bytes ? P.hbm_budget_bytes : (64ull << 30);
     const int ns = P.n_streams > 0 ? std::min(P.n_streams, 16) : 4;
     for (int k = 0; k < ns; ++k) {

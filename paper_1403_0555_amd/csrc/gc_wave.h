@@ -17,7 +17,11 @@ struct GcWaveOrbit {
 // private scratch for the single-to-double promotion.
 constexpr int GC_WAVES = 4;
 
-hipError_t gc_wave_occupancy(int d, int ns, int coef_lds, size_t lds, int *per_cu);
+// variant = coef_lds | creg << 1: coefficient table staged in LDS (else
+// read from global memory) and the number of colours (0..2) whose
+// coefficients a lane keeps in registers (gc_wave_creg_max(d, ns) at most).
+hipError_t gc_wave_occupancy(int d, int ns, int variant, size_t lds, int *per_cu);
 hipError_t gc_launch_wave(int d, int ns, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs,
-                          unsigned long long *job_next, int coef_lds, float2 *bounce, int grid, size_t lds,
+                          unsigned long long *job_next, int variant, float2 *bounce, int grid, size_t lds,
                           hipStream_t s);
+int gc_wave_creg_max(int d, int ns);

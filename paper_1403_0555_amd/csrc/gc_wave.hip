@@ -29,31 +29,54 @@ namespace {
 
 using namespace gc;
 
-// Lattice strides: s_mu and the wrap N_mu s_mu, uniform per orbit.
+// Neighbour half indices of a slot, forward mu = 0..d-1 then backward:
+// from its packed table entry (eight 16-bit half indices) ...
+struct NbWords {
+    u32x4 w;
+    __device__ __forceinline__ uint32_t operator()(int k) const
+    {
+        const uint32_t word = (k >> 1) == 0 ? w.x : (k >> 1) == 1 ? w.y : (k >> 1) == 2 ? w.z : w.w;
+        return (k & 1) ? (word >> 16) : (word & 0xFFFFu);
+    }
+};
+
+// ... or from its descriptor (site index | forward-wrap bits << 12 |
+// backward-wrap bits << 16) and the lattice strides s_mu, wraps N_mu s_mu.
 template <int D> struct Strides {
     int s[D], w[D];
 };
-
-// S for slot (c, h) of site i: sum_k coef[c][k][h] g_{n_k}, neighbours from
-// the slot descriptor (site index and the boundary-wrap bits of each
-// direction), forward mu = 0..d-1 then backward, as in the coefficients.
-template <int D, typename R, typename CP, typename SP>
-__device__ __forceinline__ typename cx<R>::T staple(CP coef, SP other, uint32_t dsc, const Strides<D> &L, int c,
-                                                    int h, int half)
-{
-    using C = typename cx<R>::T;
-    const int i = (int)(dsc & 0xFFFu);
-    R ax = 0, ay = 0;
-#pragma unroll
-    for (int k = 0; k < 2 * D; ++k) {
+template <int D> struct NbDesc {
+    uint32_t dsc;
+    const Strides<D> &L;
+    __device__ __forceinline__ uint32_t operator()(int k) const
+    {
+        const int i = (int)(dsc & 0xFFFu);
         const int mu = k < D ? k : k - D;
         int j;
         if (k < D) j = i + L.s[mu] - (((dsc >> (12 + mu)) & 1u) ? L.w[mu] : 0);
         else j = i - L.s[mu] + (((dsc >> (16 + mu)) & 1u) ? L.w[mu] : 0);
-        const C u = coef[(c * 2 * D + k) * half + h];
-        const C g = other[j >> 1];
-        ax += u.x * g.x - u.y * g.y;
-        ay += u.x * g.y + u.y * g.x;
+        return (uint32_t)(j >> 1);
+    }
+};
+
+// S = sum_k coef_k g_{n_k}, forward mu = 0..d-1 then backward, as in the
+// coefficient table, each complex product accumulated by four FMAs.  The
+// coefficients come from cf (registers, CF_REG) or from the table at
+// coef[(c 2d + k) half + h].
+template <int D, typename R, bool CF_REG, typename CP, typename SP, typename NB>
+__device__ __forceinline__ typename cx<R>::T staple(const typename cx<R>::T (&cf)[2 * D], CP coef, SP other,
+                                                    const NB &nb, int c, int h, int half)
+{
+    using C = typename cx<R>::T;
+    R ax = 0, ay = 0;
+#pragma unroll
+    for (int k = 0; k < 2 * D; ++k) {
+        const C u = CF_REG ? cf[k] : coef[(c * 2 * D + k) * half + h];
+        const C g = other[nb(k)];
+        ax = fma(u.x, g.x, ax);
+        ax = fma(-u.y, g.y, ax);
+        ay = fma(u.x, g.y, ay);
+        ay = fma(u.y, g.x, ay);
     }
     C s;
     s.x = ax;
@@ -64,31 +87,24 @@ __device__ __forceinline__ typename cx<R>::T staple(CP coef, SP other, uint32_t 
 // Sweeps of one precision on the wave's state st[2][half].  Returns status.
 // Lane l owns slots h = l + 64k, k < NS, of each colour; slots beyond the
 // half volume are computed on a clamped index and discarded, so the passes
-// have no divergent branches.
-template <int D, typename R, int NS, bool RELAX, typename CP>
-__device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<typename cx<R>::T> st,
-                            double eps, uint64_t &sweeps, double &D_out)
+// have no divergent branches.  For NS <= 2 the packed neighbour entries of
+// the lane's slots are held in registers (from the LDS copy nbt of the
+// table); otherwise they are recomputed from the slot descriptors.  CREG
+// colours (0, 1 or 2, starting with colour 0) keep the coefficients of the
+// lane's slots in registers for the whole phase.
+template <int D, typename R, int NS, bool RELAX, int CREG, typename CP>
+__device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<const u32x4> nbt,
+                            lds_ptr<typename cx<R>::T> st, double eps, uint64_t &sweeps, double &D_out)
 {
-    using C = typename cx<R>::T;
-    const int lane = threadIdx.x & 63;
     const int half = WO.half;
+    using C = typename cx<R>::T;
+    constexpr bool NB_REG = NS <= 2;
+    const int lane = threadIdx.x & 63;
     lds_ptr<C> st0 = st;
     lds_ptr<C> st1 = st + half;
     const R omega = (R)J.omega;
     const uint64_t check = J.check_every > 0 ? (uint64_t)J.check_every : 1;
     const bool maxabs = J.stop_norm != 0;
-    Strides<D> L;
-    {
-        int str = 1;
-#pragma unroll
-        for (int mu = 0; mu < D; ++mu) {
-            L.s[mu] = str;
-            L.w[mu] = str * J.orb.ext[mu];
-            str *= J.orb.ext[mu];
-        }
-    }
-    // slot descriptors stay in registers for the whole solve
-    uint32_t d0[NS], d1[NS];
     int hs[NS];
     bool valid[NS];
 #pragma unroll
@@ -96,8 +112,39 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
         const int h = lane + 64 * k;
         valid[k] = h < half;
         hs[k] = valid[k] ? h : half - 1;
-        d0[k] = WO.desc[hs[k]];
-        d1[k] = WO.desc[half + hs[k]];
+    }
+    u32x4 nr[NB_REG ? 2 : 1][NB_REG ? NS : 1];
+    uint32_t d0[NB_REG ? 1 : NS], d1[NB_REG ? 1 : NS];
+    Strides<D> L;
+    if constexpr (NB_REG) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            nr[0][k] = nbt[hs[k]];
+            nr[1][k] = nbt[half + hs[k]];
+        }
+    } else {
+        int str = 1;
+#pragma unroll
+        for (int mu = 0; mu < D; ++mu) {
+            L.s[mu] = str;
+            L.w[mu] = str * J.orb.ext[mu];
+            str *= J.orb.ext[mu];
+        }
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            d0[k] = WO.desc[hs[k]];
+            d1[k] = WO.desc[half + hs[k]];
+        }
+    }
+    constexpr int NCR = CREG > 0 ? CREG : 1;
+    C cr[NCR][NS][2 * D];
+    if constexpr (CREG > 0) {
+#pragma unroll
+        for (int c = 0; c < CREG; ++c)
+#pragma unroll
+            for (int k = 0; k < NS; ++k)
+#pragma unroll
+                for (int q = 0; q < 2 * D; ++q) cr[c][k][q] = coef[(c * 2 * D + q) * half + hs[k]];
     }
 
     uint64_t t = 0;
@@ -109,13 +156,16 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
         // sweep t; at a check point they complete the norm of sweep t
         const bool pending = (t > 0) && (t % check == 0 || t == J.max_sweeps);
         const bool last = (t == J.max_sweeps);
+        // an opaque offset keeps per-slot index arithmetic inside the sweep
         const int z = opaque_zero();
         C gnew[NS];
         double acc0 = 0.0;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             const int h = hs[k] + z;
-            const C s = staple<D, R>(coef, st1, d0[k] + (uint32_t)z, L, 0, h, half);
+            C s;
+            if constexpr (NB_REG) s = staple<D, R, (CREG >= 1)>(cr[0][k], coef, st1, NbWords{nr[0][k]}, 0, h, half);
+            else s = staple<D, R, (CREG >= 1)>(cr[0][k], coef, st1, NbDesc<D>{d0[k] + (uint32_t)z, L}, 0, h, half);
             const C g0 = st0[h];
             const double dv = (double)(g0.x * s.y - g0.y * s.x);
             const double a = maxabs ? fmax(acc0, fabs(dv)) : acc0 + dv * dv;
@@ -140,7 +190,12 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             const int h = hs[k] + z;
-            const C s = staple<D, R>(coef, st0, d1[k] + (uint32_t)z, L, 1, h, half);
+            C s;
+            if constexpr (NB_REG)
+                s = staple<D, R, (CREG >= 2)>(cr[NCR - 1][k], coef, st0, NbWords{nr[NB_REG ? 1 : 0][k]}, 1, h, half);
+            else
+                s = staple<D, R, (CREG >= 2)>(cr[NCR - 1][k], coef, st0, NbDesc<D>{d1[k] + (uint32_t)z, L}, 1, h,
+                                              half);
             const C g = local_update<RELAX, R>(st1[h], s, omega);
             if (valid[k]) st1[hs[k]] = g;
             const double dv = (double)(g.x * s.y - g.y * s.x);
@@ -154,17 +209,18 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
     return status;
 }
 
-template <int D, typename R, int NS, typename CP>
-__device__ int relax_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<typename cx<R>::T> st,
-                          double eps, uint64_t &sweeps, double &D_out)
+template <int D, typename R, int NS, int CREG, typename CP>
+__device__ int relax_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<const u32x4> nbt,
+                          lds_ptr<typename cx<R>::T> st, double eps, uint64_t &sweeps, double &D_out)
 {
-    if ((R)J.omega == (R)1) return relax_wave_t<D, R, NS, true>(J, WO, coef, st, eps, sweeps, D_out);
-    return relax_wave_t<D, R, NS, false>(J, WO, coef, st, eps, sweeps, D_out);
+    if ((R)J.omega == (R)1) return relax_wave_t<D, R, NS, true, CREG>(J, WO, coef, nbt, st, eps, sweeps, D_out);
+    return relax_wave_t<D, R, NS, false, CREG>(J, WO, coef, nbt, st, eps, sweeps, D_out);
 }
 
-template <int D, int NS, typename CP64, typename CP32>
+template <int D, int NS, int CREG, typename CP64, typename CP32>
 __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 coef64, CP32 coef32,
-                                 lds_ptr<dbl2> st64, lds_ptr<flt2> st32, glb_ptr<flt2> bounce, uint64_t local)
+                                 lds_ptr<const u32x4> nbt, lds_ptr<dbl2> st64, lds_ptr<flt2> st32,
+                                 glb_ptr<flt2> bounce, uint64_t local)
 {
     const int lane = threadIdx.x & 63;
     const GcOrbitDev &O = J.orb;
@@ -194,7 +250,7 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 
     int status;
     bool in64 = J.precision != 1;
     if (J.precision == 1) {
-        status = relax_wave<D, float, NS>(J, WO, coef32, st32, J.eps32, sw32, Dn);
+        status = relax_wave<D, float, NS, CREG>(J, WO, coef32, nbt, st32, J.eps32, sw32, Dn);
         if (status == GC_ST_CONVERGED) {
             // promotion g64 = normalise((double) g32): both states share the
             // wave's LDS region, so each lane bounces its entries through
@@ -209,10 +265,10 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 
                 st64[p] = dbl2{xr * r, xi * r};
             }
             wave_sync();
-            status = relax_wave<D, double, NS>(J, WO, coef64, st64, J.eps64, sw64, Dn);
+            status = relax_wave<D, double, NS, CREG>(J, WO, coef64, nbt, st64, J.eps64, sw64, Dn);
         }
     } else {
-        status = relax_wave<D, double, NS>(J, WO, coef64, st64, J.eps64, sw64, Dn);
+        status = relax_wave<D, double, NS, CREG>(J, WO, coef64, nbt, st64, J.eps64, sw64, Dn);
     }
     // final state in natural site order
     glb_ptr<dbl2> out = as_global(reinterpret_cast<dbl2 *>(J.states + local * (uint64_t)V));
@@ -224,10 +280,10 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 
     wave_sync();
 }
 
-// WG = WAVES wavefronts.  LDS: [coef64 | coef32 when COEF_LDS] then per wave
-// a 16V-byte state region (double2[V], or float2[V] in the single-precision
-// phase).
-template <int D, int NS, int WAVES, bool COEF_LDS>
+// WG = WAVES wavefronts.  LDS: [neighbour table 16V when NS <= 2 | coef64 |
+// coef32 when COEF_LDS] then per wave a 16V-byte state region (double2[V],
+// or float2[V] in the single-precision phase).
+template <int D, int NS, int WAVES, bool COEF_LDS, int CREG>
 __global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__restrict__ jobs,
                                                           const GcWaveOrbit *__restrict__ worbs, int n_jobs,
                                                           unsigned long long *job_next, float2 *bounce_all)
@@ -257,14 +313,22 @@ __global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__rest
         const GcWaveOrbit &WO = worbs[jn];
         const int V = J.orb.V;
         const int ncoef = 2 * D * V;      // complex entries per precision
+        // neighbour table (16 bytes per slot, 16V in all, when NS <= 2),
+        // then the coefficients when staged, then the wavefronts' states
+        lds_ptr<u32x4> nbt = as_lds(reinterpret_cast<u32x4 *>(smem));
         size_t off = 0;
+        if constexpr (NS <= 2) {
+            glb_ptr<const u32x4> nbg = as_global(reinterpret_cast<const u32x4 *>(WO.nb));
+            for (int t = threadIdx.x; t < V; t += 64 * WAVES) nbt[t] = nbg[t];
+            off = 16 * (size_t)V;
+        }
         const dbl2 *g64 = reinterpret_cast<const dbl2 *>(WO.coef64);
         const flt2 *g32 = reinterpret_cast<const flt2 *>(WO.coef32);
-        lds_ptr<dbl2> c64 = as_lds(reinterpret_cast<dbl2 *>(smem));
-        lds_ptr<flt2> c32 = as_lds(reinterpret_cast<flt2 *>(smem + 16 * (size_t)ncoef));
+        lds_ptr<dbl2> c64 = as_lds(reinterpret_cast<dbl2 *>(smem + off));
+        lds_ptr<flt2> c32 = as_lds(reinterpret_cast<flt2 *>(smem + off + 16 * (size_t)ncoef));
         if (COEF_LDS) {
             for (int t = threadIdx.x; t < ncoef; t += 64 * WAVES) c64[t] = g64[t];
-            off = 16 * (size_t)ncoef;
+            off += 16 * (size_t)ncoef;
             if (J.precision == 1) {
                 for (int t = threadIdx.x; t < ncoef; t += 64 * WAVES) c32[t] = g32[t];
                 off += 8 * (size_t)ncoef;
@@ -280,35 +344,72 @@ __global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__rest
             if (lane == 0) s = atomicAdd(&job_next[jn], 1ULL);
             s = uniform((uint64_t)s);
             if (s >= J.n_starts) break;
+            lds_ptr<const u32x4> nbc = nbt;
             if (COEF_LDS)
-                relax_start_wave<D, NS>(J, WO, c64, c32, st64, st32, bounce, s);
+                relax_start_wave<D, NS, CREG>(J, WO, c64, c32, nbc, st64, st32, bounce, s);
             else
-                relax_start_wave<D, NS>(J, WO, as_global(g64), as_global(g32), st64, st32, bounce, s);
+                relax_start_wave<D, NS, CREG>(J, WO, as_global(g64), as_global(g32), nbc, st64, st32, bounce, s);
         }
         __syncthreads();
         j0 = jn;
     }
 }
 
-template <int D, int NS, int WAVES>
-hipError_t launch_t(const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, unsigned long long *job_next,
-                    int coef_lds, float2 *bounce, int grid, size_t lds, hipStream_t s)
+template <int D, int NS, int WAVES, bool CL, int CREG>
+hipError_t launch_v(const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, unsigned long long *job_next,
+                    float2 *bounce, int grid, size_t lds, hipStream_t s)
 {
-    if (coef_lds)
-        hipLaunchKernelGGL((wave_kernel<D, NS, WAVES, true>), dim3(grid), dim3(64 * WAVES), lds, s, jobs, worbs,
-                           n_jobs, job_next, bounce);
-    else
-        hipLaunchKernelGGL((wave_kernel<D, NS, WAVES, false>), dim3(grid), dim3(64 * WAVES), lds, s, jobs, worbs,
-                           n_jobs, job_next, bounce);
+    hipLaunchKernelGGL((wave_kernel<D, NS, WAVES, CL, CREG>), dim3(grid), dim3(64 * WAVES), lds, s, jobs, worbs,
+                       n_jobs, job_next, bounce);
     return hipGetLastError();
 }
 
-template <int D, int NS, int WAVES>
-hipError_t occ_t(int coef_lds, size_t lds, int *per_cu)
+template <int D, int NS, int WAVES, bool CL, int CREG>
+hipError_t occ_v(size_t lds, int *per_cu)
 {
-    if (coef_lds)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, wave_kernel<D, NS, WAVES, true>, 64 * WAVES, lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, wave_kernel<D, NS, WAVES, false>, 64 * WAVES, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, wave_kernel<D, NS, WAVES, CL, CREG>, 64 * WAVES, lds);
+}
+
+// Register-held coefficients are instantiated where a lane's slots are few
+// (NS <= 2): creg 1 holds colour 0, creg 2 both colours.
+template <int D, int NS> constexpr bool creg_ok() { return NS <= 2; }
+
+template <int D, int NS, int WAVES>
+hipError_t launch_t(const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, unsigned long long *job_next,
+                    int variant, float2 *bounce, int grid, size_t lds, hipStream_t s)
+{
+    const bool cl = (variant & 1) != 0;
+    const int creg = variant >> 1;
+    if constexpr (creg_ok<D, NS>()) {
+        if (creg == 1)
+            return cl ? launch_v<D, NS, WAVES, true, 1>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s)
+                      : launch_v<D, NS, WAVES, false, 1>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s);
+        if (creg == 2)
+            return cl ? launch_v<D, NS, WAVES, true, 2>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s)
+                      : launch_v<D, NS, WAVES, false, 2>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s);
+    }
+    if (creg != 0) return hipErrorInvalidValue;
+    return cl ? launch_v<D, NS, WAVES, true, 0>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s)
+              : launch_v<D, NS, WAVES, false, 0>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s);
+}
+
+template <int D, int NS, int WAVES>
+hipError_t occ_t(int variant, size_t lds, int *per_cu)
+{
+    const bool cl = (variant & 1) != 0;
+    const int creg = variant >> 1;
+    if constexpr (creg_ok<D, NS>()) {
+        if (creg == 1) return cl ? occ_v<D, NS, WAVES, true, 1>(lds, per_cu) : occ_v<D, NS, WAVES, false, 1>(lds, per_cu);
+        if (creg == 2) return cl ? occ_v<D, NS, WAVES, true, 2>(lds, per_cu) : occ_v<D, NS, WAVES, false, 2>(lds, per_cu);
+    }
+    if (creg != 0) return hipErrorInvalidValue;
+    return cl ? occ_v<D, NS, WAVES, true, 0>(lds, per_cu) : occ_v<D, NS, WAVES, false, 0>(lds, per_cu);
+}
+
+int creg_max_t(int d, int ns)
+{
+    (void)d;
+    return ns <= 2 ? 2 : 0;
 }
 
 }  // namespace
@@ -330,15 +431,17 @@ hipError_t occ_t(int coef_lds, size_t lds, int *per_cu)
     default: return hipErrorInvalidValue;                                                      \
     }
 
-hipError_t gc_wave_occupancy(int d, int ns, int coef_lds, size_t lds, int *per_cu)
+hipError_t gc_wave_occupancy(int d, int ns, int variant, size_t lds, int *per_cu)
 {
-    GC_WAVE_DISPATCH(occ_t, coef_lds, lds, per_cu)
+    GC_WAVE_DISPATCH(occ_t, variant, lds, per_cu)
 }
 
 hipError_t gc_launch_wave(int d, int ns, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs,
-                          unsigned long long *job_next, int coef_lds, float2 *bounce, int grid, size_t lds,
+                          unsigned long long *job_next, int variant, float2 *bounce, int grid, size_t lds,
                           hipStream_t s)
 {
-    GC_WAVE_DISPATCH(launch_t, jobs, worbs, n_jobs, job_next, coef_lds, bounce, grid, lds, s)
+    GC_WAVE_DISPATCH(launch_t, jobs, worbs, n_jobs, job_next, variant, bounce, grid, lds, s)
 }
+
+int gc_wave_creg_max(int d, int ns) { return creg_max_t(d, ns); }
 
