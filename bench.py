@@ -25,12 +25,37 @@ import numpy as np  # noqa: E402
 
 import gribov_inputs as GI  # noqa: E402
 
-# Algorithmic floating-point operations per site update (a multiply or an add
-# counts one, a reciprocal square root one): the update S_i (16 d), its
-# normalisation (6), the over-relaxation step (22, omega != 1), and the
-# stopping test on the post-sweep state evaluated every sweep (16 d + 5).
-def flops_per_site_update(d: int, omega: float) -> int:
-    return 32 * d + 11 + (22 if omega != 1.0 else 0)
+# Algorithmic floating-point operations per site update, 16 d + 37: the
+# staple S_i (2d complex multiply-adds, 16 d), its normalisation, the
+# over-relaxation step and the divergence Im(conj(g_i) S_i) with its share of
+# the stopping norm (37 together, counted once whatever omega is).
+def flops_per_site_update(d: int) -> int:
+    return 16 * d + 37
+
+
+# HBM traffic of the relax kernel on the default workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters
+# on a plain device copy of known size.  Valid only for the kernel sources
+# they were taken on (SHA-256 of the relax sources below); otherwise null.
+RELAX_SOURCES = ("gc_wave.hip", "gc_wave.h", "gc_common.h")
+TRAFFIC = {"sources_sha256": "4092be7212fcda32916b767093bcccaaee007e4174af8158054e05f2b2f695f9",
+           "bytes_per_launch": 429505728}
+
+
+def relax_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in RELAX_SOURCES:
+        with open(os.path.join(ROOT, "paper_1403_0555_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def relax_kernel_name(extent) -> str:
+    V = int(np.prod(extent))
+    if all(e % 2 == 0 for e in extent):
+        return "wave_kernel<%d, %d, 4, ...>" % (len(extent), (V // 2 + 63) // 64)
+    return "relax_wg_kernel<...>"
 
 
 PEAK_FP64_TFLOPS = 78.6
@@ -57,6 +82,28 @@ def cpu_baseline(w: GI.Workload, phi, n_sample: int):
     return {"value": inreg / dt, "unit": "copies/s", "cores": cores, "kind": "oracle",
             "sample": "first %d starts of the same orbit and parameters (%.1f s)" % (n_sample, dt),
             "site_updates_per_s": upd / dt}
+
+
+def run_copy(args):
+    """Plain device-to-device copy of a known size: the calibration run for
+    the HBM byte counters (FETCH_SIZE / WRITE_SIZE per dispatch)."""
+    import torch
+    n = (args.copy_mib << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(args.warmup):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    nbytes = 4 * n
+    return {"metric": "device copy bandwidth", "value": 2 * nbytes / dt / 1e9, "unit": "GB/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "copy", "bytes_read": nbytes, "bytes_written": nbytes}}
 
 
 def run_batch(gc, args):
@@ -171,13 +218,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="u1_4d_4x4x4x4_relax", choices=sorted(GI.WORKLOADS) + ["batch", "serve"])
+    ap.add_argument("--workload", default="u1_4d_4x4x4x4_relax",
+                    choices=sorted(GI.WORKLOADS) + ["batch", "serve", "copy"])
+    ap.add_argument("--copy-mib", type=int, default=2048, help="copy mode: bytes per copy, MiB")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"], help="batch/serve modes")
     ap.add_argument("--requests", type=int, default=300, help="serve mode")
     ap.add_argument("--load", type=float, default=0.8, help="serve mode: offered load / capacity")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve mode")
     ap.add_argument("--starts", type=int, default=0, help="override the workload's start count")
-    ap.add_argument("--cpu-sample", type=int, default=2000)
+    ap.add_argument("--cpu-sample", type=int, default=5000, help="oracle sample: first N starts (10-30 s on 16 threads)")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
 
@@ -185,6 +234,10 @@ def main():
         print("bench.py measures one GPU: each start is independent and the path needs no "
               "collective; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "copy":
+        print(json.dumps(run_copy(args)), flush=True)
+        return
 
     import paper_1403_0555_amd as gc
 
@@ -232,11 +285,15 @@ def main():
     ctx.gc_release(h)
     ctx.close()
 
-    fl = flops_per_site_update(d, w.omega)
+    fl = flops_per_site_update(d)
     mean_kernel_s = float(np.mean(kms)) / 1e3
     upd_per_launch = upd / args.steps
     achieved_tflops = fl * upd_per_launch / mean_kernel_s / 1e12
     peak = PEAK_FP64_TFLOPS if w.precision == "fp64" else PEAK_FP32_TFLOPS
+    traffic = None
+    if (args.workload == "u1_4d_4x4x4x4_relax" and not args.starts and TRAFFIC["sources_sha256"]
+            and TRAFFIC["sources_sha256"] == relax_sources_sha256()):
+        traffic = TRAFFIC["bytes_per_launch"]
     out = {
         "metric": "converged Gribov copies/s",
         "value": conv_inreg / wall,
@@ -258,9 +315,9 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "solve_kernel_ms": float(np.mean(kms)),
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / peak, "traffic": None,
-                     "kernel": "solve_kernel", "flops_per_site_update": fl,
-                     "site_updates_per_launch": upd_per_launch},
+                     "frac": achieved_tflops / peak, "traffic": traffic,
+                     "kernel": relax_kernel_name(w.extent), "kernel_ms": float(np.mean(kms)),
+                     "flops_per_site_update": fl, "site_updates_per_launch": upd_per_launch},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, phi, min(args.cpu_sample, n))
