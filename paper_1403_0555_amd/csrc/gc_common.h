@@ -147,8 +147,16 @@ template <typename R> struct cx;
 template <> struct cx<float> { using T = flt2; };
 template <> struct cx<double> { using T = dbl2; };
 
+// 1/sqrt(x) for a positive normal x (the callers guarantee it).  Double:
+// the hardware estimate refined by one Newton step with its second-order
+// term, y (1 + e/2 + 3e^2/8), e = 1 - x y^2.
 __device__ __forceinline__ float rsq(float x) { return rsqrtf(x); }
-__device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
+__device__ __forceinline__ double rsq(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
 
 // Local maximisation of eqs. (4)-(5) in the eq. (3) convention: from the
 // staple S, g <- S/|S| (RELAX, omega = 1) or the over-relaxed

@@ -148,13 +148,15 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
     }
 
     uint64_t t = 0;
+    uint64_t until = check;      // sweeps left to the next check point
+    bool ckpt = false;           // the state after sweep t is checked
     double acc1 = 0.0;           // colour-1 part of the norm of sweep t
     int status = GC_ST_NONCONVERGED;
     D_out = INFINITY;
     for (;;) {
         // sweep t + 1 first reads the colour-0 staples of the state after
         // sweep t; at a check point they complete the norm of sweep t
-        const bool pending = (t > 0) && (t % check == 0 || t == J.max_sweeps);
+        const bool pending = (t > 0) && ckpt;
         const bool last = (t == J.max_sweeps);
         // an opaque offset keeps per-slot index arithmetic inside the sweep
         const int z = opaque_zero();
@@ -185,7 +187,10 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
         wave_sync();
         // ---- colour 1, with its part of the norm of this sweep
         ++t;
-        const bool chk = (t % check == 0 || t == J.max_sweeps);
+        --until;
+        ckpt = (until == 0) || (t == J.max_sweeps);
+        if (until == 0) until = check;
+        const bool chk = ckpt;
         double a1 = 0.0;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
