@@ -77,36 +77,70 @@ __device__ __forceinline__ void wave_sync_global()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Butterfly reductions over the 64 lanes; every lane ends with the same value
-// and the association order depends only on the lane count.
+// Reductions over the 64 lanes of a wavefront; every lane ends with the same
+// value and the association order is fixed.  Within each row of 16 lanes
+// the values are combined through DPP lane permutations (quad swaps, then
+// the half-row and row mirrors), so they never touch LDS; the four row
+// results are then read into scalar registers and combined as
+// (r0 + r1) + (r2 + r3).
+template <int CTRL> __device__ __forceinline__ int dpp32(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL> __device__ __forceinline__ double dpp64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp32<CTRL>((int)b), hi = dpp32<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double lane_value(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane), hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+constexpr int kDppQuadSwap1 = 0xB1;   // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadSwap2 = 0x4E;   // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141; // row_half_mirror
+constexpr int kDppRowMirror = 0x140;  // row_mirror
+
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp64<kDppQuadSwap1>(v);
+    v += dpp64<kDppQuadSwap2>(v);
+    v += dpp64<kDppHalfMirror>(v);
+    v += dpp64<kDppRowMirror>(v);
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 __device__ __forceinline__ double wave_max(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    v = fmax(v, dpp64<kDppQuadSwap1>(v));
+    v = fmax(v, dpp64<kDppQuadSwap2>(v));
+    v = fmax(v, dpp64<kDppHalfMirror>(v));
+    v = fmax(v, dpp64<kDppRowMirror>(v));
+    return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
 }
 __device__ __forceinline__ double wave_min(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
+    v = fmin(v, dpp64<kDppQuadSwap1>(v));
+    v = fmin(v, dpp64<kDppQuadSwap2>(v));
+    v = fmin(v, dpp64<kDppHalfMirror>(v));
+    v = fmin(v, dpp64<kDppRowMirror>(v));
+    return fmin(fmin(lane_value(v, 0), lane_value(v, 16)), fmin(lane_value(v, 32), lane_value(v, 48)));
+}
+__device__ __forceinline__ int wave_min_int(int v)
+{
+    v = min(v, dpp32<kDppQuadSwap1>(v));
+    v = min(v, dpp32<kDppQuadSwap2>(v));
+    v = min(v, dpp32<kDppHalfMirror>(v));
+    v = min(v, dpp32<kDppRowMirror>(v));
+    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ int wave_min_int(int v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
     return v;
 }
 

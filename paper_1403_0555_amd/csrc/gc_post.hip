@@ -16,6 +16,9 @@
 // and the patch of re-filtered representatives.
 #include "gc_common.h"
 
+#include <cstdio>
+#include <cstdlib>
+
 namespace {
 
 using namespace gc;
@@ -731,6 +734,16 @@ size_t gc_post_lds_bytes(int d, int V)
 
 void gc_post_shape(int V, int *block, int *sp, int *wreg)
 {
+    // tuning override: GC_POST_SHAPE=block,sites_per_thread (register weights)
+    if (const char *e = getenv("GC_POST_SHAPE")) {
+        int b = 0, k = 0;
+        if (sscanf(e, "%d,%d", &b, &k) == 2 && (long)b * k >= V) {
+            *block = b;
+            *sp = k;
+            *wreg = 1;
+            return;
+        }
+    }
     // up to 4 sites per thread with the link weights in registers; the
     // largest lattices keep them in global memory
     static const int shapes[][4] = {{64, 64, 1, 1},     {128, 64, 2, 1},    {256, 64, 4, 1},
@@ -752,6 +765,9 @@ void gc_post_shape(int V, int *block, int *sp, int *wreg)
     if (block == 64 && sp == 1 && wreg) return FN<64, 1, true>(__VA_ARGS__);        \
     if (block == 64 && sp == 2 && wreg) return FN<64, 2, true>(__VA_ARGS__);        \
     if (block == 64 && sp == 4 && wreg) return FN<64, 4, true>(__VA_ARGS__);        \
+    if (block == 128 && sp == 2 && wreg) return FN<128, 2, true>(__VA_ARGS__);      \
+    if (block == 256 && sp == 1 && wreg) return FN<256, 1, true>(__VA_ARGS__);      \
+    if (block == 256 && sp == 2 && wreg) return FN<256, 2, true>(__VA_ARGS__);      \
     if (block == 128 && sp == 4 && wreg) return FN<128, 4, true>(__VA_ARGS__);      \
     if (block == 256 && sp == 4 && wreg) return FN<256, 4, true>(__VA_ARGS__);      \
     if (block == 384 && sp == 4 && wreg) return FN<384, 4, true>(__VA_ARGS__);      \
