@@ -503,7 +503,10 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             g.coef_lds = (coef_bytes + states <= 64 * 1024) ? 1 : 0;
             g.lds = states + (g.coef_lds ? coef_bytes : 0);
             if (g.lds > ctx->lds_max) return GC_EUNSUPPORTED;
-            g.creg = 0;
+            // colour-0 coefficients in registers where a lane has at most two
+            // slots (measured faster on 4^4 despite two waves per SIMD instead
+            // of three); GC_WAVE_CREG overrides
+            g.creg = std::min(1, gc_wave_creg_max(g.d, g.ns));
             if (ctx->creg_override >= 0) g.creg = std::min(ctx->creg_override, gc_wave_creg_max(g.d, g.ns));
             hipError_t e = gc_wave_occupancy(g.d, g.ns, g.coef_lds | (g.creg << 1), g.lds, &per_cu);
             if (e != hipSuccess) return fail(ctx, e, "occupancy");

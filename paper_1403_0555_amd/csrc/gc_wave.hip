@@ -114,6 +114,7 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
         hs[k] = valid[k] ? h : half - 1;
     }
     u32x4 nr[NB_REG ? 2 : 1][NB_REG ? NS : 1];
+    C own[NB_REG ? 2 : 1][NB_REG ? NS : 1];   // the lane's own sites (NB_REG): LDS is only written
     uint32_t d0[NB_REG ? 1 : NS], d1[NB_REG ? 1 : NS];
     Strides<D> L;
     if constexpr (NB_REG) {
@@ -121,6 +122,8 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
         for (int k = 0; k < NS; ++k) {
             nr[0][k] = nbt[hs[k]];
             nr[1][k] = nbt[half + hs[k]];
+            own[0][k] = st0[hs[k]];
+            own[1][k] = st1[hs[k]];
         }
     } else {
         int str = 1;
@@ -168,7 +171,9 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
             C s;
             if constexpr (NB_REG) s = staple<D, R, (CREG >= 1)>(cr[0][k], coef, st1, NbWords{nr[0][k]}, 0, h, half);
             else s = staple<D, R, (CREG >= 1)>(cr[0][k], coef, st1, NbDesc<D>{d0[k] + (uint32_t)z, L}, 0, h, half);
-            const C g0 = st0[h];
+            C g0;
+            if constexpr (NB_REG) g0 = own[0][k];
+            else g0 = st0[h];
             const double dv = (double)(g0.x * s.y - g0.y * s.x);
             const double a = maxabs ? fmax(acc0, fabs(dv)) : acc0 + dv * dv;
             acc0 = valid[k] ? a : acc0;
@@ -182,8 +187,10 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
         }
         if (last) break;
 #pragma unroll
-        for (int k = 0; k < NS; ++k)
+        for (int k = 0; k < NS; ++k) {
+            if constexpr (NB_REG) own[0][k] = gnew[k];
             if (valid[k]) st0[hs[k]] = gnew[k];
+        }
         wave_sync();
         // ---- colour 1, with its part of the norm of this sweep
         ++t;
@@ -201,7 +208,11 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
             else
                 s = staple<D, R, (CREG >= 2)>(cr[NCR - 1][k], coef, st0, NbDesc<D>{d1[k] + (uint32_t)z, L}, 1, h,
                                               half);
-            const C g = local_update<RELAX, R>(st1[h], s, omega);
+            C g1;
+            if constexpr (NB_REG) g1 = own[NB_REG ? 1 : 0][k];
+            else g1 = st1[h];
+            const C g = local_update<RELAX, R>(g1, s, omega);
+            if constexpr (NB_REG) own[NB_REG ? 1 : 0][k] = g;
             if (valid[k]) st1[hs[k]] = g;
             const double dv = (double)(g.x * s.y - g.y * s.x);
             const double a = maxabs ? fmax(a1, fabs(dv)) : a1 + dv * dv;
