@@ -86,57 +86,64 @@ __device__ GcEntry *table_find(const GcJobDev &J, uint64_t key_hi, uint64_t key_
     return nullptr;
 }
 
-// Workgroup reductions over B threads: wave butterflies, then the waves'
+// Workgroup reductions over B threads: wave reductions, then the waves'
 // partials combined in a fixed order.  Every thread returns the result.
+// Successive calls on one scratch array alternate between its two halves
+// (ph toggles), so a call needs a single barrier: a half is rewritten only
+// after every wave has passed the barrier of the call in between, and so has
+// finished reading it.
 template <int B, int N>
-__device__ __forceinline__ void wg_sum_n(double (&v)[N], double *red)
+__device__ __forceinline__ void wg_sum_n(double (&v)[N], double *red, int &ph)
 {
 #pragma unroll
     for (int n = 0; n < N; ++n) v[n] = wave_sum(v[n]);
     if (B > 64) {
-        __syncthreads();
+        double *r = red + ph * (3 * (B / 64));
+        ph ^= 1;
         if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-            for (int n = 0; n < N; ++n) red[n * (B / 64) + (threadIdx.x >> 6)] = v[n];
+            for (int n = 0; n < N; ++n) r[n * (B / 64) + (threadIdx.x >> 6)] = v[n];
         }
         __syncthreads();
 #pragma unroll
         for (int n = 0; n < N; ++n) {
-            double t = red[n * (B / 64)];
+            double t = r[n * (B / 64)];
 #pragma unroll
-            for (int w = 1; w < B / 64; ++w) t += red[n * (B / 64) + w];
+            for (int w = 1; w < B / 64; ++w) t += r[n * (B / 64) + w];
             v[n] = t;
         }
     }
 }
 
 template <int B>
-__device__ __forceinline__ uint64_t wg_sum_u64(uint64_t v, uint64_t *red)
+__device__ __forceinline__ uint64_t wg_sum_u64(uint64_t v, uint64_t *red, int &ph)
 {
     v = wave_sum_u64(v);
     if (B > 64) {
+        uint64_t *r = red + ph * (B / 64);
+        ph ^= 1;
+        if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = v;
         __syncthreads();
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-        __syncthreads();
-        uint64_t t = red[0];
+        uint64_t t = r[0];
 #pragma unroll
-        for (int w = 1; w < B / 64; ++w) t += red[w];
+        for (int w = 1; w < B / 64; ++w) t += r[w];
         v = t;
     }
     return v;
 }
 
 template <int B>
-__device__ __forceinline__ int wg_min_int(int v, int *red)
+__device__ __forceinline__ int wg_min_int(int v, int *red, int &ph)
 {
     v = wave_min_int(v);
     if (B > 64) {
+        int *r = red + ph * (B / 64);
+        ph ^= 1;
+        if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = v;
         __syncthreads();
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-        __syncthreads();
-        int t = red[0];
+        int t = r[0];
 #pragma unroll
-        for (int w = 1; w < B / 64; ++w) t = min(t, red[w]);
+        for (int w = 1; w < B / 64; ++w) t = min(t, r[w]);
         v = t;
     }
     return v;
@@ -198,13 +205,14 @@ __device__ int sturm_count(lds_cdouble *alpha, lds_cdouble *beta2, int k, double
 // Smallest eigenvalue of the tridiagonal by (B+1)-section inside [lo, hi]
 // (count(lo) = 0, count(hi) >= 1).
 template <int B>
-__device__ double tridiag_min_eig(lds_cdouble *alpha, lds_cdouble *beta2, int k, double lo, double hi, int *ired)
+__device__ double tridiag_min_eig(lds_cdouble *alpha, lds_cdouble *beta2, int k, double lo, double hi, int *ired,
+                                  int &iph)
 {
     for (int round = 0; round < 24; ++round) {
         if (hi - lo <= 1e-15 * fmax(1.0, fabs(hi))) break;
         const double step = (hi - lo) / (double)(B + 1);
         const double x = lo + step * (double)(threadIdx.x + 1);
-        const int first = wg_min_int<B>(sturm_count(alpha, beta2, k, x) >= 1 ? (int)threadIdx.x : B, ired);
+        const int first = wg_min_int<B>(sturm_count(alpha, beta2, k, x) >= 1 ? (int)threadIdx.x : B, ired, iph);
         const double nlo = (first == 0) ? lo : lo + step * (double)first;
         const double nhi = (first == B) ? hi : lo + step * (double)(first + 1);
         lo = nlo;
@@ -218,7 +226,7 @@ __device__ double tridiag_min_eig(lds_cdouble *alpha, lds_cdouble *beta2, int k,
 // previous value bounds it above; a window below it is tried first.
 template <int B>
 __device__ double ritz_min(lds_cdouble *alpha, lds_cdouble *beta2, int k, double glo, double ghi, double prev,
-                           double prev_step, int *ired)
+                           double prev_step, int *ired, int &iph)
 {
     double lo = glo - 1e-12 * (1.0 + fabs(glo));
     double hi = ghi + 1e-12 * (1.0 + fabs(ghi));
@@ -227,10 +235,10 @@ __device__ double ritz_min(lds_cdouble *alpha, lds_cdouble *beta2, int k, double
         const double bot = top - fmax(4.0 * prev_step, 1e-9 * (1.0 + fabs(prev)));
         const bool top_ok = sturm_count(alpha, beta2, k, top) >= 1;
         if (top_ok && bot > lo && sturm_count(alpha, beta2, k, bot) == 0)
-            return tridiag_min_eig<B>(alpha, beta2, k, bot, top, ired);
+            return tridiag_min_eig<B>(alpha, beta2, k, bot, top, ired, iph);
         if (top_ok) hi = top;
     }
-    return tridiag_min_eig<B>(alpha, beta2, k, lo, hi, ired);
+    return tridiag_min_eig<B>(alpha, beta2, k, lo, hi, ired, iph);
 }
 
 __device__ uint32_t region_flags(double lam2, double tol)
@@ -276,9 +284,10 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
     constexpr int NN = WREG ? SP : 1;   // register neighbour words per thread
     glb_ptr<double> wbuf = as_global(wbuf_all + (WREG ? 0 : (uint64_t)blockIdx.x * wstride));
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[3 * (B / 64)];
-    __shared__ uint64_t ured[B / 64];
-    __shared__ int ired[B / 64];
+    __shared__ double red[2 * 3 * (B / 64)];
+    __shared__ uint64_t ured[2 * (B / 64)];
+    __shared__ int ired[2 * (B / 64)];
+    int rph = 0, uph = 0, iph = 0;   // halves of the reduction scratch in use
     __shared__ unsigned long long claim;
     __shared__ int run_sh;
     if (total_dev) total = *total_dev;
@@ -348,7 +357,7 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
             }
         }
         double tmp1[1] = {facc};
-        wg_sum_n<B, 1>(tmp1, red);
+        wg_sum_n<B, 1>(tmp1, red, rph);
         const double F = tmp1[0];
         __syncthreads();   // angles visible to the whole workgroup
         uint32_t flags = 0;
@@ -385,9 +394,9 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                 h0 += mix64(c0 ^ word);
                 h1 += mix64(c1 ^ word);
             }
-            h0 = wg_sum_u64<B>(h0, ured);
-            h1 = wg_sum_u64<B>(h1, ured);
-            const int ok = wg_min_int<B>(overflow ? 0 : 1, ired);
+            h0 = wg_sum_u64<B>(h0, ured, uph);
+            h1 = wg_sum_u64<B>(h1, ured, uph);
+            const int ok = wg_min_int<B>(overflow ? 0 : 1, ired, iph);
             key_hi = mix64(h0 + (uint64_t)O.n_elems);
             key_lo = mix64(h1 + (uint64_t)O.n_elems);
             if (key_hi == 0) key_hi = 1;
@@ -430,7 +439,7 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                     sums[0] += x;
                 }
             }
-            wg_sum_n<B, 1>(*reinterpret_cast<double(*)[1]>(&sums[0]), red);
+            wg_sum_n<B, 1>(*reinterpret_cast<double(*)[1]>(&sums[0]), red, rph);
             const double mean = sums[0] / (double)V;
             double nn[1] = {0.0};
 #pragma unroll
@@ -442,7 +451,7 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                     nn[0] += x * x;
                 }
             }
-            wg_sum_n<B, 1>(nn, red);
+            wg_sum_n<B, 1>(nn, red, rph);
             const double inv = 1.0 / sqrt(nn[0]);
             __syncthreads();   // every thread is done with g before q overwrites it
 #pragma unroll
@@ -453,6 +462,7 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
             __syncthreads();
             double beta_prev = 0.0, theta = INFINITY, theta_old = INFINITY, theta_step = 1.0;
             double rows_lo = INFINITY, rows_hi = -INFINITY;   // Gershgorin bounds of the complete rows
+            int next_check = 24;                              // iteration count of the next Ritz check
             int it = 0;
             bool conv = false;
             for (it = 0; it < lmax; ++it) {
@@ -494,7 +504,7 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                     // every neighbour of every own site in registers
                     __builtin_amdgcn_sched_barrier(0);
                 }
-                wg_sum_n<B, 3>(s3, red);
+                wg_sum_n<B, 3>(s3, red, rph);
                 const double shift = sigma * s3[1] / (double)V;
                 const double a_j = s3[0] + shift * s3[1] - beta_prev * s3[2];
                 double rr[1] = {0.0};
@@ -508,23 +518,29 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                         rr[0] += x * x;
                     }
                 }
-                wg_sum_n<B, 1>(rr, red);
+                wg_sum_n<B, 1>(rr, red, rph);
                 const double b_j = sqrt(rr[0]);
                 if (tid == 0) {
                     alpha[it] = a_j;
                     beta2[it] = b_j * b_j;
                 }
-                __syncthreads();
                 const bool breakdown = b_j <= 1e-13 * sigma;
-                if (((it + 1) % 8 == 0) || breakdown || it + 1 == lmax) {
+                if (it + 1 >= next_check || breakdown || it + 1 == lmax) {
+                    __syncthreads();   // the tridiagonal is complete in LDS
                     theta = ritz_min<B>(alpha, beta2, it + 1, fmin(rows_lo, a_j - beta_prev),
-                                        fmax(rows_hi, a_j + beta_prev), theta_old, theta_step, ired);
-                    if (breakdown || fabs(theta - theta_old) <= 1e-12 * fmax(1.0, fabs(theta))) {
+                                        fmax(rows_hi, a_j + beta_prev), theta_old, theta_step, ired, iph);
+                    const double tol = 1e-12 * fmax(1.0, fabs(theta));
+                    const double change = theta_old - theta;
+                    if (breakdown || fabs(change) <= tol) {
                         conv = true;
                         ++it;
                         break;
                     }
-                    if (theta_old < INFINITY) theta_step = theta_old - theta;
+                    // far from converged: look again later (the change is then
+                    // measured over the longer gap, a test at least as strict)
+                    const int gap = !(change <= 1e6 * tol) ? 24 : !(change <= 1e3 * tol) ? 16 : 8;
+                    next_check = it + 1 + gap;
+                    if (theta_old < INFINITY) theta_step = change;
                     theta_old = theta;
                 }
                 // row it of T now has both neighbours: into the Gershgorin bounds
