@@ -228,6 +228,7 @@ def main():
     ap.add_argument("--starts", type=int, default=0, help="override the workload's start count")
     ap.add_argument("--cpu-sample", type=int, default=5000, help="oracle sample: first N starts (10-30 s on 16 threads)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the kernel-variant autotuner")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -256,6 +257,11 @@ def main():
 
     ctx = gc.Context(0)
     h = ctx.gc_orbit_load(w.extent, phi, w.orbit_index)
+    tune = None
+    if not args.no_tune:
+        # kernel variants for this shape, chosen on a sample before timing
+        tune = ctx.gc_autotune(h, min(n, 20000), params)
+        print("autotune: %s" % tune, file=sys.stderr, flush=True)
 
     def step():
         ctx.gc_launch(h, n, params)
@@ -312,6 +318,7 @@ def main():
                    "orbit_seed": w.seed, "start_seed": w.start_seed},
         "site_updates_per_s": upd / wall,
         "distinct_copies_per_s": distinct / wall,
+        "autotune": tune,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "solve_kernel_ms": float(np.mean(kms)),
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",

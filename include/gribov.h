@@ -248,6 +248,29 @@ gc_status gc_memory_info(gc_ctx *ctx, uint64_t *budget, uint64_t *in_use, uint64
  * measured with HIP events on the stream the kernel ran on. */
 gc_status gc_kernel_time_ms(gc_ctx *ctx, gc_orbit orbit, double *solve_ms);
 
+/* Result of gc_autotune. */
+typedef struct {
+    int32_t relax_variant;          /* colours whose coefficients a lane keeps in registers (0..2) */
+    int32_t post_block;             /* post kernel: threads per workgroup */
+    int32_t post_sites_per_thread;
+    int32_t pad;
+    double relax_ms, post_ms;       /* best measured times of the chosen variants */
+} gc_tune_result;
+
+/* Kernel-variant autotuner for the shape of this orbit (Sec. III sweeps and
+ * the first-region filter; the variants compute the same quantities).  Runs
+ * timed launches of n_starts starts with params on the orbit, synchronously:
+ * a warm-up, then each relax variant (coefficients of 0, 1 or 2 colours held
+ * in registers where a lane has at most two slots) and each post-kernel
+ * workgroup shape that covers V, two launches each, timed with HIP events.
+ * The fastest choices are stored in the context and used by every later
+ * launch of an orbit with the same dimension, slots per lane and precision
+ * (relax) or volume (post).  The orbit's results afterwards are those of the
+ * last trial launch.  out may be NULL.  Errors: GC_EINVAL (no orbit,
+ * n_starts = 0), GC_EBUSY (orbit running), launch errors. */
+gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_solve_params *params,
+                      gc_tune_result *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,8 +27,14 @@ EXPORTED_SYMBOLS = [
     "gc_create", "gc_destroy", "gc_orbit_load", "gc_orbit_random", "gc_orbit_angles",
     "gc_launch", "gc_launch_batch", "gc_poll", "gc_wait", "gc_fetch", "gc_fetch_starts",
     "gc_fetch_state", "gc_release", "gc_last_error", "gc_kernel_time_ms", "gc_launch_bytes",
-    "gc_memory_info",
+    "gc_memory_info", "gc_autotune",
 ]
+
+
+class gc_tune_result(ctypes.Structure):
+    _fields_ = [("relax_variant", ctypes.c_int32), ("post_block", ctypes.c_int32),
+                ("post_sites_per_thread", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("relax_ms", ctypes.c_double), ("post_ms", ctypes.c_double)]
 
 
 class gc_ctx_params(ctypes.Structure):
@@ -112,6 +118,7 @@ def lib():
         "gc_kernel_time_ms": ([vp, u64, P(ctypes.c_double)], i32),
         "gc_launch_bytes": ([vp, u64, u64, P(gc_solve_params), P(u64)], i32),
         "gc_memory_info": ([vp, P(u64), P(u64), P(u64)], i32),
+        "gc_autotune": ([vp, u64, u64, P(gc_solve_params), P(gc_tune_result)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -308,6 +315,13 @@ class Context:
         self._check(self._L.gc_memory_info(self._h, ctypes.byref(b), ctypes.byref(u), ctypes.byref(q)),
                     "gc_memory_info")
         return {"budget": b.value, "in_use": u.value, "queued": q.value}
+
+    def gc_autotune(self, orbit: int, n_starts: int, params: SolveParams | None = None) -> dict:
+        p = (params or SolveParams()).c()
+        r = gc_tune_result()
+        self._check(self._L.gc_autotune(self._h, orbit, n_starts, ctypes.byref(p), ctypes.byref(r)), "gc_autotune")
+        return {"relax_variant": r.relax_variant, "post_block": r.post_block,
+                "post_sites_per_thread": r.post_sites_per_thread, "relax_ms": r.relax_ms, "post_ms": r.post_ms}
 
     def gc_last_error(self) -> str:
         buf = ctypes.create_string_buffer(512)

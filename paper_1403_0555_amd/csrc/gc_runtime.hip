@@ -84,6 +84,8 @@ gc_status check_lattice(const gc_lattice *lat, int *K_out, int *V_out)
     return GC_OK;
 }
 
+uint64_t creg_key(int d, int ns, bool mixed) { return ((uint64_t)d << 40) | ((uint64_t)ns << 8) | (mixed ? 1u : 0u); }
+
 int block_for(int V)
 {
     if (V <= 128) return 64;
@@ -145,7 +147,7 @@ struct Job {
     size_t bytes = 0;                // budget charge while running
     void *mem = nullptr;             // working block
     int stream = 0;
-    hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_done = nullptr;
+    hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_k2 = nullptr, ev_done = nullptr;
     hipGraph_t g = nullptr;
     hipGraphExec_t gx = nullptr;
     Clock::time_point t_submit, t_done;
@@ -153,7 +155,7 @@ struct Job {
     // pinned host results
     GcCounters *h_cnt = nullptr;               // [n_jobs]
     unsigned long long *h_ncopies = nullptr;   // [n_jobs]
-    double solve_ms = 0.0;
+    double solve_ms = 0.0, post_ms = 0.0;
     uint64_t total = 0;
 };
 
@@ -189,6 +191,12 @@ struct gc_ctx {
     int n_cu = 0;
     size_t lds_max = 0;
     int creg_override = -1;   // GC_WAVE_CREG: register-held coefficient colours (tuning)
+    // kernel variants chosen by gc_autotune: relax coefficient colours per
+    // (d, slots per lane, precision), post workgroup shape per V; and the
+    // variant forced while gc_autotune measures
+    std::map<uint64_t, int> tune_creg;
+    std::map<int, std::pair<int, int>> tune_post;
+    int force_creg = -1, force_post_block = 0, force_post_sp = 0;
     uint64_t budget = 0, used = 0;
     std::vector<hipStream_t> streams;
     std::vector<int> stream_load;
@@ -507,7 +515,10 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             // slots (measured faster on 4^4 despite two waves per SIMD instead
             // of three); GC_WAVE_CREG overrides
             g.creg = std::min(1, gc_wave_creg_max(g.d, g.ns));
+            const auto tc = ctx->tune_creg.find(creg_key(g.d, g.ns, mixed));
+            if (tc != ctx->tune_creg.end()) g.creg = tc->second;
             if (ctx->creg_override >= 0) g.creg = std::min(ctx->creg_override, gc_wave_creg_max(g.d, g.ns));
+            if (ctx->force_creg >= 0) g.creg = std::min(ctx->force_creg, gc_wave_creg_max(g.d, g.ns));
             hipError_t e = gc_wave_occupancy(g.d, g.ns, g.coef_lds | (g.creg << 1), g.lds, &per_cu);
             if (e != hipSuccess) return fail(ctx, e, "occupancy");
         } else {
@@ -533,6 +544,17 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
     for (int j = 0; j < nj; ++j) {
         int block = 0, sp = 0, wreg = 0;
         gc_post_shape(job->orbits[j]->V, &block, &sp, &wreg);
+        const auto tp = ctx->tune_post.find(job->orbits[j]->V);
+        if (tp != ctx->tune_post.end()) {
+            block = tp->second.first;
+            sp = tp->second.second;
+            wreg = 1;
+        }
+        if (ctx->force_post_block > 0) {
+            block = ctx->force_post_block;
+            sp = ctx->force_post_sp;
+            wreg = 1;
+        }
         if (block == 0) return GC_EUNSUPPORTED;
         int k = 0;
         while (k < (int)L.posts.size() &&
@@ -584,12 +606,13 @@ void free_job(gc_ctx *ctx, Job *job)
     }
     if (job->ev_k0) (void)hipEventDestroy(job->ev_k0);
     if (job->ev_k1) (void)hipEventDestroy(job->ev_k1);
+    if (job->ev_k2) (void)hipEventDestroy(job->ev_k2);
     if (job->ev_done) (void)hipEventDestroy(job->ev_done);
     if (job->gx) (void)hipGraphExecDestroy(job->gx);
     if (job->g) (void)hipGraphDestroy(job->g);
     if (job->h_cnt) (void)hipHostFree(job->h_cnt);
     if (job->h_ncopies) (void)hipHostFree(job->h_ncopies);
-    job->ev_k0 = job->ev_k1 = job->ev_done = nullptr;
+    job->ev_k0 = job->ev_k1 = job->ev_k2 = job->ev_done = nullptr;
     job->gx = nullptr;
     job->g = nullptr;
     job->h_cnt = nullptr;
@@ -659,6 +682,7 @@ gc_status start_job(gc_ctx *ctx, Job *job)
     GC_HIP(hipHostMalloc((void **)&job->h_ncopies, sizeof(unsigned long long) * nj, hipHostMallocDefault));
     GC_HIP(hipEventCreate(&job->ev_k0));
     GC_HIP(hipEventCreate(&job->ev_k1));
+    GC_HIP(hipEventCreate(&job->ev_k2));
     GC_HIP(hipEventCreateWithFlags(&job->ev_done, hipEventDisableTiming));
     GC_HIP(hipMemcpyAsync(base + L.o_fixjobs, fixjobs.data(), sizeof(GcJobDev) * nj, hipMemcpyHostToDevice, s));
     // host staging must outlive the asynchronous copies (synchronised below)
@@ -731,6 +755,10 @@ gc_status start_job(gc_ctx *ctx, Job *job)
             e = gc_launch_post(pg.block, pg.sp, pg.wreg, (const GcJobDev *)(base + pg.o_jobs), (int)pg.jobs.size(),
                                (const uint64_t *)(base + pg.o_prefix), (unsigned long long *)(base + pg.o_next),
                                pg.total, nullptr, wbuf_of(pg), pg.wstride, pg.grid, pg.lds, qs);
+            if (e != hipSuccess) return e;
+        }
+        if (!job->graph) {
+            e = hipEventRecord(job->ev_k2, qs);
             if (e != hipSuccess) return e;
         }
         e = gc_launch_finalize(job->jobs.data(), nj, qs);
@@ -816,6 +844,7 @@ void complete_locked(gc_ctx *ctx, Job *job)
     job->t_done = Clock::now();
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, job->ev_k0, job->ev_k1) == hipSuccess) job->solve_ms = ms;
+    if (!job->graph && hipEventElapsedTime(&ms, job->ev_k1, job->ev_k2) == hipSuccess) job->post_ms = ms;
     job->state = GC_ORBIT_DONE;
     ctx->stream_load[job->stream]--;
     for (size_t j = 0; j < job->orbits.size(); ++j) {
@@ -1371,6 +1400,100 @@ gc_status gc_memory_info(gc_ctx *ctx, uint64_t *budget, uint64_t *in_use, uint64
     if (budget) *budget = ctx->budget;
     if (in_use) *in_use = ctx->used;
     if (queued) *queued = ctx->queued.size();
+    return GC_OK;
+}
+
+gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_solve_params *params,
+                      gc_tune_result *out)
+{
+    if (!ctx || n_starts == 0) return GC_EINVAL;
+    gc_solve_params p;
+    if (params) p = *params; else fill_defaults(&p);
+    gc_status st = check_params(&p);
+    if (st != GC_OK) return st;
+    int d = 0, V = 0, K = 0;
+    {
+        GC_ENTER(ctx);
+        Orbit *o = find_orbit(ctx, orbit);
+        if (!o) return GC_EINVAL;
+        if (o->job && (o->job->state == GC_ORBIT_QUEUED || o->job->state == GC_ORBIT_RUNNING)) return GC_EBUSY;
+        d = o->dev.d;
+        V = o->V;
+        K = o->dev.K;
+    }
+    const bool mixed = p.precision == GC_MIXED;
+    // one measured launch with the given forced variant: relax and post ms
+    auto trial = [&](int creg, int pb, int psp, double *relax_ms, double *post_ms) -> gc_status {
+        {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            ctx->force_creg = creg;
+            ctx->force_post_block = pb;
+            ctx->force_post_sp = psp;
+        }
+        gc_status s2 = gc_launch(ctx, orbit, n_starts, &p);
+        if (s2 == GC_OK) s2 = gc_wait(ctx, orbit, -1);
+        {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            ctx->force_creg = -1;
+            ctx->force_post_block = ctx->force_post_sp = 0;
+            if (s2 == GC_OK) {
+                Orbit *o = find_orbit(ctx, orbit);
+                *relax_ms = o->job->solve_ms;
+                *post_ms = o->job->post_ms;
+            }
+        }
+        return s2;
+    };
+    gc_tune_result r{};
+    const bool wave = (K == 2) && (size_t)(GC_WAVES + 1) * 16 * V <= ctx->lds_max;
+    const int ns = (V / 2 + 63) / 64;
+    const int cmax = wave ? gc_wave_creg_max(d, ns) : 0;
+    double rm = 0, pm = 0;
+    st = trial(0, 0, 0, &rm, &pm);   // warm-up: code objects, pool
+    if (st != GC_OK) return st;
+    // relax: register-coefficient colours 0..cmax, best of two launches each
+    int best_c = 0;
+    double best_r = INFINITY;
+    for (int c = 0; c <= cmax; ++c) {
+        double t = INFINITY;
+        for (int rep = 0; rep < 2; ++rep) {
+            st = trial(c, 0, 0, &rm, &pm);
+            if (st != GC_OK) return st;
+            t = std::min(t, rm);
+        }
+        if (t < best_r) { best_r = t; best_c = c; }
+    }
+    // post: every instantiated register-weight shape with at most 4 sites per
+    // thread that covers V without quadrupling it
+    static const int shapes[][2] = {{64, 1}, {64, 2}, {64, 4}, {128, 2}, {128, 4}, {256, 1},
+                                    {256, 2}, {256, 4}, {384, 4}};
+    int best_b = 0, best_sp = 0;
+    double best_p = INFINITY;
+    int db = 0, dsp = 0, dw = 0;
+    gc_post_shape(V, &db, &dsp, &dw);
+    for (const auto &sh : shapes) {
+        const long cover = (long)sh[0] * sh[1];
+        if (cover < V || cover >= 4L * V) continue;
+        if (!dw) continue;   // large lattices keep the global-memory variant
+        double t = INFINITY;
+        for (int rep = 0; rep < 2; ++rep) {
+            st = trial(best_c, sh[0], sh[1], &rm, &pm);
+            if (st != GC_OK) return st;
+            t = std::min(t, pm);
+        }
+        if (t < best_p) { best_p = t; best_b = sh[0]; best_sp = sh[1]; }
+    }
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        if (wave) ctx->tune_creg[creg_key(d, ns, mixed)] = best_c;
+        if (best_b) ctx->tune_post[V] = std::make_pair(best_b, best_sp);
+    }
+    r.relax_variant = best_c;
+    r.relax_ms = best_r;
+    r.post_block = best_b ? best_b : db;
+    r.post_sites_per_thread = best_b ? best_sp : dsp;
+    r.post_ms = best_b ? best_p : pm;
+    if (out) *out = r;
     return GC_OK;
 }
 
