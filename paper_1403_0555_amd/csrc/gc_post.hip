@@ -784,6 +784,7 @@ void gc_post_shape(int V, int *block, int *sp, int *wreg)
     if (block == 128 && sp == 2 && wreg) return FN<128, 2, true>(__VA_ARGS__);      \
     if (block == 256 && sp == 1 && wreg) return FN<256, 1, true>(__VA_ARGS__);      \
     if (block == 256 && sp == 2 && wreg) return FN<256, 2, true>(__VA_ARGS__);      \
+    if (block == 512 && sp == 2 && wreg) return FN<512, 2, true>(__VA_ARGS__);      \
     if (block == 128 && sp == 4 && wreg) return FN<128, 4, true>(__VA_ARGS__);      \
     if (block == 256 && sp == 4 && wreg) return FN<256, 4, true>(__VA_ARGS__);      \
     if (block == 384 && sp == 4 && wreg) return FN<384, 4, true>(__VA_ARGS__);      \

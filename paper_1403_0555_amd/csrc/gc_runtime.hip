@@ -1465,8 +1465,8 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
     }
     // post: every instantiated register-weight shape with at most 4 sites per
     // thread that covers V without quadrupling it
-    static const int shapes[][2] = {{64, 1}, {64, 2}, {64, 4}, {128, 2}, {128, 4}, {256, 1},
-                                    {256, 2}, {256, 4}, {384, 4}};
+    static const int shapes[][2] = {{64, 1},  {64, 2},  {64, 4},  {128, 2}, {128, 4}, {256, 1}, {256, 2},
+                                    {256, 4}, {384, 4}, {512, 2}};
     int best_b = 0, best_sp = 0;
     double best_p = INFINITY;
     int db = 0, dsp = 0, dw = 0;
