@@ -38,8 +38,8 @@ def flops_per_site_update(d: int) -> int:
 # on a plain device copy of known size.  Valid only for the kernel sources
 # they were taken on (SHA-256 of the relax sources below); otherwise null.
 RELAX_SOURCES = ("gc_wave.hip", "gc_wave.h", "gc_common.h")
-TRAFFIC = {"sources_sha256": "4092be7212fcda32916b767093bcccaaee007e4174af8158054e05f2b2f695f9",
-           "bytes_per_launch": 429505728}
+TRAFFIC = {"sources_sha256": "98f0081bdf549e08621d1747750f25a225ae1d1a25949fca2e13c369eb9637b7",
+           "bytes_per_launch": 429401206}
 
 
 def relax_sources_sha256() -> str:
@@ -259,8 +259,9 @@ def main():
     h = ctx.gc_orbit_load(w.extent, phi, w.orbit_index)
     tune = None
     if not args.no_tune:
-        # kernel variants for this shape, chosen on a sample before timing
-        tune = ctx.gc_autotune(h, min(n, 20000), params)
+        # kernel variants for this shape, chosen before timing on launches
+        # of the same size as the timed ones
+        tune = ctx.gc_autotune(h, n, params)
         print("autotune: %s" % tune, file=sys.stderr, flush=True)
 
     def step():
