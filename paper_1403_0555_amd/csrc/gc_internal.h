@@ -106,6 +106,7 @@ struct GcJobDev {
     double2 *states;                 // [n_starts][V] final g of every start, natural site order
     GcFix *fix;                      // [n_starts] representatives to filter
     unsigned long long *n_fix;
+    uint32_t *blk;                   // [(table_mask + 1) / 256] per-block copy counts, then offsets
 };
 
 static_assert(sizeof(GcStartRec) == 64, "record layout");

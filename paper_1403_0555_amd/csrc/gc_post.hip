@@ -23,6 +23,14 @@ namespace {
 
 using namespace gc;
 
+// Home slot of a key: the top bits of key_hi (uniformly distributed), so
+// that table order is key order up to the displacement of linear probing.
+__device__ __forceinline__ uint64_t table_home(uint64_t key_hi, uint64_t mask)
+{
+    const int b = __popcll(mask);
+    return b ? (key_hi >> (64 - b)) : 0;
+}
+
 // Insert a key (one lane).  A new key is claimed by CAS on its high word; the
 // claimer then writes the low word, which is never zero, so zero means "not
 // written yet" to a start that finds the high word.  Only relaxed atomics are
@@ -37,7 +45,7 @@ __device__ void table_insert(const GcJobDev &J, uint64_t key_hi, uint64_t key_lo
     is_min = false;
     failed = true;
     const uint64_t mask = J.table_mask;
-    uint64_t idx = (key_hi ^ (key_hi >> 29)) & mask;
+    uint64_t idx = table_home(key_hi, mask);
     const uint64_t fbits = (uint64_t)__double_as_longlong(F);
     for (uint64_t probe = 0; probe <= mask; ++probe) {
         GcEntry *e = &J.table[idx];
@@ -76,7 +84,7 @@ __device__ void table_insert(const GcJobDev &J, uint64_t key_hi, uint64_t key_lo
 __device__ GcEntry *table_find(const GcJobDev &J, uint64_t key_hi, uint64_t key_lo)
 {
     const uint64_t mask = J.table_mask;
-    uint64_t idx = (key_hi ^ (key_hi >> 29)) & mask;
+    uint64_t idx = table_home(key_hi, mask);
     for (uint64_t probe = 0; probe <= mask; ++probe) {
         GcEntry *e = &J.table[idx];
         if (e->key_hi == 0) return nullptr;
@@ -634,47 +642,89 @@ __global__ void rep_kernel(GcJobDev J)
     }
 }
 
-__global__ void compact_kernel(GcJobDev J)
+// Ordered compaction of the table into the copy list, in three passes
+// over blocks of 256 slots: count the occupied slots of each block, scan the
+// counts, scatter each block's copies in slot order.
+
+__global__ __launch_bounds__(256) void count_kernel(GcJobDev J)
 {
-    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const double dV = (double)J.orb.d * (double)J.orb.V;
-    for (uint64_t t = gid; t <= J.table_mask; t += stride) {
-        const GcEntry e = J.table[t];
-        if (e.key_hi == 0) continue;
-        const uint64_t rep = e.rep_start;
-        const GcStartRec r = J.rec[rep - J.first_start];
-        GcCopyRec c;
-        c.key_hi = e.key_hi;
-        c.key_lo = e.key_lo;
-        c.F = r.F;
-        c.x = r.F / dV;
-        c.hits = e.hits;
-        c.first_start = e.first_start;
-        const double fmin = __longlong_as_double((long long)e.fmin_bits);
-        const double fmax = __longlong_as_double((long long)e.fmax_bits);
-        const uint32_t col = ((fmax - fmin) / (double)J.orb.V > GC_F_SPREAD_PER_SITE) ? GC_F_COLLISION : 0u;
-        const unsigned long long slot = atomicAdd(J.n_copies, 1ULL);
-        if (rep == e.first_start) {
-            // the lowest start ran the filter when it was inserted
-            c.lambda2 = r.lambda2;
-            c.flags = (r.flags & (GC_F_IN_REGION | GC_F_SINGULAR | GC_F_SADDLE | GC_F_LANCZOS_CAP | GC_F_KEY_OVERFLOW)) | col;
-            c.lanczos_iters = r.lanczos_iters;
-        } else {
-            c.lambda2 = NAN;
-            c.flags = col | (r.flags & GC_F_KEY_OVERFLOW);
-            c.lanczos_iters = 0;
-            const unsigned long long k = atomicAdd(J.n_fix, 1ULL);
-            GcFix f;
-            f.start = rep;
-            f.slot = slot;
-            f.lambda2 = NAN;
-            f.flags = 0;
-            f.lanczos_iters = 0;
-            J.fix[k] = f;
+    const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    const int occ = (t <= J.table_mask && J.table[t].key_hi != 0) ? 1 : 0;
+    const int n = __syncthreads_count(occ);
+    if (threadIdx.x == 0) J.blk[blockIdx.x] = (uint32_t)n;
+}
+
+// One workgroup: exclusive scan of the block counts in chunks of 1024, the
+// total into n_copies.
+__global__ __launch_bounds__(1024) void scan_kernel(GcJobDev J, uint32_t nblk)
+{
+    __shared__ uint32_t buf[1024];
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < nblk; base += 1024) {
+        const uint32_t k = base + threadIdx.x;
+        const uint32_t v = k < nblk ? J.blk[k] : 0u;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint32_t add = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0u;
+            __syncthreads();
+            buf[threadIdx.x] += add;
+            __syncthreads();
         }
-        J.copies[slot] = c;
+        if (k < nblk) J.blk[k] = carry + buf[threadIdx.x] - v;
+        carry += buf[1023];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *J.n_copies = carry;
+}
+
+__global__ __launch_bounds__(256) void scatter_kernel(GcJobDev J)
+{
+    __shared__ uint32_t wave_off[4];
+    const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool occ = t <= J.table_mask && J.table[t].key_hi != 0;
+    const uint64_t ball = __ballot(occ);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t below = (uint32_t)__popcll(ball & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_off[wave] = (uint32_t)__popcll(ball);
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int w = 0; w < wave; ++w) pre += wave_off[w];
+    if (!occ) return;
+    const uint64_t slot = (uint64_t)J.blk[blockIdx.x] + pre + below;
+    const double dV = (double)J.orb.d * (double)J.orb.V;
+    const GcEntry e = J.table[t];
+    const uint64_t rep = e.rep_start;
+    const GcStartRec r = J.rec[rep - J.first_start];
+    GcCopyRec c;
+    c.key_hi = e.key_hi;
+    c.key_lo = e.key_lo;
+    c.F = r.F;
+    c.x = r.F / dV;
+    c.hits = e.hits;
+    c.first_start = e.first_start;
+    const double fmin = __longlong_as_double((long long)e.fmin_bits);
+    const double fmax = __longlong_as_double((long long)e.fmax_bits);
+    const uint32_t col = ((fmax - fmin) / (double)J.orb.V > GC_F_SPREAD_PER_SITE) ? GC_F_COLLISION : 0u;
+    if (rep == e.first_start) {
+        // the lowest start ran the filter when it was inserted
+        c.lambda2 = r.lambda2;
+        c.flags = (r.flags & (GC_F_IN_REGION | GC_F_SINGULAR | GC_F_SADDLE | GC_F_LANCZOS_CAP | GC_F_KEY_OVERFLOW)) | col;
+        c.lanczos_iters = r.lanczos_iters;
+    } else {
+        c.lambda2 = NAN;
+        c.flags = col | (r.flags & GC_F_KEY_OVERFLOW);
+        c.lanczos_iters = 0;
+        const unsigned long long k = atomicAdd(J.n_fix, 1ULL);
+        GcFix f;
+        f.start = rep;
+        f.slot = slot;
+        f.lambda2 = NAN;
+        f.flags = 0;
+        f.lanczos_iters = 0;
+        J.fix[k] = f;
+    }
+    J.copies[slot] = c;
 }
 
 constexpr uint32_t kFilterFlags = GC_F_IN_REGION | GC_F_SINGULAR | GC_F_SADDLE | GC_F_LANCZOS_CAP;
@@ -838,7 +888,14 @@ hipError_t gc_launch_finalize(const GcJobDev *jobs_host, int n_jobs, hipStream_t
         hipLaunchKernelGGL(rep_kernel, dim3(grid_for(J.n_starts)), dim3(256), 0, s, J);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(compact_kernel, dim3(grid_for(J.table_mask + 1)), dim3(256), 0, s, J);
+        const uint32_t nblk = (uint32_t)((J.table_mask + 1 + 255) / 256);
+        hipLaunchKernelGGL(count_kernel, dim3(nblk), dim3(256), 0, s, J);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, J, nblk);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(scatter_kernel, dim3(nblk), dim3(256), 0, s, J);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -441,7 +441,7 @@ struct PostGroup {
 
 // Device memory of one job.
 struct JobLayout {
-    std::vector<size_t> o_rec, o_table, o_cnt, o_copies, o_ncopies, o_fix, o_nfix, o_states;
+    std::vector<size_t> o_rec, o_table, o_cnt, o_copies, o_ncopies, o_fix, o_nfix, o_states, o_blk;
     std::vector<uint64_t> table_cap;
     std::vector<Group> groups;
     std::vector<PostGroup> posts;
@@ -472,6 +472,7 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         L.o_ncopies.push_back(place(sizeof(unsigned long long)));
         L.o_fix.push_back(place(sizeof(GcFix) * n));
         L.o_nfix.push_back(place(sizeof(unsigned long long)));
+        L.o_blk.push_back(place(sizeof(uint32_t) * ((cap + 255) / 256)));
         L.o_states.push_back(place(sizeof(double2) * n * (uint64_t)o->V));
         maxV = std::max(maxV, o->V);
         maxd = std::max(maxd, o->d);
@@ -673,6 +674,7 @@ gc_status start_job(gc_ctx *ctx, Job *job)
         J.states = (double2 *)(base + L.o_states[j]);
         J.fix = (GcFix *)(base + L.o_fix[j]);
         J.n_fix = (unsigned long long *)(base + L.o_nfix[j]);
+        J.blk = (uint32_t *)(base + L.o_blk[j]);
         prefix.push_back(prefix.back() + job->n_starts[j]);
     }
     job->total = prefix.back();
@@ -1022,14 +1024,25 @@ gc_status ensure_copies_locked(gc_ctx *ctx, Orbit *o)
     if (o->have_copies) return GC_OK;
     Job *job = o->job;
     const uint64_t n = job->h_ncopies[o->job_index];
-    std::vector<GcCopyRec> raw(n);
-    if (n) GC_HIP(hipMemcpy(raw.data(), o->res.copies, n * sizeof(GcCopyRec), hipMemcpyDeviceToHost));
-    o->copies.resize(n);
     static_assert(sizeof(GcCopyRec) == sizeof(gc_copy), "copy layout");
-    if (n) memcpy(o->copies.data(), raw.data(), n * sizeof(gc_copy));
-    std::sort(o->copies.begin(), o->copies.end(), [](const gc_copy &a, const gc_copy &b) {
+    // the copies come in table order, which is key_hi order except where
+    // linear probing displaced an entry (past its successors, or around the
+    // end of the table): an insertion pass finishes the sort by key
+    o->copies.resize(n);
+    if (n) GC_HIP(hipMemcpy(o->copies.data(), o->res.copies, n * sizeof(gc_copy), hipMemcpyDeviceToHost));
+    auto less = [](const gc_copy &a, const gc_copy &b) {
         return a.key_hi != b.key_hi ? a.key_hi < b.key_hi : a.key_lo < b.key_lo;
-    });
+    };
+    for (uint64_t k = 1; k < n; ++k) {
+        if (!less(o->copies[k], o->copies[k - 1])) continue;
+        const gc_copy v = o->copies[k];
+        uint64_t m = k;
+        while (m > 0 && less(v, o->copies[m - 1])) {
+            o->copies[m] = o->copies[m - 1];
+            --m;
+        }
+        o->copies[m] = v;
+    }
     uint64_t inr = 0, sad = 0, sng = 0, col = 0;
     for (const gc_copy &c : o->copies) {
         if (c.flags & GC_FLAG_IN_REGION) ++inr;
