@@ -153,7 +153,7 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
     uint64_t t = 0;
     uint64_t until = check;      // sweeps left to the next check point
     bool ckpt = false;           // the state after sweep t is checked
-    double acc1 = 0.0;           // colour-1 part of the norm of sweep t
+    double part1 = 0.0;          // this lane's colour-1 part of the norm of sweep t
     int status = GC_ST_NONCONVERGED;
     D_out = INFINITY;
     for (;;) {
@@ -180,7 +180,10 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
             gnew[k] = local_update<RELAX, R>(g0, s, omega);
         }
         if (pending) {
-            const double Dn = maxabs ? fmax(wave_max(acc0), acc1) : (wave_sum(acc0) + acc1) / (double)(2 * half);
+            // one wave reduction per checked sweep, over both colours' lane parts
+            double Dn;
+            if (maxabs) Dn = wave_max(fmax(acc0, part1));
+            else Dn = wave_sum(acc0 + part1) / (double)(2 * half);
             D_out = Dn;
             if (!(Dn == Dn)) { status = GC_ST_BADNUM; break; }
             if (Dn < eps) { status = GC_ST_CONVERGED; break; }
@@ -218,7 +221,7 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
             const double a = maxabs ? fmax(a1, fabs(dv)) : a1 + dv * dv;
             a1 = valid[k] ? a : a1;
         }
-        if (chk) acc1 = maxabs ? wave_max(a1) : wave_sum(a1);
+        if (chk) part1 = a1;
         wave_sync();
     }
     sweeps = t;
