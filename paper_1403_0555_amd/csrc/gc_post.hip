@@ -375,32 +375,36 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
             const uint64_t c0 = 0x243F6A8885A308D3ULL, c1 = 0x13198A2E03707344ULL;
             uint64_t h0 = 0, h1 = 0;
             int overflow = 0;
-            for (int k = tid; k < O.n_elems; k += B) {
-                double val;
-                if (k < O.n_plaq) {
-                    const int pl = k / V, i = k - pl * V;
-                    const int mu = O.plane_mu[pl], nu = O.plane_nu[pl];
+            // one element: its wrap number e into both hash lanes
+            auto fold = [&](int k, double val) {
+                const int e = (int)val;
+                if (e < -128 || e > 127) overflow = 1;
+                const uint64_t word = ((uint64_t)k << 8) | (uint64_t)(uint8_t)(int8_t)e;
+                h0 += mix64(c0 ^ word);
+                h1 += mix64(c1 ^ word);
+            };
+            // plaquettes: planes in order (uniform), sites across the threads
+            for (int pl = 0; pl < O.n_plaq / V; ++pl) {
+                const int mu = O.plane_mu[pl], nu = O.plane_nu[pl];
+                for (int i = tid; i < V; i += B) {
                     const int fm = O.nbr[mu * V + i], fn = O.nbr[nu * V + i];
                     const double A = (double)a32[mu * V + i] + (double)a32[nu * V + fm] - (double)a32[mu * V + fn] -
                                      (double)a32[nu * V + i];
-                    val = rint((A - O.phi_plaq[k]) / kTwoPi);
-                } else {
-                    const int q = k - O.n_plaq;
-                    int mu = 0;
-                    while (q >= O.line_off[mu + 1]) ++mu;
+                    const int k = pl * V + i;
+                    fold(k, rint((A - O.phi_plaq[k]) / kTwoPi));
+                }
+            }
+            // line windings: lines of direction mu in order
+            for (int mu = 0; mu < d; ++mu) {
+                for (int q = O.line_off[mu] + tid; q < O.line_off[mu + 1]; q += B) {
                     int i = O.line_site[q];
                     double acc = 0.0;
                     for (int t = 0; t < O.ext[mu]; ++t) {
                         acc += (double)a32[mu * V + i];
                         i = O.nbr[mu * V + i];
                     }
-                    val = rint((acc - O.phi_line[q]) / kTwoPi);
+                    fold(O.n_plaq + q, rint((acc - O.phi_line[q]) / kTwoPi));
                 }
-                const int e = (int)val;
-                if (e < -128 || e > 127) overflow = 1;
-                const uint64_t word = ((uint64_t)k << 8) | (uint64_t)(uint8_t)(int8_t)e;
-                h0 += mix64(c0 ^ word);
-                h1 += mix64(c1 ^ word);
             }
             h0 = wg_sum_u64<B>(h0, ured, uph);
             h1 = wg_sum_u64<B>(h1, ured, uph);
