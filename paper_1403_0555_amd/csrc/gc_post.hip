@@ -211,13 +211,24 @@ __device__ int sturm_count(lds_cdouble *alpha, lds_cdouble *beta2, int k, double
 }
 
 // Smallest eigenvalue of the tridiagonal by (B+1)-section inside [lo, hi]
-// (count(lo) = 0, count(hi) >= 1).
+// (count(lo) = 0, count(hi) >= 1).  Unless final (or the workgroup is a
+// single wave, whose rounds are cheap), the search stops early when the
+// eigenvalue lies more than 1e6 tol_rel max(1, |theta|) below prev
+// (the previous check's upper bound) and the bracket is small against that
+// distance: the convergence test then fails whatever the remaining digits
+// are.  hi_out receives the final upper end, a guaranteed upper bound.
 template <int B>
 __device__ double tridiag_min_eig(lds_cdouble *alpha, lds_cdouble *beta2, int k, double lo, double hi, int *ired,
-                                  int &iph)
+                                  int &iph, double prev, double tol_rel, bool final, double &hi_out)
 {
     for (int round = 0; round < 24; ++round) {
         if (hi - lo <= 1e-15 * fmax(1.0, fabs(hi))) break;
+        if (!final && B > 64) {   // a round costs barriers only for several waves
+            const double gap = prev - hi, scale = fmax(1.0, fabs(hi));
+            const bool fails = gap > 1e6 * tol_rel * scale;   // far from converging
+            const double need = (prev < INFINITY) ? 0.05 * gap : 1e-4 * scale;
+            if (fails && hi - lo <= need) break;
+        }
         const double step = (hi - lo) / (double)(B + 1);
         const double x = lo + step * (double)(threadIdx.x + 1);
         const int first = wg_min_int<B>(sturm_count(alpha, beta2, k, x) >= 1 ? (int)threadIdx.x : B, ired, iph);
@@ -226,15 +237,17 @@ __device__ double tridiag_min_eig(lds_cdouble *alpha, lds_cdouble *beta2, int k,
         lo = nlo;
         hi = nhi;
     }
+    hi_out = hi;
     return 0.5 * (lo + hi);
 }
 
 // Smallest Ritz value of the k x k tridiagonal, inside the Gershgorin
 // interval [glo, ghi].  By interlacing it never increases as k grows, so the
-// previous value bounds it above; a window below it is tried first.
+// previous check's upper bound prev bounds it above; a window below it is
+// tried first.
 template <int B>
 __device__ double ritz_min(lds_cdouble *alpha, lds_cdouble *beta2, int k, double glo, double ghi, double prev,
-                           double prev_step, int *ired, int &iph)
+                           double prev_step, int *ired, int &iph, double tol_rel, bool final, double &hi_out)
 {
     double lo = glo - 1e-12 * (1.0 + fabs(glo));
     double hi = ghi + 1e-12 * (1.0 + fabs(ghi));
@@ -243,10 +256,10 @@ __device__ double ritz_min(lds_cdouble *alpha, lds_cdouble *beta2, int k, double
         const double bot = top - fmax(4.0 * prev_step, 1e-9 * (1.0 + fabs(prev)));
         const bool top_ok = sturm_count(alpha, beta2, k, top) >= 1;
         if (top_ok && bot > lo && sturm_count(alpha, beta2, k, bot) == 0)
-            return tridiag_min_eig<B>(alpha, beta2, k, bot, top, ired, iph);
+            return tridiag_min_eig<B>(alpha, beta2, k, bot, top, ired, iph, prev, tol_rel, final, hi_out);
         if (top_ok) hi = top;
     }
-    return tridiag_min_eig<B>(alpha, beta2, k, lo, hi, ired, iph);
+    return tridiag_min_eig<B>(alpha, beta2, k, lo, hi, ired, iph, prev, tol_rel, final, hi_out);
 }
 
 __device__ uint32_t region_flags(double lam2, double tol)
@@ -539,9 +552,14 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                 const bool breakdown = b_j <= 1e-13 * sigma;
                 if (it + 1 >= next_check || breakdown || it + 1 == lmax) {
                     __syncthreads();   // the tridiagonal is complete in LDS
+                    const bool final = breakdown || it + 1 == lmax;
+                    double theta_hi;
                     theta = ritz_min<B>(alpha, beta2, it + 1, fmin(rows_lo, a_j - beta_prev),
-                                        fmax(rows_hi, a_j + beta_prev), theta_old, theta_step, ired, iph);
+                                        fmax(rows_hi, a_j + beta_prev), theta_old, theta_step, ired, iph, 1e-12,
+                                        final, theta_hi);
                     const double tol = 1e-12 * fmax(1.0, fabs(theta));
+                    // theta_old is an upper bound of the previous value, so this
+                    // change is at least the true one
                     const double change = theta_old - theta;
                     if (breakdown || fabs(change) <= tol) {
                         conv = true;
@@ -553,7 +571,7 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                     const int gap = !(change <= 1e6 * tol) ? 24 : !(change <= 1e3 * tol) ? 16 : 8;
                     next_check = it + 1 + gap;
                     if (theta_old < INFINITY) theta_step = change;
-                    theta_old = theta;
+                    theta_old = theta_hi;
                 }
                 // row it of T now has both neighbours: into the Gershgorin bounds
                 rows_lo = fmin(rows_lo, a_j - beta_prev - b_j);
