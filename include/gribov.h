@@ -248,6 +248,17 @@ gc_status gc_memory_info(gc_ctx *ctx, uint64_t *budget, uint64_t *in_use, uint64
  * measured with HIP events on the stream the kernel ran on. */
 gc_status gc_kernel_time_ms(gc_ctx *ctx, gc_orbit orbit, double *solve_ms);
 
+/* Saturation curve of a completed launch (Sec. III and Figs. 1-3: the
+ * number of distinct copies found as the number of random starts grows).
+ * For each of the n_points sample sizes N, distinct_out receives the number
+ * of copies whose lowest start id lies within the first N starts of the
+ * launch (ids first_start .. first_start + N - 1); in_region_only != 0
+ * counts only copies flagged GC_FLAG_IN_REGION.  Computed on the host from
+ * the fetched copy table.  Caller owns both arrays.  Errors: GC_EINVAL,
+ * GC_ESTATE (no completed launch). */
+gc_status gc_saturation(gc_ctx *ctx, gc_orbit orbit, int32_t n_points, const uint64_t *sample_sizes,
+                        int32_t in_region_only, uint64_t *distinct_out);
+
 /* Result of gc_autotune. */
 typedef struct {
     int32_t relax_variant;          /* colours whose coefficients a lane keeps in registers (0..2) */

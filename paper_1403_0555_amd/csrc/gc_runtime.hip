@@ -1301,6 +1301,29 @@ gc_status gc_wait(gc_ctx *ctx, gc_orbit orbit, int64_t timeout_ms)
     return wait_locked(ctx, lk, o, timeout_ms);
 }
 
+gc_status gc_saturation(gc_ctx *ctx, gc_orbit orbit, int32_t n_points, const uint64_t *sample_sizes,
+                        int32_t in_region_only, uint64_t *distinct_out)
+{
+    if (n_points < 0 || (n_points > 0 && (!sample_sizes || !distinct_out))) return GC_EINVAL;
+    GC_ENTER(ctx);
+    Orbit *o = find_orbit(ctx, orbit);
+    if (!o) return GC_EINVAL;
+    if (!o->job || o->job->state != GC_ORBIT_DONE) return GC_ESTATE;
+    gc_status st = ensure_copies_locked(ctx, o);
+    if (st != GC_OK) return st;
+    // a copy is found within the first N starts of the launch iff the lowest
+    // start id reaching it is below first_start + N
+    const uint64_t base = o->job->p.first_start;
+    std::vector<uint64_t> first;
+    first.reserve(o->copies.size());
+    for (const gc_copy &c : o->copies)
+        if (!in_region_only || (c.flags & GC_FLAG_IN_REGION)) first.push_back(c.first_start - base);
+    std::sort(first.begin(), first.end());
+    for (int32_t k = 0; k < n_points; ++k)
+        distinct_out[k] = (uint64_t)(std::lower_bound(first.begin(), first.end(), sample_sizes[k]) - first.begin());
+    return GC_OK;
+}
+
 gc_status gc_fetch(gc_ctx *ctx, gc_orbit orbit, uint64_t offset, uint64_t cap, gc_copy *out, uint64_t *n_written,
                    uint64_t *n_total)
 {

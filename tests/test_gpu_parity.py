@@ -359,3 +359,24 @@ def test_batch_equals_single_launches(ctx):
         assert np.array_equal(s["sweeps64"], singles[k][1]["sweeps64"])
         assert np.max(np.abs(c["F"] - singles[k][0]["F"])) < 1e-12
         ctx.gc_release(hs[k])
+
+
+def test_saturation_curve_matches_oracle(ctx):
+    """Distinct copies within the first 2^k starts (the paper's saturation
+    curves), from the table's lowest start ids, against the oracle's table."""
+    extent = (4, 4, 4)
+    phi = GI.orbit_angles(extent, 3, 1)
+    p = gc.SolveParams(omega=1.7, first_start=1000)
+    h, copies, starts, _ = run_gpu(ctx, extent, phi, 3000, p, orbit_index=1)
+    o = O.enumerate_copies(extent, phi, 1000 + np.arange(3000), oracle_params(p, 1))
+    sizes = [1, 2, 4, 16, 64, 256, 1024, 2048, 3000]
+    got = ctx.gc_saturation(h, sizes)
+    got_in = ctx.gc_saturation(h, sizes, in_region_only=True)
+    firsts = np.array([e["first_start"] - 1000 for e in o["table"].values()])
+    firsts_in = np.array([e["first_start"] - 1000 for e in o["table"].values() if e["flags"] & O.FLAG_IN_REGION])
+    for n, g, gi in zip(sizes, got, got_in):
+        assert int(g) == int(np.sum(firsts < n)), n
+        assert int(gi) == int(np.sum(firsts_in < n)), n
+    assert int(got[-1]) == len(o["table"])
+    assert np.all(np.diff(got.astype(np.int64)) >= 0)
+    ctx.gc_release(h)
