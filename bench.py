@@ -51,10 +51,14 @@ def relax_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def relax_kernel_name(extent) -> str:
+def relax_kernel_name(extent, tune) -> str:
     V = int(np.prod(extent))
     if all(e % 2 == 0 for e in extent):
-        return "wave_kernel<%d, %d, 4, ...>" % (len(extent), (V // 2 + 63) // 64)
+        ns = (V // 2 + 63) // 64
+        if ns <= 2 or not (tune and tune["relax_variant"] & 8):
+            return "wave_kernel<%d, %d, 4, ...>" % (len(extent), min(ns, 32))
+        wps = next(w for w in (2, 4, 6, 8, 16) if 2 * w >= ns)
+        return "wps_kernel<%d, %d>" % (len(extent), wps)
     return "relax_wg_kernel<...>"
 
 
@@ -324,7 +328,7 @@ def main():
         "solve_kernel_ms": float(np.mean(kms)),
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved_tflops / peak, "traffic": traffic,
-                     "kernel": relax_kernel_name(w.extent), "kernel_ms": float(np.mean(kms)),
+                     "kernel": relax_kernel_name(w.extent, tune), "kernel_ms": float(np.mean(kms)),
                      "flops_per_site_update": fl, "site_updates_per_launch": upd_per_launch},
     }
     if not args.no_cpu:

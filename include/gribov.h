@@ -261,7 +261,8 @@ gc_status gc_saturation(gc_ctx *ctx, gc_orbit orbit, int32_t n_points, const uin
 
 /* Result of gc_autotune. */
 typedef struct {
-    int32_t relax_variant;          /* colours whose coefficients a lane keeps in registers (0..2) */
+    int32_t relax_variant;          /* colours whose coefficients a lane keeps in registers (0..2), plus 8
+                                       when a workgroup of several wavefronts shares each start */
     int32_t post_block;             /* post kernel: threads per workgroup */
     int32_t post_sites_per_thread;
     int32_t pad;
@@ -271,8 +272,10 @@ typedef struct {
 /* Kernel-variant autotuner for the shape of this orbit (Sec. III sweeps and
  * the first-region filter; the variants compute the same quantities).  Runs
  * timed launches of n_starts starts with params on the orbit, synchronously:
- * a warm-up, then each relax variant (coefficients of 0, 1 or 2 colours held
- * in registers where a lane has at most two slots) and each post-kernel
+ * a warm-up, then each relax variant (for lattices with more than two slots
+ * per lane: one wavefront or a workgroup per start; coefficients of 0, 1 or
+ * 2 colours held in registers where a lane has at most two slots) and each
+ * post-kernel
  * workgroup shape that covers V, two launches each, timed with HIP events.
  * The fastest choices are stored in the context and used by every later
  * launch of an orbit with the same dimension, slots per lane and precision

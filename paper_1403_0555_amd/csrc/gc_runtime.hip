@@ -191,12 +191,14 @@ struct gc_ctx {
     int n_cu = 0;
     size_t lds_max = 0;
     int creg_override = -1;   // GC_WAVE_CREG: register-held coefficient colours (tuning)
+    int wps_override = -1;    // GC_WPS: 1 workgroup per start where available, 0 never (tuning)
     // kernel variants chosen by gc_autotune: relax coefficient colours per
     // (d, slots per lane, precision), post workgroup shape per V; and the
     // variant forced while gc_autotune measures
     std::map<uint64_t, int> tune_creg;
+    std::map<uint64_t, int> tune_wps;   // workgroup-per-start layout on (1) or off (0)
     std::map<int, std::pair<int, int>> tune_post;
-    int force_creg = -1, force_post_block = 0, force_post_sp = 0;
+    int force_creg = -1, force_post_block = 0, force_post_sp = 0, force_wps = -1;
     uint64_t budget = 0, used = 0;
     std::vector<hipStream_t> streams;
     std::vector<int> stream_load;
@@ -423,7 +425,7 @@ struct Group {
     bool wave = false;
     int d = 0;
     std::vector<int> jobs;           // indices into Job::orbits
-    int block = 64, grid = 1, ns = 1, coef_lds = 0, creg = 0;
+    int block = 64, grid = 1, ns = 1, coef_lds = 0, creg = 0, wps = 0;
     size_t lds = 0;
     size_t o_jobs = 0, o_worbs = 0, o_next = 0, o_prefix = 0, o_bounce = 0;
     uint64_t total = 0;
@@ -477,20 +479,37 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         maxV = std::max(maxV, o->V);
         maxd = std::max(maxd, o->d);
         total += n;
-        // two colours: one wavefront per start, GC_WAVES states per workgroup
-        // in LDS; lattices too large for that take the workgroup kernel
-        const bool wave = (o->K == 2) && (size_t)(GC_WAVES + 1) * 16 * o->V <= ctx->lds_max;
-        // wave groups by dimension; workgroup-kernel groups by block size, so
-        // that an orbit's reductions run in the same order alone and batched
+        // two colours: one wavefront per start (GC_WAVES states per
+        // workgroup in LDS) up to 128 slots per colour, a workgroup of wps
+        // wavefronts per start above; other colourings take the generic
+        // workgroup kernel
+        const int o_ns = (o->V / 2 + 63) / 64;
+        int wps = (o->K == 2) ? gc_wps_for(o_ns) : -1;
+        if (wps > 0 && (size_t)(GC_WAVES + 1) * 16 * o->V <= ctx->lds_max) {
+            // both layouts fit: one wavefront per start unless tuned otherwise
+            int on = 0;
+            const auto tw = ctx->tune_wps.find(creg_key(o->d, o_ns, job->p.precision == GC_MIXED));
+            if (tw != ctx->tune_wps.end()) on = tw->second;
+            if (ctx->wps_override >= 0) on = ctx->wps_override;
+            if (ctx->force_wps >= 0) on = ctx->force_wps;
+            if (!on) wps = 0;
+        }
+        if (wps > 0 && 32 * (size_t)o->V > ctx->lds_max) wps = -1;
+        const bool wave = (o->K == 2) && wps >= 0 && (wps > 0 || (size_t)(GC_WAVES + 1) * 16 * o->V <= ctx->lds_max);
+        // groups by dimension and wavefronts per start, or (generic) by
+        // block size, so that an orbit's reductions run in the same order
+        // alone and batched
         const int gd = wave ? o->d : -block_for(o->V);
+        const int gw = wave ? std::max(wps, 0) : 0;
         Group *g = nullptr;
         for (Group &x : L.groups)
-            if (x.wave == wave && x.d == gd) g = &x;
+            if (x.wave == wave && x.d == gd && x.wps == gw) g = &x;
         if (!g) {
             L.groups.push_back(Group{});
             g = &L.groups.back();
             g->wave = wave;
             g->d = gd;
+            g->wps = gw;
         }
         g->jobs.push_back(j);
         g->total += n;
@@ -500,7 +519,12 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         int gV = 0;
         for (int j : g.jobs) gV = std::max(gV, job->orbits[j]->V);
         int per_cu = 0;
-        if (g.wave) {
+        if (g.wave && g.wps > 0) {
+            g.block = 64 * g.wps;
+            g.lds = 32 * (size_t)gV;   // neighbour table + one state
+            hipError_t e = gc_wps_occupancy(g.d, g.wps, g.lds, &per_cu);
+            if (e != hipSuccess) return fail(ctx, e, "occupancy");
+        } else if (g.wave) {
             g.ns = (gV / 2 + 63) / 64;
             g.block = 64 * GC_WAVES;
             size_t coef_bytes = 0;
@@ -530,7 +554,7 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             if (e != hipSuccess) return fail(ctx, e, "occupancy");
         }
         per_cu = std::max(per_cu, 1);
-        const uint64_t per_wg = g.wave ? GC_WAVES : 1;
+        const uint64_t per_wg = (g.wave && g.wps == 0) ? GC_WAVES : 1;
         uint64_t grid = (uint64_t)per_cu * (uint64_t)ctx->n_cu;
         grid = std::min<uint64_t>(grid, std::max<uint64_t>((g.total + per_wg - 1) / per_wg, 1));
         g.grid = (int)grid;
@@ -738,7 +762,12 @@ gc_status start_job(gc_ctx *ctx, Job *job)
             if (e != hipSuccess) return e;
         }
         for (const Group &g : L.groups) {
-            if (g.wave)
+            if (g.wave && g.wps > 0)
+                e = gc_launch_wps(g.d, g.wps, (const GcJobDev *)(base + g.o_jobs),
+                                  (const GcWaveOrbit *)(base + g.o_worbs), (int)g.jobs.size(),
+                                  (unsigned long long *)(base + g.o_next), (float2 *)(base + g.o_bounce), g.grid,
+                                  g.lds, qs);
+            else if (g.wave)
                 e = gc_launch_wave(g.d, g.ns, (const GcJobDev *)(base + g.o_jobs), (const GcWaveOrbit *)(base + g.o_worbs),
                                    (int)g.jobs.size(), (unsigned long long *)(base + g.o_next),
                                    g.coef_lds | (g.creg << 1),
@@ -1137,6 +1166,7 @@ gc_status gc_create(const gc_ctx_params *params, gc_ctx **out)
     ctx->n_cu = prop.multiProcessorCount;
     ctx->lds_max = prop.sharedMemPerBlock;
     if (const char *v = getenv("GC_WAVE_CREG")) ctx->creg_override = atoi(v);
+    if (const char *v = getenv("GC_WPS")) ctx->wps_override = atoi(v) != 0 ? 1 : 0;
     ctx->budget = P.hbm_budget_bytes ? P.hbm_budget_bytes : (64ull << 30);
     const int ns = P.n_streams > 0 ? std::min(P.n_streams, 16) : 4;
     for (int k = 0; k < ns; ++k) {
@@ -1487,6 +1517,31 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
     double rm = 0, pm = 0;
     st = trial(0, 0, 0, &rm, &pm);   // warm-up: code objects, pool
     if (st != GC_OK) return st;
+    // relax layout for more than two slots per lane: one wavefront per start
+    // or a workgroup per start (force_wps), best of two launches each
+    const bool wps_ok = (K == 2) && gc_wps_for(ns) > 0 && 32 * (size_t)V <= ctx->lds_max &&
+                        (size_t)(GC_WAVES + 1) * 16 * V <= ctx->lds_max;
+    int best_w = 0;
+    if (wps_ok) {
+        double tw[2] = {INFINITY, INFINITY};
+        for (int w = 0; w < 2; ++w)
+            for (int rep = 0; rep < 2; ++rep) {
+                {
+                    std::lock_guard<std::mutex> g(ctx->mu);
+                    ctx->force_wps = w;
+                }
+                st = trial(0, 0, 0, &rm, &pm);
+                {
+                    std::lock_guard<std::mutex> g(ctx->mu);
+                    ctx->force_wps = -1;
+                }
+                if (st != GC_OK) return st;
+                tw[w] = std::min(tw[w], rm);
+            }
+        best_w = tw[1] < tw[0] ? 1 : 0;
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->tune_wps[creg_key(d, ns, mixed)] = best_w;
+    }
     // relax: register-coefficient colours 0..cmax, best of two launches each
     int best_c = 0;
     double best_r = INFINITY;
@@ -1524,7 +1579,7 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
         if (wave) ctx->tune_creg[creg_key(d, ns, mixed)] = best_c;
         if (best_b) ctx->tune_post[V] = std::make_pair(best_b, best_sp);
     }
-    r.relax_variant = best_c;
+    r.relax_variant = best_c + (best_w ? 8 : 0);
     r.relax_ms = best_r;
     r.post_block = best_b ? best_b : db;
     r.post_sites_per_thread = best_b ? best_sp : dsp;

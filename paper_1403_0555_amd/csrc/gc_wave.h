@@ -25,3 +25,12 @@ hipError_t gc_launch_wave(int d, int ns, const GcJobDev *jobs, const GcWaveOrbit
                           unsigned long long *job_next, int variant, float2 *bounce, int grid, size_t lds,
                           hipStream_t s);
 int gc_wave_creg_max(int d, int ns);
+
+// Workgroup-per-start variant (lattices with more than 128 slots per
+// colour): wps wavefronts share a start, at most two slots per thread.
+// gc_wps_for(ns) gives wps for ns slots per lane of the one-wavefront layout
+// (0 when that layout is used, -1 when too large).  LDS: 32V bytes.
+int gc_wps_for(int ns);
+hipError_t gc_wps_occupancy(int d, int wps, size_t lds, int *per_cu);
+hipError_t gc_launch_wps(int d, int wps, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs,
+                         unsigned long long *job_next, float2 *bounce, int grid, size_t lds, hipStream_t s);

@@ -84,6 +84,43 @@ __device__ __forceinline__ typename cx<R>::T staple(const typename cx<R>::T (&cf
     return s;
 }
 
+// Synchronisation and reductions over the WPS wavefronts that share a start
+// (WPS = 1: one wavefront; otherwise the whole workgroup).  red holds at
+// least WPS doubles of LDS.
+template <int WPS> __device__ __forceinline__ void start_sync()
+{
+    if constexpr (WPS > 1) __syncthreads();
+    else wave_sync();
+}
+template <int WPS> __device__ __forceinline__ double start_sum(double v, double *red)
+{
+    v = wave_sum(v);
+    if constexpr (WPS > 1) {
+        __syncthreads();   // every wave has read the previous contents of red
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        double t = red[0];
+#pragma unroll
+        for (int w = 1; w < WPS; ++w) t += red[w];
+        v = t;
+    }
+    return v;
+}
+template <int WPS> __device__ __forceinline__ double start_max(double v, double *red)
+{
+    v = wave_max(v);
+    if constexpr (WPS > 1) {
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        double t = red[0];
+#pragma unroll
+        for (int w = 1; w < WPS; ++w) t = fmax(t, red[w]);
+        v = t;
+    }
+    return v;
+}
+
 // Sweeps of one precision on the wave's state st[2][half].  Returns status.
 // Lane l owns slots h = l + 64k, k < NS, of each colour; slots beyond the
 // half volume are computed on a clamped index and discarded, so the passes
@@ -92,14 +129,16 @@ __device__ __forceinline__ typename cx<R>::T staple(const typename cx<R>::T (&cf
 // table); otherwise they are recomputed from the slot descriptors.  CREG
 // colours (0, 1 or 2, starting with colour 0) keep the coefficients of the
 // lane's slots in registers for the whole phase.
-template <int D, typename R, int NS, bool RELAX, int CREG, typename CP>
+template <int D, typename R, int NS, bool RELAX, int CREG, int WPS, typename CP>
 __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<const u32x4> nbt,
-                            lds_ptr<typename cx<R>::T> st, double eps, uint64_t &sweeps, double &D_out)
+                            lds_ptr<typename cx<R>::T> st, double eps, uint64_t &sweeps, double &D_out, double *red)
 {
     const int half = WO.half;
     using C = typename cx<R>::T;
     constexpr bool NB_REG = NS <= 2;
-    const int lane = threadIdx.x & 63;
+    // thread index within the start: the lane, or the workgroup thread when
+    // WPS wavefronts share the start
+    const int lane = WPS > 1 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
     lds_ptr<C> st0 = st;
     lds_ptr<C> st1 = st + half;
     const R omega = (R)J.omega;
@@ -109,7 +148,7 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
     bool valid[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-        const int h = lane + 64 * k;
+        const int h = lane + 64 * WPS * k;
         valid[k] = h < half;
         hs[k] = valid[k] ? h : half - 1;
     }
@@ -182,8 +221,8 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
         if (pending) {
             // one wave reduction per checked sweep, over both colours' lane parts
             double Dn;
-            if (maxabs) Dn = wave_max(fmax(acc0, part1));
-            else Dn = wave_sum(acc0 + part1) / (double)(2 * half);
+            if (maxabs) Dn = start_max<WPS>(fmax(acc0, part1), red);
+            else Dn = start_sum<WPS>(acc0 + part1, red) / (double)(2 * half);
             D_out = Dn;
             if (!(Dn == Dn)) { status = GC_ST_BADNUM; break; }
             if (Dn < eps) { status = GC_ST_CONVERGED; break; }
@@ -194,7 +233,7 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
             if constexpr (NB_REG) own[0][k] = gnew[k];
             if (valid[k]) st0[hs[k]] = gnew[k];
         }
-        wave_sync();
+        start_sync<WPS>();
         // ---- colour 1, with its part of the norm of this sweep
         ++t;
         --until;
@@ -222,32 +261,34 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
             a1 = valid[k] ? a : a1;
         }
         if (chk) part1 = a1;
-        wave_sync();
+        start_sync<WPS>();
     }
     sweeps = t;
     return status;
 }
 
-template <int D, typename R, int NS, int CREG, typename CP>
+template <int D, typename R, int NS, int CREG, int WPS, typename CP>
 __device__ int relax_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<const u32x4> nbt,
-                          lds_ptr<typename cx<R>::T> st, double eps, uint64_t &sweeps, double &D_out)
+                          lds_ptr<typename cx<R>::T> st, double eps, uint64_t &sweeps, double &D_out, double *red)
 {
-    if ((R)J.omega == (R)1) return relax_wave_t<D, R, NS, true, CREG>(J, WO, coef, nbt, st, eps, sweeps, D_out);
-    return relax_wave_t<D, R, NS, false, CREG>(J, WO, coef, nbt, st, eps, sweeps, D_out);
+    if ((R)J.omega == (R)1)
+        return relax_wave_t<D, R, NS, true, CREG, WPS>(J, WO, coef, nbt, st, eps, sweeps, D_out, red);
+    return relax_wave_t<D, R, NS, false, CREG, WPS>(J, WO, coef, nbt, st, eps, sweeps, D_out, red);
 }
 
-template <int D, int NS, int CREG, typename CP64, typename CP32>
+template <int D, int NS, int CREG, int WPS, typename CP64, typename CP32>
 __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 coef64, CP32 coef32,
                                  lds_ptr<const u32x4> nbt, lds_ptr<dbl2> st64, lds_ptr<flt2> st32,
-                                 glb_ptr<flt2> bounce, uint64_t local)
+                                 glb_ptr<flt2> bounce, uint64_t local, double *red)
 {
-    const int lane = threadIdx.x & 63;
+    constexpr int T = 64 * WPS;   // threads on the start
+    const int lane = WPS > 1 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
     const GcOrbitDev &O = J.orb;
     const int V = O.V;
     const uint64_t sid = J.first_start + local;
 
     // random start, written at its colour-split position loc[i]
-    for (int b = lane; 4 * b < V; b += 64) {
+    for (int b = lane; 4 * b < V; b += T) {
         uint64_t c[4];
         start_block(J.start_seed, sid, O.orbit_index, (uint64_t)b, c);
 #pragma unroll 1
@@ -262,41 +303,41 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 
             }
         }
     }
-    wave_sync();
+    start_sync<WPS>();
 
     uint64_t sw32 = 0, sw64 = 0;
     double Dn = INFINITY;
     int status;
     bool in64 = J.precision != 1;
     if (J.precision == 1) {
-        status = relax_wave<D, float, NS, CREG>(J, WO, coef32, nbt, st32, J.eps32, sw32, Dn);
+        status = relax_wave<D, float, NS, CREG, WPS>(J, WO, coef32, nbt, st32, J.eps32, sw32, Dn, red);
         if (status == GC_ST_CONVERGED) {
             // promotion g64 = normalise((double) g32): both states share the
-            // wave's LDS region, so each lane bounces its entries through
-            // its private scratch
+            // start's LDS region, so each thread bounces its entries through
+            // the start's scratch (it reads back only what it wrote)
             in64 = true;
-            for (int p = lane; p < V; p += 64) bounce[p] = st32[p];
-            wave_sync();
-            for (int p = lane; p < V; p += 64) {
+            for (int p = lane; p < V; p += T) bounce[p] = st32[p];
+            start_sync<WPS>();
+            for (int p = lane; p < V; p += T) {
                 const flt2 g = bounce[p];
                 const double xr = (double)g.x, xi = (double)g.y;
                 const double r = rsqrt(xr * xr + xi * xi);
                 st64[p] = dbl2{xr * r, xi * r};
             }
-            wave_sync();
-            status = relax_wave<D, double, NS, CREG>(J, WO, coef64, nbt, st64, J.eps64, sw64, Dn);
+            start_sync<WPS>();
+            status = relax_wave<D, double, NS, CREG, WPS>(J, WO, coef64, nbt, st64, J.eps64, sw64, Dn, red);
         }
     } else {
-        status = relax_wave<D, double, NS, CREG>(J, WO, coef64, nbt, st64, J.eps64, sw64, Dn);
+        status = relax_wave<D, double, NS, CREG, WPS>(J, WO, coef64, nbt, st64, J.eps64, sw64, Dn, red);
     }
     // final state in natural site order
     glb_ptr<dbl2> out = as_global(reinterpret_cast<dbl2 *>(J.states + local * (uint64_t)V));
-    for (int i = lane; i < V; i += 64) {
+    for (int i = lane; i < V; i += T) {
         const int p = WO.loc[i];
         out[i] = in64 ? st64[p] : dbl2{(double)st32[p].x, (double)st32[p].y};
     }
     if (lane == 0) record_relax(J, local, status, sw32, sw64, Dn);
-    wave_sync();
+    start_sync<WPS>();
 }
 
 // WG = WAVES wavefronts.  LDS: [neighbour table 16V when NS <= 2 | coef64 |
@@ -365,13 +406,85 @@ __global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__rest
             if (s >= J.n_starts) break;
             lds_ptr<const u32x4> nbc = nbt;
             if (COEF_LDS)
-                relax_start_wave<D, NS, CREG>(J, WO, c64, c32, nbc, st64, st32, bounce, s);
+                relax_start_wave<D, NS, CREG, 1>(J, WO, c64, c32, nbc, st64, st32, bounce, s, nullptr);
             else
-                relax_start_wave<D, NS, CREG>(J, WO, as_global(g64), as_global(g32), nbc, st64, st32, bounce, s);
+                relax_start_wave<D, NS, CREG, 1>(J, WO, as_global(g64), as_global(g32), nbc, st64, st32, bounce, s,
+                                                 nullptr);
         }
         __syncthreads();
         j0 = jn;
     }
+}
+
+// One start per workgroup of WPS wavefronts, for lattices with more than 128
+// slots per colour: each thread keeps at most two slots per colour, the
+// colour passes synchronise the workgroup.  LDS: the neighbour table (16V)
+// and one state region (16V); the coefficients are read from global memory.
+template <int D, int WPS>
+__global__ __launch_bounds__(64 * WPS) void wps_kernel(const GcJobDev *__restrict__ jobs,
+                                                       const GcWaveOrbit *__restrict__ worbs, int n_jobs,
+                                                       unsigned long long *job_next, float2 *bounce_all)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int cur_job;
+    __shared__ unsigned long long claim;
+    __shared__ double red[WPS];
+    int j0 = (int)(blockIdx.x % (unsigned)n_jobs);
+    for (int round = 0; round < n_jobs; ++round) {
+        if (threadIdx.x == 0) {
+            int pick = -1;
+            for (int k = 0; k < n_jobs; ++k) {
+                const int j = (j0 + k) % n_jobs;
+                if (__hip_atomic_load(&job_next[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < jobs[j].n_starts) {
+                    pick = j;
+                    break;
+                }
+            }
+            cur_job = pick;
+        }
+        __syncthreads();
+        const int jn = uniform(cur_job);
+        __syncthreads();
+        if (jn < 0) break;
+        const GcJobDev &J = jobs[jn];
+        const GcWaveOrbit &WO = worbs[jn];
+        const int V = J.orb.V;
+        lds_ptr<u32x4> nbt = as_lds(reinterpret_cast<u32x4 *>(smem));
+        glb_ptr<const u32x4> nbg = as_global(reinterpret_cast<const u32x4 *>(WO.nb));
+        for (int t = threadIdx.x; t < V; t += 64 * WPS) nbt[t] = nbg[t];
+        __syncthreads();
+        lds_ptr<dbl2> st64 = as_lds(reinterpret_cast<dbl2 *>(smem + 16 * (size_t)V));
+        lds_ptr<flt2> st32 = as_lds(reinterpret_cast<flt2 *>(smem + 16 * (size_t)V));
+        glb_ptr<flt2> bounce = as_global(reinterpret_cast<flt2 *>(bounce_all) + (uint64_t)blockIdx.x * (uint64_t)V);
+        const dbl2 *g64 = reinterpret_cast<const dbl2 *>(WO.coef64);
+        const flt2 *g32 = reinterpret_cast<const flt2 *>(WO.coef32);
+        lds_ptr<const u32x4> nbc = nbt;
+        for (;;) {
+            if (threadIdx.x == 0) claim = atomicAdd(&job_next[jn], 1ULL);
+            __syncthreads();
+            const uint64_t s = uniform((uint64_t)claim);
+            __syncthreads();
+            if (s >= J.n_starts) break;
+            relax_start_wave<D, 2, 0, WPS>(J, WO, as_global(g64), as_global(g32), nbc, st64, st32, bounce, s, red);
+        }
+        __syncthreads();
+        j0 = jn;
+    }
+}
+
+template <int D, int WPS>
+hipError_t wps_launch_t(const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, unsigned long long *job_next,
+                        float2 *bounce, int grid, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((wps_kernel<D, WPS>), dim3(grid), dim3(64 * WPS), lds, s, jobs, worbs, n_jobs, job_next,
+                       bounce);
+    return hipGetLastError();
+}
+
+template <int D, int WPS>
+hipError_t wps_occ_t(size_t lds, int *per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, wps_kernel<D, WPS>, 64 * WPS, lds);
 }
 
 template <int D, int NS, int WAVES, bool CL, int CREG>
@@ -464,3 +577,42 @@ hipError_t gc_launch_wave(int d, int ns, const GcJobDev *jobs, const GcWaveOrbit
 
 int gc_wave_creg_max(int d, int ns) { return creg_max_t(d, ns); }
 
+
+// Wavefronts per start of the workgroup-per-start variant for a lattice with
+// ns slots per lane in the one-wavefront layout (0: use that layout).
+int gc_wps_for(int ns)
+{
+    if (ns <= 2) return 0;
+    static const int w[] = {2, 4, 6, 8, 16};
+    for (int x : w)
+        if (2 * x >= ns) return x;
+    return -1;
+}
+
+#define GC_WPS_DISPATCH(FN, ...)                                                                \
+    switch (d * 100 + wps) {                                                                    \
+    case 102: return FN<1, 2>(__VA_ARGS__);  case 104: return FN<1, 4>(__VA_ARGS__);           \
+    case 106: return FN<1, 6>(__VA_ARGS__);  case 108: return FN<1, 8>(__VA_ARGS__);           \
+    case 116: return FN<1, 16>(__VA_ARGS__);                                                    \
+    case 202: return FN<2, 2>(__VA_ARGS__);  case 204: return FN<2, 4>(__VA_ARGS__);           \
+    case 206: return FN<2, 6>(__VA_ARGS__);  case 208: return FN<2, 8>(__VA_ARGS__);           \
+    case 216: return FN<2, 16>(__VA_ARGS__);                                                    \
+    case 302: return FN<3, 2>(__VA_ARGS__);  case 304: return FN<3, 4>(__VA_ARGS__);           \
+    case 306: return FN<3, 6>(__VA_ARGS__);  case 308: return FN<3, 8>(__VA_ARGS__);           \
+    case 316: return FN<3, 16>(__VA_ARGS__);                                                    \
+    case 402: return FN<4, 2>(__VA_ARGS__);  case 404: return FN<4, 4>(__VA_ARGS__);           \
+    case 406: return FN<4, 6>(__VA_ARGS__);  case 408: return FN<4, 8>(__VA_ARGS__);           \
+    case 416: return FN<4, 16>(__VA_ARGS__);                                                    \
+    default: return hipErrorInvalidValue;                                                       \
+    }
+
+hipError_t gc_wps_occupancy(int d, int wps, size_t lds, int *per_cu)
+{
+    GC_WPS_DISPATCH(wps_occ_t, lds, per_cu)
+}
+
+hipError_t gc_launch_wps(int d, int wps, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs,
+                         unsigned long long *job_next, float2 *bounce, int grid, size_t lds, hipStream_t s)
+{
+    GC_WPS_DISPATCH(wps_launch_t, jobs, worbs, n_jobs, job_next, bounce, grid, lds, s)
+}

@@ -133,7 +133,7 @@ def test_autotune_keeps_results(extent, precision, n):
         ref = ctx.gc_fetch(h)
         note("autotune %s %s" % (extent, precision))
         r = ctx.gc_autotune(h, n, params)
-        assert r["relax_variant"] in (0, 1, 2)
+        assert r["relax_variant"] % 8 in (0, 1, 2) and r["relax_variant"] in (0, 1, 2, 8, 9, 10)
         assert r["post_block"] * r["post_sites_per_thread"] >= V
         assert r["relax_ms"] > 0 and r["post_ms"] > 0
         ctx.gc_launch(h, n, params)
