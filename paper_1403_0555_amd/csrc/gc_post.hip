@@ -262,6 +262,12 @@ __device__ double ritz_min(lds_cdouble *alpha, lds_cdouble *beta2, int k, double
     return tridiag_min_eig<B>(alpha, beta2, k, lo, hi, ired, iph, prev, tol_rel, final, hi_out);
 }
 
+// Lanczos stops when the lowest Ritz value moved by at most this relative
+// amount since the previous check (at least 8 iterations earlier).  Its
+// error is then of the same order, some 1e-11 in absolute terms for these
+// operators, far below the region threshold (1e-6).
+constexpr double kRitzTol = 1e-10;
+
 __device__ uint32_t region_flags(double lam2, double tol)
 {
     if (lam2 > tol) return GC_F_IN_REGION;
@@ -555,9 +561,9 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                     const bool final = breakdown || it + 1 == lmax;
                     double theta_hi;
                     theta = ritz_min<B>(alpha, beta2, it + 1, fmin(rows_lo, a_j - beta_prev),
-                                        fmax(rows_hi, a_j + beta_prev), theta_old, theta_step, ired, iph, 1e-12,
+                                        fmax(rows_hi, a_j + beta_prev), theta_old, theta_step, ired, iph, kRitzTol,
                                         final, theta_hi);
-                    const double tol = 1e-12 * fmax(1.0, fabs(theta));
+                    const double tol = kRitzTol * fmax(1.0, fabs(theta));
                     // theta_old is an upper bound of the previous value, so this
                     // change is at least the true one
                     const double change = theta_old - theta;
