@@ -380,3 +380,33 @@ def test_saturation_curve_matches_oracle(ctx):
     assert int(got[-1]) == len(o["table"])
     assert np.all(np.diff(got.astype(np.int64)) >= 0)
     ctx.gc_release(h)
+
+
+@pytest.mark.parametrize("extent,precision,n", [
+    ((8, 8, 8), "fp64", 60),          # 256 slots per colour: two wavefronts per start
+    ((10, 10, 10), "mixed", 40),      # 500: four
+    ((6, 6, 6, 6), "mixed", 24),      # 648: six
+    ((8, 8, 8, 8), "fp64", 3),        # 2048: sixteen
+])
+def test_parity_workgroup_per_start(monkeypatch, extent, precision, n):
+    """The workgroup-per-start layout (forced for the context) against the
+    oracle, start by start and copy by copy."""
+    monkeypatch.setenv("GC_WPS", "1")
+    phi = GI.orbit_angles(extent, 4, 2)
+    p = gc.SolveParams(omega=1.7, precision=precision)
+    with gc.Context(0) as c:
+        h, copies, starts, _ = run_gpu(c, extent, phi, n, p, orbit_index=2)
+        o = O.enumerate_copies(extent, phi, np.arange(n), oracle_params(p, 2))
+        if precision == "fp64":
+            compare_starts(extent, starts, o["records"])
+            compare_tables(extent, phi, copies, o, p)
+            check_start_filter(copies, starts, o)
+        else:
+            # mixed precision: keys agree start by start where the FP32 phase
+            # reached the same basin; both sides' F agree on those
+            conv = (o["records"]["status"] == O.CONVERGED) & (starts["status"] == gc.GC_START_CONVERGED)
+            same = conv & (starts["key_hi"] == o["records"]["key_hi"]) & (starts["key_lo"] == o["records"]["key_lo"])
+            assert same.sum() >= 0.9 * conv.sum()
+            V = int(np.prod(extent))
+            assert np.max(np.abs(starts["F"][same] - o["records"]["F"][same])) / V < F_TOL_PER_SITE
+        c.gc_release(h)
