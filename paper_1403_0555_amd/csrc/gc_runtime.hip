@@ -1365,8 +1365,8 @@ gc_status gc_fetch(gc_ctx *ctx, gc_orbit orbit, uint64_t offset, uint64_t cap, g
     gc_status st = ensure_copies_locked(ctx, o);
     if (st != GC_OK) return st;
     const uint64_t n = o->copies.size();
-    uint64_t w = 0;
-    for (uint64_t k = offset; k < n && w < cap; ++k, ++w) out[w] = o->copies[k];
+    const uint64_t w = offset < n ? std::min(cap, n - offset) : 0;
+    if (w) memcpy(out, o->copies.data() + offset, w * sizeof(gc_copy));
     if (n_written) *n_written = w;
     if (n_total) *n_total = n;
     return GC_OK;
@@ -1383,8 +1383,8 @@ gc_status gc_fetch_starts(gc_ctx *ctx, gc_orbit orbit, uint64_t offset, uint64_t
     gc_status st = ensure_starts_locked(ctx, o);
     if (st != GC_OK) return st;
     const uint64_t n = o->starts.size();
-    uint64_t w = 0;
-    for (uint64_t k = offset; k < n && w < cap; ++k, ++w) out[w] = o->starts[k];
+    const uint64_t w = offset < n ? std::min(cap, n - offset) : 0;
+    if (w) memcpy(out, o->starts.data() + offset, w * sizeof(gc_start_record));
     if (n_written) *n_written = w;
     return GC_OK;
 }
