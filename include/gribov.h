@@ -259,6 +259,20 @@ gc_status gc_kernel_time_ms(gc_ctx *ctx, gc_orbit orbit, double *solve_ms);
 gc_status gc_saturation(gc_ctx *ctx, gc_orbit orbit, int32_t n_points, const uint64_t *sample_sizes,
                         int32_t in_region_only, uint64_t *distinct_out);
 
+/* The paper's own count of a completed launch (Sec. III): the number of
+ * distinct values trunc(x * 1e8) among the converged starts within the first
+ * N starts of the launch, for each of the n_points sample sizes N (the paper
+ * takes N at powers of two; N past n_starts counts every start).  Different
+ * copies with equal truncated x count once, and one copy whose starts stopped
+ * on either side of a truncation boundary counts twice, so this differs from
+ * gc_saturation's count of integer keys.  sample_sizes must be
+ * nondecreasing.  Counted on the device, one bit per possible value (a
+ * 32 MiB bitmap allocated for the call).  Caller owns both arrays.  Errors:
+ * GC_EINVAL (bad arguments, decreasing sizes), GC_ESTATE (no completed
+ * launch), GC_ENOMEM. */
+gc_status gc_paper_saturation(gc_ctx *ctx, gc_orbit orbit, int32_t n_points, const uint64_t *sample_sizes,
+                              uint64_t *distinct_out);
+
 /* Result of gc_autotune. */
 typedef struct {
     int32_t relax_variant;          /* colours whose coefficients a lane keeps in registers (0..2), plus 8

@@ -27,7 +27,7 @@ EXPORTED_SYMBOLS = [
     "gc_create", "gc_destroy", "gc_orbit_load", "gc_orbit_random", "gc_orbit_angles",
     "gc_launch", "gc_launch_batch", "gc_poll", "gc_wait", "gc_fetch", "gc_fetch_starts",
     "gc_fetch_state", "gc_release", "gc_last_error", "gc_kernel_time_ms", "gc_launch_bytes",
-    "gc_memory_info", "gc_autotune", "gc_saturation",
+    "gc_memory_info", "gc_autotune", "gc_saturation", "gc_paper_saturation",
 ]
 
 
@@ -120,6 +120,7 @@ def lib():
         "gc_memory_info": ([vp, P(u64), P(u64), P(u64)], i32),
         "gc_autotune": ([vp, u64, u64, P(gc_solve_params), P(gc_tune_result)], i32),
         "gc_saturation": ([vp, u64, i32, P(u64), i32, P(u64)], i32),
+        "gc_paper_saturation": ([vp, u64, i32, P(u64), P(u64)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -330,6 +331,15 @@ class Context:
         self._check(self._L.gc_saturation(self._h, orbit, int(n.size),
                                           n.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), int(in_region_only),
                                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))), "gc_saturation")
+        return out
+
+    def gc_paper_saturation(self, orbit: int, sample_sizes) -> np.ndarray:
+        n = np.ascontiguousarray(sample_sizes, dtype=np.uint64)
+        out = np.zeros(n.size, dtype=np.uint64)
+        self._check(self._L.gc_paper_saturation(self._h, orbit, int(n.size),
+                                                n.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))),
+                    "gc_paper_saturation")
         return out
 
     def gc_last_error(self) -> str:

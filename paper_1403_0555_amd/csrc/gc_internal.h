@@ -137,3 +137,9 @@ hipError_t gc_launch_finalize(const GcJobDev *jobs_host, int n_jobs, hipStream_t
 hipError_t gc_launch_patch(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);      // fix-up results -> copies
 hipError_t gc_launch_orbit_random(double *phi, int64_t n_links, uint64_t seed, uint64_t orbit_index, hipStream_t s);
 hipError_t gc_launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
+
+// Value-based count: paper_X < GC_PAPER_VALUES (x <= 2 gives at most 2e8),
+// one bit per value.
+constexpr uint32_t GC_PAPER_VALUES = 1u << 28;
+hipError_t gc_launch_paper_mark(const GcStartRec *rec, uint64_t lo, uint64_t hi, uint32_t *bits,
+                                unsigned long long *count, hipStream_t s);

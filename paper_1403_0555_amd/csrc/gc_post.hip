@@ -943,6 +943,44 @@ hipError_t gc_launch_patch(const GcJobDev *jobs_host, int n_jobs, hipStream_t s)
     return hipSuccess;
 }
 
+// The paper's value-based count (Sec. III): distinct trunc(x * 1e8) over the
+// converged starts.  Each converged start of [lo, hi) sets its value's bit;
+// an atomic OR tells whether the bit was new, and new bits add to *count, so
+// after the launch *count holds the distinct values among all starts marked
+// so far.  The block-stride loop runs the same number of iterations on every
+// lane of a block, so the ballot sees the whole wavefront.
+__global__ void __launch_bounds__(256) paper_mark_kernel(const GcStartRec *__restrict__ rec, uint64_t lo, uint64_t hi,
+                                                         uint32_t *bits, unsigned long long *count)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = lo + (uint64_t)blockIdx.x * blockDim.x; base < hi; base += stride) {
+        const uint64_t s = base + threadIdx.x;
+        bool fresh = false;
+        if (s < hi && rec[s].status == GC_ST_CONVERGED) {
+            const uint32_t X = rec[s].paper_X;
+            if (X < GC_PAPER_VALUES) {
+                const uint32_t b = 1u << (X & 31);
+                const uint32_t old =
+                    __hip_atomic_fetch_or(&bits[X >> 5], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                fresh = !(old & b);
+            }
+        }
+        const uint64_t n = (uint64_t)__popcll(__ballot(fresh));
+        if ((threadIdx.x & 63) == 0 && n)
+            __hip_atomic_fetch_add(count, (unsigned long long)n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+hipError_t gc_launch_paper_mark(const GcStartRec *rec, uint64_t lo, uint64_t hi, uint32_t *bits,
+                                unsigned long long *count, hipStream_t s)
+{
+    if (hi <= lo) return hipSuccess;
+    const uint64_t need = (hi - lo + 255) / 256;
+    const uint64_t blocks = need < 65536 ? need : 65536;
+    hipLaunchKernelGGL(paper_mark_kernel, dim3((unsigned)blocks), dim3(256), 0, s, rec, lo, hi, bits, count);
+    return hipGetLastError();
+}
+
 hipError_t gc_launch_orbit_random(double *phi, int64_t n_links, uint64_t seed, uint64_t orbit_index, hipStream_t s)
 {
     const int64_t blocks4 = (n_links + 3) / 4;

@@ -1354,6 +1354,47 @@ gc_status gc_saturation(gc_ctx *ctx, gc_orbit orbit, int32_t n_points, const uin
     return GC_OK;
 }
 
+gc_status gc_paper_saturation(gc_ctx *ctx, gc_orbit orbit, int32_t n_points, const uint64_t *sample_sizes,
+                              uint64_t *distinct_out)
+{
+    if (n_points < 0 || (n_points > 0 && (!sample_sizes || !distinct_out))) return GC_EINVAL;
+    for (int32_t k = 1; k < n_points; ++k)
+        if (sample_sizes[k] < sample_sizes[k - 1]) return GC_EINVAL;
+    GC_ENTER(ctx);
+    Orbit *o = find_orbit(ctx, orbit);
+    if (!o) return GC_EINVAL;
+    if (!o->job || o->job->state != GC_ORBIT_DONE) return GC_ESTATE;
+    if (n_points == 0) return GC_OK;
+    const uint64_t n = o->job->n_starts[o->job_index];
+    // [GC_PAPER_VALUES / 64] bitmap words, the running count, one snapshot per point
+    const size_t words = GC_PAPER_VALUES / 64;
+    unsigned long long *buf = nullptr;
+    if (hipMalloc((void **)&buf, sizeof(unsigned long long) * (words + 1 + (size_t)n_points)) != hipSuccess) {
+        (void)hipGetLastError();
+        return GC_ENOMEM;
+    }
+    unsigned long long *count = buf + words, *snap = count + 1;
+    std::vector<unsigned long long> host(n_points);
+    hipStream_t s = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = gc_launch_zero_u64(buf, (int)(words + 1), s);
+    uint64_t done = 0;
+    for (int32_t k = 0; k < n_points && e == hipSuccess; ++k) {
+        const uint64_t upto = std::min<uint64_t>(sample_sizes[k], n);
+        e = gc_launch_paper_mark((const GcStartRec *)o->res.rec, done, upto, (uint32_t *)buf, count, s);
+        done = std::max(done, upto);
+        if (e == hipSuccess) e = hipMemcpyAsync(snap + k, count, sizeof *count, hipMemcpyDeviceToDevice, s);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host.data(), snap, sizeof(unsigned long long) * n_points, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (s) (void)hipStreamDestroy(s);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return fail(ctx, e, "gc_paper_saturation");
+    for (int32_t k = 0; k < n_points; ++k) distinct_out[k] = host[k];
+    return GC_OK;
+}
+
 gc_status gc_fetch(gc_ctx *ctx, gc_orbit orbit, uint64_t offset, uint64_t cap, gc_copy *out, uint64_t *n_written,
                    uint64_t *n_total)
 {

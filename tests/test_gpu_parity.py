@@ -382,6 +382,35 @@ def test_saturation_curve_matches_oracle(ctx):
     ctx.gc_release(h)
 
 
+def test_paper_count_matches_oracle(ctx):
+    """The paper's own count (distinct trunc(x * 1e8) over converged starts,
+    Sec. III) within the first 2^k starts, counted on the device, against the
+    oracle's records of the same starts; in the paper's mode (omega = 1,
+    max |div| < 1e-12)."""
+    extent = (4, 4)
+    phi = GI.orbit_angles(extent, 5, 2)
+    p = gc.SolveParams(omega=1.0, stop_norm="max_abs", eps64=1e-12)
+    n = 4096
+    h, copies, starts, prog = run_gpu(ctx, extent, phi, n, p, orbit_index=2)
+    rec, _, _ = O.solve(extent, phi, np.arange(n), oracle_params(p, 2))
+    sizes = [0, 1, 2, 4, 8, 16, 64, 256, 1024, 2048, 4096, 10000]
+    got = ctx.gc_paper_saturation(h, sizes).astype(np.int64)
+    conv_o = rec["status"] == O.CONVERGED
+    conv_g = starts["status"] == gc.GC_START_CONVERGED
+    # values differ between the two sides only where x * 1e8 lands within
+    # rounding of an integer; each such start moves a count by at most one
+    moved = int(np.sum(starts["paper_X"][conv_o] != rec["paper_X"][conv_o]))
+    for m, g in zip(sizes, got):
+        want = np.unique(rec["paper_X"][:m][conv_o[:m]]).size
+        assert abs(int(g) - want) <= moved, (m, int(g), want)
+        assert int(g) == np.unique(starts["paper_X"][:m][conv_g[:m]]).size, m
+    assert int(got[-1]) == int(prog["paper_count"])
+    assert np.all(np.diff(got) >= 0)
+    with pytest.raises(gc.GcError):
+        ctx.gc_paper_saturation(h, [4, 2])
+    ctx.gc_release(h)
+
+
 @pytest.mark.parametrize("extent,precision,n", [
     ((8, 8, 8), "fp64", 60),          # 256 slots per colour: two wavefronts per start
     ((10, 10, 10), "mixed", 40),      # 500: four
