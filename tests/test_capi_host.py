@@ -72,6 +72,13 @@ def test_null_arguments_rejected_without_device():
     assert L.gc_lattice_check(None, None) == gc.GC_EINVAL
     assert L.gc_launch(None, 1, 10, None) == gc.GC_EINVAL
     assert L.gc_poll(None, 1, None) == gc.GC_EINVAL
+    sizes = (ctypes.c_uint64 * 2)(4, 2)
+    out = (ctypes.c_uint64 * 2)()
+    # bad counts, missing arrays and decreasing sizes fail before any device call
+    assert L.gc_paper_saturation(None, 1, -1, None, None) == gc.GC_EINVAL
+    assert L.gc_paper_saturation(None, 1, 2, None, out) == gc.GC_EINVAL
+    assert L.gc_paper_saturation(None, 1, 2, sizes, out) == gc.GC_EINVAL
+    assert L.gc_saturation(None, 1, 2, sizes, 0, None) == gc.GC_EINVAL
 
 
 def test_no_device_is_reported(monkeypatch):
