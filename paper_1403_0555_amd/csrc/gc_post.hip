@@ -211,7 +211,10 @@ __device__ int sturm_count(lds_cdouble *alpha, lds_cdouble *beta2, int k, double
 }
 
 // Smallest eigenvalue of the tridiagonal by (B+1)-section inside [lo, hi]
-// (count(lo) = 0, count(hi) >= 1).  Unless final (or the workgroup is a
+// (count(lo) = 0, count(hi) >= 1), to a bracket of 1e-15 max(1, |theta|)
+// when final, else of tol_rel / 100 of that (the convergence test compares
+// values at tol_rel, and the value it accepts is this one, so its bracket
+// error stays a hundredth of the test's tolerance).  Unless final (or the workgroup is a
 // single wave, whose rounds are cheap), the search stops early when the
 // eigenvalue lies more than 1e6 tol_rel max(1, |theta|) below prev
 // (the previous check's upper bound) and the bracket is small against that
@@ -221,8 +224,9 @@ template <int B>
 __device__ double tridiag_min_eig(lds_cdouble *alpha, lds_cdouble *beta2, int k, double lo, double hi, int *ired,
                                   int &iph, double prev, double tol_rel, bool final, double &hi_out)
 {
+    const double width = final ? 1e-15 : 1e-2 * tol_rel;
     for (int round = 0; round < 24; ++round) {
-        if (hi - lo <= 1e-15 * fmax(1.0, fabs(hi))) break;
+        if (hi - lo <= width * fmax(1.0, fabs(hi))) break;
         if (!final && B > 64) {   // a round costs barriers only for several waves
             const double gap = prev - hi, scale = fmax(1.0, fabs(hi));
             const bool fails = gap > 1e6 * tol_rel * scale;   // far from converging
