@@ -111,9 +111,12 @@ WORKLOADS = {
     "u1_2d_4x4_or": Workload("u1_2d_4x4_or", (4, 4), 1000, 1.7, "fp64"),
     # 4D 4^4, 1e5 starts, plain relaxation (omega = 1), FP64.
     "u1_4d_4x4x4x4_relax": Workload("u1_4d_4x4x4x4_relax", (4, 4, 4, 4), 100_000, 1.0, "fp64"),
-    # 4D 6^4 and 3D 10^3, 1e6 starts, FP32 overrelaxation to 1e-6 then FP64 polish.
+    # 4D 6^4 and 3D 10^3, 1e6 starts, FP32 overrelaxation to 1e-6 then FP64 polish,
+    # and the same orbits and starts in double precision throughout.
     "u1_4d_6x6x6x6_mixed": Workload("u1_4d_6x6x6x6_mixed", (6, 6, 6, 6), 1_000_000, 1.7, "mixed"),
     "u1_3d_10x10x10_mixed": Workload("u1_3d_10x10x10_mixed", (10, 10, 10), 1_000_000, 1.7, "mixed"),
+    "u1_4d_6x6x6x6_fp64": Workload("u1_4d_6x6x6x6_fp64", (6, 6, 6, 6), 1_000_000, 1.7, "fp64"),
+    "u1_3d_10x10x10_fp64": Workload("u1_3d_10x10x10_fp64", (10, 10, 10), 1_000_000, 1.7, "fp64"),
 }
 
 # Shapes of the uneven multi-orbit batch (even extents only).

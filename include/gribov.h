@@ -38,7 +38,7 @@ typedef int32_t gc_status;
 enum {
     GC_OK = 0,
     GC_EINVAL = -1,        /* bad argument (shape, NaN/Inf angle, null pointer, bad handle) */
-    GC_ENOMEM = -2,        /* request larger than the context's whole HBM budget */
+    GC_ENOMEM = -2,        /* request larger than the HBM budget, or device memory exhausted */
     GC_EUNSUPPORTED = -3,  /* lattice has no proper colouring (see gc_lattice_check) */
     GC_EDEVICE = -4,       /* HIP runtime or kernel error; context is sticky-failed */
     GC_EBUSY = -5,         /* orbit already has a launch in flight */
@@ -76,13 +76,24 @@ typedef uint64_t gc_orbit;      /* 0 is never a valid handle */
 
 typedef struct {
     int32_t device;             /* HIP device ordinal */
-    int32_t n_streams;          /* streams for concurrent launches (0 -> 4) */
-    uint64_t hbm_budget_bytes;  /* device bytes the context may hold for orbits and launches (0 -> 64 GiB) */
+    int32_t n_streams;          /* streams for concurrent launches (0 -> 4); ignored when hip_stream is set */
+    uint64_t hbm_budget_bytes;  /* device bytes the context may hold for orbits, launches and unreleased
+                                   results (0 -> 64 GiB); a hard limit */
+    void *hip_stream;           /* NULL: the context creates its own streams.  Otherwise a hipStream_t of the
+                                   caller (e.g. a PyTorch stream) on params->device: every launch is enqueued
+                                   on it, after whatever the caller enqueued before the call, and the caller
+                                   keeps ownership (it must outlive the context) */
+    const char *tune_cache;     /* NULL or a file path: kernel-variant choices of gc_autotune are read from
+                                   it at gc_create and written back after every gc_autotune */
 } gc_ctx_params;
 
 typedef struct {
     int32_t dim;                /* 1..4 */
     int32_t extent[4];          /* N_mu >= 2 for mu < dim; V = prod N_mu <= 4096 (a start's state is held on chip) */
+    uint32_t antiperiodic;      /* bit mu set: gauge transformations are antiperiodic in direction mu,
+                                   g_{i + N_mu e_mu} = -g_i (Sec. II names antiperiodic boundary conditions
+                                   beside the periodic ones of Sec. I), which is the periodic problem with
+                                   every link that wraps around direction mu multiplied by -1; 0: periodic */
 } gc_lattice;
 
 typedef struct {
@@ -97,6 +108,12 @@ typedef struct {
     uint64_t max_sweeps;        /* per phase; beyond it a start is NONCONVERGED and not keyed */
     uint64_t start_seed;        /* Philox key word for the random starts */
     uint64_t first_start;       /* start ids are first_start .. first_start + n_starts - 1 */
+    uint32_t sync_batch;        /* 0: every start stops on its own.  k > 0: the paper's batch-synchronous
+                                   stop (Sec. III: the stopping test runs over all concurrently relaxed
+                                   samples): the starts of each batch of k consecutive ids all run the same
+                                   number of sweeps, the largest of the batch's own stopping sweeps, and a
+                                   start is converged if its norm is below eps64 after them.  GC_FP64 only */
+    uint32_t pad;
 } gc_solve_params;
 
 typedef struct {
@@ -116,7 +133,9 @@ typedef struct {
     uint64_t lanczos_runs;
     uint64_t paper_count;       /* distinct trunc(x * 1e8) over converged starts (valid when DONE) */
     double submit_to_done_ms;   /* latency of the last launch (valid when DONE) */
-    double device_ms;           /* device time of the last launch (valid when DONE) */
+    double device_ms;           /* device time of the last launch's relax kernel, or of the whole graph of a
+                                   batch (valid when DONE) */
+    double post_ms;             /* device time of the last launch's post kernel (single-orbit launches) */
 } gc_progress;
 
 /* One distinct copy. */
@@ -128,6 +147,7 @@ typedef struct {
     double lambda2;             /* lowest eigenvalue of M_FP orthogonal to the constant mode, at the representative */
     uint64_t hits;              /* starts that converged to this key */
     uint64_t first_start;       /* lowest start id reaching it */
+    uint64_t rep_start;         /* the representative start (F, lambda2 and gc_fetch_state refer to it) */
     uint32_t flags;             /* GC_FLAG_* */
     uint32_t lanczos_iters;
 } gc_copy;
@@ -193,15 +213,24 @@ gc_status gc_orbit_angles(gc_ctx *ctx, gc_orbit orbit, double *phi_out);
  * until its stopping norm falls below eps, computes F, x, the integer key,
  * inserts the key in the orbit's copy table and, for the lowest start id of
  * each key, the lowest non-constant eigenvalue lambda2 of M_FP by Lanczos.
- * Returns at once.  The launch waits in a queue while the context's HBM
- * budget is in use; a launch larger than the whole budget is GC_ENOMEM.
- * A second launch on the same orbit replaces its table (GC_EBUSY while one
- * is in flight).  params NULL: defaults. */
+ * Returns at once: the call only enqueues device work (it never waits for
+ * the device).  A launch starts when its bytes fit the context's HBM budget
+ * (device memory of running launches and of results not yet released
+ * counts) and one of the context's streams is idle; until then it waits in a
+ * FIFO queue.  A launch larger than the whole budget is GC_ENOMEM.  A second
+ * launch on the same orbit replaces its results (GC_EBUSY while one is in
+ * flight).  params NULL: defaults. */
 gc_status gc_launch(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_solve_params *params);
 
-/* Launch several orbits as one batch: one persistent kernel launch (captured
- * in a HIP graph) serves every orbit's starts.  Same semantics per orbit as
- * gc_launch; all orbits share params. */
+/* Launch several orbits as one batch, captured once into a HIP graph: the
+ * orbits are grouped by relax kernel (dimension, layout, slots per lane) and
+ * each group is one chain of persistent kernel launches (relax, post,
+ * table compaction) in which workgroups claim the group's starts from device
+ * counters; the chains are concurrent branches of the graph, so one group's
+ * slowest starts overlap the other groups' work.  Relaunching the same
+ * orbits with the same start counts and params replays the graph on the
+ * same device memory.  Same semantics per orbit as gc_launch; all orbits
+ * share params. */
 gc_status gc_launch_batch(gc_ctx *ctx, int32_t n_orbits, const gc_orbit *orbits,
                           const uint64_t *n_starts, const gc_solve_params *params);
 
@@ -209,7 +238,10 @@ gc_status gc_launch_batch(gc_ctx *ctx, int32_t n_orbits, const gc_orbit *orbits,
 gc_status gc_poll(gc_ctx *ctx, gc_orbit orbit, gc_progress *out);
 
 /* Block until the orbit's launch is DONE (timeout_ms < 0: forever).
- * GC_ETIMEOUT leaves the launch running. */
+ * GC_ETIMEOUT leaves the launch running.  GC_ENOMEM: the launch is queued
+ * and nothing is running, so only gc_release of earlier results can make
+ * room for it (it stays queued).  A launch that could not start returns its
+ * error (GC_ENOMEM when device memory ran out). */
 gc_status gc_wait(gc_ctx *ctx, gc_orbit orbit, int64_t timeout_ms);
 
 /* Distinct copies of a DONE orbit, sorted by (key_hi, key_lo): writes up to
@@ -223,13 +255,22 @@ gc_status gc_fetch(gc_ctx *ctx, gc_orbit orbit, uint64_t offset, uint64_t cap,
 gc_status gc_fetch_starts(gc_ctx *ctx, gc_orbit orbit, uint64_t offset, uint64_t cap,
                           gc_start_record *out, uint64_t *n_written);
 
-/* Final state of one start of the orbit's last (DONE) launch: writes
- * theta_i - theta_{V-1} wrapped to (-pi, pi] (the global phase removed by
- * fixing the last site, Sec. I) to theta_out [V].  Any start id of that
- * launch, converged or not. */
-gc_status gc_fetch_state(gc_ctx *ctx, gc_orbit orbit, uint64_t start_id, double *theta_out);
+/* Representative gauge transformation of one distinct copy of a DONE orbit
+ * (the copy with key (key_hi, key_lo); its representative start is
+ * gc_copy.rep_start): writes theta_i - theta_{V-1} wrapped to (-pi, pi] to
+ * theta_out [V], the global phase removed by fixing the last site (Sec. I).
+ * Errors: GC_EINVAL (bad handle, NULL theta_out), GC_ESTATE (no completed
+ * launch), GC_ENOTFOUND (no copy with that key). */
+gc_status gc_fetch_state(gc_ctx *ctx, gc_orbit orbit, uint64_t key_hi, uint64_t key_lo, double *theta_out);
 
-/* Free the orbit and its tables (waits for its launch first). */
+/* Final state of any start of the orbit's last (DONE) launch, converged or
+ * not, in the same form as gc_fetch_state (theta_i - theta_{V-1}).  Errors:
+ * GC_EINVAL (start id outside the launch), GC_ESTATE. */
+gc_status gc_fetch_start_state(gc_ctx *ctx, gc_orbit orbit, uint64_t start_id, double *theta_out);
+
+/* Free the orbit and its results (waits for a running launch first; a
+ * launch still queued is withdrawn).  Device memory returns to the
+ * context's pool, so the call never waits for other launches. */
 gc_status gc_release(gc_ctx *ctx, gc_orbit orbit);
 
 /* Sticky error text of the context (always NUL-terminated when cap > 0). */

@@ -477,7 +477,7 @@ typedef struct {
     int32_t precision;    /* 0: double throughout, 1: float sweeps then double polish */
     int32_t stop_norm;    /* 0: mean square, 1: max abs */
     int32_t check_every;
-    int32_t pad;
+    int32_t fixed;          /* 1: run exactly max_sweeps double sweeps, norm after the last (batch-synchronous pass) */
     int64_t max_sweeps;
     uint64_t start_seed;
     uint64_t orbit_index;
@@ -542,14 +542,20 @@ static void or_solve_one(const or_lattice *L, const double *phi, const double *U
         }
     }
     {
+        /* The paper stops all concurrently relaxed samples together (Sec. III,
+         * stopping criterion); in the fixed mode a sample runs the number of
+         * sweeps its batch needed and its norm is tested after the last. */
         int64_t t = 0;
         while (t < p->max_sweeps) {
             or_sweep64(L, Ur, Ui, gr, gi, p->omega);
             ++t;
-            if (t % check == 0 || t == p->max_sweeps) {
+            if ((!p->fixed && t % check == 0) || t == p->max_sweeps) {
                 D = or_norm64(L, Ur, Ui, gr, gi, p->stop_norm);
                 if (!(D == D)) { status = OR_BADNUM; break; }
-                if (D < p->eps64) { status = OR_CONVERGED; break; }
+                if (D < p->eps64) {
+                    status = OR_CONVERGED;
+                    if (!p->fixed) break;
+                }
             }
         }
         rec->sweeps64 = (int32_t)t;

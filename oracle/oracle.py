@@ -22,6 +22,7 @@ This module adds, in numpy:
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -46,7 +47,7 @@ RECORD_DTYPE = np.dtype([
 class _Params(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_double), ("eps32", ctypes.c_double), ("eps64", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("stop_norm", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("fixed", ctypes.c_int32),
                 ("max_sweeps", ctypes.c_int64), ("start_seed", ctypes.c_uint64),
                 ("orbit_index", ctypes.c_uint64)]
 
@@ -164,11 +165,33 @@ class SolveParams:
     max_sweeps: int = 100_000
     start_seed: int = 0
     orbit_index: int = 0
+    fixed: bool = False            # run exactly max_sweeps double sweeps (batch-synchronous second pass)
 
     def c(self) -> _Params:
         return _Params(self.omega, self.eps32, self.eps64, 1 if self.precision == "mixed" else 0,
-                       1 if self.stop_norm == "max_abs" else 0, self.check_every, 0,
+                       1 if self.stop_norm == "max_abs" else 0, self.check_every, 1 if self.fixed else 0,
                        self.max_sweeps, self.start_seed, self.orbit_index)
+
+
+def twisted(extent, phi, antiperiodic: int = 0) -> np.ndarray:
+    """Link angles of the periodic problem equivalent to antiperiodic gauge
+    transformations in the directions of the bit mask (Sec. II names
+    antiperiodic boundary conditions).  With g_{x + N_mu e_mu} = -g_x the
+    term of a link (x, mu) with x_mu = N_mu - 1 reads
+    Re(conj(g_x) U (-g_{x'})) = Re(conj(g_x) (-U) g_{x'}), x' the periodic
+    image: the link angle gains pi."""
+    d, V = len(extent), volume(extent)
+    out = np.array(phi, dtype=np.float64).reshape(d, V).copy()
+    if not antiperiodic:
+        return out
+    idx = np.arange(V)
+    stride = 1
+    for mu, n in enumerate(extent):
+        x = (idx // stride) % n
+        if (antiperiodic >> mu) & 1:
+            out[mu, x == n - 1] += math.pi
+        stride *= n
+    return out
 
 
 def solve(extent, phi, start_ids, params: SolveParams, theta_init=None, threads: int = 0,
@@ -276,8 +299,32 @@ def region_flags(lam2: float, tol: float = LAMBDA_TOL) -> int:
 F_SPREAD_PER_SITE = 1e-9
 
 
+def solve_sync(extent, phi, start_ids, params: SolveParams, batch: int, threads: int = 0,
+               want_state: bool = False):
+    """The paper's batch-synchronous stop (Sec. III: one stopping test over
+    all samples relaxed together): the starts are taken in batches of
+    `batch` consecutive entries of start_ids; every start of a batch runs
+    the largest number of sweeps any start of the batch needs to stop on its
+    own, and is converged if its norm is below eps64 after them.  FP64."""
+    assert params.precision == "fp64"
+    ids = np.ascontiguousarray(start_ids, dtype=np.uint64)
+    first, _, _ = solve(extent, phi, ids, params, threads=threads)
+    rec = np.zeros(ids.size, dtype=RECORD_DTYPE)
+    V = volume(extent)
+    g = np.empty((ids.size, V, 2)) if want_state else None
+    for lo in range(0, ids.size, batch):
+        hi = min(ids.size, lo + batch)
+        T = int(first["sweeps64"][lo:hi].max())
+        p2 = SolveParams(**{**params.__dict__, "max_sweeps": T, "fixed": True})
+        r, gg, _ = solve(extent, phi, ids[lo:hi], p2, threads=threads, want_state=want_state)
+        rec[lo:hi] = r
+        if want_state:
+            g[lo:hi] = gg
+    return rec, g
+
+
 def enumerate_copies(extent, phi, start_ids, params: SolveParams, threads: int = 0,
-                     with_lambda: bool = True, lambda_keys=None):
+                     with_lambda: bool = True, lambda_keys=None, sync_batch: int = 0):
     """Run the listed starts and build the copy table.
 
     A key can be reached by starts that stopped at different stationary
@@ -292,7 +339,10 @@ def enumerate_copies(extent, phi, start_ids, params: SolveParams, threads: int =
     Returns dict with 'records' (per start), 'table' {(key_hi, key_lo): entry},
     'paper_count' (distinct trunc(x*1e8) over converged starts)."""
     ids = np.ascontiguousarray(start_ids, dtype=np.uint64)
-    rec, g, _ = solve(extent, phi, ids, params, threads=threads, want_state=with_lambda)
+    if sync_batch:
+        rec, g = solve_sync(extent, phi, ids, params, sync_batch, threads=threads, want_state=with_lambda)
+    else:
+        rec, g, _ = solve(extent, phi, ids, params, threads=threads, want_state=with_lambda)
     V = volume(extent)
     hits = {}
     for s in range(ids.size):

@@ -26,7 +26,7 @@ EXPORTED_SYMBOLS = [
     "gc_version", "gc_status_str", "gc_lattice_check", "gc_solve_params_default",
     "gc_create", "gc_destroy", "gc_orbit_load", "gc_orbit_random", "gc_orbit_angles",
     "gc_launch", "gc_launch_batch", "gc_poll", "gc_wait", "gc_fetch", "gc_fetch_starts",
-    "gc_fetch_state", "gc_release", "gc_last_error", "gc_kernel_time_ms", "gc_launch_bytes",
+    "gc_fetch_state", "gc_fetch_start_state", "gc_release", "gc_last_error", "gc_kernel_time_ms", "gc_launch_bytes",
     "gc_memory_info", "gc_autotune", "gc_saturation", "gc_paper_saturation",
 ]
 
@@ -38,18 +38,20 @@ class gc_tune_result(ctypes.Structure):
 
 
 class gc_ctx_params(ctypes.Structure):
-    _fields_ = [("device", ctypes.c_int32), ("n_streams", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64)]
+    _fields_ = [("device", ctypes.c_int32), ("n_streams", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64),
+                ("hip_stream", ctypes.c_void_p), ("tune_cache", ctypes.c_char_p)]
 
 
 class gc_lattice(ctypes.Structure):
-    _fields_ = [("dim", ctypes.c_int32), ("extent", ctypes.c_int32 * 4)]
+    _fields_ = [("dim", ctypes.c_int32), ("extent", ctypes.c_int32 * 4), ("antiperiodic", ctypes.c_uint32)]
 
 
 class gc_solve_params(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_double), ("eps32", ctypes.c_double), ("eps64", ctypes.c_double),
                 ("lambda_tol", ctypes.c_double), ("precision", ctypes.c_int32), ("stop_norm", ctypes.c_int32),
                 ("check_every", ctypes.c_uint32), ("lanczos_max_iter", ctypes.c_uint32),
-                ("max_sweeps", ctypes.c_uint64), ("start_seed", ctypes.c_uint64), ("first_start", ctypes.c_uint64)]
+                ("max_sweeps", ctypes.c_uint64), ("start_seed", ctypes.c_uint64), ("first_start", ctypes.c_uint64),
+                ("sync_batch", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
 
 
 class gc_progress(ctypes.Structure):
@@ -57,17 +59,17 @@ class gc_progress(ctypes.Structure):
         (n, ctypes.c_uint64) for n in ("n_starts", "starts_done", "converged", "nonconverged", "distinct",
                                        "in_region", "saddles", "singular", "collisions", "sweeps_total",
                                        "site_updates", "lanczos_runs", "paper_count")] + [
-        ("submit_to_done_ms", ctypes.c_double), ("device_ms", ctypes.c_double)]
+        ("submit_to_done_ms", ctypes.c_double), ("device_ms", ctypes.c_double), ("post_ms", ctypes.c_double)]
 
 
 COPY_DTYPE = np.dtype([("key_hi", np.uint64), ("key_lo", np.uint64), ("F", np.float64), ("x", np.float64),
                        ("lambda2", np.float64), ("hits", np.uint64), ("first_start", np.uint64),
-                       ("flags", np.uint32), ("lanczos_iters", np.uint32)])
+                       ("rep_start", np.uint64), ("flags", np.uint32), ("lanczos_iters", np.uint32)])
 START_DTYPE = np.dtype([("status", np.int32), ("sweeps32", np.uint32), ("sweeps64", np.uint32),
                         ("lanczos_iters", np.uint32), ("F", np.float64), ("D", np.float64),
                         ("lambda2", np.float64), ("key_hi", np.uint64), ("key_lo", np.uint64),
                         ("paper_X", np.uint32), ("flags", np.uint32)])
-assert COPY_DTYPE.itemsize == 64 and START_DTYPE.itemsize == 64
+assert COPY_DTYPE.itemsize == 72 and START_DTYPE.itemsize == 64
 
 
 class GcError(RuntimeError):
@@ -112,7 +114,8 @@ def lib():
         "gc_wait": ([vp, u64, i64], i32),
         "gc_fetch": ([vp, u64, u64, u64, vp, P(u64), P(u64)], i32),
         "gc_fetch_starts": ([vp, u64, u64, u64, vp, P(u64)], i32),
-        "gc_fetch_state": ([vp, u64, u64, P(ctypes.c_double)], i32),
+        "gc_fetch_state": ([vp, u64, u64, u64, P(ctypes.c_double)], i32),
+        "gc_fetch_start_state": ([vp, u64, u64, P(ctypes.c_double)], i32),
         "gc_release": ([vp, u64], i32),
         "gc_last_error": ([vp, ctypes.c_char_p, ctypes.c_size_t], i32),
         "gc_kernel_time_ms": ([vp, u64, P(ctypes.c_double)], i32),
@@ -138,19 +141,20 @@ def gc_status_str(s: int) -> str:
     return lib().gc_status_str(int(s)).decode()
 
 
-def _lattice(extent) -> gc_lattice:
+def _lattice(extent, antiperiodic: int = 0) -> gc_lattice:
     ext = [int(n) for n in extent]
     lat = gc_lattice()
     lat.dim = len(ext)
     for k in range(4):
         lat.extent[k] = ext[k] if k < len(ext) else 0
+    lat.antiperiodic = int(antiperiodic)
     return lat
 
 
-def gc_lattice_check(extent):
+def gc_lattice_check(extent, antiperiodic: int = 0):
     """Returns (status, n_colours)."""
     K = ctypes.c_int32(0)
-    lat = _lattice(extent)
+    lat = _lattice(extent, antiperiodic)
     st = lib().gc_lattice_check(ctypes.byref(lat), ctypes.byref(K))
     return int(st), int(K.value)
 
@@ -174,6 +178,7 @@ class SolveParams:
     max_sweeps: int = 100_000
     start_seed: int = 0
     first_start: int = 0
+    sync_batch: int = 0           # > 0: batch-synchronous stop over batches of this many starts
 
     def c(self) -> gc_solve_params:
         p = gc_solve_params()
@@ -183,15 +188,18 @@ class SolveParams:
         p.check_every = self.check_every
         p.lanczos_max_iter = self.lanczos_max_iter
         p.max_sweeps, p.start_seed, p.first_start = self.max_sweeps, self.start_seed, self.first_start
+        p.sync_batch = self.sync_batch
         return p
 
 
 class Context:
     """One gc_ctx.  Methods mirror the C entry points."""
 
-    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, n_streams: int = 0):
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, n_streams: int = 0, hip_stream: int = 0,
+                 tune_cache: str | None = None):
         self._L = lib()
-        prm = gc_ctx_params(device, n_streams, hbm_budget_bytes)
+        self._tune_cache = tune_cache.encode() if tune_cache else None
+        prm = gc_ctx_params(device, n_streams, hbm_budget_bytes, hip_stream or None, self._tune_cache)
         h = ctypes.c_void_p()
         st = self._L.gc_create(ctypes.byref(prm), ctypes.byref(h))
         if st != GC_OK:
@@ -224,8 +232,8 @@ class Context:
             pass
 
     # -- orbits --------------------------------------------------------------
-    def gc_orbit_load(self, extent, phi, orbit_index: int = 0) -> int:
-        lat = _lattice(extent)
+    def gc_orbit_load(self, extent, phi, orbit_index: int = 0, antiperiodic: int = 0) -> int:
+        lat = _lattice(extent, antiperiodic)
         phi = np.ascontiguousarray(phi, dtype=np.float64)
         out = ctypes.c_uint64()
         st = self._L.gc_orbit_load(self._h, ctypes.byref(lat), phi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -234,8 +242,8 @@ class Context:
         self.extent[out.value] = tuple(int(n) for n in extent)
         return out.value
 
-    def gc_orbit_random(self, extent, seed: int = 0, orbit_index: int = 0) -> int:
-        lat = _lattice(extent)
+    def gc_orbit_random(self, extent, seed: int = 0, orbit_index: int = 0, antiperiodic: int = 0) -> int:
+        lat = _lattice(extent, antiperiodic)
         out = ctypes.c_uint64()
         self._check(self._L.gc_orbit_random(self._h, ctypes.byref(lat), seed, orbit_index, ctypes.byref(out)),
                     "gc_orbit_random")
@@ -289,11 +297,19 @@ class Context:
                                             ctypes.byref(nw)), "gc_fetch_starts")
         return out[:nw.value]
 
-    def gc_fetch_state(self, orbit: int, start_id: int) -> np.ndarray:
+    def gc_fetch_state(self, orbit: int, key_hi: int, key_lo: int) -> np.ndarray:
         ext = self.extent[orbit]
         out = np.empty(int(np.prod(ext)), dtype=np.float64)
-        self._check(self._L.gc_fetch_state(self._h, orbit, start_id,
+        self._check(self._L.gc_fetch_state(self._h, orbit, int(key_hi), int(key_lo),
                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "gc_fetch_state")
+        return out
+
+    def gc_fetch_start_state(self, orbit: int, start_id: int) -> np.ndarray:
+        ext = self.extent[orbit]
+        out = np.empty(int(np.prod(ext)), dtype=np.float64)
+        self._check(self._L.gc_fetch_start_state(self._h, orbit, start_id,
+                                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                    "gc_fetch_start_state")
         return out
 
     def gc_release(self, orbit: int):

@@ -25,6 +25,7 @@
 
 // Job flags.
 #define GC_JOB_FIX 2u          // post-process the representatives listed in fix[], always run the filter
+#define GC_JOB_SYNC2 4u        // batch-synchronous second pass: start s runs exactly fixed_sweeps[s] sweeps
 
 // Relative spread of F (per site) above which one key is flagged as reached
 // by different stationary points.
@@ -86,7 +87,7 @@ struct GcCounters {
 struct GcCopyRec {
     uint64_t key_hi, key_lo;
     double F, x, lambda2;
-    uint64_t hits, first_start;
+    uint64_t hits, first_start, rep_start;
     uint32_t flags, lanczos_iters;
 };
 
@@ -96,7 +97,7 @@ struct GcJobDev {
     double omega, eps32, eps64, lambda_tol;
     int32_t precision, stop_norm, check_every, lanczos_max;
     uint64_t max_sweeps, start_seed, first_start, n_starts;
-    uint32_t flags, pad;
+    uint32_t flags, sync_batch;      // sync_batch: starts per batch of the batch-synchronous stop (0: off)
     GcStartRec *rec;                 // [n_starts]
     GcEntry *table;                  // [table_mask + 1]
     uint64_t table_mask;
@@ -107,11 +108,12 @@ struct GcJobDev {
     GcFix *fix;                      // [n_starts] representatives to filter
     unsigned long long *n_fix;
     uint32_t *blk;                   // [(table_mask + 1) / 256] per-block copy counts, then offsets
+    uint32_t *fixed_sweeps;          // [n_starts] batch-synchronous sweep counts (sync_batch > 0), else null
 };
 
 static_assert(sizeof(GcStartRec) == 64, "record layout");
 static_assert(sizeof(GcEntry) == 64, "entry layout");
-static_assert(sizeof(GcCopyRec) == 64, "copy layout");
+static_assert(sizeof(GcCopyRec) == 72, "copy layout");
 
 // Relax kernel, one workgroup per start (any colouring).
 size_t gc_relax_wg_lds_bytes(int V);
@@ -137,6 +139,10 @@ hipError_t gc_launch_finalize(const GcJobDev *jobs_host, int n_jobs, hipStream_t
 hipError_t gc_launch_patch(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);      // fix-up results -> copies
 hipError_t gc_launch_orbit_random(double *phi, int64_t n_links, uint64_t seed, uint64_t orbit_index, hipStream_t s);
 hipError_t gc_launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
+// Batch-synchronous stop: per batch of sync_batch starts, the largest
+// first-pass sweep count, written per start to fixed_sweeps; relax counters
+// cleared for the second pass.
+hipError_t gc_launch_sync(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);
 
 // Value-based count: paper_X < GC_PAPER_VALUES (x <= 2 gives at most 2e8),
 // one bit per value.

@@ -735,6 +735,7 @@ __global__ __launch_bounds__(256) void scatter_kernel(GcJobDev J)
     c.x = r.F / dV;
     c.hits = e.hits;
     c.first_start = e.first_start;
+    c.rep_start = rep;
     const double fmin = __longlong_as_double((long long)e.fmin_bits);
     const double fmax = __longlong_as_double((long long)e.fmax_bits);
     const uint32_t col = ((fmax - fmin) / (double)J.orb.V > GC_F_SPREAD_PER_SITE) ? GC_F_COLLISION : 0u;
@@ -805,6 +806,30 @@ __global__ void orbit_random_kernel(double *phi, int64_t n_links, uint64_t seed,
 #pragma unroll
     for (int k = 0; k < 4; ++k)
         if (4 * b + k < n_links) phi[4 * b + k] = angle_of(c[k]);
+}
+
+// Batch-synchronous stop (Sec. III: one stopping test over all samples
+// relaxed together): after a first pass in which every start stopped on its
+// own, each start of the batch [b k, (b + 1) k) of the launch gets the
+// batch's largest sweep count; the second pass runs exactly that many.  The
+// relax counters are cleared so that they count the second pass.
+__global__ void sync_kernel(GcJobDev J)
+{
+    const uint64_t k = J.sync_batch;
+    const uint64_t nb = (J.n_starts + k - 1) / k;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += stride) {
+        const uint64_t lo = b * k, hi = min(J.n_starts, lo + k);
+        uint32_t T = 0;
+        for (uint64_t s = lo; s < hi; ++s) T = max(T, J.rec[s].sweeps64);
+        for (uint64_t s = lo; s < hi; ++s) J.fixed_sweeps[s] = T;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        J.cnt->starts_done = 0;
+        J.cnt->converged = 0;
+        J.cnt->nonconverged = 0;
+        J.cnt->sweeps_total = 0;
+    }
 }
 
 __global__ void zero_u64_kernel(unsigned long long *p, int n)
@@ -991,6 +1016,18 @@ hipError_t gc_launch_orbit_random(double *phi, int64_t n_links, uint64_t seed, u
     hipLaunchKernelGGL(orbit_random_kernel, dim3((unsigned)((blocks4 + 255) / 256)), dim3(256), 0, s, phi, n_links,
                        seed, orbit_index);
     return hipGetLastError();
+}
+
+hipError_t gc_launch_sync(const GcJobDev *jobs_host, int n_jobs, hipStream_t s)
+{
+    for (int j = 0; j < n_jobs; ++j) {
+        const GcJobDev &J = jobs_host[j];
+        const uint64_t nb = (J.n_starts + J.sync_batch - 1) / J.sync_batch;
+        hipLaunchKernelGGL(sync_kernel, dim3(grid_for(nb)), dim3(256), 0, s, J);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t gc_launch_zero_u64(unsigned long long *p, int n, hipStream_t s)

@@ -77,9 +77,12 @@ __device__ __forceinline__ typename cx<R>::T staple(const GcOrbitDev &O, const t
     return s;
 }
 
+// Sweeps of one precision until the stopping norm is below eps (checked
+// every check_every sweeps and at the cap), or, with fixed, exactly cap
+// sweeps with the norm taken after the last (batch-synchronous pass).
 template <typename R, int B>
-__device__ int relax_phase(const GcJobDev &J, typename cx<R>::T *st, double eps, uint64_t &sweeps, double &D,
-                           double *red)
+__device__ int relax_phase(const GcJobDev &J, typename cx<R>::T *st, double eps, uint64_t cap, bool fixed,
+                           uint64_t &sweeps, double &D, double *red)
 {
     using C = typename cx<R>::T;
     const GcOrbitDev &O = J.orb;
@@ -91,7 +94,7 @@ __device__ int relax_phase(const GcJobDev &J, typename cx<R>::T *st, double eps,
     uint64_t t = 0;
     int status = GC_ST_NONCONVERGED;
     D = INFINITY;
-    while (t < J.max_sweeps) {
+    while (t < cap) {
         for (int c = 0; c < K; ++c) {
             const int lo = O.coff[c], hi = O.coff[c + 1];
             for (int p = lo + tid; p < hi; p += B) {
@@ -102,7 +105,7 @@ __device__ int relax_phase(const GcJobDev &J, typename cx<R>::T *st, double eps,
             __syncthreads();
         }
         ++t;
-        if (t % check == 0 || t == J.max_sweeps) {
+        if ((!fixed && t % check == 0) || t == cap) {
             double acc = 0.0;
             for (int i = tid; i < V; i += B) {
                 const C s = staple<R>(O, U, st, i);
@@ -112,7 +115,12 @@ __device__ int relax_phase(const GcJobDev &J, typename cx<R>::T *st, double eps,
             }
             D = J.stop_norm ? wg_max<B>(acc, red) : wg_sum<B>(acc, red) / (double)V;
             if (!(D == D)) { status = GC_ST_BADNUM; break; }
-            if (D < eps) { status = GC_ST_CONVERGED; break; }
+            if (D < eps) {
+                status = GC_ST_CONVERGED;
+                if (!fixed) break;
+            } else {
+                status = GC_ST_NONCONVERGED;
+            }
         }
     }
     sweeps = t;
@@ -165,8 +173,10 @@ __global__ __launch_bounds__(B) void relax_wg_kernel(const GcJobDev *__restrict_
         double D = INFINITY;
         int status;
         bool in64 = J.precision != 1;
+        const bool fixed = (J.flags & GC_JOB_SYNC2) != 0;
+        const uint64_t cap = fixed ? (uint64_t)J.fixed_sweeps[local] : J.max_sweeps;
         if (J.precision == 1) {
-            status = relax_phase<float, B>(J, st32, J.eps32, sw32, D, red);
+            status = relax_phase<float, B>(J, st32, J.eps32, J.max_sweeps, false, sw32, D, red);
             if (status == GC_ST_CONVERGED) {
                 in64 = true;
                 for (int i = tid; i < V; i += B) {
@@ -176,10 +186,10 @@ __global__ __launch_bounds__(B) void relax_wg_kernel(const GcJobDev *__restrict_
                     st64[i] = dbl2{xr * r, xi * r};
                 }
                 __syncthreads();
-                status = relax_phase<double, B>(J, st64, J.eps64, sw64, D, red);
+                status = relax_phase<double, B>(J, st64, J.eps64, J.max_sweeps, false, sw64, D, red);
             }
         } else {
-            status = relax_phase<double, B>(J, st64, J.eps64, sw64, D, red);
+            status = relax_phase<double, B>(J, st64, J.eps64, cap, fixed, sw64, D, red);
         }
         dbl2 *out = reinterpret_cast<dbl2 *>(J.states + local * (uint64_t)V);
         for (int i = tid; i < V; i += B)

@@ -50,6 +50,7 @@ uint64_t next_pow2(uint64_t x)
 // Lattice checks and geometry (Sec. I: periodic lattice; Sec. III: checkerboard)
 // ---------------------------------------------------------------------------
 constexpr int kMaxV = 4096;
+constexpr double kPiD = 3.14159265358979311599796346854;   // fl(pi)
 
 int num_colours(int d, const int *n)
 {
@@ -77,6 +78,7 @@ gc_status check_lattice(const gc_lattice *lat, int *K_out, int *V_out)
         V *= lat->extent[mu];
         if (V > 65536) return GC_EUNSUPPORTED;
     }
+    if (lat->antiperiodic >> lat->dim) return GC_EINVAL;
     const int K = num_colours(lat->dim, lat->extent);
     if (K == 0) return GC_EUNSUPPORTED;
     if (K_out) *K_out = K;
@@ -136,27 +138,100 @@ struct Pool {
     }
 };
 
+// Pinned host blocks for a job's descriptor staging and its result
+// counters, reused like the device pool: hipHostMalloc and hipHostFree are
+// kept off the launch and release paths (a free waits for the device).
+struct PinnedPool {
+    std::multimap<size_t, void *> free_blocks;
+
+    hipError_t get(size_t bytes, void **p, size_t *got)
+    {
+        bytes = std::max<size_t>(next_pow2(bytes), 4096);
+        auto it = free_blocks.find(bytes);
+        if (it != free_blocks.end()) {
+            *p = it->second;
+            *got = bytes;
+            free_blocks.erase(it);
+            return hipSuccess;
+        }
+        *got = bytes;
+        return hipHostMalloc(p, bytes, hipHostMallocDefault);
+    }
+    void put(void *p, size_t bytes)
+    {
+        if (p) free_blocks.emplace(bytes, p);
+    }
+    void drain()
+    {
+        for (auto &kv : free_blocks) (void)hipHostFree(kv.second);
+        free_blocks.clear();
+    }
+};
+
 struct Orbit;
+
+// Relax launch groups: orbits with odd extents use the workgroup-per-start
+// kernel; orbits with even extents the wavefront-per-start kernel, one launch
+// per dimension, layout and slot count (the kernel is specialised on them).
+struct Group {
+    bool wave = false;
+    int d = 0;
+    std::vector<int> jobs;           // indices into Job::orbits
+    int block = 64, grid = 1, ns = 1, coef_lds = 0, creg = 0, wps = 0;
+    size_t lds = 0;
+    size_t o_jobs = 0, o_worbs = 0, o_next = 0, o_prefix = 0, o_bounce = 0;
+    size_t o_jobs1 = 0;              // first-pass descriptors of a batch-synchronous launch
+    uint64_t total = 0;
+};
+
+// Orbits of one relax group sharing one post-kernel shape (workgroup size by
+// V), so that an orbit's per-start arithmetic is the same alone and in a
+// batch.
+struct PostGroup {
+    int block = 64, sp = 1, wreg = 1, grid = 1;
+    size_t lds = 0;
+    uint64_t total = 0, wstride = 0;
+    std::vector<int> jobs;
+    int chain = 0;                   // relax group whose orbits these are
+    size_t o_jobs = 0, o_prefix = 0, o_next = 0, o_wbuf = 0;
+};
+
+// Device memory of one job.
+struct JobLayout {
+    std::vector<size_t> o_rec, o_table, o_cnt, o_copies, o_ncopies, o_fix, o_nfix, o_states, o_blk, o_sync;
+    std::vector<uint64_t> table_cap;
+    std::vector<Group> groups;
+    std::vector<PostGroup> posts;
+    std::vector<int> post_of;   // job -> post group
+    std::vector<size_t> o_fixjobs, o_fixnext;   // per job
+    size_t total = 0;
+};
 
 struct Job {
     std::vector<Orbit *> orbits;     // one for gc_launch, several for a batch
     std::vector<uint64_t> n_starts;
     gc_solve_params p{};
     int state = GC_ORBIT_QUEUED;
+    gc_status err = GC_OK;           // why the job ended in GC_ORBIT_ERROR
     bool graph = false;
-    size_t bytes = 0;                // budget charge while running
-    void *mem = nullptr;             // working block
-    int stream = 0;
+    size_t bytes = 0;                // budget charge while its memory is held
+    void *mem = nullptr;             // working block (results stay in it)
+    void *staging = nullptr;         // pinned descriptors + result counters
+    size_t staging_bytes = 0;
+    int stream = -1;
     hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_k2 = nullptr, ev_done = nullptr;
     hipGraph_t g = nullptr;
     hipGraphExec_t gx = nullptr;
+    JobLayout L;
     Clock::time_point t_submit, t_done;
     std::vector<GcJobDev> jobs;      // host images of the per-orbit job structs
-    // pinned host results
+    // pinned host results (inside staging)
     GcCounters *h_cnt = nullptr;               // [n_jobs]
     unsigned long long *h_ncopies = nullptr;   // [n_jobs]
     double solve_ms = 0.0, post_ms = 0.0;
     uint64_t total = 0;
+    // kernel variants forced for this job (gc_autotune trials), -1 / 0: none
+    int force_creg = -1, force_post_block = 0, force_post_sp = 0, force_wps = -1;
 };
 
 struct Orbit {
@@ -164,18 +239,17 @@ struct Orbit {
     gc_lattice lat{};
     int d = 0, V = 0, K = 0;
     uint64_t orbit_index = 0;
-    std::vector<double> phi;
+    std::vector<double> phi;         // as loaded
     void *tables = nullptr;
     size_t table_bytes = 0;
     GcOrbitDev dev{};
     GcWaveOrbit wdev{};              // colour-split tables (K == 2 only)
     void *wave_tables = nullptr;
+    size_t wave_bytes = 0;
     // results of the last launch
     Job *job = nullptr;
     int job_index = 0;               // position inside a batch job
-    void *res_mem = nullptr;         // device block with rec/table/copies kept after DONE
-    size_t res_bytes = 0;
-    GcJobDev res{};                  // pointers into res_mem
+    GcJobDev res{};                  // pointers into the job's block
     bool have_copies = false;
     std::vector<gc_copy> copies;
     bool have_starts = false;
@@ -192,17 +266,21 @@ struct gc_ctx {
     size_t lds_max = 0;
     int creg_override = -1;   // GC_WAVE_CREG: register-held coefficient colours (tuning)
     int wps_override = -1;    // GC_WPS: 1 workgroup per start where available, 0 never (tuning)
-    // kernel variants chosen by gc_autotune: relax coefficient colours per
-    // (d, slots per lane, precision), post workgroup shape per V; and the
-    // variant forced while gc_autotune measures
+    // kernel variants chosen by gc_autotune: relax coefficient colours and
+    // layout per (d, slots per lane, precision), post workgroup shape per V
     std::map<uint64_t, int> tune_creg;
     std::map<uint64_t, int> tune_wps;   // workgroup-per-start layout on (1) or off (0)
     std::map<int, std::pair<int, int>> tune_post;
-    int force_creg = -1, force_post_block = 0, force_post_sp = 0, force_wps = -1;
+    std::string tune_cache;             // file the choices persist in ("" none)
     uint64_t budget = 0, used = 0;
-    std::vector<hipStream_t> streams;
+    std::vector<hipStream_t> streams;   // launch streams (the caller's one when given)
+    bool own_streams = true;
+    std::vector<hipStream_t> aux;       // fork streams for graph capture of batches
+    hipStream_t util = nullptr;         // small synchronous helpers (orbit generation, counts)
     std::vector<int> stream_load;
     Pool pool;
+    PinnedPool pinned;
+    std::vector<hipEvent_t> events, events_nt;   // reusable timing / non-timing events
     std::mutex mu;
     std::condition_variable cv;       // wakes the scheduler
     std::condition_variable done_cv;  // wakes waiters
@@ -271,10 +349,19 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
             if (col[i] == c) perm.push_back((uint16_t)i);
     }
     coff[o->K] = V;
+    // antiperiodic gauge transformations in direction mu are the periodic
+    // problem with U -> -U on the links that wrap around mu, i.e. phi + pi
+    // there: that angle enters U and the plaquette and line sums of the key
+    std::vector<double> pe(o->phi);
+    for (int mu = 0; mu < d; ++mu) {
+        if (!((o->lat.antiperiodic >> mu) & 1u)) continue;
+        for (int i = 0; i < V; ++i)
+            if (coord[(size_t)i * d + mu] == n[mu] - 1) pe[(size_t)mu * V + i] += kPiD;
+    }
     std::vector<double2> U64((size_t)d * V);
     std::vector<float2> U32((size_t)d * V);
     for (size_t l = 0; l < (size_t)d * V; ++l) {
-        U64[l] = make_double2(std::cos(o->phi[l]), std::sin(o->phi[l]));
+        U64[l] = make_double2(std::cos(pe[l]), std::sin(pe[l]));
         U32[l] = make_float2((float)U64[l].x, (float)U64[l].y);
     }
     GcOrbitDev &D = o->dev;
@@ -292,7 +379,7 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
         }
     D.n_plaq = np * V;
     std::vector<double> phi_plaq((size_t)D.n_plaq);
-    const double *phi = o->phi.data();
+    const double *phi = pe.data();
     for (int p = 0; p < np; ++p) {
         const int mu = D.plane_mu[p], nu = D.plane_nu[p];
         for (int i = 0; i < V; ++i) {
@@ -341,7 +428,10 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
     memcpy(&host[o_pl], phi_line.data(), phi_line.size() * 8);
     memcpy(&host[o_ls], line_site.data(), line_site.size() * 2);
     void *dev = nullptr;
-    GC_HIP(hipMalloc(&dev, off));
+    size_t got = 0;
+    GC_HIP(ctx->pool.get(off, &dev, &got));
+    o->tables = dev;
+    o->table_bytes = got;
     GC_HIP(hipMemcpy(dev, host.data(), off, hipMemcpyHostToDevice));
     unsigned char *b = (unsigned char *)dev;
     D.coff = (const int32_t *)(b + o_coff);
@@ -352,8 +442,6 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
     D.phi_plaq = (const double *)(b + o_pp);
     D.phi_line = (const double *)(b + o_pl);
     D.line_site = (const uint16_t *)(b + o_ls);
-    o->tables = dev;
-    o->table_bytes = off;
     memset(&o->wdev, 0, sizeof o->wdev);
     if (o->K == 2) {
         // colour-split tables: (c, h) with c the colour, h = i >> 1
@@ -404,7 +492,9 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
         memcpy(&wh[w_c32], c32.data(), c32.size() * 8);
         memcpy(&wh[w_desc], desc.data(), desc.size() * 4);
         void *wdevmem = nullptr;
-        GC_HIP(hipMalloc(&wdevmem, woff));
+        GC_HIP(ctx->pool.get(woff, &wdevmem, &got));
+        o->wave_tables = wdevmem;
+        o->wave_bytes = got;
         GC_HIP(hipMemcpy(wdevmem, wh.data(), woff, hipMemcpyHostToDevice));
         unsigned char *wb = (unsigned char *)wdevmem;
         o->wdev.half = half;
@@ -413,54 +503,73 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
         o->wdev.coef64 = (const double2 *)(wb + w_c64);
         o->wdev.coef32 = (const float2 *)(wb + w_c32);
         o->wdev.desc = (const uint32_t *)(wb + w_desc);
-        o->wave_tables = wdevmem;
     }
     return GC_OK;
 }
 
-// Relax launch groups: orbits with odd extents use the workgroup-per-start
-// kernel; orbits with even extents the wavefront-per-start kernel, one launch
-// per dimension (that kernel is specialised on d).
-struct Group {
-    bool wave = false;
-    int d = 0;
-    std::vector<int> jobs;           // indices into Job::orbits
-    int block = 64, grid = 1, ns = 1, coef_lds = 0, creg = 0, wps = 0;
-    size_t lds = 0;
-    size_t o_jobs = 0, o_worbs = 0, o_next = 0, o_prefix = 0, o_bounce = 0;
-    uint64_t total = 0;
-};
+// Device block from the context's pool; on exhaustion the cached blocks are
+// returned to the device once and the request retried.  Out of memory is
+// GC_ENOMEM (the context stays usable).
+gc_status pool_get(gc_ctx *ctx, size_t bytes, void **p, size_t *got)
+{
+    hipError_t e = ctx->pool.get(bytes, p, got);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        ctx->pool.drain();
+        e = ctx->pool.get(bytes, p, got);
+    }
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return GC_ENOMEM;
+    }
+    if (e != hipSuccess) return fail(ctx, e, "hipMalloc");
+    return GC_OK;
+}
 
-// Orbits sharing one post-kernel shape (workgroup size by V), so that an
-// orbit's per-start arithmetic is the same alone and in a batch.
-struct PostGroup {
-    int block = 64, sp = 1, wreg = 1, grid = 1;
-    size_t lds = 0;
-    uint64_t total = 0, wstride = 0;
-    std::vector<int> jobs;
-    size_t o_jobs = 0, o_prefix = 0, o_next = 0, o_wbuf = 0;
-};
+hipEvent_t take_event(gc_ctx *ctx, bool timing)
+{
+    std::vector<hipEvent_t> &v = timing ? ctx->events : ctx->events_nt;
+    if (!v.empty()) {
+        hipEvent_t e = v.back();
+        v.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, timing ? hipEventDefault : hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
 
-// Device memory of one job.
-struct JobLayout {
-    std::vector<size_t> o_rec, o_table, o_cnt, o_copies, o_ncopies, o_fix, o_nfix, o_states, o_blk;
-    std::vector<uint64_t> table_cap;
-    std::vector<Group> groups;
-    std::vector<PostGroup> posts;
-    std::vector<int> post_of;   // job -> post group
-    size_t o_fixjobs = 0, o_fixnext = 0;
-    size_t total = 0;
-};
+void give_event(gc_ctx *ctx, hipEvent_t &e, bool timing)
+{
+    if (e) (timing ? ctx->events : ctx->events_nt).push_back(e);
+    e = nullptr;
+}
 
+// The instantiated slot count of the one-wavefront kernel for ns slots per
+// lane (orbits of one bucket share a kernel).
+int ns_bucket(int d, int ns)
+{
+    static const int b1[] = {1, 4, 12, 32}, b2[] = {1, 2, 4, 12, 32}, b3[] = {2, 4, 8, 32}, b4[] = {1, 2, 4, 11, 32};
+    const int *b = d == 1 ? b1 : d == 2 ? b2 : d == 3 ? b3 : b4;
+    const int nb = d == 1 ? 4 : d == 2 ? 5 : d == 3 ? 4 : 5;
+    for (int k = 0; k < nb; ++k)
+        if (ns <= b[k]) return b[k];
+    return 32;
+}
+
+// Layout of a job's device block and its launch groups.  Each orbit runs the
+// context's tuned kernel variant for its shape unless the job forces one
+// (autotune trials).  Orbits are grouped by relax kernel; each group is one
+// chain of launches (relax, post, finalize) that a batch runs concurrently
+// with the other chains.
 gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
 {
+    L = JobLayout{};
     const int nj = (int)job->orbits.size();
+    const bool mixed = job->p.precision == GC_MIXED;
     size_t off = 0;
     auto place = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes, 256); return at; };
-    L.o_fixjobs = place(sizeof(GcJobDev) * nj);
-    L.o_fixnext = place(sizeof(unsigned long long));
-    int maxV = 0, maxd = 0;
-    uint64_t total = 0;
     for (int j = 0; j < nj; ++j) {
         Orbit *o = job->orbits[j];
         const uint64_t n = job->n_starts[j];
@@ -476,9 +585,9 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         L.o_nfix.push_back(place(sizeof(unsigned long long)));
         L.o_blk.push_back(place(sizeof(uint32_t) * ((cap + 255) / 256)));
         L.o_states.push_back(place(sizeof(double2) * n * (uint64_t)o->V));
-        maxV = std::max(maxV, o->V);
-        maxd = std::max(maxd, o->d);
-        total += n;
+        L.o_sync.push_back(job->p.sync_batch ? place(sizeof(uint32_t) * n) : 0);
+        L.o_fixjobs.push_back(place(sizeof(GcJobDev)));
+        L.o_fixnext.push_back(place(sizeof(unsigned long long)));
         // two colours: one wavefront per start (GC_WAVES states per
         // workgroup in LDS) up to 128 slots per colour, a workgroup of wps
         // wavefronts per start above; other colourings take the generic
@@ -488,33 +597,34 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         if (wps > 0 && (size_t)(GC_WAVES + 1) * 16 * o->V <= ctx->lds_max) {
             // both layouts fit: one wavefront per start unless tuned otherwise
             int on = 0;
-            const auto tw = ctx->tune_wps.find(creg_key(o->d, o_ns, job->p.precision == GC_MIXED));
+            const auto tw = ctx->tune_wps.find(creg_key(o->d, o_ns, mixed));
             if (tw != ctx->tune_wps.end()) on = tw->second;
             if (ctx->wps_override >= 0) on = ctx->wps_override;
-            if (ctx->force_wps >= 0) on = ctx->force_wps;
+            if (job->force_wps >= 0) on = job->force_wps;
             if (!on) wps = 0;
         }
         if (wps > 0 && 32 * (size_t)o->V > ctx->lds_max) wps = -1;
         const bool wave = (o->K == 2) && wps >= 0 && (wps > 0 || (size_t)(GC_WAVES + 1) * 16 * o->V <= ctx->lds_max);
-        // groups by dimension and wavefronts per start, or (generic) by
-        // block size, so that an orbit's reductions run in the same order
-        // alone and batched
+        // groups by kernel: dimension, layout and instantiated slot count,
+        // or (generic) block size; an orbit's arithmetic does not depend on
+        // the other orbits of its group
         const int gd = wave ? o->d : -block_for(o->V);
         const int gw = wave ? std::max(wps, 0) : 0;
+        const int gb = (wave && gw == 0) ? ns_bucket(o->d, o_ns) : 0;
         Group *g = nullptr;
         for (Group &x : L.groups)
-            if (x.wave == wave && x.d == gd && x.wps == gw) g = &x;
+            if (x.wave == wave && x.d == gd && x.wps == gw && x.ns == gb) g = &x;
         if (!g) {
             L.groups.push_back(Group{});
             g = &L.groups.back();
             g->wave = wave;
             g->d = gd;
             g->wps = gw;
+            g->ns = gb;
         }
         g->jobs.push_back(j);
         g->total += n;
     }
-    const bool mixed = job->p.precision == GC_MIXED;
     for (Group &g : L.groups) {
         int gV = 0;
         for (int j : g.jobs) gV = std::max(gV, job->orbits[j]->V);
@@ -541,9 +651,9 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             // of three); GC_WAVE_CREG overrides
             g.creg = std::min(1, gc_wave_creg_max(g.d, g.ns));
             const auto tc = ctx->tune_creg.find(creg_key(g.d, g.ns, mixed));
-            if (tc != ctx->tune_creg.end()) g.creg = tc->second;
+            if (tc != ctx->tune_creg.end()) g.creg = std::min(tc->second, gc_wave_creg_max(g.d, g.ns));
             if (ctx->creg_override >= 0) g.creg = std::min(ctx->creg_override, gc_wave_creg_max(g.d, g.ns));
-            if (ctx->force_creg >= 0) g.creg = std::min(ctx->force_creg, gc_wave_creg_max(g.d, g.ns));
+            if (job->force_creg >= 0) g.creg = std::min(job->force_creg, gc_wave_creg_max(g.d, g.ns));
             hipError_t e = gc_wave_occupancy(g.d, g.ns, g.coef_lds | (g.creg << 1), g.lds, &per_cu);
             if (e != hipSuccess) return fail(ctx, e, "occupancy");
         } else {
@@ -559,41 +669,46 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         grid = std::min<uint64_t>(grid, std::max<uint64_t>((g.total + per_wg - 1) / per_wg, 1));
         g.grid = (int)grid;
         g.o_jobs = place(sizeof(GcJobDev) * g.jobs.size());
+        g.o_jobs1 = job->p.sync_batch ? place(sizeof(GcJobDev) * g.jobs.size()) : 0;
         g.o_worbs = place(sizeof(GcWaveOrbit) * g.jobs.size());
         g.o_next = place(sizeof(unsigned long long) * g.jobs.size());
         g.o_prefix = place(sizeof(uint64_t) * (g.jobs.size() + 1));
         g.o_bounce = g.wave ? place(sizeof(float2) * (size_t)gV * per_wg * g.grid) : 0;
     }
     // post pass: one workgroup per start, one launch per workgroup shape
+    // within each relax group's chain
     L.post_of.assign(nj, -1);
-    for (int j = 0; j < nj; ++j) {
-        int block = 0, sp = 0, wreg = 0;
-        gc_post_shape(job->orbits[j]->V, &block, &sp, &wreg);
-        const auto tp = ctx->tune_post.find(job->orbits[j]->V);
-        if (tp != ctx->tune_post.end()) {
-            block = tp->second.first;
-            sp = tp->second.second;
-            wreg = 1;
+    for (size_t gi = 0; gi < L.groups.size(); ++gi) {
+        for (int j : L.groups[gi].jobs) {
+            int block = 0, sp = 0, wreg = 0;
+            gc_post_shape(job->orbits[j]->V, &block, &sp, &wreg);
+            const auto tp = ctx->tune_post.find(job->orbits[j]->V);
+            if (tp != ctx->tune_post.end()) {
+                block = tp->second.first;
+                sp = tp->second.second;
+                wreg = 1;
+            }
+            if (job->force_post_block > 0) {
+                block = job->force_post_block;
+                sp = job->force_post_sp;
+                wreg = 1;
+            }
+            if (block == 0) return GC_EUNSUPPORTED;
+            int k = 0;
+            while (k < (int)L.posts.size() && !(L.posts[k].chain == (int)gi && L.posts[k].block == block &&
+                                                L.posts[k].sp == sp && L.posts[k].wreg == wreg))
+                ++k;
+            if (k == (int)L.posts.size()) {
+                L.posts.push_back(PostGroup{});
+                L.posts[k].block = block;
+                L.posts[k].sp = sp;
+                L.posts[k].wreg = wreg;
+                L.posts[k].chain = (int)gi;
+            }
+            L.posts[k].jobs.push_back(j);
+            L.posts[k].total += job->n_starts[j];
+            L.post_of[j] = k;
         }
-        if (ctx->force_post_block > 0) {
-            block = ctx->force_post_block;
-            sp = ctx->force_post_sp;
-            wreg = 1;
-        }
-        if (block == 0) return GC_EUNSUPPORTED;
-        int k = 0;
-        while (k < (int)L.posts.size() &&
-               !(L.posts[k].block == block && L.posts[k].sp == sp && L.posts[k].wreg == wreg))
-            ++k;
-        if (k == (int)L.posts.size()) {
-            L.posts.push_back(PostGroup{});
-            L.posts[k].block = block;
-            L.posts[k].sp = sp;
-            L.posts[k].wreg = wreg;
-        }
-        L.posts[k].jobs.push_back(j);
-        L.posts[k].total += job->n_starts[j];
-        L.post_of[j] = k;
     }
     for (PostGroup &pg : L.posts) {
         int pV = 0, pd = 0;
@@ -616,62 +731,81 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             pg.o_wbuf = place(sizeof(double) * pg.wstride * pg.grid);
         }
     }
-    (void)maxV;
-    (void)maxd;
-    (void)total;
     L.total = off;
     return GC_OK;
 }
 
+// Return a job's device block, pinned staging, events and graph to the
+// context's pools.  Nothing here waits for the device.
 void free_job(gc_ctx *ctx, Job *job)
 {
     if (job->mem) {
         ctx->pool.put(job->mem, job->bytes);
         job->mem = nullptr;
     }
-    if (job->ev_k0) (void)hipEventDestroy(job->ev_k0);
-    if (job->ev_k1) (void)hipEventDestroy(job->ev_k1);
-    if (job->ev_k2) (void)hipEventDestroy(job->ev_k2);
-    if (job->ev_done) (void)hipEventDestroy(job->ev_done);
+    if (job->staging) {
+        ctx->pinned.put(job->staging, job->staging_bytes);
+        job->staging = nullptr;
+    }
+    give_event(ctx, job->ev_k0, true);
+    give_event(ctx, job->ev_k1, true);
+    give_event(ctx, job->ev_k2, true);
+    give_event(ctx, job->ev_done, false);
     if (job->gx) (void)hipGraphExecDestroy(job->gx);
     if (job->g) (void)hipGraphDestroy(job->g);
-    if (job->h_cnt) (void)hipHostFree(job->h_cnt);
-    if (job->h_ncopies) (void)hipHostFree(job->h_ncopies);
-    job->ev_k0 = job->ev_k1 = job->ev_k2 = job->ev_done = nullptr;
     job->gx = nullptr;
     job->g = nullptr;
     job->h_cnt = nullptr;
     job->h_ncopies = nullptr;
 }
 
-// Enqueue a job's device work.  Caller holds ctx->mu and has checked the budget.
+// A job that cannot run: its orbits report GC_ORBIT_ERROR and gc_wait
+// returns err.  Its memory goes back to the pools.
+void fail_job(gc_ctx *ctx, Job *job, gc_status err)
+{
+    if (job->mem) ctx->used -= job->bytes;
+    free_job(ctx, job);
+    job->bytes = 0;
+    job->state = GC_ORBIT_ERROR;
+    job->err = err;
+    for (Orbit *o : job->orbits)
+        if (o->job == job) o->last.state = GC_ORBIT_ERROR;
+    ctx->done_cv.notify_all();
+}
+
+// Enqueue a job's device work on its stream without waiting for anything.
+// Caller holds ctx->mu, has charged nothing yet and has picked an idle
+// stream.  A batch (job->graph) is captured once into a HIP graph whose
+// relax groups run as concurrent branches; relaunching the same batch
+// replays that graph on the same device block.
 gc_status start_job(gc_ctx *ctx, Job *job)
 {
-    JobLayout L;
+    hipStream_t s = ctx->streams[job->stream];
+    const int nj = (int)job->orbits.size();
+    if (job->gx) {
+        // replay: the captured graph rewrites its own descriptors and resets
+        ctx->used += job->bytes;
+        ctx->stream_load[job->stream]++;
+        GC_HIP(hipEventRecord(job->ev_k0, s));
+        GC_HIP(hipGraphLaunch(job->gx, s));
+        GC_HIP(hipEventRecord(job->ev_k1, s));
+        GC_HIP(hipEventRecord(job->ev_done, s));
+        job->state = GC_ORBIT_RUNNING;
+        for (int j = 0; j < nj; ++j) job->orbits[j]->res = job->jobs[j];
+        ctx->running.push_back(job);
+        return GC_OK;
+    }
+    JobLayout &L = job->L;
     gc_status st = plan_job(ctx, job, L);
     if (st != GC_OK) return st;
     size_t got = 0;
-    hipError_t pe = ctx->pool.get(L.total, &job->mem, &got);
-    if (pe == hipErrorOutOfMemory || pe == hipErrorMemoryAllocation) {
-        // cached blocks may be holding the memory: return them and retry once
-        (void)hipGetLastError();
-        ctx->pool.drain();
-        pe = ctx->pool.get(L.total, &job->mem, &got);
-    }
-    GC_HIP(pe);
+    st = pool_get(ctx, L.total, &job->mem, &got);
+    if (st != GC_OK) return st;
     job->bytes = got;
     ctx->used += job->bytes;
-    const int nj = (int)job->orbits.size();
     unsigned char *base = (unsigned char *)job->mem;
-    int si = 0;   // least-loaded stream
-    for (int k = 1; k < (int)ctx->streams.size(); ++k)
-        if (ctx->stream_load[k] < ctx->stream_load[si]) si = k;
-    job->stream = si;
-    ctx->stream_load[si]++;
-    hipStream_t s = ctx->streams[si];
 
     job->jobs.assign(nj, GcJobDev{});
-    std::vector<uint64_t> prefix(1, 0);
     for (int j = 0; j < nj; ++j) {
         Orbit *o = job->orbits[j];
         GcJobDev &J = job->jobs[j];
@@ -699,112 +833,191 @@ gc_status start_job(gc_ctx *ctx, Job *job)
         J.fix = (GcFix *)(base + L.o_fix[j]);
         J.n_fix = (unsigned long long *)(base + L.o_nfix[j]);
         J.blk = (uint32_t *)(base + L.o_blk[j]);
-        prefix.push_back(prefix.back() + job->n_starts[j]);
+        J.sync_batch = job->p.sync_batch;
+        J.fixed_sweeps = job->p.sync_batch ? (uint32_t *)(base + L.o_sync[j]) : nullptr;
     }
-    job->total = prefix.back();
-    std::vector<GcJobDev> fixjobs(job->jobs);
-    for (GcJobDev &F : fixjobs) F.flags |= GC_JOB_FIX;
-    GC_HIP(hipHostMalloc((void **)&job->h_cnt, sizeof(GcCounters) * nj, hipHostMallocDefault));
-    GC_HIP(hipHostMalloc((void **)&job->h_ncopies, sizeof(unsigned long long) * nj, hipHostMallocDefault));
-    GC_HIP(hipEventCreate(&job->ev_k0));
-    GC_HIP(hipEventCreate(&job->ev_k1));
-    GC_HIP(hipEventCreate(&job->ev_k2));
-    GC_HIP(hipEventCreateWithFlags(&job->ev_done, hipEventDisableTiming));
-    GC_HIP(hipMemcpyAsync(base + L.o_fixjobs, fixjobs.data(), sizeof(GcJobDev) * nj, hipMemcpyHostToDevice, s));
-    // host staging must outlive the asynchronous copies (synchronised below)
-    std::vector<std::vector<GcJobDev>> pjobs(L.posts.size());
-    std::vector<std::vector<uint64_t>> pprefix(L.posts.size());
-    for (size_t k = 0; k < L.posts.size(); ++k) {
-        const PostGroup &pg = L.posts[k];
-        pprefix[k].assign(1, 0);
+    job->total = 0;
+    for (uint64_t n : job->n_starts) job->total += n;
+
+    // pinned staging: every descriptor array the kernels read, copied to
+    // the device block by the stream itself, then the result counters
+    struct Piece {
+        size_t dst, src, bytes;
+    };
+    std::vector<Piece> pieces;
+    size_t soff = 0;
+    auto stage = [&](size_t dst, size_t bytes) {
+        pieces.push_back(Piece{dst, soff, bytes});
+        soff = align_up(soff + bytes, 64);
+        return pieces.back().src;
+    };
+    std::vector<std::pair<size_t, std::vector<unsigned char>>> blobs;
+    auto add_blob = [&](size_t dst, const void *src, size_t bytes) {
+        const size_t at = stage(dst, bytes);
+        blobs.emplace_back(at, std::vector<unsigned char>((const unsigned char *)src, (const unsigned char *)src + bytes));
+    };
+    for (int j = 0; j < nj; ++j) {
+        GcJobDev F = job->jobs[j];
+        F.flags |= GC_JOB_FIX;
+        add_blob(L.o_fixjobs[j], &F, sizeof F);
+    }
+    for (const PostGroup &pg : L.posts) {
+        std::vector<GcJobDev> pj;
+        std::vector<uint64_t> pp(1, 0);
         for (int j : pg.jobs) {
-            pjobs[k].push_back(job->jobs[j]);
-            pprefix[k].push_back(pprefix[k].back() + job->n_starts[j]);
+            pj.push_back(job->jobs[j]);
+            pp.push_back(pp.back() + job->n_starts[j]);
         }
-        GC_HIP(hipMemcpyAsync(base + pg.o_jobs, pjobs[k].data(), sizeof(GcJobDev) * pjobs[k].size(),
-                              hipMemcpyHostToDevice, s));
-        GC_HIP(hipMemcpyAsync(base + pg.o_prefix, pprefix[k].data(), sizeof(uint64_t) * pprefix[k].size(),
-                              hipMemcpyHostToDevice, s));
+        add_blob(pg.o_jobs, pj.data(), sizeof(GcJobDev) * pj.size());
+        add_blob(pg.o_prefix, pp.data(), sizeof(uint64_t) * pp.size());
     }
-    std::vector<std::vector<GcJobDev>> rjobs(L.groups.size());
-    std::vector<std::vector<GcWaveOrbit>> rworbs(L.groups.size());
-    std::vector<std::vector<uint64_t>> rprefix(L.groups.size());
-    for (size_t k = 0; k < L.groups.size(); ++k) {
-        const Group &g = L.groups[k];
-        std::vector<GcJobDev> &gj = rjobs[k];
-        std::vector<GcWaveOrbit> &gw = rworbs[k];
-        std::vector<uint64_t> &gp = rprefix[k];
-        gp.assign(1, 0);
+    for (const Group &g : L.groups) {
+        std::vector<GcJobDev> gj;
+        std::vector<GcWaveOrbit> gw;
+        std::vector<uint64_t> gp(1, 0);
         for (int j : g.jobs) {
             gj.push_back(job->jobs[j]);
             gw.push_back(job->orbits[j]->wdev);
             gp.push_back(gp.back() + job->n_starts[j]);
         }
-        GC_HIP(hipMemcpyAsync(base + g.o_jobs, gj.data(), sizeof(GcJobDev) * gj.size(), hipMemcpyHostToDevice, s));
-        GC_HIP(hipMemcpyAsync(base + g.o_worbs, gw.data(), sizeof(GcWaveOrbit) * gw.size(), hipMemcpyHostToDevice, s));
-        GC_HIP(hipMemcpyAsync(base + g.o_prefix, gp.data(), sizeof(uint64_t) * gp.size(), hipMemcpyHostToDevice, s));
+        if (job->p.sync_batch) {
+            // first pass: every start stops on its own; second pass: fixed counts
+            add_blob(g.o_jobs1, gj.data(), sizeof(GcJobDev) * gj.size());
+            for (GcJobDev &J : gj) J.flags |= GC_JOB_SYNC2;
+        }
+        add_blob(g.o_jobs, gj.data(), sizeof(GcJobDev) * gj.size());
+        add_blob(g.o_worbs, gw.data(), sizeof(GcWaveOrbit) * gw.size());
+        add_blob(g.o_prefix, gp.data(), sizeof(uint64_t) * gp.size());
     }
-    GC_HIP(hipStreamSynchronize(s));
+    const size_t o_hcnt = soff;
+    soff = align_up(soff + sizeof(GcCounters) * nj, 64);
+    const size_t o_hnc = soff;
+    soff = align_up(soff + sizeof(unsigned long long) * nj, 64);
+    {
+        hipError_t e = ctx->pinned.get(soff, &job->staging, &job->staging_bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return GC_ENOMEM;
+        }
+    }
+    unsigned char *sb = (unsigned char *)job->staging;
+    for (auto &b : blobs) memcpy(sb + b.first, b.second.data(), b.second.size());
+    job->h_cnt = (GcCounters *)(sb + o_hcnt);
+    job->h_ncopies = (unsigned long long *)(sb + o_hnc);
+    memset(job->h_cnt, 0, sizeof(GcCounters) * nj);
+    memset(job->h_ncopies, 0, sizeof(unsigned long long) * nj);
+
+    job->ev_k0 = take_event(ctx, true);
+    job->ev_k1 = take_event(ctx, true);
+    job->ev_k2 = take_event(ctx, true);
+    job->ev_done = take_event(ctx, false);
+    if (!job->ev_k0 || !job->ev_k1 || !job->ev_k2 || !job->ev_done) return fail(ctx, hipErrorOutOfMemory, "event");
+
+    const int nchain = (int)L.groups.size();
+    const bool fork = job->graph && nchain > 1;
+    std::vector<hipEvent_t> fork_ev;
+    if (fork) {
+        while ((int)ctx->aux.size() < nchain - 1) {
+            hipStream_t a = nullptr;
+            GC_HIP(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+            ctx->aux.push_back(a);
+        }
+        for (int k = 0; k < nchain; ++k) {
+            hipEvent_t e = take_event(ctx, false);
+            if (!e) return fail(ctx, hipErrorOutOfMemory, "event");
+            fork_ev.push_back(e);
+        }
+    }
     auto wbuf_of = [&](const PostGroup &pg) { return pg.wreg ? nullptr : (double *)(base + pg.o_wbuf); };
-    auto enqueue_body = [&](hipStream_t qs) -> hipError_t {
-        hipError_t e = gc_launch_reset(job->jobs.data(), nj, qs);
+    // one chain: the relax group's kernel, its orbits' post passes, their
+    // table compaction and representative fix-ups
+    auto enqueue_chain = [&](int gi, hipStream_t qs, bool timed) -> hipError_t {
+        const Group &g = L.groups[gi];
+        hipError_t e = hipSuccess;
+        for (int j : g.jobs) {
+            e = gc_launch_reset(&job->jobs[j], 1, qs);
+            if (e != hipSuccess) return e;
+        }
+        e = gc_launch_zero_u64((unsigned long long *)(base + g.o_next), (int)g.jobs.size(), qs);
         if (e != hipSuccess) return e;
         for (const PostGroup &pg : L.posts) {
+            if (pg.chain != gi) continue;
             e = gc_launch_zero_u64((unsigned long long *)(base + pg.o_next), 1, qs);
             if (e != hipSuccess) return e;
         }
-        for (const Group &g : L.groups) {
+        if (timed && (e = hipEventRecord(job->ev_k0, qs)) != hipSuccess) return e;
+        auto relax = [&](size_t o_jobs) -> hipError_t {
+            if (g.wave && g.wps > 0)
+                return gc_launch_wps(g.d, g.wps, (const GcJobDev *)(base + o_jobs),
+                                     (const GcWaveOrbit *)(base + g.o_worbs), (int)g.jobs.size(),
+                                     (unsigned long long *)(base + g.o_next), (float2 *)(base + g.o_bounce), g.grid,
+                                     g.lds, qs);
+            if (g.wave)
+                return gc_launch_wave(g.d, g.ns, (const GcJobDev *)(base + o_jobs),
+                                      (const GcWaveOrbit *)(base + g.o_worbs), (int)g.jobs.size(),
+                                      (unsigned long long *)(base + g.o_next), g.coef_lds | (g.creg << 1),
+                                      (float2 *)(base + g.o_bounce), g.grid, g.lds, qs);
+            return gc_launch_relax_wg(g.block, (const GcJobDev *)(base + o_jobs), (int)g.jobs.size(),
+                                      (const uint64_t *)(base + g.o_prefix), (unsigned long long *)(base + g.o_next),
+                                      g.total, g.grid, g.lds, qs);
+        };
+        if (job->p.sync_batch) {
+            // batch-synchronous stop: a first pass finds every start's own
+            // stopping sweep, the second runs each batch to its largest
+            if ((e = relax(g.o_jobs1)) != hipSuccess) return e;
+            for (int j : g.jobs)
+                if ((e = gc_launch_sync(&job->jobs[j], 1, qs)) != hipSuccess) return e;
             e = gc_launch_zero_u64((unsigned long long *)(base + g.o_next), (int)g.jobs.size(), qs);
             if (e != hipSuccess) return e;
         }
-        if (!job->graph) {
-            e = hipEventRecord(job->ev_k0, qs);
-            if (e != hipSuccess) return e;
-        }
-        for (const Group &g : L.groups) {
-            if (g.wave && g.wps > 0)
-                e = gc_launch_wps(g.d, g.wps, (const GcJobDev *)(base + g.o_jobs),
-                                  (const GcWaveOrbit *)(base + g.o_worbs), (int)g.jobs.size(),
-                                  (unsigned long long *)(base + g.o_next), (float2 *)(base + g.o_bounce), g.grid,
-                                  g.lds, qs);
-            else if (g.wave)
-                e = gc_launch_wave(g.d, g.ns, (const GcJobDev *)(base + g.o_jobs), (const GcWaveOrbit *)(base + g.o_worbs),
-                                   (int)g.jobs.size(), (unsigned long long *)(base + g.o_next),
-                                   g.coef_lds | (g.creg << 1),
-                                   (float2 *)(base + g.o_bounce), g.grid, g.lds, qs);
-            else
-                e = gc_launch_relax_wg(g.block, (const GcJobDev *)(base + g.o_jobs), (int)g.jobs.size(),
-                                       (const uint64_t *)(base + g.o_prefix), (unsigned long long *)(base + g.o_next),
-                                       g.total, g.grid, g.lds, qs);
-            if (e != hipSuccess) return e;
-        }
-        if (!job->graph) {
-            e = hipEventRecord(job->ev_k1, qs);
-            if (e != hipSuccess) return e;
-        }
+        if ((e = relax(g.o_jobs)) != hipSuccess) return e;
+        if (timed && (e = hipEventRecord(job->ev_k1, qs)) != hipSuccess) return e;
         for (const PostGroup &pg : L.posts) {
+            if (pg.chain != gi) continue;
             e = gc_launch_post(pg.block, pg.sp, pg.wreg, (const GcJobDev *)(base + pg.o_jobs), (int)pg.jobs.size(),
                                (const uint64_t *)(base + pg.o_prefix), (unsigned long long *)(base + pg.o_next),
                                pg.total, nullptr, wbuf_of(pg), pg.wstride, pg.grid, pg.lds, qs);
             if (e != hipSuccess) return e;
         }
-        if (!job->graph) {
-            e = hipEventRecord(job->ev_k2, qs);
+        if (timed && (e = hipEventRecord(job->ev_k2, qs)) != hipSuccess) return e;
+        for (int j : g.jobs) {
+            e = gc_launch_finalize(&job->jobs[j], 1, qs);
             if (e != hipSuccess) return e;
-        }
-        e = gc_launch_finalize(job->jobs.data(), nj, qs);
-        if (e != hipSuccess) return e;
-        for (int j = 0; j < nj; ++j) {
-            e = gc_launch_zero_u64((unsigned long long *)(base + L.o_fixnext), 1, qs);
+            e = gc_launch_zero_u64((unsigned long long *)(base + L.o_fixnext[j]), 1, qs);
             if (e != hipSuccess) return e;
             const PostGroup &pg = L.posts[L.post_of[j]];
-            e = gc_launch_post(pg.block, pg.sp, pg.wreg, (const GcJobDev *)(base + L.o_fixjobs) + j, 1, nullptr,
-                               (unsigned long long *)(base + L.o_fixnext), 0, job->jobs[j].n_fix, wbuf_of(pg),
+            e = gc_launch_post(pg.block, pg.sp, pg.wreg, (const GcJobDev *)(base + L.o_fixjobs[j]), 1, nullptr,
+                               (unsigned long long *)(base + L.o_fixnext[j]), 0, job->jobs[j].n_fix, wbuf_of(pg),
                                pg.wstride, std::min(pg.grid, 64), pg.lds, qs);
             if (e != hipSuccess) return e;
+            e = gc_launch_patch(&job->jobs[j], 1, qs);
+            if (e != hipSuccess) return e;
         }
-        e = gc_launch_patch(job->jobs.data(), nj, qs);
-        if (e != hipSuccess) return e;
+        return hipSuccess;
+    };
+    auto enqueue_body = [&](hipStream_t qs) -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (const Piece &pc : pieces) {
+            e = hipMemcpyAsync(base + pc.dst, sb + pc.src, pc.bytes, hipMemcpyHostToDevice, qs);
+            if (e != hipSuccess) return e;
+        }
+        if (!fork) {
+            for (int gi = 0; gi < nchain; ++gi) {
+                e = enqueue_chain(gi, qs, !job->graph && nchain == 1);
+                if (e != hipSuccess) return e;
+            }
+        } else {
+            if ((e = hipEventRecord(fork_ev[0], qs)) != hipSuccess) return e;
+            for (int gi = 1; gi < nchain; ++gi) {
+                hipStream_t as = ctx->aux[gi - 1];
+                if ((e = hipStreamWaitEvent(as, fork_ev[0], 0)) != hipSuccess) return e;
+                if ((e = enqueue_chain(gi, as, false)) != hipSuccess) return e;
+                if ((e = hipEventRecord(fork_ev[gi], as)) != hipSuccess) return e;
+            }
+            if ((e = enqueue_chain(0, qs, false)) != hipSuccess) return e;
+            for (int gi = 1; gi < nchain; ++gi)
+                if ((e = hipStreamWaitEvent(qs, fork_ev[gi], 0)) != hipSuccess) return e;
+        }
         for (int j = 0; j < nj; ++j) {
             e = hipMemcpyAsync(&job->h_cnt[j], job->jobs[j].cnt, sizeof(GcCounters), hipMemcpyDeviceToHost, qs);
             if (e != hipSuccess) return e;
@@ -819,6 +1032,7 @@ gc_status start_job(gc_ctx *ctx, Job *job)
         hipError_t e = enqueue_body(s);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(s, &g);
+        for (hipEvent_t &fe : fork_ev) give_event(ctx, fe, false);
         if (e != hipSuccess) return fail(ctx, e, "batch capture");
         if (e2 != hipSuccess) return fail(ctx, e2, "hipStreamEndCapture");
         job->g = g;
@@ -831,6 +1045,7 @@ gc_status start_job(gc_ctx *ctx, Job *job)
         if (e != hipSuccess) return fail(ctx, e, "launch");
     }
     GC_HIP(hipEventRecord(job->ev_done, s));
+    ctx->stream_load[job->stream]++;
     job->state = GC_ORBIT_RUNNING;
     for (int j = 0; j < nj; ++j) job->orbits[j]->res = job->jobs[j];
     ctx->running.push_back(job);
@@ -840,6 +1055,10 @@ gc_status start_job(gc_ctx *ctx, Job *job)
 // Budget charge of a queued job (computed without allocating).
 gc_status job_bytes(gc_ctx *ctx, Job *job, size_t *bytes)
 {
+    if (job->gx) {
+        *bytes = job->bytes;
+        return GC_OK;
+    }
     JobLayout L;
     gc_status st = plan_job(ctx, job, L);
     if (st != GC_OK) return st;
@@ -847,29 +1066,41 @@ gc_status job_bytes(gc_ctx *ctx, Job *job, size_t *bytes)
     return GC_OK;
 }
 
+int idle_stream(gc_ctx *ctx)
+{
+    for (int k = 0; k < (int)ctx->stream_load.size(); ++k)
+        if (ctx->stream_load[k] == 0) return k;
+    return -1;
+}
+
+// Start queued jobs in arrival order while their bytes fit the budget
+// (device memory held by running jobs and unreleased results counts) and a
+// stream is idle.  Never waits for the device.
 void admit_locked(gc_ctx *ctx)
 {
     while (!ctx->queued.empty() && !ctx->failed) {
         Job *job = ctx->queued.front();
         size_t need = 0;
-        if (job_bytes(ctx, job, &need) != GC_OK) {
-            job->state = GC_ORBIT_ERROR;
+        gc_status st = job_bytes(ctx, job, &need);
+        if (st != GC_OK) {
             ctx->queued.pop_front();
+            fail_job(ctx, job, st);
             continue;
         }
-        if (ctx->used + need > ctx->budget && !ctx->running.empty()) break;
+        if (ctx->used + need > ctx->budget) break;
+        const int si = idle_stream(ctx);
+        if (si < 0) break;
         ctx->queued.pop_front();
-        if (start_job(ctx, job) != GC_OK) {
-            job->state = GC_ORBIT_ERROR;
-            ctx->done_cv.notify_all();
-        }
+        job->stream = si;
+        st = start_job(ctx, job);
+        if (st != GC_OK) fail_job(ctx, job, st);
+        else ctx->cv.notify_all();   // the scheduler watches running jobs
     }
 }
 
-// Move a finished job's results out of its working block.  The working block
-// stays allocated until the orbits are released or relaunched (the per-start
-// records and copies live in it), but it no longer counts toward admission
-// once every orbit in it has been fetched or released.
+// A finished job: its counters are on the host; the results stay in its
+// block (and count against the budget) until the orbits are released or
+// relaunched.
 void complete_locked(gc_ctx *ctx, Job *job)
 {
     job->t_done = Clock::now();
@@ -894,6 +1125,7 @@ void complete_locked(gc_ctx *ctx, Job *job)
         P.lanczos_runs = c.lanczos_runs;
         P.submit_to_done_ms = ms_since(job->t_submit, job->t_done);
         P.device_ms = job->solve_ms;
+        P.post_ms = job->post_ms;
         if (c.errors) {
             ctx->failed = true;
             ctx->err = "copy table insert failed (table full or spin limit)";
@@ -906,7 +1138,7 @@ void scheduler_main(gc_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     std::unique_lock<std::mutex> lk(ctx->mu);
     while (!ctx->stop) {
-        if (ctx->running.empty() && ctx->queued.empty()) {
+        if (ctx->running.empty()) {
             ctx->cv.wait(lk);
             continue;
         }
@@ -921,6 +1153,7 @@ void scheduler_main(gc_ctx *ctx)
             } else if (q != hipErrorNotReady) {
                 fail(ctx, q, "kernel");
                 job->state = GC_ORBIT_ERROR;
+                job->err = GC_EDEVICE;
                 ctx->running.erase(ctx->running.begin() + k);
                 changed = true;
             } else {
@@ -941,8 +1174,9 @@ Orbit *find_orbit(gc_ctx *ctx, gc_orbit h)
     return it == ctx->orbits.end() ? nullptr : it->second.get();
 }
 
-// Release the results block a finished job keeps for one orbit; the job's
-// working block is returned to the pool once no orbit refers to it.
+// Release the results a finished job keeps for one orbit; the job's block is
+// returned to the pool (and stops counting against the budget) once no orbit
+// refers to it.
 void drop_results_locked(gc_ctx *ctx, Orbit *o)
 {
     Job *job = o->job;
@@ -966,14 +1200,20 @@ gc_status wait_locked(gc_ctx *ctx, std::unique_lock<std::mutex> &lk, Orbit *o, i
 {
     Job *job = o->job;
     if (!job) return GC_ESTATE;
-    auto pred = [&] { return ctx->failed || job->state == GC_ORBIT_DONE || job->state == GC_ORBIT_ERROR; };
+    // a queued job with nothing running waits for memory that only
+    // gc_release (or another launch replacing results) can free
+    auto stalled = [&] { return job->state == GC_ORBIT_QUEUED && ctx->running.empty(); };
+    auto pred = [&] {
+        return ctx->failed || job->state == GC_ORBIT_DONE || job->state == GC_ORBIT_ERROR || stalled();
+    };
     if (timeout_ms < 0) {
         ctx->done_cv.wait(lk, pred);
     } else if (!ctx->done_cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred)) {
         return GC_ETIMEOUT;
     }
     if (ctx->failed) return GC_EDEVICE;
-    if (job->state == GC_ORBIT_ERROR) return GC_EDEVICE;
+    if (job->state == GC_ORBIT_ERROR) return job->err != GC_OK ? job->err : GC_EDEVICE;
+    if (stalled()) return GC_ENOMEM;
     return GC_OK;
 }
 
@@ -991,6 +1231,7 @@ void fill_defaults(gc_solve_params *p)
     p->max_sweeps = 100000;
     p->start_seed = 0;
     p->first_start = 0;
+    p->sync_batch = 0;
 }
 
 gc_status check_params(const gc_solve_params *p)
@@ -1001,6 +1242,7 @@ gc_status check_params(const gc_solve_params *p)
     if (p->stop_norm != GC_MEAN_SQ && p->stop_norm != GC_MAX_ABS) return GC_EINVAL;
     if (p->max_sweeps < 1 || p->max_sweeps > 0xFFFFFFFFull) return GC_EINVAL;
     if (!(p->lambda_tol >= 0.0)) return GC_EINVAL;
+    if (p->sync_batch && p->precision != GC_FP64) return GC_EINVAL;
     return GC_OK;
 }
 
@@ -1019,20 +1261,67 @@ gc_status new_orbit(gc_ctx *ctx, const gc_lattice *lat, std::vector<double> &&ph
     o->orbit_index = orbit_index;
     o->phi = std::move(phi);
     st = build_orbit(ctx, o.get());
-    if (st != GC_OK) return st;
+    if (st != GC_OK) {
+        if (o->tables) ctx->pool.put(o->tables, o->table_bytes);
+        if (o->wave_tables) ctx->pool.put(o->wave_tables, o->wave_bytes);
+        return st;
+    }
+    ctx->used += o->table_bytes + o->wave_bytes;
     o->handle = ctx->next_handle++;
     *out = o->handle;
     ctx->orbits[o->handle] = std::move(o);
     return GC_OK;
 }
 
+bool same_params(const gc_solve_params &a, const gc_solve_params &b) { return memcmp(&a, &b, sizeof a) == 0; }
+
+// A batch relaunched with the same orbits, start counts and parameters
+// reuses the previous launch's device block and captured graph (the replay
+// overwrites the previous results, which the relaunch replaces anyway).
+Job *reusable_graph_locked(gc_ctx *ctx, Job *job)
+{
+    if (!job->graph || job->orbits.empty()) return nullptr;
+    Job *prev = job->orbits[0]->job;
+    if (!prev || !prev->graph || !prev->gx || prev->state != GC_ORBIT_DONE) return nullptr;
+    if (prev->orbits != job->orbits || prev->n_starts != job->n_starts || !same_params(prev->p, job->p)) return nullptr;
+    for (Orbit *o : job->orbits)
+        if (o->job != prev) return nullptr;
+    return prev;
+}
+
 gc_status enqueue_locked(gc_ctx *ctx, Job *job)
 {
-    size_t need = 0;
-    gc_status st = job_bytes(ctx, job, &need);
-    if (st != GC_OK) return st;
-    if (need > ctx->budget) return GC_ENOMEM;
     job->t_submit = Clock::now();
+    Job *prev = reusable_graph_locked(ctx, job);
+    if (prev) {
+        // take over the block, staging, events and graph of the previous launch
+        ctx->used -= prev->bytes;
+        job->bytes = prev->bytes;
+        job->mem = prev->mem;
+        job->staging = prev->staging;
+        job->staging_bytes = prev->staging_bytes;
+        job->ev_k0 = prev->ev_k0;
+        job->ev_k1 = prev->ev_k1;
+        job->ev_k2 = prev->ev_k2;
+        job->ev_done = prev->ev_done;
+        job->g = prev->g;
+        job->gx = prev->gx;
+        job->L = prev->L;
+        job->jobs = prev->jobs;
+        job->h_cnt = prev->h_cnt;
+        job->h_ncopies = prev->h_ncopies;
+        job->total = prev->total;
+        prev->mem = prev->staging = nullptr;
+        prev->ev_k0 = prev->ev_k1 = prev->ev_k2 = prev->ev_done = nullptr;
+        prev->g = nullptr;
+        prev->gx = nullptr;
+        prev->bytes = 0;
+    } else {
+        size_t need = 0;
+        gc_status st = job_bytes(ctx, job, &need);
+        if (st != GC_OK) return st;
+        if (need > ctx->budget) return GC_ENOMEM;
+    }
     for (size_t j = 0; j < job->orbits.size(); ++j) {
         Orbit *o = job->orbits[j];
         drop_results_locked(ctx, o);
@@ -1105,6 +1394,80 @@ gc_status ensure_starts_locked(gc_ctx *ctx, Orbit *o)
     return GC_OK;
 }
 
+// Create and enqueue a job (caller holds ctx->mu).  force: kernel variants
+// of an autotune trial, or NULL.
+gc_status launch_locked(gc_ctx *ctx, const std::vector<Orbit *> &orbits, const std::vector<uint64_t> &n_starts,
+                        const gc_solve_params &p, bool graph, const Job *force)
+{
+    for (Orbit *o : orbits)
+        if (o->job && (o->job->state == GC_ORBIT_QUEUED || o->job->state == GC_ORBIT_RUNNING)) return GC_EBUSY;
+    Job *job = new Job;
+    job->orbits = orbits;
+    job->n_starts = n_starts;
+    job->p = p;
+    job->graph = graph;
+    if (force) {
+        job->force_creg = force->force_creg;
+        job->force_wps = force->force_wps;
+        job->force_post_block = force->force_post_block;
+        job->force_post_sp = force->force_post_sp;
+    }
+    gc_status st = enqueue_locked(ctx, job);
+    if (st != GC_OK) delete job;
+    return st;
+}
+
+// Tuning cache: one line per choice, "creg <key> <value>", "wps <key>
+// <value>" or "post <V> <block> <sites per thread>".
+void load_tune_cache(gc_ctx *ctx)
+{
+    FILE *f = fopen(ctx->tune_cache.c_str(), "r");
+    if (!f) return;
+    char kind[16];
+    unsigned long long k = 0;
+    int a = 0, b = 0;
+    while (fscanf(f, "%15s %llu %d", kind, &k, &a) == 3) {
+        if (!strcmp(kind, "creg")) ctx->tune_creg[(uint64_t)k] = a;
+        else if (!strcmp(kind, "wps")) ctx->tune_wps[(uint64_t)k] = a;
+        else if (!strcmp(kind, "post") && fscanf(f, "%d", &b) == 1) ctx->tune_post[(int)k] = std::make_pair(a, b);
+        else break;
+    }
+    fclose(f);
+}
+
+void save_tune_cache(gc_ctx *ctx)
+{
+    if (ctx->tune_cache.empty()) return;
+    const std::string tmp = ctx->tune_cache + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (auto &kv : ctx->tune_creg) fprintf(f, "creg %llu %d\n", (unsigned long long)kv.first, kv.second);
+    for (auto &kv : ctx->tune_wps) fprintf(f, "wps %llu %d\n", (unsigned long long)kv.first, kv.second);
+    for (auto &kv : ctx->tune_post) fprintf(f, "post %d %d %d\n", kv.first, kv.second.first, kv.second.second);
+    fclose(f);
+    (void)rename(tmp.c_str(), ctx->tune_cache.c_str());
+}
+
+// theta_i - theta_{V-1} of one start of the orbit's DONE launch.
+gc_status start_state_locked(gc_ctx *ctx, Orbit *o, uint64_t start_id, double *theta_out)
+{
+    const gc_solve_params &p = o->job->p;
+    const uint64_t n = o->job->n_starts[o->job_index];
+    if (start_id < p.first_start || start_id - p.first_start >= n) return GC_EINVAL;
+    const int V = o->V;
+    std::vector<double2> g(V);
+    GC_HIP(hipMemcpy(g.data(), o->res.states + (start_id - p.first_start) * (uint64_t)V, sizeof(double2) * V,
+                     hipMemcpyDeviceToHost));
+    // theta_i - theta_{V-1} = arg(g_i conj(g_{V-1})), exactly 0 at the last site
+    const double2 gl = g[V - 1];
+    for (int i = 0; i < V; ++i) {
+        const double im = g[i].y * gl.x - g[i].x * gl.y;
+        const double re = g[i].x * gl.x + g[i].y * gl.y;
+        theta_out[i] = std::atan2(im, re);
+    }
+    return GC_OK;
+}
+
 #define GC_ENTER(ctx)                                  \
     if (!(ctx)) return GC_EINVAL;                      \
     std::unique_lock<std::mutex> lk((ctx)->mu);        \
@@ -1168,12 +1531,23 @@ gc_status gc_create(const gc_ctx_params *params, gc_ctx **out)
     if (const char *v = getenv("GC_WAVE_CREG")) ctx->creg_override = atoi(v);
     if (const char *v = getenv("GC_WPS")) ctx->wps_override = atoi(v) != 0 ? 1 : 0;
     ctx->budget = P.hbm_budget_bytes ? P.hbm_budget_bytes : (64ull << 30);
-    const int ns = P.n_streams > 0 ? std::min(P.n_streams, 16) : 4;
-    for (int k = 0; k < ns; ++k) {
-        hipStream_t s;
-        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return GC_EDEVICE;
-        ctx->streams.push_back(s);
+    if (P.hip_stream) {
+        ctx->streams.push_back((hipStream_t)P.hip_stream);
         ctx->stream_load.push_back(0);
+        ctx->own_streams = false;
+    } else {
+        const int ns = P.n_streams > 0 ? std::min(P.n_streams, 16) : 4;
+        for (int k = 0; k < ns; ++k) {
+            hipStream_t s;
+            if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return GC_EDEVICE;
+            ctx->streams.push_back(s);
+            ctx->stream_load.push_back(0);
+        }
+    }
+    if (hipStreamCreateWithFlags(&ctx->util, hipStreamNonBlocking) != hipSuccess) return GC_EDEVICE;
+    if (P.tune_cache) {
+        ctx->tune_cache = P.tune_cache;
+        load_tune_cache(ctx.get());
     }
     gc_ctx *raw = ctx.release();
     raw->sched = std::thread(scheduler_main, raw);
@@ -1188,6 +1562,7 @@ gc_status gc_destroy(gc_ctx *ctx)
         std::unique_lock<std::mutex> lk(ctx->mu);
         (void)hipSetDevice(ctx->device);
         for (hipStream_t s : ctx->streams) (void)hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(ctx->util);
         ctx->stop = true;
         ctx->cv.notify_all();
     }
@@ -1204,11 +1579,17 @@ gc_status gc_destroy(gc_ctx *ctx)
         delete j;
     }
     for (auto &kv : ctx->orbits) {
-        if (kv.second->tables) (void)hipFree(kv.second->tables);
-        if (kv.second->wave_tables) (void)hipFree(kv.second->wave_tables);
+        ctx->pool.put(kv.second->tables, kv.second->table_bytes);
+        ctx->pool.put(kv.second->wave_tables, kv.second->wave_bytes);
     }
     ctx->pool.drain();
-    for (hipStream_t s : ctx->streams) (void)hipStreamDestroy(s);
+    ctx->pinned.drain();
+    for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->events_nt) (void)hipEventDestroy(e);
+    if (ctx->own_streams)
+        for (hipStream_t s : ctx->streams) (void)hipStreamDestroy(s);
+    for (hipStream_t s : ctx->aux) (void)hipStreamDestroy(s);
+    (void)hipStreamDestroy(ctx->util);
     delete ctx;
     return GC_OK;
 }
@@ -1235,14 +1616,16 @@ gc_status gc_orbit_random(gc_ctx *ctx, const gc_lattice *lat, uint64_t seed, uin
     if (st != GC_OK) return st;
     GC_ENTER(ctx);
     const int64_t n = (int64_t)lat->dim * V;
-    double *dphi = nullptr;
-    GC_HIP(hipMalloc(&dphi, sizeof(double) * n));
-    hipStream_t s = ctx->streams[0];
-    hipError_t e = gc_launch_orbit_random(dphi, n, seed, orbit_index, s);
+    void *blk = nullptr;
+    size_t got = 0;
+    st = pool_get(ctx, sizeof(double) * n, &blk, &got);
+    if (st != GC_OK) return st;
+    hipStream_t s = ctx->util;
+    hipError_t e = gc_launch_orbit_random((double *)blk, n, seed, orbit_index, s);
     std::vector<double> v(n);
-    if (e == hipSuccess) e = hipMemcpyAsync(v.data(), dphi, sizeof(double) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(v.data(), blk, sizeof(double) * n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(dphi);
+    ctx->pool.put(blk, got);
     if (e != hipSuccess) return fail(ctx, e, "orbit_random");
     return new_orbit(ctx, lat, std::move(v), orbit_index, out);
 }
@@ -1267,14 +1650,7 @@ gc_status gc_launch(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_sol
     GC_ENTER(ctx);
     Orbit *o = find_orbit(ctx, orbit);
     if (!o) return GC_EINVAL;
-    if (o->job && (o->job->state == GC_ORBIT_QUEUED || o->job->state == GC_ORBIT_RUNNING)) return GC_EBUSY;
-    Job *job = new Job;
-    job->orbits.push_back(o);
-    job->n_starts.push_back(n_starts);
-    job->p = p;
-    st = enqueue_locked(ctx, job);
-    if (st != GC_OK) delete job;
-    return st;
+    return launch_locked(ctx, {o}, {n_starts}, p, false, nullptr);
 }
 
 gc_status gc_launch_batch(gc_ctx *ctx, int32_t n_orbits, const gc_orbit *orbits, const uint64_t *n_starts,
@@ -1286,20 +1662,16 @@ gc_status gc_launch_batch(gc_ctx *ctx, int32_t n_orbits, const gc_orbit *orbits,
     gc_status st = check_params(&p);
     if (st != GC_OK) return st;
     GC_ENTER(ctx);
-    Job *job = new Job;
-    job->graph = true;
-    job->p = p;
+    std::vector<Orbit *> os;
+    std::vector<uint64_t> ns;
     for (int k = 0; k < n_orbits; ++k) {
         Orbit *o = find_orbit(ctx, orbits[k]);
-        if (!o || n_starts[k] == 0 || n_starts[k] > (1ull << 32)) { delete job; return GC_EINVAL; }
-        if (std::find(job->orbits.begin(), job->orbits.end(), o) != job->orbits.end()) { delete job; return GC_EINVAL; }
-        if (o->job && (o->job->state == GC_ORBIT_QUEUED || o->job->state == GC_ORBIT_RUNNING)) { delete job; return GC_EBUSY; }
-        job->orbits.push_back(o);
-        job->n_starts.push_back(n_starts[k]);
+        if (!o || n_starts[k] == 0 || n_starts[k] > (1ull << 32)) return GC_EINVAL;
+        if (std::find(os.begin(), os.end(), o) != os.end()) return GC_EINVAL;
+        os.push_back(o);
+        ns.push_back(n_starts[k]);
     }
-    st = enqueue_locked(ctx, job);
-    if (st != GC_OK) delete job;
-    return st;
+    return launch_locked(ctx, os, ns, p, true, nullptr);
 }
 
 gc_status gc_poll(gc_ctx *ctx, gc_orbit orbit, gc_progress *out)
@@ -1368,16 +1740,15 @@ gc_status gc_paper_saturation(gc_ctx *ctx, gc_orbit orbit, int32_t n_points, con
     const uint64_t n = o->job->n_starts[o->job_index];
     // [GC_PAPER_VALUES / 64] bitmap words, the running count, one snapshot per point
     const size_t words = GC_PAPER_VALUES / 64;
-    unsigned long long *buf = nullptr;
-    if (hipMalloc((void **)&buf, sizeof(unsigned long long) * (words + 1 + (size_t)n_points)) != hipSuccess) {
-        (void)hipGetLastError();
-        return GC_ENOMEM;
-    }
+    void *blk = nullptr;
+    size_t got = 0;
+    gc_status st = pool_get(ctx, sizeof(unsigned long long) * (words + 1 + (size_t)n_points), &blk, &got);
+    if (st != GC_OK) return st;
+    unsigned long long *buf = (unsigned long long *)blk;
     unsigned long long *count = buf + words, *snap = count + 1;
     std::vector<unsigned long long> host(n_points);
-    hipStream_t s = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    if (e == hipSuccess) e = gc_launch_zero_u64(buf, (int)(words + 1), s);
+    hipStream_t s = ctx->util;
+    hipError_t e = gc_launch_zero_u64(buf, (int)(words + 1), s);
     uint64_t done = 0;
     for (int32_t k = 0; k < n_points && e == hipSuccess; ++k) {
         const uint64_t upto = std::min<uint64_t>(sample_sizes[k], n);
@@ -1388,8 +1759,7 @@ gc_status gc_paper_saturation(gc_ctx *ctx, gc_orbit orbit, int32_t n_points, con
     if (e == hipSuccess)
         e = hipMemcpyAsync(host.data(), snap, sizeof(unsigned long long) * n_points, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (s) (void)hipStreamDestroy(s);
-    (void)hipFree(buf);
+    ctx->pool.put(blk, got);
     if (e != hipSuccess) return fail(ctx, e, "gc_paper_saturation");
     for (int32_t k = 0; k < n_points; ++k) distinct_out[k] = host[k];
     return GC_OK;
@@ -1430,28 +1800,32 @@ gc_status gc_fetch_starts(gc_ctx *ctx, gc_orbit orbit, uint64_t offset, uint64_t
     return GC_OK;
 }
 
-gc_status gc_fetch_state(gc_ctx *ctx, gc_orbit orbit, uint64_t start_id, double *theta_out)
+gc_status gc_fetch_start_state(gc_ctx *ctx, gc_orbit orbit, uint64_t start_id, double *theta_out)
 {
     if (!theta_out) return GC_EINVAL;
     GC_ENTER(ctx);
     Orbit *o = find_orbit(ctx, orbit);
     if (!o) return GC_EINVAL;
     if (!o->job || o->job->state != GC_ORBIT_DONE) return GC_ESTATE;
-    const gc_solve_params &p = o->job->p;
-    const uint64_t n = o->job->n_starts[o->job_index];
-    if (start_id < p.first_start || start_id - p.first_start >= n) return GC_EINVAL;
-    const int V = o->V;
-    std::vector<double2> g(V);
-    GC_HIP(hipMemcpy(g.data(), o->res.states + (start_id - p.first_start) * (uint64_t)V, sizeof(double2) * V,
-                     hipMemcpyDeviceToHost));
-    // theta_i - theta_{V-1} = arg(g_i conj(g_{V-1})), exactly 0 at the last site
-    const double2 gl = g[V - 1];
-    for (int i = 0; i < V; ++i) {
-        const double im = g[i].y * gl.x - g[i].x * gl.y;
-        const double re = g[i].x * gl.x + g[i].y * gl.y;
-        theta_out[i] = std::atan2(im, re);
-    }
-    return GC_OK;
+    return start_state_locked(ctx, o, start_id, theta_out);
+}
+
+gc_status gc_fetch_state(gc_ctx *ctx, gc_orbit orbit, uint64_t key_hi, uint64_t key_lo, double *theta_out)
+{
+    if (!theta_out) return GC_EINVAL;
+    GC_ENTER(ctx);
+    Orbit *o = find_orbit(ctx, orbit);
+    if (!o) return GC_EINVAL;
+    if (!o->job || o->job->state != GC_ORBIT_DONE) return GC_ESTATE;
+    gc_status st = ensure_copies_locked(ctx, o);
+    if (st != GC_OK) return st;
+    // the copies are sorted by key
+    auto it = std::lower_bound(o->copies.begin(), o->copies.end(), std::make_pair(key_hi, key_lo),
+                               [](const gc_copy &c, const std::pair<uint64_t, uint64_t> &k) {
+                                   return c.key_hi != k.first ? c.key_hi < k.first : c.key_lo < k.second;
+                               });
+    if (it == o->copies.end() || it->key_hi != key_hi || it->key_lo != key_lo) return GC_ENOTFOUND;
+    return start_state_locked(ctx, o, it->rep_start, theta_out);
 }
 
 gc_status gc_release(gc_ctx *ctx, gc_orbit orbit)
@@ -1461,13 +1835,22 @@ gc_status gc_release(gc_ctx *ctx, gc_orbit orbit)
     if (!o) return GC_EINVAL;
     if (o->job && (o->job->state == GC_ORBIT_QUEUED || o->job->state == GC_ORBIT_RUNNING)) {
         gc_status st = wait_locked(ctx, lk, o, -1);
-        if (st != GC_OK) return st;
+        if (st != GC_OK && st != GC_ENOMEM) return st;
+        if (st == GC_ENOMEM) {
+            // still queued: withdraw it
+            Job *job = o->job;
+            ctx->queued.erase(std::remove(ctx->queued.begin(), ctx->queued.end(), job), ctx->queued.end());
+            fail_job(ctx, job, GC_ENOMEM);
+        }
     }
     drop_results_locked(ctx, o);
-    if (o->tables) (void)hipFree(o->tables);
-    if (o->wave_tables) (void)hipFree(o->wave_tables);
+    // the tables go back to the pool: no free (which waits for the device)
+    ctx->pool.put(o->tables, o->table_bytes);
+    ctx->pool.put(o->wave_tables, o->wave_bytes);
+    ctx->used -= o->table_bytes + o->wave_bytes;
     ctx->orbits.erase(orbit);
     admit_locked(ctx);
+    ctx->done_cv.notify_all();
     return GC_OK;
 }
 
@@ -1513,7 +1896,7 @@ gc_status gc_memory_info(gc_ctx *ctx, uint64_t *budget, uint64_t *in_use, uint64
 gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_solve_params *params,
                       gc_tune_result *out)
 {
-    if (!ctx || n_starts == 0) return GC_EINVAL;
+    if (!ctx || n_starts == 0 || n_starts > (1ull << 32)) return GC_EINVAL;
     gc_solve_params p;
     if (params) p = *params; else fill_defaults(&p);
     gc_status st = check_params(&p);
@@ -1529,22 +1912,23 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
         K = o->dev.K;
     }
     const bool mixed = p.precision == GC_MIXED;
-    // one measured launch with the given forced variant: relax and post ms
-    auto trial = [&](int creg, int pb, int psp, double *relax_ms, double *post_ms) -> gc_status {
+    // one measured launch with the given variant forced on that launch only
+    // (launches of other orbits meanwhile use the context's choices)
+    auto trial = [&](int creg, int wps, int pb, int psp, double *relax_ms, double *post_ms) -> gc_status {
+        Job force;
+        force.force_creg = creg;
+        force.force_wps = wps;
+        force.force_post_block = pb;
+        force.force_post_sp = psp;
+        gc_status s2;
         {
-            std::lock_guard<std::mutex> g(ctx->mu);
-            ctx->force_creg = creg;
-            ctx->force_post_block = pb;
-            ctx->force_post_sp = psp;
-        }
-        gc_status s2 = gc_launch(ctx, orbit, n_starts, &p);
-        if (s2 == GC_OK) s2 = gc_wait(ctx, orbit, -1);
-        {
-            std::lock_guard<std::mutex> g(ctx->mu);
-            ctx->force_creg = -1;
-            ctx->force_post_block = ctx->force_post_sp = 0;
+            std::unique_lock<std::mutex> lk(ctx->mu);
+            if (ctx->failed) return GC_EDEVICE;
+            Orbit *o = find_orbit(ctx, orbit);
+            if (!o) return GC_EINVAL;
+            s2 = launch_locked(ctx, {o}, {n_starts}, p, false, &force);
+            if (s2 == GC_OK) s2 = wait_locked(ctx, lk, o, -1);
             if (s2 == GC_OK) {
-                Orbit *o = find_orbit(ctx, orbit);
                 *relax_ms = o->job->solve_ms;
                 *post_ms = o->job->post_ms;
             }
@@ -1556,44 +1940,40 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
     const int ns = (V / 2 + 63) / 64;
     const int cmax = wave ? gc_wave_creg_max(d, ns) : 0;
     double rm = 0, pm = 0;
-    st = trial(0, 0, 0, &rm, &pm);   // warm-up: code objects, pool
+    st = trial(-1, -1, 0, 0, &rm, &pm);   // warm-up: code objects, pool
     if (st != GC_OK) return st;
     // relax layout for more than two slots per lane: one wavefront per start
-    // or a workgroup per start (force_wps), best of two launches each
+    // or a workgroup per start, best of two launches each
     const bool wps_ok = (K == 2) && gc_wps_for(ns) > 0 && 32 * (size_t)V <= ctx->lds_max &&
                         (size_t)(GC_WAVES + 1) * 16 * V <= ctx->lds_max;
     int best_w = 0;
+    double best_r = INFINITY;
     if (wps_ok) {
         double tw[2] = {INFINITY, INFINITY};
         for (int w = 0; w < 2; ++w)
             for (int rep = 0; rep < 2; ++rep) {
-                {
-                    std::lock_guard<std::mutex> g(ctx->mu);
-                    ctx->force_wps = w;
-                }
-                st = trial(0, 0, 0, &rm, &pm);
-                {
-                    std::lock_guard<std::mutex> g(ctx->mu);
-                    ctx->force_wps = -1;
-                }
+                st = trial(0, w, 0, 0, &rm, &pm);
                 if (st != GC_OK) return st;
                 tw[w] = std::min(tw[w], rm);
             }
         best_w = tw[1] < tw[0] ? 1 : 0;
-        std::lock_guard<std::mutex> g(ctx->mu);
-        ctx->tune_wps[creg_key(d, ns, mixed)] = best_w;
+        best_r = tw[best_w];
     }
-    // relax: register-coefficient colours 0..cmax, best of two launches each
+    // relax: register-coefficient colours 0..cmax of the one-wavefront
+    // layout (the workgroup layout has no such variants), best of two each
     int best_c = 0;
-    double best_r = INFINITY;
-    for (int c = 0; c <= cmax; ++c) {
-        double t = INFINITY;
-        for (int rep = 0; rep < 2; ++rep) {
-            st = trial(c, 0, 0, &rm, &pm);
-            if (st != GC_OK) return st;
-            t = std::min(t, rm);
+    if (!best_w) {
+        double bc = INFINITY;
+        for (int c = 0; c <= cmax; ++c) {
+            double t = INFINITY;
+            for (int rep = 0; rep < 2; ++rep) {
+                st = trial(c, 0, 0, 0, &rm, &pm);
+                if (st != GC_OK) return st;
+                t = std::min(t, rm);
+            }
+            if (t < bc) { bc = t; best_c = c; }
         }
-        if (t < best_r) { best_r = t; best_c = c; }
+        best_r = bc;
     }
     // post: every instantiated register-weight shape with at most 4 sites per
     // thread that covers V without quadrupling it
@@ -1609,7 +1989,7 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
         if (!dw) continue;   // large lattices keep the global-memory variant
         double t = INFINITY;
         for (int rep = 0; rep < 2; ++rep) {
-            st = trial(best_c, sh[0], sh[1], &rm, &pm);
+            st = trial(best_c, best_w, sh[0], sh[1], &rm, &pm);
             if (st != GC_OK) return st;
             t = std::min(t, pm);
         }
@@ -1617,8 +1997,10 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
     }
     {
         std::lock_guard<std::mutex> g(ctx->mu);
-        if (wave) ctx->tune_creg[creg_key(d, ns, mixed)] = best_c;
+        if (wps_ok) ctx->tune_wps[creg_key(d, ns, mixed)] = best_w;
+        if (wave && !best_w) ctx->tune_creg[creg_key(d, ns, mixed)] = best_c;
         if (best_b) ctx->tune_post[V] = std::make_pair(best_b, best_sp);
+        save_tune_cache(ctx);
     }
     r.relax_variant = best_c + (best_w ? 8 : 0);
     r.relax_ms = best_r;

@@ -1,582 +1,53 @@
-// Wavefront-per-start solver for lattices with even extents (two colours).
-//
-// Each 64-lane wavefront relaxes one random start with its state resident in
-// LDS and never synchronises with other wavefronts: a start finishes on its
-// own schedule and the wavefront pulls the next start of its job from a
-// per-job counter.  The workgroup only synchronises when it moves to another
-// job (the orbit's coefficient table may be staged in LDS and is shared by
-// its wavefronts).
-//
-// Layout (colour split, Sec. III checkerboard): site i has colour
-// c = (sum_mu x_mu) mod 2 and half index h = i >> 1 (x_0 runs over an even
-// extent, so sites 2h and 2h+1 have opposite colours).  A start's state is
-// st[c][h] (complex), the update of (c, h) reads its 2d neighbours in
-// st[1-c][.], and the orbit supplies per (c, h):
-//   nb[c][h]      the 2d neighbour half indices (forward mu = 0..d-1, then backward)
-//   coef[c][k][h] U_{i,k} for forward k, conj(U_{i-k,k}) for backward k,
-// so that S_i = sum_k coef_k g_{n_k} (eqs. (4)-(5) in the eq. (3) convention).
-//
-// The stopping norm of sweep t needs div_i on the post-sweep state.  For the
-// colour updated last it is formed right after the update; for colour 0 the
-// staple S_i of the post-sweep state is exactly the one sweep t+1 computes
-// first, so the norm of sweep t is completed there, before sweep t+1's new
-// values are written, and the sweep is discarded if the norm has fallen
-// below the threshold.  The arithmetic is that of a separate check pass.
-#include "gc_common.h"
+// Dispatch of the two-colour relax kernels by lattice dimension (the kernels
+// themselves are in gc_wave_kern.h, instantiated per dimension in
+// gc_wave1.hip .. gc_wave4.hip).
 #include "gc_wave.h"
 
-namespace {
-
-using namespace gc;
-
-// Neighbour half indices of a slot, forward mu = 0..d-1 then backward:
-// from its packed table entry (eight 16-bit half indices) ...
-struct NbWords {
-    u32x4 w;
-    __device__ __forceinline__ uint32_t operator()(int k) const
-    {
-        const uint32_t word = (k >> 1) == 0 ? w.x : (k >> 1) == 1 ? w.y : (k >> 1) == 2 ? w.z : w.w;
-        return (k & 1) ? (word >> 16) : (word & 0xFFFFu);
-    }
-};
-
-// ... or from its descriptor (site index | forward-wrap bits << 12 |
-// backward-wrap bits << 16) and the lattice strides s_mu, wraps N_mu s_mu.
-template <int D> struct Strides {
-    int s[D], w[D];
-};
-template <int D> struct NbDesc {
-    uint32_t dsc;
-    const Strides<D> &L;
-    __device__ __forceinline__ uint32_t operator()(int k) const
-    {
-        const int i = (int)(dsc & 0xFFFu);
-        const int mu = k < D ? k : k - D;
-        int j;
-        if (k < D) j = i + L.s[mu] - (((dsc >> (12 + mu)) & 1u) ? L.w[mu] : 0);
-        else j = i - L.s[mu] + (((dsc >> (16 + mu)) & 1u) ? L.w[mu] : 0);
-        return (uint32_t)(j >> 1);
-    }
-};
-
-// S = sum_k coef_k g_{n_k}, forward mu = 0..d-1 then backward, as in the
-// coefficient table, each complex product accumulated by four FMAs.  The
-// coefficients come from cf (registers, CF_REG) or from the table at
-// coef[(c 2d + k) half + h].
-template <int D, typename R, bool CF_REG, typename CP, typename SP, typename NB>
-__device__ __forceinline__ typename cx<R>::T staple(const typename cx<R>::T (&cf)[2 * D], CP coef, SP other,
-                                                    const NB &nb, int c, int h, int half)
-{
-    using C = typename cx<R>::T;
-    R ax = 0, ay = 0;
-#pragma unroll
-    for (int k = 0; k < 2 * D; ++k) {
-        const C u = CF_REG ? cf[k] : coef[(c * 2 * D + k) * half + h];
-        const C g = other[nb(k)];
-        ax = fma(u.x, g.x, ax);
-        ax = fma(-u.y, g.y, ax);
-        ay = fma(u.x, g.y, ay);
-        ay = fma(u.y, g.x, ay);
-    }
-    C s;
-    s.x = ax;
-    s.y = ay;
-    return s;
-}
-
-// Synchronisation and reductions over the WPS wavefronts that share a start
-// (WPS = 1: one wavefront; otherwise the whole workgroup).  red holds at
-// least WPS doubles of LDS.
-template <int WPS> __device__ __forceinline__ void start_sync()
-{
-    if constexpr (WPS > 1) __syncthreads();
-    else wave_sync();
-}
-template <int WPS> __device__ __forceinline__ double start_sum(double v, double *red)
-{
-    v = wave_sum(v);
-    if constexpr (WPS > 1) {
-        __syncthreads();   // every wave has read the previous contents of red
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-        __syncthreads();
-        double t = red[0];
-#pragma unroll
-        for (int w = 1; w < WPS; ++w) t += red[w];
-        v = t;
-    }
-    return v;
-}
-template <int WPS> __device__ __forceinline__ double start_max(double v, double *red)
-{
-    v = wave_max(v);
-    if constexpr (WPS > 1) {
-        __syncthreads();
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-        __syncthreads();
-        double t = red[0];
-#pragma unroll
-        for (int w = 1; w < WPS; ++w) t = fmax(t, red[w]);
-        v = t;
-    }
-    return v;
-}
-
-// Sweeps of one precision on the wave's state st[2][half].  Returns status.
-// Lane l owns slots h = l + 64k, k < NS, of each colour; slots beyond the
-// half volume are computed on a clamped index and discarded, so the passes
-// have no divergent branches.  For NS <= 2 the packed neighbour entries of
-// the lane's slots are held in registers (from the LDS copy nbt of the
-// table); otherwise they are recomputed from the slot descriptors.  CREG
-// colours (0, 1 or 2, starting with colour 0) keep the coefficients of the
-// lane's slots in registers for the whole phase.
-template <int D, typename R, int NS, bool RELAX, int CREG, int WPS, typename CP>
-__device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<const u32x4> nbt,
-                            lds_ptr<typename cx<R>::T> st, double eps, uint64_t &sweeps, double &D_out, double *red)
-{
-    const int half = WO.half;
-    using C = typename cx<R>::T;
-    constexpr bool NB_REG = NS <= 2;
-    // thread index within the start: the lane, or the workgroup thread when
-    // WPS wavefronts share the start
-    const int lane = WPS > 1 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
-    lds_ptr<C> st0 = st;
-    lds_ptr<C> st1 = st + half;
-    const R omega = (R)J.omega;
-    const uint64_t check = J.check_every > 0 ? (uint64_t)J.check_every : 1;
-    const bool maxabs = J.stop_norm != 0;
-    int hs[NS];
-    bool valid[NS];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        const int h = lane + 64 * WPS * k;
-        valid[k] = h < half;
-        hs[k] = valid[k] ? h : half - 1;
-    }
-    u32x4 nr[NB_REG ? 2 : 1][NB_REG ? NS : 1];
-    C own[NB_REG ? 2 : 1][NB_REG ? NS : 1];   // the lane's own sites (NB_REG): LDS is only written
-    uint32_t d0[NB_REG ? 1 : NS], d1[NB_REG ? 1 : NS];
-    Strides<D> L;
-    if constexpr (NB_REG) {
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            nr[0][k] = nbt[hs[k]];
-            nr[1][k] = nbt[half + hs[k]];
-            own[0][k] = st0[hs[k]];
-            own[1][k] = st1[hs[k]];
-        }
-    } else {
-        int str = 1;
-#pragma unroll
-        for (int mu = 0; mu < D; ++mu) {
-            L.s[mu] = str;
-            L.w[mu] = str * J.orb.ext[mu];
-            str *= J.orb.ext[mu];
-        }
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            d0[k] = WO.desc[hs[k]];
-            d1[k] = WO.desc[half + hs[k]];
-        }
-    }
-    constexpr int NCR = CREG > 0 ? CREG : 1;
-    C cr[NCR][NS][2 * D];
-    if constexpr (CREG > 0) {
-#pragma unroll
-        for (int c = 0; c < CREG; ++c)
-#pragma unroll
-            for (int k = 0; k < NS; ++k)
-#pragma unroll
-                for (int q = 0; q < 2 * D; ++q) cr[c][k][q] = coef[(c * 2 * D + q) * half + hs[k]];
-    }
-
-    uint64_t t = 0;
-    uint64_t until = check;      // sweeps left to the next check point
-    bool ckpt = false;           // the state after sweep t is checked
-    double part1 = 0.0;          // this lane's colour-1 part of the norm of sweep t
-    int status = GC_ST_NONCONVERGED;
-    D_out = INFINITY;
-    for (;;) {
-        // sweep t + 1 first reads the colour-0 staples of the state after
-        // sweep t; at a check point they complete the norm of sweep t
-        const bool pending = (t > 0) && ckpt;
-        const bool last = (t == J.max_sweeps);
-        // an opaque offset keeps per-slot index arithmetic inside the sweep
-        const int z = opaque_zero();
-        C gnew[NS];
-        double acc0 = 0.0;
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            const int h = hs[k] + z;
-            C s;
-            if constexpr (NB_REG) s = staple<D, R, (CREG >= 1)>(cr[0][k], coef, st1, NbWords{nr[0][k]}, 0, h, half);
-            else s = staple<D, R, (CREG >= 1)>(cr[0][k], coef, st1, NbDesc<D>{d0[k] + (uint32_t)z, L}, 0, h, half);
-            C g0;
-            if constexpr (NB_REG) g0 = own[0][k];
-            else g0 = st0[h];
-            const double dv = (double)(g0.x * s.y - g0.y * s.x);
-            const double a = maxabs ? fmax(acc0, fabs(dv)) : acc0 + dv * dv;
-            acc0 = valid[k] ? a : acc0;
-            gnew[k] = local_update<RELAX, R>(g0, s, omega);
-        }
-        if (pending) {
-            // one wave reduction per checked sweep, over both colours' lane parts
-            double Dn;
-            if (maxabs) Dn = start_max<WPS>(fmax(acc0, part1), red);
-            else Dn = start_sum<WPS>(acc0 + part1, red) / (double)(2 * half);
-            D_out = Dn;
-            if (!(Dn == Dn)) { status = GC_ST_BADNUM; break; }
-            if (Dn < eps) { status = GC_ST_CONVERGED; break; }
-        }
-        if (last) break;
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            if constexpr (NB_REG) own[0][k] = gnew[k];
-            if (valid[k]) st0[hs[k]] = gnew[k];
-        }
-        start_sync<WPS>();
-        // ---- colour 1, with its part of the norm of this sweep
-        ++t;
-        --until;
-        ckpt = (until == 0) || (t == J.max_sweeps);
-        if (until == 0) until = check;
-        const bool chk = ckpt;
-        double a1 = 0.0;
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            const int h = hs[k] + z;
-            C s;
-            if constexpr (NB_REG)
-                s = staple<D, R, (CREG >= 2)>(cr[NCR - 1][k], coef, st0, NbWords{nr[NB_REG ? 1 : 0][k]}, 1, h, half);
-            else
-                s = staple<D, R, (CREG >= 2)>(cr[NCR - 1][k], coef, st0, NbDesc<D>{d1[k] + (uint32_t)z, L}, 1, h,
-                                              half);
-            C g1;
-            if constexpr (NB_REG) g1 = own[NB_REG ? 1 : 0][k];
-            else g1 = st1[h];
-            const C g = local_update<RELAX, R>(g1, s, omega);
-            if constexpr (NB_REG) own[NB_REG ? 1 : 0][k] = g;
-            if (valid[k]) st1[hs[k]] = g;
-            const double dv = (double)(g.x * s.y - g.y * s.x);
-            const double a = maxabs ? fmax(a1, fabs(dv)) : a1 + dv * dv;
-            a1 = valid[k] ? a : a1;
-        }
-        if (chk) part1 = a1;
-        start_sync<WPS>();
-    }
-    sweeps = t;
-    return status;
-}
-
-template <int D, typename R, int NS, int CREG, int WPS, typename CP>
-__device__ int relax_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<const u32x4> nbt,
-                          lds_ptr<typename cx<R>::T> st, double eps, uint64_t &sweeps, double &D_out, double *red)
-{
-    if ((R)J.omega == (R)1)
-        return relax_wave_t<D, R, NS, true, CREG, WPS>(J, WO, coef, nbt, st, eps, sweeps, D_out, red);
-    return relax_wave_t<D, R, NS, false, CREG, WPS>(J, WO, coef, nbt, st, eps, sweeps, D_out, red);
-}
-
-template <int D, int NS, int CREG, int WPS, typename CP64, typename CP32>
-__device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 coef64, CP32 coef32,
-                                 lds_ptr<const u32x4> nbt, lds_ptr<dbl2> st64, lds_ptr<flt2> st32,
-                                 glb_ptr<flt2> bounce, uint64_t local, double *red)
-{
-    constexpr int T = 64 * WPS;   // threads on the start
-    const int lane = WPS > 1 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
-    const GcOrbitDev &O = J.orb;
-    const int V = O.V;
-    const uint64_t sid = J.first_start + local;
-
-    // random start, written at its colour-split position loc[i]
-    for (int b = lane; 4 * b < V; b += T) {
-        uint64_t c[4];
-        start_block(J.start_seed, sid, O.orbit_index, (uint64_t)b, c);
-#pragma unroll 1
-        for (int k = 0; k < 4; ++k) {
-            const int i = 4 * b + k;
-            if (i < V) {
-                double sn, cs;
-                sincos(angle_of(c[k]), &sn, &cs);
-                const int p = WO.loc[i];
-                if (J.precision == 1) st32[p] = flt2{(float)cs, (float)sn};
-                else st64[p] = dbl2{cs, sn};
-            }
-        }
-    }
-    start_sync<WPS>();
-
-    uint64_t sw32 = 0, sw64 = 0;
-    double Dn = INFINITY;
-    int status;
-    bool in64 = J.precision != 1;
-    if (J.precision == 1) {
-        status = relax_wave<D, float, NS, CREG, WPS>(J, WO, coef32, nbt, st32, J.eps32, sw32, Dn, red);
-        if (status == GC_ST_CONVERGED) {
-            // promotion g64 = normalise((double) g32): both states share the
-            // start's LDS region, so each thread bounces its entries through
-            // the start's scratch (it reads back only what it wrote)
-            in64 = true;
-            for (int p = lane; p < V; p += T) bounce[p] = st32[p];
-            start_sync<WPS>();
-            for (int p = lane; p < V; p += T) {
-                const flt2 g = bounce[p];
-                const double xr = (double)g.x, xi = (double)g.y;
-                const double r = rsqrt(xr * xr + xi * xi);
-                st64[p] = dbl2{xr * r, xi * r};
-            }
-            start_sync<WPS>();
-            status = relax_wave<D, double, NS, CREG, WPS>(J, WO, coef64, nbt, st64, J.eps64, sw64, Dn, red);
-        }
-    } else {
-        status = relax_wave<D, double, NS, CREG, WPS>(J, WO, coef64, nbt, st64, J.eps64, sw64, Dn, red);
-    }
-    // final state in natural site order
-    glb_ptr<dbl2> out = as_global(reinterpret_cast<dbl2 *>(J.states + local * (uint64_t)V));
-    for (int i = lane; i < V; i += T) {
-        const int p = WO.loc[i];
-        out[i] = in64 ? st64[p] : dbl2{(double)st32[p].x, (double)st32[p].y};
-    }
-    if (lane == 0) record_relax(J, local, status, sw32, sw64, Dn);
-    start_sync<WPS>();
-}
-
-// WG = WAVES wavefronts.  LDS: [neighbour table 16V when NS <= 2 | coef64 |
-// coef32 when COEF_LDS] then per wave a 16V-byte state region (double2[V],
-// or float2[V] in the single-precision phase).
-template <int D, int NS, int WAVES, bool COEF_LDS, int CREG>
-__global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__restrict__ jobs,
-                                                          const GcWaveOrbit *__restrict__ worbs, int n_jobs,
-                                                          unsigned long long *job_next, float2 *bounce_all)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int cur_job;
-    const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    int j0 = (int)(blockIdx.x % (unsigned)n_jobs);
-    for (int round = 0; round < n_jobs; ++round) {
-        if (threadIdx.x == 0) {
-            int pick = -1;
-            for (int k = 0; k < n_jobs; ++k) {
-                const int j = (j0 + k) % n_jobs;
-                if (__hip_atomic_load(&job_next[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < jobs[j].n_starts) {
-                    pick = j;
-                    break;
-                }
-            }
-            cur_job = pick;
-        }
-        __syncthreads();
-        const int jn = uniform(cur_job);
-        __syncthreads();
-        if (jn < 0) break;
-        const GcJobDev &J = jobs[jn];
-        const GcWaveOrbit &WO = worbs[jn];
-        const int V = J.orb.V;
-        const int ncoef = 2 * D * V;      // complex entries per precision
-        // neighbour table (16 bytes per slot, 16V in all, when NS <= 2),
-        // then the coefficients when staged, then the wavefronts' states
-        lds_ptr<u32x4> nbt = as_lds(reinterpret_cast<u32x4 *>(smem));
-        size_t off = 0;
-        if constexpr (NS <= 2) {
-            glb_ptr<const u32x4> nbg = as_global(reinterpret_cast<const u32x4 *>(WO.nb));
-            for (int t = threadIdx.x; t < V; t += 64 * WAVES) nbt[t] = nbg[t];
-            off = 16 * (size_t)V;
-        }
-        const dbl2 *g64 = reinterpret_cast<const dbl2 *>(WO.coef64);
-        const flt2 *g32 = reinterpret_cast<const flt2 *>(WO.coef32);
-        lds_ptr<dbl2> c64 = as_lds(reinterpret_cast<dbl2 *>(smem + off));
-        lds_ptr<flt2> c32 = as_lds(reinterpret_cast<flt2 *>(smem + off + 16 * (size_t)ncoef));
-        if (COEF_LDS) {
-            for (int t = threadIdx.x; t < ncoef; t += 64 * WAVES) c64[t] = g64[t];
-            off += 16 * (size_t)ncoef;
-            if (J.precision == 1) {
-                for (int t = threadIdx.x; t < ncoef; t += 64 * WAVES) c32[t] = g32[t];
-                off += 8 * (size_t)ncoef;
-            }
-        }
-        __syncthreads();
-        lds_ptr<dbl2> st64 = as_lds(reinterpret_cast<dbl2 *>(smem + off + (size_t)wave * 16 * V));
-        lds_ptr<flt2> st32 = as_lds(reinterpret_cast<flt2 *>(smem + off + (size_t)wave * 16 * V));
-        glb_ptr<flt2> bounce =
-            as_global(reinterpret_cast<flt2 *>(bounce_all) + ((uint64_t)blockIdx.x * WAVES + wave) * (uint64_t)V);
-        for (;;) {
-            unsigned long long s = 0;
-            if (lane == 0) s = atomicAdd(&job_next[jn], 1ULL);
-            s = uniform((uint64_t)s);
-            if (s >= J.n_starts) break;
-            lds_ptr<const u32x4> nbc = nbt;
-            if (COEF_LDS)
-                relax_start_wave<D, NS, CREG, 1>(J, WO, c64, c32, nbc, st64, st32, bounce, s, nullptr);
-            else
-                relax_start_wave<D, NS, CREG, 1>(J, WO, as_global(g64), as_global(g32), nbc, st64, st32, bounce, s,
-                                                 nullptr);
-        }
-        __syncthreads();
-        j0 = jn;
-    }
-}
-
-// One start per workgroup of WPS wavefronts, for lattices with more than 128
-// slots per colour: each thread keeps at most two slots per colour, the
-// colour passes synchronise the workgroup.  LDS: the neighbour table (16V)
-// and one state region (16V); the coefficients are read from global memory.
-template <int D, int WPS>
-__global__ __launch_bounds__(64 * WPS) void wps_kernel(const GcJobDev *__restrict__ jobs,
-                                                       const GcWaveOrbit *__restrict__ worbs, int n_jobs,
-                                                       unsigned long long *job_next, float2 *bounce_all)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int cur_job;
-    __shared__ unsigned long long claim;
-    __shared__ double red[WPS];
-    int j0 = (int)(blockIdx.x % (unsigned)n_jobs);
-    for (int round = 0; round < n_jobs; ++round) {
-        if (threadIdx.x == 0) {
-            int pick = -1;
-            for (int k = 0; k < n_jobs; ++k) {
-                const int j = (j0 + k) % n_jobs;
-                if (__hip_atomic_load(&job_next[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < jobs[j].n_starts) {
-                    pick = j;
-                    break;
-                }
-            }
-            cur_job = pick;
-        }
-        __syncthreads();
-        const int jn = uniform(cur_job);
-        __syncthreads();
-        if (jn < 0) break;
-        const GcJobDev &J = jobs[jn];
-        const GcWaveOrbit &WO = worbs[jn];
-        const int V = J.orb.V;
-        lds_ptr<u32x4> nbt = as_lds(reinterpret_cast<u32x4 *>(smem));
-        glb_ptr<const u32x4> nbg = as_global(reinterpret_cast<const u32x4 *>(WO.nb));
-        for (int t = threadIdx.x; t < V; t += 64 * WPS) nbt[t] = nbg[t];
-        __syncthreads();
-        lds_ptr<dbl2> st64 = as_lds(reinterpret_cast<dbl2 *>(smem + 16 * (size_t)V));
-        lds_ptr<flt2> st32 = as_lds(reinterpret_cast<flt2 *>(smem + 16 * (size_t)V));
-        glb_ptr<flt2> bounce = as_global(reinterpret_cast<flt2 *>(bounce_all) + (uint64_t)blockIdx.x * (uint64_t)V);
-        const dbl2 *g64 = reinterpret_cast<const dbl2 *>(WO.coef64);
-        const flt2 *g32 = reinterpret_cast<const flt2 *>(WO.coef32);
-        lds_ptr<const u32x4> nbc = nbt;
-        for (;;) {
-            if (threadIdx.x == 0) claim = atomicAdd(&job_next[jn], 1ULL);
-            __syncthreads();
-            const uint64_t s = uniform((uint64_t)claim);
-            __syncthreads();
-            if (s >= J.n_starts) break;
-            relax_start_wave<D, 2, 0, WPS>(J, WO, as_global(g64), as_global(g32), nbc, st64, st32, bounce, s, red);
-        }
-        __syncthreads();
-        j0 = jn;
-    }
-}
-
-template <int D, int WPS>
-hipError_t wps_launch_t(const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, unsigned long long *job_next,
-                        float2 *bounce, int grid, size_t lds, hipStream_t s)
-{
-    hipLaunchKernelGGL((wps_kernel<D, WPS>), dim3(grid), dim3(64 * WPS), lds, s, jobs, worbs, n_jobs, job_next,
-                       bounce);
-    return hipGetLastError();
-}
-
-template <int D, int WPS>
-hipError_t wps_occ_t(size_t lds, int *per_cu)
-{
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, wps_kernel<D, WPS>, 64 * WPS, lds);
-}
-
-template <int D, int NS, int WAVES, bool CL, int CREG>
-hipError_t launch_v(const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, unsigned long long *job_next,
-                    float2 *bounce, int grid, size_t lds, hipStream_t s)
-{
-    hipLaunchKernelGGL((wave_kernel<D, NS, WAVES, CL, CREG>), dim3(grid), dim3(64 * WAVES), lds, s, jobs, worbs,
-                       n_jobs, job_next, bounce);
-    return hipGetLastError();
-}
-
-template <int D, int NS, int WAVES, bool CL, int CREG>
-hipError_t occ_v(size_t lds, int *per_cu)
-{
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, wave_kernel<D, NS, WAVES, CL, CREG>, 64 * WAVES, lds);
-}
-
-// Register-held coefficients are instantiated where a lane's slots are few
-// (NS <= 2): creg 1 holds colour 0, creg 2 both colours.
-template <int D, int NS> constexpr bool creg_ok() { return NS <= 2; }
-
-template <int D, int NS, int WAVES>
-hipError_t launch_t(const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, unsigned long long *job_next,
-                    int variant, float2 *bounce, int grid, size_t lds, hipStream_t s)
-{
-    const bool cl = (variant & 1) != 0;
-    const int creg = variant >> 1;
-    if constexpr (creg_ok<D, NS>()) {
-        if (creg == 1)
-            return cl ? launch_v<D, NS, WAVES, true, 1>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s)
-                      : launch_v<D, NS, WAVES, false, 1>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s);
-        if (creg == 2)
-            return cl ? launch_v<D, NS, WAVES, true, 2>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s)
-                      : launch_v<D, NS, WAVES, false, 2>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s);
-    }
-    if (creg != 0) return hipErrorInvalidValue;
-    return cl ? launch_v<D, NS, WAVES, true, 0>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s)
-              : launch_v<D, NS, WAVES, false, 0>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s);
-}
-
-template <int D, int NS, int WAVES>
-hipError_t occ_t(int variant, size_t lds, int *per_cu)
-{
-    const bool cl = (variant & 1) != 0;
-    const int creg = variant >> 1;
-    if constexpr (creg_ok<D, NS>()) {
-        if (creg == 1) return cl ? occ_v<D, NS, WAVES, true, 1>(lds, per_cu) : occ_v<D, NS, WAVES, false, 1>(lds, per_cu);
-        if (creg == 2) return cl ? occ_v<D, NS, WAVES, true, 2>(lds, per_cu) : occ_v<D, NS, WAVES, false, 2>(lds, per_cu);
-    }
-    if (creg != 0) return hipErrorInvalidValue;
-    return cl ? occ_v<D, NS, WAVES, true, 0>(lds, per_cu) : occ_v<D, NS, WAVES, false, 0>(lds, per_cu);
-}
-
-int creg_max_t(int d, int ns)
-{
-    (void)d;
-    return ns <= 2 ? 2 : 0;
-}
-
-}  // namespace
-
-// NS = slots per lane per colour = ceil(half / 64); instantiated for the
-// half-volumes up to 2048 sites (V <= 4096).
-#define GC_WAVE_DISPATCH(FN, ...)                                                              \
-    switch (d) {                                                                               \
-    case 1: return ns <= 1 ? FN<1, 1, 4>(__VA_ARGS__) : ns <= 4 ? FN<1, 4, 4>(__VA_ARGS__)     \
-                 : ns <= 12 ? FN<1, 12, 4>(__VA_ARGS__) : FN<1, 32, 4>(__VA_ARGS__);           \
-    case 2: return ns <= 1 ? FN<2, 1, 4>(__VA_ARGS__) : ns <= 2 ? FN<2, 2, 4>(__VA_ARGS__)     \
-                 : ns <= 4 ? FN<2, 4, 4>(__VA_ARGS__) : ns <= 12 ? FN<2, 12, 4>(__VA_ARGS__)   \
-                 : FN<2, 32, 4>(__VA_ARGS__);                                                  \
-    case 3: return ns <= 2 ? FN<3, 2, 4>(__VA_ARGS__) : ns <= 4 ? FN<3, 4, 4>(__VA_ARGS__)     \
-                 : ns <= 8 ? FN<3, 8, 4>(__VA_ARGS__) : FN<3, 32, 4>(__VA_ARGS__);             \
-    case 4: return ns <= 1 ? FN<4, 1, 4>(__VA_ARGS__) : ns <= 2 ? FN<4, 2, 4>(__VA_ARGS__)     \
-                 : ns <= 4 ? FN<4, 4, 4>(__VA_ARGS__) : ns <= 11 ? FN<4, 11, 4>(__VA_ARGS__)   \
-                 : FN<4, 32, 4>(__VA_ARGS__);                                                  \
-    default: return hipErrorInvalidValue;                                                      \
-    }
+#define GC_WAVE_DECLARE_DIM(D)                                                                              \
+    hipError_t gc_wave_occupancy_d##D(int ns, int variant, size_t lds, int *per_cu);                         \
+    hipError_t gc_launch_wave_d##D(int ns, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs,      \
+                                   unsigned long long *job_next, int variant, float2 *bounce, int grid,      \
+                                   size_t lds, hipStream_t s);                                               \
+    hipError_t gc_wps_occupancy_d##D(int wps, size_t lds, int *per_cu);                                      \
+    hipError_t gc_launch_wps_d##D(int wps, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs,      \
+                                  unsigned long long *job_next, float2 *bounce, int grid, size_t lds,        \
+                                  hipStream_t s);
+GC_WAVE_DECLARE_DIM(1)
+GC_WAVE_DECLARE_DIM(2)
+GC_WAVE_DECLARE_DIM(3)
+GC_WAVE_DECLARE_DIM(4)
 
 hipError_t gc_wave_occupancy(int d, int ns, int variant, size_t lds, int *per_cu)
 {
-    GC_WAVE_DISPATCH(occ_t, variant, lds, per_cu)
+    switch (d) {
+    case 1: return gc_wave_occupancy_d1(ns, variant, lds, per_cu);
+    case 2: return gc_wave_occupancy_d2(ns, variant, lds, per_cu);
+    case 3: return gc_wave_occupancy_d3(ns, variant, lds, per_cu);
+    case 4: return gc_wave_occupancy_d4(ns, variant, lds, per_cu);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t gc_launch_wave(int d, int ns, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs,
                           unsigned long long *job_next, int variant, float2 *bounce, int grid, size_t lds,
                           hipStream_t s)
 {
-    GC_WAVE_DISPATCH(launch_t, jobs, worbs, n_jobs, job_next, variant, bounce, grid, lds, s)
+    switch (d) {
+    case 1: return gc_launch_wave_d1(ns, jobs, worbs, n_jobs, job_next, variant, bounce, grid, lds, s);
+    case 2: return gc_launch_wave_d2(ns, jobs, worbs, n_jobs, job_next, variant, bounce, grid, lds, s);
+    case 3: return gc_launch_wave_d3(ns, jobs, worbs, n_jobs, job_next, variant, bounce, grid, lds, s);
+    case 4: return gc_launch_wave_d4(ns, jobs, worbs, n_jobs, job_next, variant, bounce, grid, lds, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
-int gc_wave_creg_max(int d, int ns) { return creg_max_t(d, ns); }
-
+// Register-held coefficients are instantiated where a lane's slots are few
+// (at most two per colour): creg 1 holds colour 0, creg 2 both colours.
+int gc_wave_creg_max(int d, int ns)
+{
+    (void)d;
+    return ns <= 2 ? 2 : 0;
+}
 
 // Wavefronts per start of the workgroup-per-start variant for a lattice with
 // ns slots per lane in the one-wavefront layout (0: use that layout).
@@ -589,30 +60,25 @@ int gc_wps_for(int ns)
     return -1;
 }
 
-#define GC_WPS_DISPATCH(FN, ...)                                                                \
-    switch (d * 100 + wps) {                                                                    \
-    case 102: return FN<1, 2>(__VA_ARGS__);  case 104: return FN<1, 4>(__VA_ARGS__);           \
-    case 106: return FN<1, 6>(__VA_ARGS__);  case 108: return FN<1, 8>(__VA_ARGS__);           \
-    case 116: return FN<1, 16>(__VA_ARGS__);                                                    \
-    case 202: return FN<2, 2>(__VA_ARGS__);  case 204: return FN<2, 4>(__VA_ARGS__);           \
-    case 206: return FN<2, 6>(__VA_ARGS__);  case 208: return FN<2, 8>(__VA_ARGS__);           \
-    case 216: return FN<2, 16>(__VA_ARGS__);                                                    \
-    case 302: return FN<3, 2>(__VA_ARGS__);  case 304: return FN<3, 4>(__VA_ARGS__);           \
-    case 306: return FN<3, 6>(__VA_ARGS__);  case 308: return FN<3, 8>(__VA_ARGS__);           \
-    case 316: return FN<3, 16>(__VA_ARGS__);                                                    \
-    case 402: return FN<4, 2>(__VA_ARGS__);  case 404: return FN<4, 4>(__VA_ARGS__);           \
-    case 406: return FN<4, 6>(__VA_ARGS__);  case 408: return FN<4, 8>(__VA_ARGS__);           \
-    case 416: return FN<4, 16>(__VA_ARGS__);                                                    \
-    default: return hipErrorInvalidValue;                                                       \
-    }
-
 hipError_t gc_wps_occupancy(int d, int wps, size_t lds, int *per_cu)
 {
-    GC_WPS_DISPATCH(wps_occ_t, lds, per_cu)
+    switch (d) {
+    case 1: return gc_wps_occupancy_d1(wps, lds, per_cu);
+    case 2: return gc_wps_occupancy_d2(wps, lds, per_cu);
+    case 3: return gc_wps_occupancy_d3(wps, lds, per_cu);
+    case 4: return gc_wps_occupancy_d4(wps, lds, per_cu);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t gc_launch_wps(int d, int wps, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs,
                          unsigned long long *job_next, float2 *bounce, int grid, size_t lds, hipStream_t s)
 {
-    GC_WPS_DISPATCH(wps_launch_t, jobs, worbs, n_jobs, job_next, bounce, grid, lds, s)
+    switch (d) {
+    case 1: return gc_launch_wps_d1(wps, jobs, worbs, n_jobs, job_next, bounce, grid, lds, s);
+    case 2: return gc_launch_wps_d2(wps, jobs, worbs, n_jobs, job_next, bounce, grid, lds, s);
+    case 3: return gc_launch_wps_d3(wps, jobs, worbs, n_jobs, job_next, bounce, grid, lds, s);
+    case 4: return gc_launch_wps_d4(wps, jobs, worbs, n_jobs, job_next, bounce, grid, lds, s);
+    default: return hipErrorInvalidValue;
+    }
 }

@@ -70,15 +70,23 @@ def compare_starts(extent, g, o, allow_sweep_slack=1):
             np.max(np.abs(g["paper_X"][conv].astype(np.int64) - o["paper_X"][conv])) <= 1
 
 
+def assert_key_order(copies):
+    """gc_fetch returns the copies in strictly increasing (key_hi, key_lo)."""
+    k = [(int(a), int(b)) for a, b in zip(copies["key_hi"], copies["key_lo"])]
+    assert all(x < y for x, y in zip(k, k[1:]))
+
+
 def compare_tables(extent, phi, copies, o_res, params, check_lambda=True):
     V = int(np.prod(extent))
     tab = o_res["table"]
+    assert_key_order(copies)
     gk = {(int(c["key_hi"]), int(c["key_lo"])): c for c in copies}
     assert set(gk) == set(tab)
     for k, e in tab.items():
         c = gk[k]
         assert int(c["hits"]) == e["hits"]
         assert int(c["first_start"]) == e["first_start"]
+        assert int(c["rep_start"]) == e["rep_start"]
         assert abs(c["F"] - e["F"]) / V < F_TOL_PER_SITE
         assert (int(c["flags"]) & gc.GC_FLAG_COLLISION) == (e["flags"] & O.FLAG_COLLISION)
         if check_lambda:
@@ -216,15 +224,16 @@ def test_invalid_inputs(ctx):
     ctx.gc_release(h)
 
 
-def test_representative_state_matches_oracle(ctx):
-    """gc_fetch_state re-runs a start: theta_i - theta_{V-1} equals the oracle's."""
+def test_start_state_matches_oracle(ctx):
+    """gc_fetch_start_state: theta_i - theta_{V-1} of a start's final state
+    equals the oracle's."""
     extent = (4, 4, 4, 4)
     phi = GI.orbit_angles(extent, 0, 0)
     p = gc.SolveParams(omega=1.7)
     h, copies, starts, _ = run_gpu(ctx, extent, phi, 20, p)
     rec, g, _ = O.solve(extent, phi, np.arange(20), oracle_params(p), want_state=True)
     for s in [0, 7, 19]:
-        th = ctx.gc_fetch_state(h, s)
+        th = ctx.gc_fetch_start_state(h, s)
         ref = O.theta_of(g[s])
         ref = np.angle(np.exp(1j * (ref - ref[-1])))
         d = np.angle(np.exp(1j * (th - ref)))
@@ -247,6 +256,12 @@ def V_of(extent):
 
 def _check_table_properties(extent, copies, starts, prog):
     V = int(np.prod(extent))
+    assert_key_order(copies)
+    # the representative start reaches its copy's key and carries its F
+    rep = copies["rep_start"].astype(np.int64)
+    assert np.array_equal(starts["key_hi"][rep], copies["key_hi"])
+    assert np.array_equal(starts["key_lo"][rep], copies["key_lo"])
+    assert np.array_equal(starts["F"][rep], copies["F"])
     conv = starts["status"] == gc.GC_START_CONVERGED
     keys = set(zip(starts["key_hi"][conv].tolist(), starts["key_lo"][conv].tolist()))
     assert len(keys) == len(copies) == prog["distinct"]
@@ -270,8 +285,10 @@ def _check_table_properties(extent, copies, starts, prog):
 
 @pytest.mark.parametrize("extent,n,omega,precision,sample", [
     ((4, 4, 4, 4), 100_000, 1.0, "fp64", 160),
-    ((6, 6, 6, 6), 200_000, 1.7, "mixed", 96),
-    ((10, 10, 10), 200_000, 1.7, "mixed", 96),
+    ((6, 6, 6, 6), 200_000, 1.7, "fp64", 300),
+    ((10, 10, 10), 200_000, 1.7, "fp64", 300),
+    ((6, 6, 6, 6), 200_000, 1.7, "mixed", 400),
+    ((10, 10, 10), 200_000, 1.7, "mixed", 400),
 ])
 def test_full_size_sampled_parity(ctx, extent, n, omega, precision, sample):
     phi = GI.orbit_angles(extent, 0, 0)
@@ -293,7 +310,21 @@ def test_full_size_sampled_parity(ctx, extent, n, omega, precision, sample):
             e = o["table"][k]
             assert abs(gk[k]["lambda2"] - e["lambda2"]) < LAMBDA_TOL
             assert (int(gk[k]["flags"]) & 15) == (e["flags"] & 15)
-        note("full parity: %d copies, %d flagged" % (len(copies), len(flagged)))
+        # representatives fetched by key: copies whose lowest start is not
+        # their representative (it halted next to a saddle), and a few others
+        moved = [k for k, e in o["table"].items() if e["rep_start"] != e["first_start"]]
+        for k in moved + sorted(pick)[:4]:
+            e = o["table"][k]
+            th = ctx.gc_fetch_state(h, k[0], k[1])
+            _, gr, _ = O.solve(extent, phi, [e["rep_start"]], oracle_params(p), want_state=True)
+            ref = O.theta_of(gr[0])
+            d = np.angle(np.exp(1j * (th - (ref - ref[-1]))))
+            assert np.max(np.abs(d)) < 1e-9 and th[-1] == 0.0
+        with pytest.raises(gc.GcError) as err:
+            ctx.gc_fetch_state(h, 1, 1)
+        assert err.value.status == gc.GC_ENOTFOUND
+        note("full parity: %d copies, %d flagged, %d with a moved representative" %
+             (len(copies), len(flagged), len(moved)))
         ctx.gc_release(h)
         return
     ids = np.unique(np.concatenate([[0, n - 1], np.linspace(0, n - 1, sample).astype(np.int64)]))
@@ -305,13 +336,15 @@ def test_full_size_sampled_parity(ctx, extent, n, omega, precision, sample):
     if precision == "fp64":
         compare_starts(extent, gs, o64)
     else:
-        # keys agree wherever the single-precision bulk reaches the double basin
-        assert same.mean() >= 0.97
+        # keys agree wherever the single-precision bulk reaches the double basin;
+        # the FP32 rounding moves the basin of about 0.1 % of the starts on
+        # these lattices, so more than 1 % of a 400-start sample is an error
+        assert same.mean() >= 0.99
         assert np.max(np.abs(gs["F"][same] - o64["F"][same])) / V < F_TOL_PER_SITE
         # a start whose basin moved still converged to a genuine FP64 minimum
         land = BF.Landscape(extent, phi)
         for s in ids[~same][:4]:
-            th = ctx.gc_fetch_state(h, int(s))
+            th = ctx.gc_fetch_start_state(h, int(s))
             grad = land.grad(th)
             assert np.mean(grad ** 2) < 2e-14
             r, _, _, w = O.observe(extent, phi, th)
@@ -435,7 +468,76 @@ def test_parity_workgroup_per_start(monkeypatch, extent, precision, n):
             # reached the same basin; both sides' F agree on those
             conv = (o["records"]["status"] == O.CONVERGED) & (starts["status"] == gc.GC_START_CONVERGED)
             same = conv & (starts["key_hi"] == o["records"]["key_hi"]) & (starts["key_lo"] == o["records"]["key_lo"])
-            assert same.sum() >= 0.9 * conv.sum()
+            assert same.sum() >= 0.97 * conv.sum()
             V = int(np.prod(extent))
             assert np.max(np.abs(starts["F"][same] - o["records"]["F"][same])) / V < F_TOL_PER_SITE
         c.gc_release(h)
+
+
+@pytest.mark.parametrize("extent,mask,omega,n", [
+    ((8,), 1, 1.0, 300),            # 1D ring: closed form below
+    ((4, 6), 1, 1.7, 300),
+    ((6, 6), 3, 1.0, 200),
+    ((3, 3), 2, 1.7, 200),          # three colours
+    ((4, 4, 4, 4), 5, 1.7, 300),
+    ((6, 6, 6), 7, 1.0, 100),
+])
+def test_parity_antiperiodic(ctx, extent, mask, omega, n):
+    """Antiperiodic gauge transformations in the directions of the mask
+    (Sec. II): start by start and copy by copy against the oracle on the
+    twisted orbit."""
+    phi = GI.orbit_angles(extent, 2, 4)
+    p = gc.SolveParams(omega=omega)
+    note("antiperiodic extent=%s mask=%d" % (extent, mask))
+    h = ctx.gc_orbit_load(extent, phi, 4, antiperiodic=mask)
+    assert np.array_equal(ctx.gc_orbit_angles(h), phi)
+    ctx.gc_launch(h, n, p)
+    assert ctx.gc_wait(h, 600_000) == gc.GC_OK
+    copies, starts = ctx.gc_fetch(h), ctx.gc_fetch_starts(h, n)
+    o = O.enumerate_copies(extent, O.twisted(extent, phi, mask), np.arange(n), oracle_params(p, 4))
+    compare_starts(extent, starts, o["records"])
+    compare_tables(extent, phi, copies, o, p)
+    check_start_filter(copies, starts, o)
+    if len(extent) == 1:
+        N = extent[0]
+        Phi = float(np.sum(phi[0]))
+        want = [N * (1 - math.cos((Phi + math.pi + 2 * math.pi * k) / N)) for k in range(-N - 1, N + 1)
+                if abs(Phi + math.pi + 2 * math.pi * k) < N * math.pi / 2]
+        for F in copies["F"]:
+            assert min(abs(F - w) for w in want) < 1e-10
+    ctx.gc_release(h)
+    with pytest.raises(gc.GcError) as e:
+        ctx.gc_orbit_load(extent, phi, 4, antiperiodic=1 << len(extent))
+    assert e.value.status == gc.GC_EINVAL
+
+
+@pytest.mark.parametrize("extent,batch,n,norm", [
+    ((4, 4), 16, 200, "max_abs"),
+    ((2, 2, 2, 2), 64, 300, "max_abs"),
+    ((3, 3), 32, 100, "mean_sq"),
+    ((4, 4, 4, 4), 1024, 3000, "max_abs"),
+])
+def test_parity_batch_synchronous_stop(ctx, extent, batch, n, norm):
+    """The paper's batch-synchronous stop (Sec. III): every start of a batch
+    runs as many sweeps as the batch's slowest; start by start against the
+    oracle's two-pass definition."""
+    phi = GI.orbit_angles(extent, 0, 6)
+    eps = 1e-12 if norm == "max_abs" else 1e-14
+    p = gc.SolveParams(omega=1.0, stop_norm=norm, eps64=eps, sync_batch=batch)
+    note("sync extent=%s batch=%d n=%d" % (extent, batch, n))
+    h = ctx.gc_orbit_load(extent, phi, 6)
+    ctx.gc_launch(h, n, p)
+    assert ctx.gc_wait(h, 600_000) == gc.GC_OK
+    copies, starts, prog = ctx.gc_fetch(h), ctx.gc_fetch_starts(h, n), ctx.gc_poll(h)
+    op = oracle_params(gc.SolveParams(omega=1.0, stop_norm=norm, eps64=eps), 6)
+    pick = {(int(c["key_hi"]), int(c["key_lo"])) for c in copies[:: max(1, len(copies) // 16)]}
+    o = O.enumerate_copies(extent, phi, np.arange(n), op, sync_batch=batch, lambda_keys=pick)
+    compare_starts(extent, starts, o["records"])
+    compare_tables(extent, phi, copies, o, p, check_lambda=False)
+    for lo in range(0, n, batch):
+        assert len(set(starts["sweeps64"][lo:lo + batch].tolist())) == 1
+    assert prog["sweeps_total"] == int(starts["sweeps64"].sum())
+    with pytest.raises(gc.GcError) as e:
+        ctx.gc_launch(h, 10, gc.SolveParams(precision="mixed", sync_batch=8))
+    assert e.value.status == gc.GC_EINVAL
+    ctx.gc_release(h)

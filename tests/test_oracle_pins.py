@@ -489,3 +489,81 @@ def test_saddle_stop_is_not_the_representative():
     (e,) = res["table"].values()
     assert e["hits"] == 8 and e["first_start"] == 4312 and e["rep_start"] == 4312
     assert e["flags"] & O.FLAG_COLLISION and e["flags"] & O.FLAG_IN_REGION
+
+
+# --------------------------------------------------------------------------
+# Antiperiodic boundary conditions (Sec. II) and the paper's batch-synchronous
+# stop (Sec. III)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("extent,mask", [((4, 6), 1), ((4, 6), 3), ((3, 4, 2), 2), ((5,), 1)])
+def test_antiperiodic_functional_definition(extent, mask):
+    """With gauge transformations antiperiodic in direction mu
+    (g_{x + N_mu e_mu} = -g_x, i.e. theta gains pi across the boundary), eq. (3)
+    written out directly over the links equals the oracle's functional on the
+    orbit whose wrapping links carry the extra angle pi."""
+    d, V = len(extent), int(np.prod(extent))
+    rng = np.random.default_rng(7)
+    phi = rng.uniform(-math.pi, math.pi, (d, V))
+    coords = np.array(np.unravel_index(np.arange(V), extent[::-1]))[::-1]
+    fwd, _ = O.neighbours(extent)
+    for _ in range(3):
+        theta = rng.uniform(-math.pi, math.pi, V)
+        F = 0.0
+        for mu in range(d):
+            for i in range(V):
+                tf = theta[fwd[mu, i]]
+                if (mask >> mu) & 1 and coords[mu, i] == extent[mu] - 1:
+                    tf += math.pi
+                F += 1.0 - math.cos(phi[mu, i] + tf - theta[i])
+        r, _, _, _ = O.observe(extent, O.twisted(extent, phi, mask), theta)
+        assert abs(r["F"] - F) < 1e-11
+
+
+@pytest.mark.parametrize("N,seed", [(6, 4), (7, 5), (8, 6)])
+def test_1d_antiperiodic_ring_closed_form(N, seed):
+    """1D ring with antiperiodic gauge transformations: the link angles of a
+    stationary point again share their sine, and now sum to Phi + pi modulo
+    2 pi, so the minima are uniform, a_k = (Phi + pi + 2 pi k)/N with
+    cos a_k > 0, F_k = N (1 - cos a_k)."""
+    phi = GI.orbit_angles((N,), seed, 0)
+    Phi = float(np.sum(phi[0]))
+    ks = [k for k in range(-N - 1, N + 1) if abs(Phi + math.pi + TWO_PI * k) < N * math.pi / 2]
+    res = O.enumerate_copies((N,), O.twisted((N,), phi, 1), np.arange(3000), O.SolveParams(omega=1.0),
+                             with_lambda=False)
+    got = sorted(e["F"] for e in res["table"].values())
+    want = sorted(N * (1 - math.cos((Phi + math.pi + TWO_PI * k) / N)) for k in ks)
+    # every minimum found is one of the closed-form ones (the highest, whose
+    # basin is smallest, may be missed by a finite sample), the lowest two are found
+    assert all(min(abs(F - w) for w in want) < 1e-10 for F in got)
+    assert len(got) >= min(2, len(want)) and abs(got[0] - want[0]) < 1e-10
+
+
+def test_sync_batch_of_one_is_the_per_start_rule():
+    extent = (4, 4)
+    phi = GI.orbit_angles(extent, 0, 0)
+    p = O.SolveParams(omega=1.0, stop_norm="max_abs", eps64=1e-12)
+    r1, _, _ = O.solve(extent, phi, np.arange(40), p)
+    rs, _ = O.solve_sync(extent, phi, np.arange(40), p, batch=1)
+    for f in ("status", "sweeps64", "key_hi", "key_lo", "F", "D"):
+        assert np.array_equal(r1[f], rs[f]), f
+
+
+def test_sync_batch_runs_each_batch_to_its_slowest_start():
+    """Sec. III: one stopping test over all samples relaxed together, so
+    every sample of a batch runs as long as the slowest needs; samples that
+    had already stopped keep their minimum (same key, functional within the
+    paper's 1e-10 plateau) and end far below the threshold."""
+    extent = (6, 6)
+    phi = GI.orbit_angles(extent, 0, 3)
+    p = O.SolveParams(omega=1.0, stop_norm="max_abs", eps64=1e-12, orbit_index=3)
+    ids = np.arange(96)
+    own, _, _ = O.solve(extent, phi, ids, p)
+    rs, _ = O.solve_sync(extent, phi, ids, p, batch=32)
+    for lo in range(0, 96, 32):
+        assert np.all(rs["sweeps64"][lo:lo + 32] == own["sweeps64"][lo:lo + 32].max())
+    assert np.all(rs["status"] == O.CONVERGED) and np.all(rs["D"] < 1e-12)
+    assert np.array_equal(rs["key_hi"], own["key_hi"]) and np.array_equal(rs["key_lo"], own["key_lo"])
+    assert np.max(np.abs(rs["F"] - own["F"])) < 1e-10
+    longer = rs["sweeps64"] > own["sweeps64"]
+    assert longer.any() and np.all(rs["D"][longer] <= own["D"][longer])
