@@ -314,6 +314,29 @@ gc_status gc_saturation(gc_ctx *ctx, gc_orbit orbit, int32_t n_points, const uin
 gc_status gc_paper_saturation(gc_ctx *ctx, gc_orbit orbit, int32_t n_points, const uint64_t *sample_sizes,
                               uint64_t *distinct_out);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  The path
+ * of gc_launch for one loaded orbit (same kernels and results), enqueued on
+ * hip_stream (NULL: the null stream) without any device or pinned
+ * allocation and without waiting for the device.  Working memory is one
+ * static device array of 64 MiB per GPU, resident from the library's load
+ * until the process ends; every call on a GPU uses the same array and a call
+ * clears what it needs, so calls that overlap on one GPU race: keep them on
+ * one stream.  It is not charged to the context's HBM budget.
+ * Outputs, device memory owned by the caller and written when the stream
+ * reaches them: copies_dev[copies_cap] (copies_cap >= n_starts) the
+ * distinct copies with the fields of gc_copy, in table order (ascending
+ * key_hi except where probing displaced an entry: sort for key order);
+ * *n_copies_dev their number; counters_dev NULL or 8 uint64 (starts done,
+ * converged, nonconverged, distinct, sweeps total, Lanczos runs, table
+ * insert errors, reserved).  The orbit's gc_fetch results are untouched.
+ * Errors: GC_EINVAL (bad handle or arguments), GC_ENOMEM (the launch needs
+ * more than the static array, e.g. more than about 13000 starts of a 4^4
+ * lattice; gc_last_error says how much), launch errors. */
+gc_status gc_launch_static(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_solve_params *params,
+                           void *hip_stream, gc_copy *copies_dev, uint64_t copies_cap, uint64_t *n_copies_dev,
+                           uint64_t *counters_dev);
+
 /* Result of gc_autotune. */
 typedef struct {
     int32_t relax_variant;          /* colours whose coefficients a lane keeps in registers (0..2), plus 8

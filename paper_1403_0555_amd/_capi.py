@@ -27,7 +27,7 @@ EXPORTED_SYMBOLS = [
     "gc_create", "gc_destroy", "gc_orbit_load", "gc_orbit_random", "gc_orbit_angles",
     "gc_launch", "gc_launch_batch", "gc_poll", "gc_wait", "gc_fetch", "gc_fetch_starts",
     "gc_fetch_state", "gc_fetch_start_state", "gc_release", "gc_last_error", "gc_kernel_time_ms", "gc_launch_bytes",
-    "gc_memory_info", "gc_autotune", "gc_saturation", "gc_paper_saturation",
+    "gc_memory_info", "gc_autotune", "gc_saturation", "gc_paper_saturation", "gc_launch_static",
 ]
 
 
@@ -124,6 +124,7 @@ def lib():
         "gc_autotune": ([vp, u64, u64, P(gc_solve_params), P(gc_tune_result)], i32),
         "gc_saturation": ([vp, u64, i32, P(u64), i32, P(u64)], i32),
         "gc_paper_saturation": ([vp, u64, i32, P(u64), P(u64)], i32),
+        "gc_launch_static": ([vp, u64, u64, P(gc_solve_params), vp, vp, u64, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -357,6 +358,14 @@ class Context:
                                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))),
                     "gc_paper_saturation")
         return out
+
+    def gc_launch_static(self, orbit: int, n_starts: int, params: SolveParams | None, hip_stream: int,
+                         copies_dev: int, copies_cap: int, n_copies_dev: int, counters_dev: int = 0):
+        """Device pointers (integers) owned by the caller; enqueues and returns."""
+        p = (params or SolveParams()).c()
+        self._check(self._L.gc_launch_static(self._h, orbit, n_starts, ctypes.byref(p), hip_stream or None,
+                                             copies_dev, copies_cap, n_copies_dev, counters_dev or None),
+                    "gc_launch_static")
 
     def gc_last_error(self) -> str:
         buf = ctypes.create_string_buffer(512)

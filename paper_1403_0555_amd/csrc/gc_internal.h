@@ -139,6 +139,8 @@ hipError_t gc_launch_finalize(const GcJobDev *jobs_host, int n_jobs, hipStream_t
 hipError_t gc_launch_patch(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);      // fix-up results -> copies
 hipError_t gc_launch_orbit_random(double *phi, int64_t n_links, uint64_t seed, uint64_t orbit_index, hipStream_t s);
 hipError_t gc_launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
+// Write bytes (host source, copied into kernel arguments) to device memory.
+hipError_t gc_launch_store(void *dst, const void *src, size_t bytes, hipStream_t s);
 // Batch-synchronous stop: per batch of sync_batch starts, the largest
 // first-pass sweep count, written per start to fixed_sweeps; relax counters
 // cleared for the second pass.

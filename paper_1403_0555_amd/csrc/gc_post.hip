@@ -18,6 +18,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 
 namespace {
 
@@ -832,6 +833,18 @@ __global__ void sync_kernel(GcJobDev J)
     }
 }
 
+// Bytes carried in a kernel argument and written to device memory: lets a
+// caller enqueue descriptors without host staging memory.
+constexpr size_t kStoreMax = 2048;
+struct StoreBytes {
+    unsigned char b[kStoreMax];
+};
+
+__global__ void store_kernel(StoreBytes v, uint32_t n, unsigned char *dst)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = v.b[i];
+}
+
 __global__ void zero_u64_kernel(unsigned long long *p, int n)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1024,6 +1037,19 @@ hipError_t gc_launch_sync(const GcJobDev *jobs_host, int n_jobs, hipStream_t s)
         const GcJobDev &J = jobs_host[j];
         const uint64_t nb = (J.n_starts + J.sync_batch - 1) / J.sync_batch;
         hipLaunchKernelGGL(sync_kernel, dim3(grid_for(nb)), dim3(256), 0, s, J);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t gc_launch_store(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    for (size_t off = 0; off < bytes; off += kStoreMax) {
+        StoreBytes v;
+        const size_t n = bytes - off < kStoreMax ? bytes - off : kStoreMax;
+        memcpy(v.b, (const unsigned char *)src + off, n);
+        hipLaunchKernelGGL(store_kernel, dim3(1), dim3(256), 0, s, v, (uint32_t)n, (unsigned char *)dst + off);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

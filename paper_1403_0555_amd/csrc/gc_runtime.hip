@@ -28,9 +28,37 @@
 #include <thread>
 #include <vector>
 
+// Working memory of gc_launch_static, for callers that cannot allocate: one
+// array per GPU, resident from the module load until the process ends.  Host
+// code reaches it only through the device address hipGetSymbolAddress
+// returns (kept per device), never through this name.
+#define GC_STATIC_SCRATCH_BYTES (64ull << 20)
+static __device__ __align__(256) unsigned char scratch[GC_STATIC_SCRATCH_BYTES];
+
 namespace {
 
 using Clock = std::chrono::steady_clock;
+
+// Device address of scratch per device ordinal, looked up once per device
+// with that device current.
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;
+
+hipError_t scratch_address(int device, void **out)
+{
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+    *out = p;
+    return hipSuccess;
+}
 
 double ms_since(Clock::time_point a, Clock::time_point b)
 {
@@ -277,6 +305,7 @@ struct gc_ctx {
     bool own_streams = true;
     std::vector<hipStream_t> aux;       // fork streams for graph capture of batches
     hipStream_t util = nullptr;         // small synchronous helpers (orbit generation, counts)
+    unsigned char *scratch = nullptr;   // device address of the static array of gc_launch_static
     std::vector<int> stream_load;
     Pool pool;
     PinnedPool pinned;
@@ -773,38 +802,12 @@ void fail_job(gc_ctx *ctx, Job *job, gc_status err)
     ctx->done_cv.notify_all();
 }
 
-// Enqueue a job's device work on its stream without waiting for anything.
-// Caller holds ctx->mu, has charged nothing yet and has picked an idle
-// stream.  A batch (job->graph) is captured once into a HIP graph whose
-// relax groups run as concurrent branches; relaunching the same batch
-// replays that graph on the same device block.
-gc_status start_job(gc_ctx *ctx, Job *job)
+// Host images of a job's per-orbit descriptors, pointing into the block at
+// base.
+void fill_job_devs(Job *job, unsigned char *base)
 {
-    hipStream_t s = ctx->streams[job->stream];
     const int nj = (int)job->orbits.size();
-    if (job->gx) {
-        // replay: the captured graph rewrites its own descriptors and resets
-        ctx->used += job->bytes;
-        ctx->stream_load[job->stream]++;
-        GC_HIP(hipEventRecord(job->ev_k0, s));
-        GC_HIP(hipGraphLaunch(job->gx, s));
-        GC_HIP(hipEventRecord(job->ev_k1, s));
-        GC_HIP(hipEventRecord(job->ev_done, s));
-        job->state = GC_ORBIT_RUNNING;
-        for (int j = 0; j < nj; ++j) job->orbits[j]->res = job->jobs[j];
-        ctx->running.push_back(job);
-        return GC_OK;
-    }
-    JobLayout &L = job->L;
-    gc_status st = plan_job(ctx, job, L);
-    if (st != GC_OK) return st;
-    size_t got = 0;
-    st = pool_get(ctx, L.total, &job->mem, &got);
-    if (st != GC_OK) return st;
-    job->bytes = got;
-    ctx->used += job->bytes;
-    unsigned char *base = (unsigned char *)job->mem;
-
+    const JobLayout &L = job->L;
     job->jobs.assign(nj, GcJobDev{});
     for (int j = 0; j < nj; ++j) {
         Orbit *o = job->orbits[j];
@@ -836,25 +839,23 @@ gc_status start_job(gc_ctx *ctx, Job *job)
         J.sync_batch = job->p.sync_batch;
         J.fixed_sweeps = job->p.sync_batch ? (uint32_t *)(base + L.o_sync[j]) : nullptr;
     }
-    job->total = 0;
-    for (uint64_t n : job->n_starts) job->total += n;
+}
 
-    // pinned staging: every descriptor array the kernels read, copied to
-    // the device block by the stream itself, then the result counters
-    struct Piece {
-        size_t dst, src, bytes;
-    };
-    std::vector<Piece> pieces;
-    size_t soff = 0;
-    auto stage = [&](size_t dst, size_t bytes) {
-        pieces.push_back(Piece{dst, soff, bytes});
-        soff = align_up(soff + bytes, 64);
-        return pieces.back().src;
-    };
-    std::vector<std::pair<size_t, std::vector<unsigned char>>> blobs;
+// Descriptor arrays the kernels of a job read, each with its offset in the
+// job's block: the fix-up pass's job, the post groups' and relax groups' job
+// arrays and start prefixes, the wave tables.
+struct Blob {
+    size_t dst;
+    std::vector<unsigned char> bytes;
+};
+
+std::vector<Blob> job_blobs(Job *job)
+{
+    const int nj = (int)job->orbits.size();
+    const JobLayout &L = job->L;
+    std::vector<Blob> blobs;
     auto add_blob = [&](size_t dst, const void *src, size_t bytes) {
-        const size_t at = stage(dst, bytes);
-        blobs.emplace_back(at, std::vector<unsigned char>((const unsigned char *)src, (const unsigned char *)src + bytes));
+        blobs.push_back(Blob{dst, std::vector<unsigned char>((const unsigned char *)src, (const unsigned char *)src + bytes)});
     };
     for (int j = 0; j < nj; ++j) {
         GcJobDev F = job->jobs[j];
@@ -889,6 +890,130 @@ gc_status start_job(gc_ctx *ctx, Job *job)
         add_blob(g.o_worbs, gw.data(), sizeof(GcWaveOrbit) * gw.size());
         add_blob(g.o_prefix, gp.data(), sizeof(uint64_t) * gp.size());
     }
+    return blobs;
+}
+
+// One chain of a job: the relax group's kernel, its orbits' post passes,
+// their table compaction and representative fix-ups, on stream qs.  timed:
+// HIP events around the relax and post kernels (single-orbit launches).
+hipError_t enqueue_chain(Job *job, unsigned char *base, int gi, hipStream_t qs, bool timed)
+{
+    const JobLayout &L = job->L;
+    auto wbuf_of = [&](const PostGroup &pg) { return pg.wreg ? nullptr : (double *)(base + pg.o_wbuf); };
+    const Group &g = L.groups[gi];
+    hipError_t e = hipSuccess;
+    for (int j : g.jobs) {
+        e = gc_launch_reset(&job->jobs[j], 1, qs);
+        if (e != hipSuccess) return e;
+    }
+    e = gc_launch_zero_u64((unsigned long long *)(base + g.o_next), (int)g.jobs.size(), qs);
+    if (e != hipSuccess) return e;
+    for (const PostGroup &pg : L.posts) {
+        if (pg.chain != gi) continue;
+        e = gc_launch_zero_u64((unsigned long long *)(base + pg.o_next), 1, qs);
+        if (e != hipSuccess) return e;
+    }
+    if (timed && (e = hipEventRecord(job->ev_k0, qs)) != hipSuccess) return e;
+    auto relax = [&](size_t o_jobs) -> hipError_t {
+        if (g.wave && g.wps > 0)
+            return gc_launch_wps(g.d, g.wps, (const GcJobDev *)(base + o_jobs),
+                                 (const GcWaveOrbit *)(base + g.o_worbs), (int)g.jobs.size(),
+                                 (unsigned long long *)(base + g.o_next), (float2 *)(base + g.o_bounce), g.grid,
+                                 g.lds, qs);
+        if (g.wave)
+            return gc_launch_wave(g.d, g.ns, (const GcJobDev *)(base + o_jobs),
+                                  (const GcWaveOrbit *)(base + g.o_worbs), (int)g.jobs.size(),
+                                  (unsigned long long *)(base + g.o_next), g.coef_lds | (g.creg << 1),
+                                  (float2 *)(base + g.o_bounce), g.grid, g.lds, qs);
+        return gc_launch_relax_wg(g.block, (const GcJobDev *)(base + o_jobs), (int)g.jobs.size(),
+                                  (const uint64_t *)(base + g.o_prefix), (unsigned long long *)(base + g.o_next),
+                                  g.total, g.grid, g.lds, qs);
+    };
+    if (job->p.sync_batch) {
+        // batch-synchronous stop: a first pass finds every start's own
+        // stopping sweep, the second runs each batch to its largest
+        if ((e = relax(g.o_jobs1)) != hipSuccess) return e;
+        for (int j : g.jobs)
+            if ((e = gc_launch_sync(&job->jobs[j], 1, qs)) != hipSuccess) return e;
+        e = gc_launch_zero_u64((unsigned long long *)(base + g.o_next), (int)g.jobs.size(), qs);
+        if (e != hipSuccess) return e;
+    }
+    if ((e = relax(g.o_jobs)) != hipSuccess) return e;
+    if (timed && (e = hipEventRecord(job->ev_k1, qs)) != hipSuccess) return e;
+    for (const PostGroup &pg : L.posts) {
+        if (pg.chain != gi) continue;
+        e = gc_launch_post(pg.block, pg.sp, pg.wreg, (const GcJobDev *)(base + pg.o_jobs), (int)pg.jobs.size(),
+                           (const uint64_t *)(base + pg.o_prefix), (unsigned long long *)(base + pg.o_next),
+                           pg.total, nullptr, wbuf_of(pg), pg.wstride, pg.grid, pg.lds, qs);
+        if (e != hipSuccess) return e;
+    }
+    if (timed && (e = hipEventRecord(job->ev_k2, qs)) != hipSuccess) return e;
+    for (int j : g.jobs) {
+        e = gc_launch_finalize(&job->jobs[j], 1, qs);
+        if (e != hipSuccess) return e;
+        e = gc_launch_zero_u64((unsigned long long *)(base + L.o_fixnext[j]), 1, qs);
+        if (e != hipSuccess) return e;
+        const PostGroup &pg = L.posts[L.post_of[j]];
+        e = gc_launch_post(pg.block, pg.sp, pg.wreg, (const GcJobDev *)(base + L.o_fixjobs[j]), 1, nullptr,
+                           (unsigned long long *)(base + L.o_fixnext[j]), 0, job->jobs[j].n_fix, wbuf_of(pg),
+                           pg.wstride, std::min(pg.grid, 64), pg.lds, qs);
+        if (e != hipSuccess) return e;
+        e = gc_launch_patch(&job->jobs[j], 1, qs);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Enqueue a job's device work on its stream without waiting for anything.
+// Caller holds ctx->mu, has charged nothing yet and has picked an idle
+// stream.  A batch (job->graph) is captured once into a HIP graph whose
+// relax groups run as concurrent branches; relaunching the same batch
+// replays that graph on the same device block.
+gc_status start_job(gc_ctx *ctx, Job *job)
+{
+    hipStream_t s = ctx->streams[job->stream];
+    const int nj = (int)job->orbits.size();
+    if (job->gx) {
+        // replay: the captured graph rewrites its own descriptors and resets
+        ctx->used += job->bytes;
+        ctx->stream_load[job->stream]++;
+        GC_HIP(hipEventRecord(job->ev_k0, s));
+        GC_HIP(hipGraphLaunch(job->gx, s));
+        GC_HIP(hipEventRecord(job->ev_k1, s));
+        GC_HIP(hipEventRecord(job->ev_done, s));
+        job->state = GC_ORBIT_RUNNING;
+        for (int j = 0; j < nj; ++j) job->orbits[j]->res = job->jobs[j];
+        ctx->running.push_back(job);
+        return GC_OK;
+    }
+    JobLayout &L = job->L;
+    gc_status st = plan_job(ctx, job, L);
+    if (st != GC_OK) return st;
+    size_t got = 0;
+    st = pool_get(ctx, L.total, &job->mem, &got);
+    if (st != GC_OK) return st;
+    job->bytes = got;
+    ctx->used += job->bytes;
+    unsigned char *base = (unsigned char *)job->mem;
+
+    fill_job_devs(job, base);
+    job->total = 0;
+    for (uint64_t n : job->n_starts) job->total += n;
+
+    // pinned staging: every descriptor array the kernels read, copied to
+    // the device block by the stream itself, then the result counters
+    struct Piece {
+        size_t dst, src, bytes;
+    };
+    std::vector<Piece> pieces;
+    size_t soff = 0;
+    auto stage = [&](size_t dst, size_t bytes) {
+        pieces.push_back(Piece{dst, soff, bytes});
+        soff = align_up(soff + bytes, 64);
+        return pieces.back().src;
+    };
+    const std::vector<Blob> blobs = job_blobs(job);
+    for (const Blob &bl : blobs) stage(bl.dst, bl.bytes.size());
     const size_t o_hcnt = soff;
     soff = align_up(soff + sizeof(GcCounters) * nj, 64);
     const size_t o_hnc = soff;
@@ -901,7 +1026,7 @@ gc_status start_job(gc_ctx *ctx, Job *job)
         }
     }
     unsigned char *sb = (unsigned char *)job->staging;
-    for (auto &b : blobs) memcpy(sb + b.first, b.second.data(), b.second.size());
+    for (size_t k = 0; k < blobs.size(); ++k) memcpy(sb + pieces[k].src, blobs[k].bytes.data(), blobs[k].bytes.size());
     job->h_cnt = (GcCounters *)(sb + o_hcnt);
     job->h_ncopies = (unsigned long long *)(sb + o_hnc);
     memset(job->h_cnt, 0, sizeof(GcCounters) * nj);
@@ -928,73 +1053,6 @@ gc_status start_job(gc_ctx *ctx, Job *job)
             fork_ev.push_back(e);
         }
     }
-    auto wbuf_of = [&](const PostGroup &pg) { return pg.wreg ? nullptr : (double *)(base + pg.o_wbuf); };
-    // one chain: the relax group's kernel, its orbits' post passes, their
-    // table compaction and representative fix-ups
-    auto enqueue_chain = [&](int gi, hipStream_t qs, bool timed) -> hipError_t {
-        const Group &g = L.groups[gi];
-        hipError_t e = hipSuccess;
-        for (int j : g.jobs) {
-            e = gc_launch_reset(&job->jobs[j], 1, qs);
-            if (e != hipSuccess) return e;
-        }
-        e = gc_launch_zero_u64((unsigned long long *)(base + g.o_next), (int)g.jobs.size(), qs);
-        if (e != hipSuccess) return e;
-        for (const PostGroup &pg : L.posts) {
-            if (pg.chain != gi) continue;
-            e = gc_launch_zero_u64((unsigned long long *)(base + pg.o_next), 1, qs);
-            if (e != hipSuccess) return e;
-        }
-        if (timed && (e = hipEventRecord(job->ev_k0, qs)) != hipSuccess) return e;
-        auto relax = [&](size_t o_jobs) -> hipError_t {
-            if (g.wave && g.wps > 0)
-                return gc_launch_wps(g.d, g.wps, (const GcJobDev *)(base + o_jobs),
-                                     (const GcWaveOrbit *)(base + g.o_worbs), (int)g.jobs.size(),
-                                     (unsigned long long *)(base + g.o_next), (float2 *)(base + g.o_bounce), g.grid,
-                                     g.lds, qs);
-            if (g.wave)
-                return gc_launch_wave(g.d, g.ns, (const GcJobDev *)(base + o_jobs),
-                                      (const GcWaveOrbit *)(base + g.o_worbs), (int)g.jobs.size(),
-                                      (unsigned long long *)(base + g.o_next), g.coef_lds | (g.creg << 1),
-                                      (float2 *)(base + g.o_bounce), g.grid, g.lds, qs);
-            return gc_launch_relax_wg(g.block, (const GcJobDev *)(base + o_jobs), (int)g.jobs.size(),
-                                      (const uint64_t *)(base + g.o_prefix), (unsigned long long *)(base + g.o_next),
-                                      g.total, g.grid, g.lds, qs);
-        };
-        if (job->p.sync_batch) {
-            // batch-synchronous stop: a first pass finds every start's own
-            // stopping sweep, the second runs each batch to its largest
-            if ((e = relax(g.o_jobs1)) != hipSuccess) return e;
-            for (int j : g.jobs)
-                if ((e = gc_launch_sync(&job->jobs[j], 1, qs)) != hipSuccess) return e;
-            e = gc_launch_zero_u64((unsigned long long *)(base + g.o_next), (int)g.jobs.size(), qs);
-            if (e != hipSuccess) return e;
-        }
-        if ((e = relax(g.o_jobs)) != hipSuccess) return e;
-        if (timed && (e = hipEventRecord(job->ev_k1, qs)) != hipSuccess) return e;
-        for (const PostGroup &pg : L.posts) {
-            if (pg.chain != gi) continue;
-            e = gc_launch_post(pg.block, pg.sp, pg.wreg, (const GcJobDev *)(base + pg.o_jobs), (int)pg.jobs.size(),
-                               (const uint64_t *)(base + pg.o_prefix), (unsigned long long *)(base + pg.o_next),
-                               pg.total, nullptr, wbuf_of(pg), pg.wstride, pg.grid, pg.lds, qs);
-            if (e != hipSuccess) return e;
-        }
-        if (timed && (e = hipEventRecord(job->ev_k2, qs)) != hipSuccess) return e;
-        for (int j : g.jobs) {
-            e = gc_launch_finalize(&job->jobs[j], 1, qs);
-            if (e != hipSuccess) return e;
-            e = gc_launch_zero_u64((unsigned long long *)(base + L.o_fixnext[j]), 1, qs);
-            if (e != hipSuccess) return e;
-            const PostGroup &pg = L.posts[L.post_of[j]];
-            e = gc_launch_post(pg.block, pg.sp, pg.wreg, (const GcJobDev *)(base + L.o_fixjobs[j]), 1, nullptr,
-                               (unsigned long long *)(base + L.o_fixnext[j]), 0, job->jobs[j].n_fix, wbuf_of(pg),
-                               pg.wstride, std::min(pg.grid, 64), pg.lds, qs);
-            if (e != hipSuccess) return e;
-            e = gc_launch_patch(&job->jobs[j], 1, qs);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
-    };
     auto enqueue_body = [&](hipStream_t qs) -> hipError_t {
         hipError_t e = hipSuccess;
         for (const Piece &pc : pieces) {
@@ -1003,7 +1061,7 @@ gc_status start_job(gc_ctx *ctx, Job *job)
         }
         if (!fork) {
             for (int gi = 0; gi < nchain; ++gi) {
-                e = enqueue_chain(gi, qs, !job->graph && nchain == 1);
+                e = enqueue_chain(job, base, gi, qs, !job->graph && nchain == 1);
                 if (e != hipSuccess) return e;
             }
         } else {
@@ -1011,10 +1069,10 @@ gc_status start_job(gc_ctx *ctx, Job *job)
             for (int gi = 1; gi < nchain; ++gi) {
                 hipStream_t as = ctx->aux[gi - 1];
                 if ((e = hipStreamWaitEvent(as, fork_ev[0], 0)) != hipSuccess) return e;
-                if ((e = enqueue_chain(gi, as, false)) != hipSuccess) return e;
+                if ((e = enqueue_chain(job, base, gi, as, false)) != hipSuccess) return e;
                 if ((e = hipEventRecord(fork_ev[gi], as)) != hipSuccess) return e;
             }
-            if ((e = enqueue_chain(0, qs, false)) != hipSuccess) return e;
+            if ((e = enqueue_chain(job, base, 0, qs, false)) != hipSuccess) return e;
             for (int gi = 1; gi < nchain; ++gi)
                 if ((e = hipStreamWaitEvent(qs, fork_ev[gi], 0)) != hipSuccess) return e;
         }
@@ -1545,6 +1603,11 @@ gc_status gc_create(const gc_ctx_params *params, gc_ctx **out)
         }
     }
     if (hipStreamCreateWithFlags(&ctx->util, hipStreamNonBlocking) != hipSuccess) return GC_EDEVICE;
+    {
+        void *sp = nullptr;
+        if (scratch_address(P.device, &sp) != hipSuccess) return GC_EDEVICE;
+        ctx->scratch = (unsigned char *)sp;
+    }
     if (P.tune_cache) {
         ctx->tune_cache = P.tune_cache;
         load_tune_cache(ctx.get());
@@ -2008,6 +2071,49 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
     r.post_sites_per_thread = best_b ? best_sp : dsp;
     r.post_ms = best_b ? best_p : pm;
     if (out) *out = r;
+    return GC_OK;
+}
+
+gc_status gc_launch_static(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_solve_params *params,
+                           void *hip_stream, gc_copy *copies_dev, uint64_t copies_cap, uint64_t *n_copies_dev,
+                           uint64_t *counters_dev)
+{
+    gc_solve_params p;
+    if (params) p = *params; else fill_defaults(&p);
+    gc_status st = check_params(&p);
+    if (st != GC_OK) return st;
+    if (n_starts == 0 || n_starts > (1ull << 32) || !copies_dev || !n_copies_dev || copies_cap < n_starts)
+        return GC_EINVAL;
+    GC_ENTER(ctx);
+    Orbit *o = find_orbit(ctx, orbit);
+    if (!o) return GC_EINVAL;
+    if (!ctx->scratch) return GC_EUNSUPPORTED;
+    // nothing of this job outlives the call: descriptors go to the static
+    // array through kernel arguments, results to the caller's buffers
+    Job job;
+    job.orbits.push_back(o);
+    job.n_starts.push_back(n_starts);
+    job.p = p;
+    st = plan_job(ctx, &job, job.L);
+    if (st != GC_OK) return st;
+    if (job.L.total > GC_STATIC_SCRATCH_BYTES) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "gc_launch_static: %llu starts need %llu bytes, the static array holds %llu",
+                 (unsigned long long)n_starts, (unsigned long long)job.L.total,
+                 (unsigned long long)GC_STATIC_SCRATCH_BYTES);
+        ctx->err = buf;
+        return GC_ENOMEM;
+    }
+    unsigned char *base = ctx->scratch;
+    fill_job_devs(&job, base);
+    GcJobDev &J = job.jobs[0];
+    J.copies = (GcCopyRec *)copies_dev;
+    J.n_copies = (unsigned long long *)n_copies_dev;
+    if (counters_dev) J.cnt = (GcCounters *)counters_dev;
+    hipStream_t s = (hipStream_t)hip_stream;
+    for (const Blob &bl : job_blobs(&job))
+        GC_HIP(gc_launch_store(base + bl.dst, bl.bytes.data(), bl.bytes.size(), s));
+    for (int gi = 0; gi < (int)job.L.groups.size(); ++gi) GC_HIP(enqueue_chain(&job, base, gi, s, false));
     return GC_OK;
 }
 
