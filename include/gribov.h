@@ -135,7 +135,9 @@ typedef struct {
     double submit_to_done_ms;   /* latency of the last launch (valid when DONE) */
     double device_ms;           /* device time of the last launch's relax kernel, or of the whole graph of a
                                    batch (valid when DONE) */
-    double post_ms;             /* device time of the last launch's post kernel (single-orbit launches) */
+    double post_ms;             /* device time of the last launch's key pass and table compaction (single-orbit
+                                   launches) */
+    double filter_ms;           /* device time of the last launch's FP filter pass (single-orbit launches) */
 } gc_progress;
 
 /* One distinct copy. */
@@ -341,8 +343,8 @@ gc_status gc_launch_static(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const
 typedef struct {
     int32_t relax_variant;          /* colours whose coefficients a lane keeps in registers (0..2), plus 8
                                        when a workgroup of several wavefronts shares each start */
-    int32_t post_block;             /* post kernel: threads per workgroup */
-    int32_t post_sites_per_thread;
+    int32_t post_block;             /* FP filter kernel of this lattice: threads per workgroup */
+    int32_t post_sites_per_thread;  /* and sites per thread (not tuned: the shape follows from the lattice) */
     int32_t pad;
     double relax_ms, post_ms;       /* best measured times of the chosen variants */
 } gc_tune_result;

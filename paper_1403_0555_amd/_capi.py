@@ -59,7 +59,8 @@ class gc_progress(ctypes.Structure):
         (n, ctypes.c_uint64) for n in ("n_starts", "starts_done", "converged", "nonconverged", "distinct",
                                        "in_region", "saddles", "singular", "collisions", "sweeps_total",
                                        "site_updates", "lanczos_runs", "paper_count")] + [
-        ("submit_to_done_ms", ctypes.c_double), ("device_ms", ctypes.c_double), ("post_ms", ctypes.c_double)]
+        ("submit_to_done_ms", ctypes.c_double), ("device_ms", ctypes.c_double), ("post_ms", ctypes.c_double),
+        ("filter_ms", ctypes.c_double)]
 
 
 COPY_DTYPE = np.dtype([("key_hi", np.uint64), ("key_lo", np.uint64), ("F", np.float64), ("x", np.float64),

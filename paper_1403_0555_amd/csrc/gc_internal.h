@@ -24,7 +24,6 @@
 #define GC_F_KEY_OVERFLOW 32u
 
 // Job flags.
-#define GC_JOB_FIX 2u          // post-process the representatives listed in fix[], always run the filter
 #define GC_JOB_SYNC2 4u        // batch-synchronous second pass: start s runs exactly fixed_sweeps[s] sweeps
 
 // Relative spread of F (per site) above which one key is flagged as reached
@@ -67,16 +66,6 @@ struct GcEntry {
     uint64_t rep_start;              // lowest start id with F within tolerance of the minimum F
 };
 
-// A copy whose representative start is not its lowest start id (its hits
-// include a start that stopped next to another stationary point of the same
-// class): the representative's stored state is filtered afterwards.
-struct GcFix {
-    uint64_t start;                  // representative start id
-    uint64_t slot;                   // index into the job's compact copy array
-    double lambda2;
-    uint32_t flags, lanczos_iters;
-};
-
 // Device counters of one job.
 struct GcCounters {
     unsigned long long starts_done, converged, nonconverged, distinct;
@@ -105,8 +94,6 @@ struct GcJobDev {
     GcCopyRec *copies;               // [n_starts] finalize output
     unsigned long long *n_copies;
     double2 *states;                 // [n_starts][V] final g of every start, natural site order
-    GcFix *fix;                      // [n_starts] representatives to filter
-    unsigned long long *n_fix;
     uint32_t *blk;                   // [(table_mask + 1) / 256] per-block copy counts, then offsets
     uint32_t *fixed_sweeps;          // [n_starts] batch-synchronous sweep counts (sync_batch > 0), else null
 };
@@ -121,22 +108,29 @@ hipError_t gc_relax_wg_occupancy(int block, size_t lds_bytes, int *blocks_per_cu
 hipError_t gc_launch_relax_wg(int block, const GcJobDev *jobs, int n_jobs, const uint64_t *prefix,
                               unsigned long long *next, uint64_t total, int grid, size_t lds_bytes, hipStream_t s);
 
-// Post kernel, one workgroup per start: functional, key, table insertion and
-// the FP-operator filter.  total_dev (device count) overrides total.
+// Post kernels.  Key pass (keys = 1): one workgroup per start, functional,
+// key and table insertion.  Filter pass (keys = 0): one workgroup per copy
+// of the compacted tables, the FP-operator Lanczos at its representative.
 // Workgroup shape for V sites: block threads, sp sites per thread, link
 // weights in registers (wreg) or in a global buffer of (d + 3) V doubles per
 // workgroup (wbuf, wstride doubles apart).
-size_t gc_post_lds_bytes(int d, int V);
+size_t gc_post_lds_bytes(int d, int V, int keys, int lmax);
 void gc_post_shape(int V, int *block, int *sites_per_thread, int *wreg);
-hipError_t gc_post_occupancy(int block, int sp, int wreg, size_t lds_bytes, int *blocks_per_cu);
-hipError_t gc_launch_post(int block, int sp, int wreg, const GcJobDev *jobs, int n_jobs, const uint64_t *prefix,
-                          unsigned long long *next, uint64_t total, const unsigned long long *total_dev,
-                          double *wbuf, uint64_t wstride, int grid, size_t lds_bytes, hipStream_t s);
+hipError_t gc_post_occupancy(int block, int sp, int wreg, int keys, size_t lds_bytes, int *blocks_per_cu);
+hipError_t gc_launch_post(int block, int sp, int wreg, int keys, const GcJobDev *jobs, int n_jobs,
+                          const uint64_t *prefix, unsigned long long *next, uint64_t total, double *wbuf,
+                          uint64_t wstride, int grid, size_t lds_bytes, hipStream_t s);
+// Filter pass in the line-segment layout (seg sites per thread along
+// direction 0): gc_lanczos_shape returns 0 when no instantiated shape fits.
+int gc_lanczos_shape(int d, const int *ext, int V, int *block, int *seg);
+size_t gc_lanczos_lds_bytes(int d, int N0, int seg, int V, int lmax);
+hipError_t gc_lanczos_occupancy(int block, int seg, size_t lds_bytes, int *blocks_per_cu);
+hipError_t gc_launch_lanczos(int block, int seg, const GcJobDev *jobs, int n_jobs, unsigned long long *next, int grid,
+                             size_t lds_bytes, hipStream_t s);
 
 // Table and bookkeeping kernels.
 hipError_t gc_launch_reset(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);
 hipError_t gc_launch_finalize(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);   // representatives + compaction
-hipError_t gc_launch_patch(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);      // fix-up results -> copies
 hipError_t gc_launch_orbit_random(double *phi, int64_t n_links, uint64_t seed, uint64_t orbit_index, hipStream_t s);
 hipError_t gc_launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
 // Write bytes (host source, copied into kernel arguments) to device memory.

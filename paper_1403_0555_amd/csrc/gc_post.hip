@@ -16,6 +16,7 @@
 // and the patch of re-filtered representatives.
 #include "gc_common.h"
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -107,7 +108,7 @@ __device__ __forceinline__ void wg_sum_n(double (&v)[N], double *red, int &ph)
 #pragma unroll
     for (int n = 0; n < N; ++n) v[n] = wave_sum(v[n]);
     if (B > 64) {
-        double *r = red + ph * (3 * (B / 64));
+        double *r = red + ph * (4 * (B / 64));
         ph ^= 1;
         if ((threadIdx.x & 63) == 0) {
 #pragma unroll
@@ -167,8 +168,8 @@ typedef __attribute__((address_space(3))) const double lds_cdouble;
 // a vanishing term; the next term then takes that sign too).  Division- and
 // branch-free: one dependent FMA and a select per step, sign changes counted
 // from the sign bits.  The diagonal and off-diagonal are fetched from LDS
-// eight rows ahead of the recurrence, and the pair (p_{j-1}, p_j) is rescaled
-// by a power of two after every eight rows, which keeps it in range and
+// four rows ahead of the recurrence, and the pair (p_{j-1}, p_j) is rescaled
+// by a power of two after every four rows, which keeps it in range and
 // leaves every sign unchanged.
 __device__ __forceinline__ double sturm_nonzero(double p, double prev)
 {
@@ -193,15 +194,15 @@ __device__ int sturm_count(lds_cdouble *alpha, lds_cdouble *beta2, int k, double
     double p0 = 1.0, p1 = sturm_nonzero(alpha[0] - x, 1.0);
     int cnt = sign_change(p1, 1.0);
     int j = 1;
-    for (; j + 8 <= k; j += 8) {
-        double a[8], b[8];
+    for (; j + 4 <= k; j += 4) {
+        double a[4], b[4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 4; ++u) {
             a[u] = alpha[j + u];
             b[u] = beta2[j + u - 1];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) sturm_step(a[u], b[u], x, p0, p1, cnt);
+        for (int u = 0; u < 4; ++u) sturm_step(a[u], b[u], x, p0, p1, cnt);
         int e;
         (void)frexp(p1, &e);
         p0 = ldexp(p0, -e);
@@ -280,6 +281,38 @@ __device__ uint32_t region_flags(double lam2, double tol)
     return GC_F_SINGULAR;
 }
 
+constexpr uint32_t kFilterFlags = GC_F_IN_REGION | GC_F_SINGULAR | GC_F_SADDLE | GC_F_LANCZOS_CAP;
+
+// The filter's results: into the copy and its representative's start record.
+__device__ void write_filter(const GcJobDev &J, uint64_t c, uint64_t local, double lam2, uint32_t flags, uint32_t lit)
+{
+    GcCopyRec &cp = J.copies[c];
+    cp.lambda2 = lam2;
+    cp.flags |= flags & kFilterFlags;
+    cp.lanczos_iters = lit;
+    GcStartRec &r = J.rec[local];
+    r.lambda2 = lam2;
+    r.flags = (r.flags & ~kFilterFlags) | (flags & kFilterFlags);
+    r.lanczos_iters = lit;
+}
+
+// The item of a filter pass: copy s of the concatenated copy lists of the
+// jobs (job order), or jn = -1 past the end.
+__device__ __forceinline__ void copy_item(const GcJobDev *jobs, int n_jobs, uint64_t s, int &jn, uint64_t &c)
+{
+    uint64_t base = 0;
+    jn = -1;
+    for (int j = 0; j < n_jobs; ++j) {
+        const uint64_t nc = *jobs[j].n_copies;
+        if (s < base + nc) {
+            jn = j;
+            break;
+        }
+        base += nc;
+    }
+    c = s - base;
+}
+
 // Values at a thread's own sites i = tid + B k: registers, or a strided
 // view of the workgroup's global slice.
 template <bool REG, int SP> struct OwnVec;
@@ -295,55 +328,76 @@ template <int SP> struct OwnVec<false, SP> {
     __device__ __forceinline__ void set(int k, double x) { p[k * stride] = x; }
 };
 
-// One workgroup of B threads per start; thread t owns sites i = t + B k,
-// k < SP.  With WREG the link weights, neighbour indices and the entries of
-// q_prev, the residual and M q of the own sites stay in registers (SP <= 4);
-// otherwise they live in the workgroup's slice of wbuf ((d + 3) V doubles:
-// forward link weights, then q_prev, residual and M q).
-// LDS: the state g (16V bytes, later the Lanczos vector q), then the link
-// angles as floats (4dV bytes) during the key, reused for the tridiagonal.
+// Post pass over the relaxed starts (KEYS) or filter pass over the copies of
+// the compacted tables (!KEYS), one workgroup of B threads per item; thread t
+// owns sites i = t + B k, k < SP.
+//   KEYS: observables (F, x, the paper's X), the integer key and the table
+//         insert of every converged start.
+//   !KEYS: for each distinct copy, the FP filter at its representative
+//         start: Lanczos on A = M + sigma 11^T/V.  With WREG the link weights,
+//         neighbour indices and the entries of q_prev and M u of the own sites
+//         stay in registers; otherwise they live in the workgroup's slice of
+//         wbuf ((d + 3) V doubles: forward link weights, then q_prev and M u).
+//         This is the general layout; lanczos_kernel below is the faster one
+//         for the shapes it is instantiated for.
+// LDS: the state g (16V bytes, later the Lanczos vector u), then the link
+// angles as floats (4dV bytes) during the key, or the tridiagonal.
 // The angle of a link is atan2 in single precision: the branch cut at +-pi is
 // decided by the sign of Im u alone, which rounding keeps, and a plaquette or
 // line sum then lies within about 1e-5 of its multiple of 2pi, so the wrap
 // numbers are the ones double precision gives.
-template <int B, int SP, bool WREG>
+template <int B, int SP, bool WREG, bool KEYS>
 __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jobs, int n_jobs,
                                                  const uint64_t *__restrict__ prefix, unsigned long long *next,
-                                                 uint64_t total, const unsigned long long *total_dev,
-                                                 double *wbuf_all, uint64_t wstride)
+                                                 uint64_t total, double *wbuf_all, uint64_t wstride)
 {
-    constexpr int NW = WREG ? SP : 1;   // register weights per thread (dummy when !WREG)
-    constexpr int NN = WREG ? SP : 1;   // register neighbour words per thread
+    constexpr int NW = (WREG && !KEYS) ? SP : 1;   // register weights per thread (dummy otherwise)
+    constexpr int NN = (WREG && !KEYS) ? SP : 1;   // register neighbour words per thread
     glb_ptr<double> wbuf = as_global(wbuf_all + (WREG ? 0 : (uint64_t)blockIdx.x * wstride));
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[2 * 3 * (B / 64)];
+    __shared__ double red[2 * 4 * (B / 64)];
     __shared__ uint64_t ured[2 * (B / 64)];
     __shared__ int ired[2 * (B / 64)];
     int rph = 0, uph = 0, iph = 0;   // halves of the reduction scratch in use
     __shared__ unsigned long long claim;
-    __shared__ int run_sh;
-    if (total_dev) total = *total_dev;
     for (;;) {
-        // re-derived per start so that nothing indexed by it is hoisted out of
-        // the start loop and held in registers across it
+        // re-derived per item so that nothing indexed by it is hoisted out of
+        // the item loop and held in registers across it
         const int tid = (int)threadIdx.x + opaque_zero();
         if (tid == 0) claim = atomicAdd(next, 1ULL);
         __syncthreads();
         const uint64_t s = uniform((uint64_t)claim);
         __syncthreads();
-        if (s >= total) break;
         int jn = 0;
-        if (prefix)
+        uint64_t local = 0, c = 0;
+        if constexpr (KEYS) {
+            if (s >= total) break;
             while (jn + 1 < n_jobs && prefix[jn + 1] <= s) ++jn;
-        jn = uniform(jn);
+            jn = uniform(jn);
+            local = s - prefix[jn];
+        } else {
+            // copies of the jobs' tables, in job order
+            uint64_t base = 0;
+            jn = -1;
+            for (int j = 0; j < n_jobs; ++j) {
+                const uint64_t nc = *jobs[j].n_copies;
+                if (s < base + nc) {
+                    jn = j;
+                    break;
+                }
+                base += nc;
+            }
+            jn = uniform(jn);
+            if (jn < 0) break;
+            c = s - base;
+            local = jobs[jn].copies[c].rep_start - jobs[jn].first_start;
+        }
         const GcJobDev &J = jobs[jn];
         const GcOrbitDev &O = J.orb;
         const int V = O.V, d = O.d;
-        const bool fixmode = (J.flags & GC_JOB_FIX) != 0;
-        const uint64_t local = fixmode ? J.fix[s].start - J.first_start : s - (prefix ? prefix[jn] : 0);
         const uint64_t sid = J.first_start + local;
         const GcStartRec rec0 = J.rec[local];
-        if (rec0.status != GC_ST_CONVERGED) continue;   // uniform across the workgroup
+        if (KEYS && rec0.status != GC_ST_CONVERGED) continue;   // uniform across the workgroup
 
         lds_ptr<dbl2> g = as_lds(reinterpret_cast<dbl2 *>(smem));
         // the link angles (key phase) and the tridiagonal (Lanczos) share LDS
@@ -355,8 +409,8 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
         for (int i = tid; i < V; i += B) g[i] = src[i];
         __syncthreads();
 
-        // ---- observables of the own sites: forward links (F, angles) and the
-        // FP weights w = Re u of every link touching the site
+        // ---- own sites: forward links (F, angles) for the key, or the FP
+        // weights w = Re u of every link touching the site for the filter
         glb_ptr<const dbl2> U = as_global(reinterpret_cast<const dbl2 *>(O.U64));
         double wf[NW][GC_MAXD], wb[NW][GC_MAXD];
         uint32_t nfb[NN][GC_MAXD];   // forward | backward << 16
@@ -366,35 +420,41 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
             const int i = tid + B * k;
 #pragma unroll
             for (int mu = 0; mu < GC_MAXD; ++mu) {
-                if (WREG) {
+                if (WREG && !KEYS) {
                     wf[k % NW][mu] = 0.0;
                     wb[k % NW][mu] = 0.0;
+                    nfb[k % NN][mu] = 0;
                 }
-                if (WREG) nfb[k % NN][mu] = 0;
                 if (i < V && mu < d) {
                     const int f = O.nbr[mu * V + i], b = O.nbr[(d + mu) * V + i];
-                    if (WREG) nfb[k % NN][mu] = (uint32_t)f | ((uint32_t)b << 16);
-                    const dbl2 gi = g[i], gf = g[f], gb = g[b];
+                    const dbl2 gi = g[i], gf = g[f];
                     const dbl2 u = U[mu * V + i];
                     const double tr = u.x * gf.x - u.y * gf.y, ti = u.x * gf.y + u.y * gf.x;
                     const double ur = gi.x * tr + gi.y * ti, ui = gi.x * ti - gi.y * tr;
-                    facc += 1.0 - ur;
-                    a32[mu * V + i] = atan2f((float)ui, (float)ur);
-                    if (WREG) wf[k % NW][mu] = ur;
-                    else wbuf[mu * V + i] = ur;
-                    const dbl2 v = U[mu * V + b];
-                    const double sr = v.x * gi.x - v.y * gi.y, si = v.x * gi.y + v.y * gi.x;
-                    if (WREG) wb[k % NW][mu] = gb.x * sr + gb.y * si;
+                    if constexpr (KEYS) {
+                        facc += 1.0 - ur;
+                        a32[mu * V + i] = atan2f((float)ui, (float)ur);
+                    } else {
+                        if (WREG) {
+                            nfb[k % NN][mu] = (uint32_t)f | ((uint32_t)b << 16);
+                            wf[k % NW][mu] = ur;
+                            const dbl2 gb = g[b];
+                            const dbl2 v = U[mu * V + b];
+                            const double sr = v.x * gi.x - v.y * gi.y, si = v.x * gi.y + v.y * gi.x;
+                            wb[k % NW][mu] = gb.x * sr + gb.y * si;
+                        } else {
+                            wbuf[mu * V + i] = ur;
+                        }
+                    }
                 }
             }
         }
-        double tmp1[1] = {facc};
-        wg_sum_n<B, 1>(tmp1, red, rph);
-        const double F = tmp1[0];
-        __syncthreads();   // angles visible to the whole workgroup
-        uint32_t flags = 0;
-        uint64_t key_hi = rec0.key_hi, key_lo = rec0.key_lo;
-        if (!fixmode) {
+        if constexpr (KEYS) {
+            double tmp1[1] = {facc};
+            wg_sum_n<B, 1>(tmp1, red, rph);
+            const double F = tmp1[0];
+            __syncthreads();   // angles visible to the whole workgroup
+            uint32_t flags = 0;
             // ---- integer key: plaquette wrap numbers, then line windings
             const uint64_t c0 = 0x243F6A8885A308D3ULL, c1 = 0x13198A2E03707344ULL;
             uint64_t h0 = 0, h1 = 0;
@@ -433,146 +493,166 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
             h0 = wg_sum_u64<B>(h0, ured, uph);
             h1 = wg_sum_u64<B>(h1, ured, uph);
             const int ok = wg_min_int<B>(overflow ? 0 : 1, ired, iph);
-            key_hi = mix64(h0 + (uint64_t)O.n_elems);
-            key_lo = mix64(h1 + (uint64_t)O.n_elems);
+            uint64_t key_hi = mix64(h0 + (uint64_t)O.n_elems);
+            uint64_t key_lo = mix64(h1 + (uint64_t)O.n_elems);
             if (key_hi == 0) key_hi = 1;
             if (key_lo == 0) key_lo = 1;
             if (!ok) flags |= GC_F_KEY_OVERFLOW;
             if (tid == 0) {
                 bool claimed, is_min, failed;
                 table_insert(J, key_hi, key_lo, sid, F, claimed, is_min, failed);
-                run_sh = is_min ? 1 : 0;
                 if (claimed) atomicAdd(&J.cnt->distinct, 1ULL);
                 if (failed) atomicAdd(&J.cnt->errors, 1ULL);
+                GcStartRec rc = rec0;
+                rc.F = F;
+                rc.key_hi = key_hi;
+                rc.key_lo = key_lo;
+                rc.paper_X = (uint32_t)(F / ((double)d * (double)V) * 1e8);
+                rc.flags = flags;
+                rc.lambda2 = NAN;
+                rc.lanczos_iters = 0;
+                J.rec[local] = rc;
             }
-        } else if (tid == 0) {
-            run_sh = 1;
+            __syncthreads();
+            continue;
         }
-        __syncthreads();
-        const bool run = uniform(run_sh) != 0;
+        uint32_t flags = 0;
         double lam2 = NAN;
         uint32_t lit = 0;
-        if (run) {
-            // ---- Lanczos on A = M + sigma 11^T/V, M = B^T diag(w) B; q in LDS
-            // over the state, q_prev and the residual in registers
+        {
+            // ---- Lanczos on A = M + sigma 11^T/V, M = B^T diag(w) B, with one
+            // reduction per iteration.  The vector u in LDS (over the state) is
+            // the unnormalised residual r_{j-1} of the previous iteration (the
+            // mean-free start vector at first); its norm beta_{j-1} comes out of
+            // this iteration's reduction together with u.(M u), sum u and
+            // u.q_{j-2}, and then q_j = u/beta, M q_j = (M u)/beta,
+            // alpha_j = q_j.(A q_j) - beta_{j-1} q_j.q_{j-1} and the residual
+            // r_j = A q_j - beta_{j-1} q_{j-1} - alpha_j q_j follow site by site.
+            // q_{j-1} and M u of the own sites stay in registers.
             const double sigma = 4.0 * d + 1.0;
-            lds_ptr<double> vq = as_lds(reinterpret_cast<double *>(smem));
-            OwnVec<WREG, SP> qp, r, mq;
+            lds_ptr<double> vu = as_lds(reinterpret_cast<double *>(smem));
+            OwnVec<WREG, SP> qp, mu;
             if constexpr (!WREG) {
                 qp.p = wbuf + (size_t)d * V + tid;
-                r.p = qp.p + V;
-                mq.p = r.p + V;
-                qp.stride = r.stride = mq.stride = B;
+                mu.p = qp.p + V;
+                qp.stride = mu.stride = B;
             }
-            double sums[2] = {0.0, 0.0};
+            double sums[1] = {0.0};
 #pragma unroll
             for (int k = 0; k < SP; ++k) {
                 const int i = tid + B * k;
                 if (i < V) {
                     const double x = (double)(mix64((uint64_t)i + 0x5851F42D4C957F2DULL) >> 11) * 0x1.0p-53 - 0.5;
                     qp.set(k, 0.0);
-                    r.set(k, x);
+                    mu.set(k, x);
                     sums[0] += x;
                 }
             }
-            wg_sum_n<B, 1>(*reinterpret_cast<double(*)[1]>(&sums[0]), red, rph);
+            wg_sum_n<B, 1>(sums, red, rph);
             const double mean = sums[0] / (double)V;
-            double nn[1] = {0.0};
+            if (B > 64) __syncthreads();   // every thread is done with g before u overwrites it
+            else wave_sync();
 #pragma unroll
             for (int k = 0; k < SP; ++k) {
                 const int i = tid + B * k;
-                if (i < V) {
-                    const double x = r.get(k) - mean;
-                    r.set(k, x);
-                    nn[0] += x * x;
-                }
+                if (i < V) vu[i] = mu.get(k) - mean;
             }
-            wg_sum_n<B, 1>(nn, red, rph);
-            const double inv = 1.0 / sqrt(nn[0]);
-            __syncthreads();   // every thread is done with g before q overwrites it
-#pragma unroll
-            for (int k = 0; k < SP; ++k) {
-                const int i = tid + B * k;
-                if (i < V) vq[i] = r.get(k) * inv;
-            }
-            __syncthreads();
-            double beta_prev = 0.0, theta = INFINITY, theta_old = INFINITY, theta_step = 1.0;
+            double theta = INFINITY, theta_old = INFINITY, theta_step = 1.0;
             double rows_lo = INFINITY, rows_hi = -INFINITY;   // Gershgorin bounds of the complete rows
-            int next_check = 24;                              // iteration count of the next Ritz check
+            double a_prev = 0.0, b_prev2 = 0.0;                // alpha_{j-1}, beta_{j-2}
+            int next_check = 24;                               // iteration count of the next Ritz check
             int it = 0;
             bool conv = false;
             for (it = 0; it < lmax; ++it) {
+                if (B > 64) __syncthreads();   // u complete in LDS
+                else wave_sync();
                 // per-iteration copy of the thread index: the site addresses are
                 // recomputed each iteration instead of being held in registers
                 const int ti = tid + opaque_zero();
-                // (M q)_i for the own sites, then q.Mq, sum q, q.q_prev at once
-                double s3[3] = {0.0, 0.0, 0.0};
+                // (M u)_i for the own sites, then u.u, u.Mu, sum u, u.q_prev at once
+                double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int k = 0; k < SP; ++k) {
                     const int i = ti + B * k;
                     if (i < V) {
-                        const double qi = vq[i];
+                        const double ui = vu[i];
                         double m = 0.0;
 #pragma unroll
-                        for (int mu = 0; mu < GC_MAXD; ++mu)
-                            if (mu < d) {
+                        for (int mu_ = 0; mu_ < GC_MAXD; ++mu_)
+                            if (mu_ < d) {
                                 uint32_t f, b;
                                 double w1, w2;
                                 if constexpr (WREG) {
-                                    f = nfb[k % NN][mu] & 0xFFFFu;
-                                    b = nfb[k % NN][mu] >> 16;
-                                    w1 = wf[k % NW][mu];
-                                    w2 = wb[k % NW][mu];
+                                    f = nfb[k % NN][mu_] & 0xFFFFu;
+                                    b = nfb[k % NN][mu_] >> 16;
+                                    w1 = wf[k % NW][mu_];
+                                    w2 = wb[k % NW][mu_];
                                 } else {
-                                    f = O.nbr[mu * V + i];
-                                    b = O.nbr[(d + mu) * V + i];
-                                    w1 = wbuf[mu * V + i];
-                                    w2 = wbuf[mu * V + b];
+                                    f = O.nbr[mu_ * V + i];
+                                    b = O.nbr[(d + mu_) * V + i];
+                                    w1 = wbuf[mu_ * V + i];
+                                    w2 = wbuf[mu_ * V + b];
                                 }
-                                m += w1 * (qi - vq[f]) + w2 * (qi - vq[b]);
+                                m += w1 * (ui - vu[f]) + w2 * (ui - vu[b]);
                             }
-                        mq.set(k, m);
-                        s3[0] += qi * m;
-                        s3[1] += qi;
-                        s3[2] += qi * qp.get(k);
+                        mu.set(k, m);
+                        s4[0] += ui * ui;
+                        s4[1] += ui * m;
+                        s4[2] += ui;
+                        s4[3] += ui * qp.get(k);
                     }
                     // one site at a time: keeps the scheduler from holding
                     // every neighbour of every own site in registers
                     __builtin_amdgcn_sched_barrier(0);
                 }
-                wg_sum_n<B, 3>(s3, red, rph);
-                const double shift = sigma * s3[1] / (double)V;
-                const double a_j = s3[0] + shift * s3[1] - beta_prev * s3[2];
-                double rr[1] = {0.0};
+                wg_sum_n<B, 4>(s4, red, rph);
+                const double bt = sqrt(s4[0]);
+                const double bp = it > 0 ? bt : 0.0;      // beta_{j-1} (the start vector's norm is not in T)
+                if (it > 0) {
+                    if (tid == 0) beta2[it - 1] = s4[0];
+                    // row it - 1 of T now has both neighbours
+                    rows_lo = fmin(rows_lo, a_prev - b_prev2 - bt);
+                    rows_hi = fmax(rows_hi, a_prev + b_prev2 + bt);
+                    if (bt <= 1e-13 * sigma) {
+                        // the Krylov space is exhausted: T of it rows is exact
+                        if (B > 64) __syncthreads();
+                        else wave_sync();
+                        double theta_hi;
+                        theta = ritz_min<B>(alpha, beta2, it, rows_lo, rows_hi, theta_old, theta_step, ired, iph,
+                                            kRitzTol, true, theta_hi);
+                        conv = true;
+                        break;
+                    }
+                }
+                const double inv = 1.0 / bt;
+                const double sq = s4[2] * inv;
+                const double shift = sigma * sq / (double)V;
+                const double a_j = s4[1] * inv * inv + shift * sq - bp * (s4[3] * inv);
+                if (tid == 0) alpha[it] = a_j;
+                // the residual over u: every thread finished reading u in the
+                // reduction above
 #pragma unroll
                 for (int k = 0; k < SP; ++k) {
                     const int i = ti + B * k;
                     if (i < V) {
-                        const double qi = vq[i];
-                        const double x = mq.get(k) + shift - beta_prev * qp.get(k) - a_j * qi;
-                        r.set(k, x);
-                        rr[0] += x * x;
+                        const double q = vu[i] * inv;
+                        const double r = mu.get(k) * inv + shift - bp * qp.get(k) - a_j * q;
+                        qp.set(k, q);
+                        vu[i] = r;
                     }
                 }
-                wg_sum_n<B, 1>(rr, red, rph);
-                const double b_j = sqrt(rr[0]);
-                if (tid == 0) {
-                    alpha[it] = a_j;
-                    beta2[it] = b_j * b_j;
-                }
-                const bool breakdown = b_j <= 1e-13 * sigma;
-                if (it + 1 >= next_check || breakdown || it + 1 == lmax) {
-                    __syncthreads();   // the tridiagonal is complete in LDS
-                    const bool final = breakdown || it + 1 == lmax;
+                if (it + 1 >= next_check || it + 1 == lmax) {
+                    if (B > 64) __syncthreads();   // the tridiagonal is complete in LDS
+                    else wave_sync();
+                    const bool final = it + 1 == lmax;
                     double theta_hi;
-                    theta = ritz_min<B>(alpha, beta2, it + 1, fmin(rows_lo, a_j - beta_prev),
-                                        fmax(rows_hi, a_j + beta_prev), theta_old, theta_step, ired, iph, kRitzTol,
-                                        final, theta_hi);
+                    theta = ritz_min<B>(alpha, beta2, it + 1, fmin(rows_lo, a_j - bp), fmax(rows_hi, a_j + bp),
+                                        theta_old, theta_step, ired, iph, kRitzTol, final, theta_hi);
                     const double tol = kRitzTol * fmax(1.0, fabs(theta));
                     // theta_old is an upper bound of the previous value, so this
                     // change is at least the true one
                     const double change = theta_old - theta;
-                    if (breakdown || fabs(change) <= tol) {
+                    if (fabs(change) <= tol) {
                         conv = true;
                         ++it;
                         break;
@@ -584,43 +664,229 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                     if (theta_old < INFINITY) theta_step = change;
                     theta_old = theta_hi;
                 }
-                // row it of T now has both neighbours: into the Gershgorin bounds
-                rows_lo = fmin(rows_lo, a_j - beta_prev - b_j);
-                rows_hi = fmax(rows_hi, a_j + beta_prev + b_j);
-                const double ib = 1.0 / b_j;
-#pragma unroll
-                for (int k = 0; k < SP; ++k) {
-                    const int i = ti + B * k;
-                    if (i < V) {
-                        qp.set(k, vq[i]);
-                        vq[i] = r.get(k) * ib;
-                    }
-                }
-                beta_prev = b_j;
-                __syncthreads();
+                b_prev2 = bp;
+                a_prev = a_j;
             }
             lam2 = theta;
             lit = (uint32_t)it;
             if (!conv) flags |= GC_F_LANCZOS_CAP;
             flags |= region_flags(lam2, J.lambda_tol);
             if (tid == 0) atomicAdd(&J.cnt->lanczos_runs, 1ULL);
-        }
-        if (tid == 0) {
-            if (fixmode) {
-                J.fix[s].lambda2 = lam2;
-                J.fix[s].flags = flags;
-                J.fix[s].lanczos_iters = lit;
-            } else {
-                GcStartRec rc = rec0;
-                rc.F = F;
-                rc.key_hi = key_hi;
-                rc.key_lo = key_lo;
-                rc.paper_X = (uint32_t)(F / ((double)d * (double)V) * 1e8);
-                rc.flags = flags;
-                rc.lambda2 = lam2;
-                rc.lanczos_iters = lit;
-                J.rec[local] = rc;
+                }
+        if (tid == 0) write_filter(J, c, local, lam2, flags, lit);
+        __syncthreads();
+    }
+}
+
+// FP filter in the line-segment layout, one workgroup of B threads per copy
+// of the compacted tables (at the copy's representative start): thread t
+// owns S consecutive sites along direction 0 (x_0 runs fastest, so they are
+// consecutive site indices), segment t % (N_0/S) of line t / (N_0/S).  The
+// Lanczos vector u of the own sites, q_{j-1} and M u stay in registers, and
+// so do the direction-0 link weights; direction-0 neighbours inside the
+// segment are the thread's own entries.  LDS holds u (8V bytes) for the
+// other threads, the forward link weights of directions 1..d-1 (and of
+// direction 0 when a line has several segments), V doubles each, and the
+// tridiagonal; the state g is staged over the weights at the start.  The
+// iteration is post_kernel's: one reduction per iteration, the same formulas
+// per site.
+template <int B, int S>
+__global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__ jobs, int n_jobs,
+                                                    unsigned long long *next)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[2 * 4 * (B / 64)];
+    __shared__ int ired[2 * (B / 64)];
+    __shared__ unsigned long long claim;
+    int rph = 0, iph = 0;   // halves of the reduction scratch in use
+    for (;;) {
+        const int tid = (int)threadIdx.x + opaque_zero();
+        if (tid == 0) claim = atomicAdd(next, 1ULL);
+        __syncthreads();
+        const uint64_t s = uniform((uint64_t)claim);
+        __syncthreads();
+        int jn;
+        uint64_t c;
+        copy_item(jobs, n_jobs, s, jn, c);
+        jn = uniform(jn);
+        if (jn < 0) break;
+        const GcJobDev &J = jobs[jn];
+        const GcOrbitDev &O = J.orb;
+        const int V = O.V, d = O.d, N0 = O.ext[0];
+        const uint64_t local = J.copies[c].rep_start - J.first_start;
+        const int nseg = N0 / S;
+        const bool act = tid < V / S;
+        const int line = act ? tid / nseg : 0, o = act ? (tid % nseg) * S : 0;
+        const int i0 = line * N0 + o;
+        const bool whole = (S == N0);   // the segment is a whole line
+        const int nw = whole ? d - 1 : d;   // weight arrays in LDS
+        const int w0off = whole ? -1 : 0;   // LDS array of direction mu: mu + w0off
+        lds_ptr<double> u = as_lds(reinterpret_cast<double *>(smem));
+        lds_ptr<double> wl = u + V;
+        const int lmax = min(min(J.lanczos_max, GC_LMAX), V);
+        lds_ptr<double> alpha = wl + (size_t)nw * V;
+        lds_ptr<double> beta2 = alpha + lmax;
+
+        // own link weights w = Re(conj(g_i) U_{i,mu} g_{i+mu}) from the
+        // representative's state in global memory: direction 0 into
+        // registers, the others into LDS
+        glb_ptr<const dbl2> src = as_global(reinterpret_cast<const dbl2 *>(J.states + local * (uint64_t)V));
+        glb_ptr<const dbl2> Ug = as_global(reinterpret_cast<const dbl2 *>(O.U64));
+        double w0[S];
+        int df[GC_MAXD], db[GC_MAXD];   // neighbour offsets of directions >= 1 (the same for every own site)
+#pragma unroll
+        for (int mu = 0; mu < GC_MAXD; ++mu) {
+            df[mu] = 0;
+            db[mu] = 0;
+            if (act && mu > 0 && mu < d) {
+                df[mu] = (int)O.nbr[mu * V + i0] - i0;
+                db[mu] = (int)O.nbr[(d + mu) * V + i0] - i0;
             }
+        }
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            const int i = i0 + k;
+            w0[k] = 0.0;
+            if (act) {
+                const dbl2 gi = src[i];
+#pragma unroll
+                for (int mu = 0; mu < GC_MAXD; ++mu) {
+                    if (mu < d) {
+                        const dbl2 gf = src[O.nbr[mu * V + i]];
+                        const dbl2 uu = Ug[mu * V + i];
+                        const double tr = uu.x * gf.x - uu.y * gf.y, ti = uu.x * gf.y + uu.y * gf.x;
+                        const double ur = gi.x * tr + gi.y * ti;
+                        if (mu == 0) w0[k] = ur;
+                        if (mu + w0off >= 0) wl[(mu + w0off) * V + i] = ur;
+                    }
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        double uo[S], qp[S], mv[S];
+        double sums[1] = {0.0};
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            const int i = i0 + k;
+            qp[k] = 0.0;
+            uo[k] = 0.0;
+            mv[k] = 0.0;
+            if (act) {
+                const double x = (double)(mix64((uint64_t)i + 0x5851F42D4C957F2DULL) >> 11) * 0x1.0p-53 - 0.5;
+                uo[k] = x;
+                sums[0] += x;
+            }
+        }
+        wg_sum_n<B, 1>(sums, red, rph);
+        const double mean = sums[0] / (double)V;
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            if (act) {
+                uo[k] -= mean;
+                u[i0 + k] = uo[k];
+            }
+        }
+        const double sigma = 4.0 * d + 1.0;
+        double theta = INFINITY, theta_old = INFINITY, theta_step = 1.0;
+        double rows_lo = INFINITY, rows_hi = -INFINITY;   // Gershgorin bounds of the complete rows
+        double a_prev = 0.0, b_prev2 = 0.0;                // alpha_{j-1}, beta_{j-2}
+        int next_check = 24;                               // iteration count of the next Ritz check
+        int it = 0;
+        bool conv = false;
+        // the neighbours across the ends of a segment that is not a whole line
+        const int ia = line * N0 + (o + S) % N0, ib = line * N0 + (o + N0 - 1) % N0;
+        for (it = 0; it < lmax; ++it) {
+            if (B > 64) __syncthreads();   // u and the weights complete in LDS
+            else wave_sync();
+            double s4[4] = {0.0, 0.0, 0.0, 0.0};
+            if (act) {
+                const double ua = whole ? uo[0] : u[ia];
+                const double ub = whole ? uo[S - 1] : u[ib];
+                const double wbe = whole ? w0[S - 1] : wl[ib];
+#pragma unroll
+                for (int k = 0; k < S; ++k) {
+                    const int i = i0 + k + opaque_zero();
+                    const double ui = uo[k];
+                    // direction 0: neighbours and weights of the own segment
+                    const double uf = (k + 1 < S) ? uo[k + 1] : ua;
+                    const double ubk = (k > 0) ? uo[k - 1] : ub;
+                    const double wb0 = (k > 0) ? w0[k - 1] : wbe;
+                    double m = w0[k] * (ui - uf) + wb0 * (ui - ubk);
+#pragma unroll
+                    for (int mu = 1; mu < GC_MAXD; ++mu)
+                        if (mu < d) {
+                            const int a = (mu + w0off) * V;
+                            m += wl[a + i] * (ui - u[i + df[mu]]) + wl[a + i + db[mu]] * (ui - u[i + db[mu]]);
+                        }
+                    mv[k] = m;
+                    s4[0] += ui * ui;
+                    s4[1] += ui * m;
+                    s4[2] += ui;
+                    s4[3] += ui * qp[k];
+                    // one site at a time: bounds the loads in flight
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            wg_sum_n<B, 4>(s4, red, rph);
+            const double bt = sqrt(s4[0]);
+            const double bp = it > 0 ? bt : 0.0;      // beta_{j-1} (the start vector's norm is not in T)
+            if (it > 0) {
+                if (tid == 0) beta2[it - 1] = s4[0];
+                rows_lo = fmin(rows_lo, a_prev - b_prev2 - bt);
+                rows_hi = fmax(rows_hi, a_prev + b_prev2 + bt);
+                if (bt <= 1e-13 * sigma) {
+                    // the Krylov space is exhausted: T of it rows is exact
+                    if (B > 64) __syncthreads();
+                    else wave_sync();
+                    double theta_hi;
+                    theta = ritz_min<B>(alpha, beta2, it, rows_lo, rows_hi, theta_old, theta_step, ired, iph,
+                                        kRitzTol, true, theta_hi);
+                    conv = true;
+                    break;
+                }
+            }
+            const double inv = 1.0 / bt;
+            const double sq = s4[2] * inv;
+            const double shift = sigma * sq / (double)V;
+            const double a_j = s4[1] * inv * inv + shift * sq - bp * (s4[3] * inv);
+            if (tid == 0) alpha[it] = a_j;
+            if (act) {
+#pragma unroll
+                for (int k = 0; k < S; ++k) {
+                    const double q = uo[k] * inv;
+                    const double r = mv[k] * inv + shift - bp * qp[k] - a_j * q;
+                    qp[k] = q;
+                    uo[k] = r;
+                    u[i0 + k] = r;
+                }
+            }
+            if (it + 1 >= next_check || it + 1 == lmax) {
+                if (B > 64) __syncthreads();   // the tridiagonal is complete in LDS
+                else wave_sync();
+                const bool final = it + 1 == lmax;
+                double theta_hi;
+                theta = ritz_min<B>(alpha, beta2, it + 1, fmin(rows_lo, a_j - bp), fmax(rows_hi, a_j + bp),
+                                    theta_old, theta_step, ired, iph, kRitzTol, final, theta_hi);
+                const double tol = kRitzTol * fmax(1.0, fabs(theta));
+                const double change = theta_old - theta;
+                if (fabs(change) <= tol) {
+                    conv = true;
+                    ++it;
+                    break;
+                }
+                const int gap = !(change <= 1e6 * tol) ? 24 : !(change <= 1e3 * tol) ? 16 : 8;
+                next_check = it + 1 + gap;
+                if (theta_old < INFINITY) theta_step = change;
+                theta_old = theta_hi;
+            }
+            b_prev2 = bp;
+            a_prev = a_j;
+        }
+        uint32_t flags = region_flags(theta, J.lambda_tol);
+        if (!conv) flags |= GC_F_LANCZOS_CAP;
+        if (tid == 0) {
+            write_filter(J, c, local, theta, flags, (uint32_t)it);
+            atomicAdd(&J.cnt->lanczos_runs, 1ULL);
         }
         __syncthreads();
     }
@@ -652,7 +918,6 @@ __global__ void reset_kernel(GcJobDev J)
         GcCounters z = {};
         *J.cnt = z;
         *J.n_copies = 0ULL;
-        *J.n_fix = 0ULL;
     }
 }
 
@@ -740,63 +1005,13 @@ __global__ __launch_bounds__(256) void scatter_kernel(GcJobDev J)
     const double fmin = __longlong_as_double((long long)e.fmin_bits);
     const double fmax = __longlong_as_double((long long)e.fmax_bits);
     const uint32_t col = ((fmax - fmin) / (double)J.orb.V > GC_F_SPREAD_PER_SITE) ? GC_F_COLLISION : 0u;
-    if (rep == e.first_start) {
-        // the lowest start ran the filter when it was inserted
-        c.lambda2 = r.lambda2;
-        c.flags = (r.flags & (GC_F_IN_REGION | GC_F_SINGULAR | GC_F_SADDLE | GC_F_LANCZOS_CAP | GC_F_KEY_OVERFLOW)) | col;
-        c.lanczos_iters = r.lanczos_iters;
-    } else {
-        c.lambda2 = NAN;
-        c.flags = col | (r.flags & GC_F_KEY_OVERFLOW);
-        c.lanczos_iters = 0;
-        const unsigned long long k = atomicAdd(J.n_fix, 1ULL);
-        GcFix f;
-        f.start = rep;
-        f.slot = slot;
-        f.lambda2 = NAN;
-        f.flags = 0;
-        f.lanczos_iters = 0;
-        J.fix[k] = f;
-    }
+    // the filter pass fills in lambda2, its flags and iterations
+    c.lambda2 = NAN;
+    c.flags = col | (r.flags & GC_F_KEY_OVERFLOW);
+    c.lanczos_iters = 0;
     J.copies[slot] = c;
 }
 
-constexpr uint32_t kFilterFlags = GC_F_IN_REGION | GC_F_SINGULAR | GC_F_SADDLE | GC_F_LANCZOS_CAP;
-
-// Which other starts of a key also ran the filter depends on the order of
-// insertion; their results are dropped so that a start record carries the
-// filter exactly when the start is its copy's representative.
-__global__ void scrub_kernel(GcJobDev J)
-{
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < J.n_starts; k += stride) {
-        GcStartRec &r = J.rec[k];
-        if (r.status != GC_ST_CONVERGED || r.lanczos_iters == 0) continue;
-        const GcEntry *e = table_find(J, r.key_hi, r.key_lo);
-        if (e && e->rep_start == J.first_start + k) continue;
-        r.lambda2 = NAN;
-        r.lanczos_iters = 0;
-        r.flags &= ~kFilterFlags;
-    }
-}
-
-// Filter results recomputed at representatives: into the copy and the
-// representative's start record.
-__global__ void patch_kernel(GcJobDev J)
-{
-    const uint64_t n = *J.n_fix;
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
-        const GcFix f = J.fix[k];
-        GcCopyRec &c = J.copies[f.slot];
-        c.lambda2 = f.lambda2;
-        c.flags |= f.flags & kFilterFlags;
-        c.lanczos_iters = f.lanczos_iters;
-        GcStartRec &r = J.rec[f.start - J.first_start];
-        r.lambda2 = f.lambda2;
-        r.lanczos_iters = f.lanczos_iters;
-        r.flags = (r.flags & ~kFilterFlags) | (f.flags & kFilterFlags);
-    }
-}
 
 __global__ void orbit_random_kernel(double *phi, int64_t n_links, uint64_t seed, uint64_t orbit_index)
 {
@@ -861,29 +1076,20 @@ int grid_for(uint64_t work)
 
 }  // namespace
 
-size_t gc_post_lds_bytes(int d, int V)
+size_t gc_post_lds_bytes(int d, int V, int keys, int lmax)
 {
-    const size_t lmax = V < GC_LMAX ? V : GC_LMAX;
-    const size_t angles = 4 * (size_t)d * V, tri = 2 * sizeof(double) * lmax;
-    return 16 * (size_t)V + (angles > tri ? angles : tri);
+    // the state, then the link angles (key pass) or the tridiagonal (filter)
+    if (keys) return 16 * (size_t)V + 4 * (size_t)d * V;
+    const size_t l = (size_t)std::min(std::min(lmax, GC_LMAX), V);
+    return 16 * (size_t)V + 16 * l;
 }
 
 void gc_post_shape(int V, int *block, int *sp, int *wreg)
 {
-    // tuning override: GC_POST_SHAPE=block,sites_per_thread (register weights)
-    if (const char *e = getenv("GC_POST_SHAPE")) {
-        int b = 0, k = 0;
-        if (sscanf(e, "%d,%d", &b, &k) == 2 && (long)b * k >= V) {
-            *block = b;
-            *sp = k;
-            *wreg = 1;
-            return;
-        }
-    }
-    // up to 4 sites per thread with the link weights in registers; the
+    // up to 6 sites per thread with the link weights in registers; the
     // largest lattices keep them in global memory
     static const int shapes[][4] = {{64, 64, 1, 1},     {128, 64, 2, 1},    {256, 64, 4, 1},
-                                    {512, 128, 4, 1},   {1024, 256, 4, 1},  {1536, 384, 4, 1},
+                                    {512, 128, 4, 1},   {1024, 256, 4, 1},  {1536, 256, 6, 1},
                                     {4096, 512, 8, 0}};
     for (const auto &t : shapes)
         if (V <= t[0]) {
@@ -897,46 +1103,126 @@ void gc_post_shape(int V, int *block, int *sp, int *wreg)
     *wreg = 0;
 }
 
-#define GC_POST_DISPATCH(FN, ...)                                                   \
-    if (block == 64 && sp == 1 && wreg) return FN<64, 1, true>(__VA_ARGS__);        \
-    if (block == 64 && sp == 2 && wreg) return FN<64, 2, true>(__VA_ARGS__);        \
-    if (block == 64 && sp == 4 && wreg) return FN<64, 4, true>(__VA_ARGS__);        \
-    if (block == 128 && sp == 2 && wreg) return FN<128, 2, true>(__VA_ARGS__);      \
-    if (block == 256 && sp == 1 && wreg) return FN<256, 1, true>(__VA_ARGS__);      \
-    if (block == 256 && sp == 2 && wreg) return FN<256, 2, true>(__VA_ARGS__);      \
-    if (block == 512 && sp == 2 && wreg) return FN<512, 2, true>(__VA_ARGS__);      \
-    if (block == 128 && sp == 4 && wreg) return FN<128, 4, true>(__VA_ARGS__);      \
-    if (block == 256 && sp == 4 && wreg) return FN<256, 4, true>(__VA_ARGS__);      \
-    if (block == 384 && sp == 4 && wreg) return FN<384, 4, true>(__VA_ARGS__);      \
-    if (block == 512 && sp == 8 && !wreg) return FN<512, 8, false>(__VA_ARGS__);    \
+#define GC_POST_DISPATCH(FN, ...)                                                                         \
+    if (block == 64 && sp == 1 && wreg) return keys ? FN<64, 1, true, true>(__VA_ARGS__)                 \
+                                                    : FN<64, 1, true, false>(__VA_ARGS__);               \
+    if (block == 64 && sp == 2 && wreg) return keys ? FN<64, 2, true, true>(__VA_ARGS__)                 \
+                                                    : FN<64, 2, true, false>(__VA_ARGS__);               \
+    if (block == 64 && sp == 4 && wreg) return keys ? FN<64, 4, true, true>(__VA_ARGS__)                 \
+                                                    : FN<64, 4, true, false>(__VA_ARGS__);               \
+    if (block == 128 && sp == 4 && wreg) return keys ? FN<128, 4, true, true>(__VA_ARGS__)               \
+                                                     : FN<128, 4, true, false>(__VA_ARGS__);             \
+    if (block == 256 && sp == 4 && wreg) return keys ? FN<256, 4, true, true>(__VA_ARGS__)               \
+                                                     : FN<256, 4, true, false>(__VA_ARGS__);             \
+    if (block == 256 && sp == 6 && wreg) return keys ? FN<256, 6, true, true>(__VA_ARGS__)               \
+                                                     : FN<256, 6, true, false>(__VA_ARGS__);             \
+    if (block == 512 && sp == 8 && !wreg) return keys ? FN<512, 8, false, true>(__VA_ARGS__)             \
+                                                      : FN<512, 8, false, false>(__VA_ARGS__);           \
     return hipErrorInvalidValue;
 
-template <int B, int SP, bool WREG>
+template <int B, int SP, bool WREG, bool KEYS>
 static hipError_t post_occ_t(size_t lds, int *per_cu)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, post_kernel<B, SP, WREG>, B, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, post_kernel<B, SP, WREG, KEYS>, B, lds);
 }
 
-template <int B, int SP, bool WREG>
+template <int B, int SP, bool WREG, bool KEYS>
 static hipError_t post_launch_t(const GcJobDev *jobs, int n_jobs, const uint64_t *prefix, unsigned long long *next,
-                                uint64_t total, const unsigned long long *total_dev, double *wbuf, uint64_t wstride,
-                                int grid, size_t lds, hipStream_t s)
+                                uint64_t total, double *wbuf, uint64_t wstride, int grid, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((post_kernel<B, SP, WREG>), dim3(grid), dim3(B), lds, s, jobs, n_jobs, prefix, next, total,
-                       total_dev, wbuf, wstride);
+    hipLaunchKernelGGL((post_kernel<B, SP, WREG, KEYS>), dim3(grid), dim3(B), lds, s, jobs, n_jobs, prefix, next,
+                       total, wbuf, wstride);
     return hipGetLastError();
 }
 
-hipError_t gc_post_occupancy(int block, int sp, int wreg, size_t lds_bytes, int *blocks_per_cu)
+hipError_t gc_post_occupancy(int block, int sp, int wreg, int keys, size_t lds_bytes, int *blocks_per_cu)
 {
     GC_POST_DISPATCH(post_occ_t, lds_bytes, blocks_per_cu)
 }
 
-hipError_t gc_launch_post(int block, int sp, int wreg, const GcJobDev *jobs, int n_jobs, const uint64_t *prefix,
-                          unsigned long long *next, uint64_t total, const unsigned long long *total_dev,
-                          double *wbuf, uint64_t wstride, int grid, size_t lds_bytes, hipStream_t s)
+hipError_t gc_launch_post(int block, int sp, int wreg, int keys, const GcJobDev *jobs, int n_jobs,
+                          const uint64_t *prefix, unsigned long long *next, uint64_t total, double *wbuf,
+                          uint64_t wstride, int grid, size_t lds_bytes, hipStream_t s)
 {
-    GC_POST_DISPATCH(post_launch_t, jobs, n_jobs, prefix, next, total, total_dev, wbuf, wstride, grid, lds_bytes, s)
+    GC_POST_DISPATCH(post_launch_t, jobs, n_jobs, prefix, next, total, wbuf, wstride, grid, lds_bytes, s)
+}
+
+// Line-segment filter shapes: S sites per thread along direction 0 (a
+// divisor of N_0), the fewest wavefronts, then the shortest segment.
+static const int kSegs[] = {1, 2, 3, 4, 5, 6, 7, 8, 10};
+
+int gc_lanczos_shape(int d, const int *ext, int V, int *block, int *seg)
+{
+    (void)d;
+    const int N0 = ext[0];
+    int best_w = 1 << 30, best_s = 0;
+    for (int S : kSegs) {
+        if (N0 % S) continue;
+        const int w = (V / S + 63) / 64;
+        if (w > 8) continue;
+        if (w < best_w) {
+            best_w = w;
+            best_s = S;
+        }
+    }
+    if (!best_s) return 0;
+    *seg = best_s;
+    *block = best_w <= 1 ? 64 : best_w <= 2 ? 128 : best_w <= 4 ? 256 : 512;
+    return 1;
+}
+
+size_t gc_lanczos_lds_bytes(int d, int N0, int S, int V, int lmax)
+{
+    const int nw = (S == N0) ? d - 1 : d;
+    const size_t l = (size_t)std::min(std::min(lmax, GC_LMAX), V);
+    return 8 * (size_t)V + 8 * (size_t)nw * V + 16 * l;
+}
+
+#define GC_LANCZOS_SEG(FN, B, ...)                                                                        \
+    switch (seg) {                                                                                        \
+    case 1: return FN<B, 1>(__VA_ARGS__);                                                                 \
+    case 2: return FN<B, 2>(__VA_ARGS__);                                                                 \
+    case 3: return FN<B, 3>(__VA_ARGS__);                                                                 \
+    case 4: return FN<B, 4>(__VA_ARGS__);                                                                 \
+    case 5: return FN<B, 5>(__VA_ARGS__);                                                                 \
+    case 6: return FN<B, 6>(__VA_ARGS__);                                                                 \
+    case 7: return FN<B, 7>(__VA_ARGS__);                                                                 \
+    case 8: return FN<B, 8>(__VA_ARGS__);                                                                 \
+    case 10: return FN<B, 10>(__VA_ARGS__);                                                               \
+    default: return hipErrorInvalidValue;                                                                 \
+    }
+#define GC_LANCZOS_DISPATCH(FN, ...)                                                                      \
+    switch (block) {                                                                                      \
+    case 64: GC_LANCZOS_SEG(FN, 64, __VA_ARGS__)                                                          \
+    case 128: GC_LANCZOS_SEG(FN, 128, __VA_ARGS__)                                                        \
+    case 256: GC_LANCZOS_SEG(FN, 256, __VA_ARGS__)                                                        \
+    case 512: GC_LANCZOS_SEG(FN, 512, __VA_ARGS__)                                                        \
+    default: return hipErrorInvalidValue;                                                                 \
+    }
+
+template <int B, int S>
+static hipError_t lanczos_occ_t(size_t lds, int *per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, lanczos_kernel<B, S>, B, lds);
+}
+
+template <int B, int S>
+static hipError_t lanczos_launch_t(const GcJobDev *jobs, int n_jobs, unsigned long long *next, int grid, size_t lds,
+                                   hipStream_t s)
+{
+    hipLaunchKernelGGL((lanczos_kernel<B, S>), dim3(grid), dim3(B), lds, s, jobs, n_jobs, next);
+    return hipGetLastError();
+}
+
+hipError_t gc_lanczos_occupancy(int block, int seg, size_t lds_bytes, int *blocks_per_cu)
+{
+    GC_LANCZOS_DISPATCH(lanczos_occ_t, lds_bytes, blocks_per_cu)
+}
+
+hipError_t gc_launch_lanczos(int block, int seg, const GcJobDev *jobs, int n_jobs, unsigned long long *next, int grid,
+                             size_t lds_bytes, hipStream_t s)
+{
+    GC_LANCZOS_DISPATCH(lanczos_launch_t, jobs, n_jobs, next, grid, lds_bytes, s)
 }
 
 hipError_t gc_launch_reset(const GcJobDev *jobs_host, int n_jobs, hipStream_t s)
@@ -966,19 +1252,6 @@ hipError_t gc_launch_finalize(const GcJobDev *jobs_host, int n_jobs, hipStream_t
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(scatter_kernel, dim3(nblk), dim3(256), 0, s, J);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
-
-hipError_t gc_launch_patch(const GcJobDev *jobs_host, int n_jobs, hipStream_t s)
-{
-    for (int j = 0; j < n_jobs; ++j) {
-        hipLaunchKernelGGL(scrub_kernel, dim3(grid_for(jobs_host[j].n_starts)), dim3(256), 0, s, jobs_host[j]);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(patch_kernel, dim3(64), dim3(256), 0, s, jobs_host[j]);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -224,14 +224,26 @@ struct PostGroup {
     size_t o_jobs = 0, o_prefix = 0, o_next = 0, o_wbuf = 0;
 };
 
+// Orbits of one relax group sharing one filter-pass kernel: the
+// line-segment Lanczos kernel (fast, seg sites per thread) or the general
+// post kernel in its filter mode.
+struct FilterGroup {
+    bool fast = false;
+    int block = 64, seg = 1, sp = 1, wreg = 1, grid = 1;
+    size_t lds = 0;
+    uint64_t total = 0, wstride = 0;   // total: an upper bound of the copies (the starts)
+    std::vector<int> jobs;
+    int chain = 0;
+    size_t o_jobs = 0, o_next = 0, o_wbuf = 0;
+};
+
 // Device memory of one job.
 struct JobLayout {
-    std::vector<size_t> o_rec, o_table, o_cnt, o_copies, o_ncopies, o_fix, o_nfix, o_states, o_blk, o_sync;
+    std::vector<size_t> o_rec, o_table, o_cnt, o_copies, o_ncopies, o_states, o_blk, o_sync;
     std::vector<uint64_t> table_cap;
     std::vector<Group> groups;
     std::vector<PostGroup> posts;
-    std::vector<int> post_of;   // job -> post group
-    std::vector<size_t> o_fixjobs, o_fixnext;   // per job
+    std::vector<FilterGroup> filters;
     size_t total = 0;
 };
 
@@ -247,7 +259,7 @@ struct Job {
     void *staging = nullptr;         // pinned descriptors + result counters
     size_t staging_bytes = 0;
     int stream = -1;
-    hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_k2 = nullptr, ev_done = nullptr;
+    hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_k2 = nullptr, ev_k3 = nullptr, ev_done = nullptr;
     hipGraph_t g = nullptr;
     hipGraphExec_t gx = nullptr;
     JobLayout L;
@@ -256,10 +268,10 @@ struct Job {
     // pinned host results (inside staging)
     GcCounters *h_cnt = nullptr;               // [n_jobs]
     unsigned long long *h_ncopies = nullptr;   // [n_jobs]
-    double solve_ms = 0.0, post_ms = 0.0;
+    double solve_ms = 0.0, post_ms = 0.0, filter_ms = 0.0;
     uint64_t total = 0;
     // kernel variants forced for this job (gc_autotune trials), -1 / 0: none
-    int force_creg = -1, force_post_block = 0, force_post_sp = 0, force_wps = -1;
+    int force_creg = -1, force_wps = -1;
 };
 
 struct Orbit {
@@ -298,7 +310,6 @@ struct gc_ctx {
     // layout per (d, slots per lane, precision), post workgroup shape per V
     std::map<uint64_t, int> tune_creg;
     std::map<uint64_t, int> tune_wps;   // workgroup-per-start layout on (1) or off (0)
-    std::map<int, std::pair<int, int>> tune_post;
     std::string tune_cache;             // file the choices persist in ("" none)
     uint64_t budget = 0, used = 0;
     std::vector<hipStream_t> streams;   // launch streams (the caller's one when given)
@@ -610,13 +621,9 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         L.o_cnt.push_back(place(sizeof(GcCounters)));
         L.o_copies.push_back(place(sizeof(GcCopyRec) * n));
         L.o_ncopies.push_back(place(sizeof(unsigned long long)));
-        L.o_fix.push_back(place(sizeof(GcFix) * n));
-        L.o_nfix.push_back(place(sizeof(unsigned long long)));
         L.o_blk.push_back(place(sizeof(uint32_t) * ((cap + 255) / 256)));
         L.o_states.push_back(place(sizeof(double2) * n * (uint64_t)o->V));
         L.o_sync.push_back(job->p.sync_batch ? place(sizeof(uint32_t) * n) : 0);
-        L.o_fixjobs.push_back(place(sizeof(GcJobDev)));
-        L.o_fixnext.push_back(place(sizeof(unsigned long long)));
         // two colours: one wavefront per start (GC_WAVES states per
         // workgroup in LDS) up to 128 slots per colour, a workgroup of wps
         // wavefronts per start above; other colourings take the generic
@@ -704,24 +711,17 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         g.o_prefix = place(sizeof(uint64_t) * (g.jobs.size() + 1));
         g.o_bounce = g.wave ? place(sizeof(float2) * (size_t)gV * per_wg * g.grid) : 0;
     }
-    // post pass: one workgroup per start, one launch per workgroup shape
-    // within each relax group's chain
-    L.post_of.assign(nj, -1);
+    // key pass: one workgroup per start, one launch per workgroup shape
+    // within each relax group's chain; filter pass: one workgroup per copy,
+    // one launch per kernel shape within the chain.  Both shapes depend on
+    // the lattice only, so an orbit's results do not depend on tuning or on
+    // the other orbits of a batch.
+    const int lmax = (int)std::min<uint32_t>(std::max<uint32_t>(job->p.lanczos_max_iter, 1), GC_LMAX);
     for (size_t gi = 0; gi < L.groups.size(); ++gi) {
         for (int j : L.groups[gi].jobs) {
+            const Orbit *o = job->orbits[j];
             int block = 0, sp = 0, wreg = 0;
-            gc_post_shape(job->orbits[j]->V, &block, &sp, &wreg);
-            const auto tp = ctx->tune_post.find(job->orbits[j]->V);
-            if (tp != ctx->tune_post.end()) {
-                block = tp->second.first;
-                sp = tp->second.second;
-                wreg = 1;
-            }
-            if (job->force_post_block > 0) {
-                block = job->force_post_block;
-                sp = job->force_post_sp;
-                wreg = 1;
-            }
+            gc_post_shape(o->V, &block, &sp, &wreg);
             if (block == 0) return GC_EUNSUPPORTED;
             int k = 0;
             while (k < (int)L.posts.size() && !(L.posts[k].chain == (int)gi && L.posts[k].block == block &&
@@ -736,7 +736,29 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             }
             L.posts[k].jobs.push_back(j);
             L.posts[k].total += job->n_starts[j];
-            L.post_of[j] = k;
+            // filter: the line-segment kernel where one is instantiated and
+            // fits, else the general kernel with the key pass's shape
+            FilterGroup f;
+            f.chain = (int)gi;
+            int fb = 0, fs = 0;
+            if (gc_lanczos_shape(o->d, o->lat.extent, o->V, &fb, &fs) &&
+                gc_lanczos_lds_bytes(o->d, o->lat.extent[0], fs, o->V, lmax) <= ctx->lds_max) {
+                f.fast = true;
+                f.block = fb;
+                f.seg = fs;
+            } else {
+                f.block = block;
+                f.sp = sp;
+                f.wreg = wreg;
+            }
+            int m = 0;
+            while (m < (int)L.filters.size() &&
+                   !(L.filters[m].chain == f.chain && L.filters[m].fast == f.fast && L.filters[m].block == f.block &&
+                     L.filters[m].seg == f.seg && L.filters[m].sp == f.sp && L.filters[m].wreg == f.wreg))
+                ++m;
+            if (m == (int)L.filters.size()) L.filters.push_back(f);
+            L.filters[m].jobs.push_back(j);
+            L.filters[m].total += job->n_starts[j];
         }
     }
     for (PostGroup &pg : L.posts) {
@@ -745,19 +767,40 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             pV = std::max(pV, job->orbits[j]->V);
             pd = std::max(pd, job->orbits[j]->d);
         }
-        pg.lds = gc_post_lds_bytes(pd, pV);
+        pg.lds = gc_post_lds_bytes(pd, pV, 1, lmax);
         if (pg.lds > ctx->lds_max) return GC_EUNSUPPORTED;
         int per_cu = 0;
-        hipError_t e = gc_post_occupancy(pg.block, pg.sp, pg.wreg, pg.lds, &per_cu);
+        hipError_t e = gc_post_occupancy(pg.block, pg.sp, pg.wreg, 1, pg.lds, &per_cu);
         if (e != hipSuccess) return fail(ctx, e, "occupancy");
         per_cu = std::max(per_cu, 1);
         pg.grid = (int)std::min<uint64_t>((uint64_t)per_cu * ctx->n_cu, std::max<uint64_t>(pg.total, 1));
         pg.o_jobs = place(sizeof(GcJobDev) * pg.jobs.size());
         pg.o_prefix = place(sizeof(uint64_t) * (pg.jobs.size() + 1));
         pg.o_next = place(sizeof(unsigned long long));
-        if (!pg.wreg) {
-            pg.wstride = ((uint64_t)(pd + 3) * pV + 31) & ~(uint64_t)31;
-            pg.o_wbuf = place(sizeof(double) * pg.wstride * pg.grid);
+    }
+    for (FilterGroup &fg : L.filters) {
+        size_t lds = 0;
+        int fV = 0, fd = 0;
+        for (int j : fg.jobs) {
+            const Orbit *o = job->orbits[j];
+            fV = std::max(fV, o->V);
+            fd = std::max(fd, o->d);
+            lds = std::max(lds, fg.fast ? gc_lanczos_lds_bytes(o->d, o->lat.extent[0], fg.seg, o->V, lmax)
+                                        : gc_post_lds_bytes(o->d, o->V, 0, lmax));
+        }
+        if (lds > ctx->lds_max) return GC_EUNSUPPORTED;
+        fg.lds = lds;
+        int per_cu = 0;
+        hipError_t e = fg.fast ? gc_lanczos_occupancy(fg.block, fg.seg, lds, &per_cu)
+                               : gc_post_occupancy(fg.block, fg.sp, fg.wreg, 0, lds, &per_cu);
+        if (e != hipSuccess) return fail(ctx, e, "occupancy");
+        per_cu = std::max(per_cu, 1);
+        fg.grid = (int)std::min<uint64_t>((uint64_t)per_cu * ctx->n_cu, std::max<uint64_t>(fg.total, 1));
+        fg.o_jobs = place(sizeof(GcJobDev) * fg.jobs.size());
+        fg.o_next = place(sizeof(unsigned long long));
+        if (!fg.fast && !fg.wreg) {
+            fg.wstride = ((uint64_t)(fd + 3) * fV + 31) & ~(uint64_t)31;
+            fg.o_wbuf = place(sizeof(double) * fg.wstride * fg.grid);
         }
     }
     L.total = off;
@@ -779,6 +822,7 @@ void free_job(gc_ctx *ctx, Job *job)
     give_event(ctx, job->ev_k0, true);
     give_event(ctx, job->ev_k1, true);
     give_event(ctx, job->ev_k2, true);
+    give_event(ctx, job->ev_k3, true);
     give_event(ctx, job->ev_done, false);
     if (job->gx) (void)hipGraphExecDestroy(job->gx);
     if (job->g) (void)hipGraphDestroy(job->g);
@@ -833,8 +877,6 @@ void fill_job_devs(Job *job, unsigned char *base)
         J.copies = (GcCopyRec *)(base + L.o_copies[j]);
         J.n_copies = (unsigned long long *)(base + L.o_ncopies[j]);
         J.states = (double2 *)(base + L.o_states[j]);
-        J.fix = (GcFix *)(base + L.o_fix[j]);
-        J.n_fix = (unsigned long long *)(base + L.o_nfix[j]);
         J.blk = (uint32_t *)(base + L.o_blk[j]);
         J.sync_batch = job->p.sync_batch;
         J.fixed_sweeps = job->p.sync_batch ? (uint32_t *)(base + L.o_sync[j]) : nullptr;
@@ -851,16 +893,15 @@ struct Blob {
 
 std::vector<Blob> job_blobs(Job *job)
 {
-    const int nj = (int)job->orbits.size();
     const JobLayout &L = job->L;
     std::vector<Blob> blobs;
     auto add_blob = [&](size_t dst, const void *src, size_t bytes) {
         blobs.push_back(Blob{dst, std::vector<unsigned char>((const unsigned char *)src, (const unsigned char *)src + bytes)});
     };
-    for (int j = 0; j < nj; ++j) {
-        GcJobDev F = job->jobs[j];
-        F.flags |= GC_JOB_FIX;
-        add_blob(L.o_fixjobs[j], &F, sizeof F);
+    for (const FilterGroup &fg : L.filters) {
+        std::vector<GcJobDev> fj;
+        for (int j : fg.jobs) fj.push_back(job->jobs[j]);
+        add_blob(fg.o_jobs, fj.data(), sizeof(GcJobDev) * fj.size());
     }
     for (const PostGroup &pg : L.posts) {
         std::vector<GcJobDev> pj;
@@ -899,7 +940,6 @@ std::vector<Blob> job_blobs(Job *job)
 hipError_t enqueue_chain(Job *job, unsigned char *base, int gi, hipStream_t qs, bool timed)
 {
     const JobLayout &L = job->L;
-    auto wbuf_of = [&](const PostGroup &pg) { return pg.wreg ? nullptr : (double *)(base + pg.o_wbuf); };
     const Group &g = L.groups[gi];
     hipError_t e = hipSuccess;
     for (int j : g.jobs) {
@@ -911,6 +951,11 @@ hipError_t enqueue_chain(Job *job, unsigned char *base, int gi, hipStream_t qs, 
     for (const PostGroup &pg : L.posts) {
         if (pg.chain != gi) continue;
         e = gc_launch_zero_u64((unsigned long long *)(base + pg.o_next), 1, qs);
+        if (e != hipSuccess) return e;
+    }
+    for (const FilterGroup &fg : L.filters) {
+        if (fg.chain != gi) continue;
+        e = gc_launch_zero_u64((unsigned long long *)(base + fg.o_next), 1, qs);
         if (e != hipSuccess) return e;
     }
     if (timed && (e = hipEventRecord(job->ev_k0, qs)) != hipSuccess) return e;
@@ -940,27 +985,32 @@ hipError_t enqueue_chain(Job *job, unsigned char *base, int gi, hipStream_t qs, 
     }
     if ((e = relax(g.o_jobs)) != hipSuccess) return e;
     if (timed && (e = hipEventRecord(job->ev_k1, qs)) != hipSuccess) return e;
+    // key pass over the starts, then each orbit's table compacted in key
+    // order, then the filter pass over the copies
     for (const PostGroup &pg : L.posts) {
         if (pg.chain != gi) continue;
-        e = gc_launch_post(pg.block, pg.sp, pg.wreg, (const GcJobDev *)(base + pg.o_jobs), (int)pg.jobs.size(),
+        e = gc_launch_post(pg.block, pg.sp, pg.wreg, 1, (const GcJobDev *)(base + pg.o_jobs), (int)pg.jobs.size(),
                            (const uint64_t *)(base + pg.o_prefix), (unsigned long long *)(base + pg.o_next),
-                           pg.total, nullptr, wbuf_of(pg), pg.wstride, pg.grid, pg.lds, qs);
+                           pg.total, nullptr, 0, pg.grid, pg.lds, qs);
         if (e != hipSuccess) return e;
     }
-    if (timed && (e = hipEventRecord(job->ev_k2, qs)) != hipSuccess) return e;
     for (int j : g.jobs) {
         e = gc_launch_finalize(&job->jobs[j], 1, qs);
         if (e != hipSuccess) return e;
-        e = gc_launch_zero_u64((unsigned long long *)(base + L.o_fixnext[j]), 1, qs);
-        if (e != hipSuccess) return e;
-        const PostGroup &pg = L.posts[L.post_of[j]];
-        e = gc_launch_post(pg.block, pg.sp, pg.wreg, (const GcJobDev *)(base + L.o_fixjobs[j]), 1, nullptr,
-                           (unsigned long long *)(base + L.o_fixnext[j]), 0, job->jobs[j].n_fix, wbuf_of(pg),
-                           pg.wstride, std::min(pg.grid, 64), pg.lds, qs);
-        if (e != hipSuccess) return e;
-        e = gc_launch_patch(&job->jobs[j], 1, qs);
+    }
+    if (timed && (e = hipEventRecord(job->ev_k2, qs)) != hipSuccess) return e;
+    for (const FilterGroup &fg : L.filters) {
+        if (fg.chain != gi) continue;
+        if (fg.fast)
+            e = gc_launch_lanczos(fg.block, fg.seg, (const GcJobDev *)(base + fg.o_jobs), (int)fg.jobs.size(),
+                                  (unsigned long long *)(base + fg.o_next), fg.grid, fg.lds, qs);
+        else
+            e = gc_launch_post(fg.block, fg.sp, fg.wreg, 0, (const GcJobDev *)(base + fg.o_jobs), (int)fg.jobs.size(),
+                               nullptr, (unsigned long long *)(base + fg.o_next), 0,
+                               fg.wreg ? nullptr : (double *)(base + fg.o_wbuf), fg.wstride, fg.grid, fg.lds, qs);
         if (e != hipSuccess) return e;
     }
+    if (timed && (e = hipEventRecord(job->ev_k3, qs)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -1035,8 +1085,10 @@ gc_status start_job(gc_ctx *ctx, Job *job)
     job->ev_k0 = take_event(ctx, true);
     job->ev_k1 = take_event(ctx, true);
     job->ev_k2 = take_event(ctx, true);
+    job->ev_k3 = take_event(ctx, true);
     job->ev_done = take_event(ctx, false);
-    if (!job->ev_k0 || !job->ev_k1 || !job->ev_k2 || !job->ev_done) return fail(ctx, hipErrorOutOfMemory, "event");
+    if (!job->ev_k0 || !job->ev_k1 || !job->ev_k2 || !job->ev_k3 || !job->ev_done)
+        return fail(ctx, hipErrorOutOfMemory, "event");
 
     const int nchain = (int)L.groups.size();
     const bool fork = job->graph && nchain > 1;
@@ -1165,6 +1217,7 @@ void complete_locked(gc_ctx *ctx, Job *job)
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, job->ev_k0, job->ev_k1) == hipSuccess) job->solve_ms = ms;
     if (!job->graph && hipEventElapsedTime(&ms, job->ev_k1, job->ev_k2) == hipSuccess) job->post_ms = ms;
+    if (!job->graph && hipEventElapsedTime(&ms, job->ev_k2, job->ev_k3) == hipSuccess) job->filter_ms = ms;
     job->state = GC_ORBIT_DONE;
     ctx->stream_load[job->stream]--;
     for (size_t j = 0; j < job->orbits.size(); ++j) {
@@ -1184,6 +1237,7 @@ void complete_locked(gc_ctx *ctx, Job *job)
         P.submit_to_done_ms = ms_since(job->t_submit, job->t_done);
         P.device_ms = job->solve_ms;
         P.post_ms = job->post_ms;
+        P.filter_ms = job->filter_ms;
         if (c.errors) {
             ctx->failed = true;
             ctx->err = "copy table insert failed (table full or spin limit)";
@@ -1361,6 +1415,7 @@ gc_status enqueue_locked(gc_ctx *ctx, Job *job)
         job->ev_k0 = prev->ev_k0;
         job->ev_k1 = prev->ev_k1;
         job->ev_k2 = prev->ev_k2;
+        job->ev_k3 = prev->ev_k3;
         job->ev_done = prev->ev_done;
         job->g = prev->g;
         job->gx = prev->gx;
@@ -1370,7 +1425,7 @@ gc_status enqueue_locked(gc_ctx *ctx, Job *job)
         job->h_ncopies = prev->h_ncopies;
         job->total = prev->total;
         prev->mem = prev->staging = nullptr;
-        prev->ev_k0 = prev->ev_k1 = prev->ev_k2 = prev->ev_done = nullptr;
+        prev->ev_k0 = prev->ev_k1 = prev->ev_k2 = prev->ev_k3 = prev->ev_done = nullptr;
         prev->g = nullptr;
         prev->gx = nullptr;
         prev->bytes = 0;
@@ -1467,27 +1522,24 @@ gc_status launch_locked(gc_ctx *ctx, const std::vector<Orbit *> &orbits, const s
     if (force) {
         job->force_creg = force->force_creg;
         job->force_wps = force->force_wps;
-        job->force_post_block = force->force_post_block;
-        job->force_post_sp = force->force_post_sp;
     }
     gc_status st = enqueue_locked(ctx, job);
     if (st != GC_OK) delete job;
     return st;
 }
 
-// Tuning cache: one line per choice, "creg <key> <value>", "wps <key>
-// <value>" or "post <V> <block> <sites per thread>".
+// Tuning cache: one line per choice, "creg <key> <value>" or "wps <key>
+// <value>".
 void load_tune_cache(gc_ctx *ctx)
 {
     FILE *f = fopen(ctx->tune_cache.c_str(), "r");
     if (!f) return;
     char kind[16];
     unsigned long long k = 0;
-    int a = 0, b = 0;
+    int a = 0;
     while (fscanf(f, "%15s %llu %d", kind, &k, &a) == 3) {
         if (!strcmp(kind, "creg")) ctx->tune_creg[(uint64_t)k] = a;
         else if (!strcmp(kind, "wps")) ctx->tune_wps[(uint64_t)k] = a;
-        else if (!strcmp(kind, "post") && fscanf(f, "%d", &b) == 1) ctx->tune_post[(int)k] = std::make_pair(a, b);
         else break;
     }
     fclose(f);
@@ -1501,7 +1553,6 @@ void save_tune_cache(gc_ctx *ctx)
     if (!f) return;
     for (auto &kv : ctx->tune_creg) fprintf(f, "creg %llu %d\n", (unsigned long long)kv.first, kv.second);
     for (auto &kv : ctx->tune_wps) fprintf(f, "wps %llu %d\n", (unsigned long long)kv.first, kv.second);
-    for (auto &kv : ctx->tune_post) fprintf(f, "post %d %d %d\n", kv.first, kv.second.first, kv.second.second);
     fclose(f);
     (void)rename(tmp.c_str(), ctx->tune_cache.c_str());
 }
@@ -1977,12 +2028,10 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
     const bool mixed = p.precision == GC_MIXED;
     // one measured launch with the given variant forced on that launch only
     // (launches of other orbits meanwhile use the context's choices)
-    auto trial = [&](int creg, int wps, int pb, int psp, double *relax_ms, double *post_ms) -> gc_status {
+    auto trial = [&](int creg, int wps, double *relax_ms, double *post_ms) -> gc_status {
         Job force;
         force.force_creg = creg;
         force.force_wps = wps;
-        force.force_post_block = pb;
-        force.force_post_sp = psp;
         gc_status s2;
         {
             std::unique_lock<std::mutex> lk(ctx->mu);
@@ -1993,7 +2042,7 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
             if (s2 == GC_OK) s2 = wait_locked(ctx, lk, o, -1);
             if (s2 == GC_OK) {
                 *relax_ms = o->job->solve_ms;
-                *post_ms = o->job->post_ms;
+                *post_ms = o->job->post_ms + o->job->filter_ms;
             }
         }
         return s2;
@@ -2003,7 +2052,7 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
     const int ns = (V / 2 + 63) / 64;
     const int cmax = wave ? gc_wave_creg_max(d, ns) : 0;
     double rm = 0, pm = 0;
-    st = trial(-1, -1, 0, 0, &rm, &pm);   // warm-up: code objects, pool
+    st = trial(-1, -1, &rm, &pm);   // warm-up: code objects, pool
     if (st != GC_OK) return st;
     // relax layout for more than two slots per lane: one wavefront per start
     // or a workgroup per start, best of two launches each
@@ -2015,7 +2064,7 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
         double tw[2] = {INFINITY, INFINITY};
         for (int w = 0; w < 2; ++w)
             for (int rep = 0; rep < 2; ++rep) {
-                st = trial(0, w, 0, 0, &rm, &pm);
+                st = trial(0, w, &rm, &pm);
                 if (st != GC_OK) return st;
                 tw[w] = std::min(tw[w], rm);
             }
@@ -2030,7 +2079,7 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
         for (int c = 0; c <= cmax; ++c) {
             double t = INFINITY;
             for (int rep = 0; rep < 2; ++rep) {
-                st = trial(c, 0, 0, 0, &rm, &pm);
+                st = trial(c, 0, &rm, &pm);
                 if (st != GC_OK) return st;
                 t = std::min(t, rm);
             }
@@ -2038,38 +2087,29 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
         }
         best_r = bc;
     }
-    // post: every instantiated register-weight shape with at most 4 sites per
-    // thread that covers V without quadrupling it
-    static const int shapes[][2] = {{64, 1},  {64, 2},  {64, 4},  {128, 2}, {128, 4}, {256, 1}, {256, 2},
-                                    {256, 4}, {384, 4}, {512, 2}};
-    int best_b = 0, best_sp = 0;
-    double best_p = INFINITY;
-    int db = 0, dsp = 0, dw = 0;
-    gc_post_shape(V, &db, &dsp, &dw);
-    for (const auto &sh : shapes) {
-        const long cover = (long)sh[0] * sh[1];
-        if (cover < V || cover >= 4L * V) continue;
-        if (!dw) continue;   // large lattices keep the global-memory variant
-        double t = INFINITY;
-        for (int rep = 0; rep < 2; ++rep) {
-            st = trial(best_c, best_w, sh[0], sh[1], &rm, &pm);
-            if (st != GC_OK) return st;
-            t = std::min(t, pm);
-        }
-        if (t < best_p) { best_p = t; best_b = sh[0]; best_sp = sh[1]; }
-    }
     {
         std::lock_guard<std::mutex> g(ctx->mu);
         if (wps_ok) ctx->tune_wps[creg_key(d, ns, mixed)] = best_w;
         if (wave && !best_w) ctx->tune_creg[creg_key(d, ns, mixed)] = best_c;
-        if (best_b) ctx->tune_post[V] = std::make_pair(best_b, best_sp);
         save_tune_cache(ctx);
+    }
+    // the filter's shape depends on the lattice only: reported, not tuned
+    int fb = 0, fs = 0, db = 0, dsp = 0, dw = 0;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        Orbit *o = find_orbit(ctx, orbit);
+        if (o && gc_lanczos_shape(o->d, o->lat.extent, o->V, &fb, &fs)) {
+            db = fb;
+            dsp = fs;
+        } else {
+            gc_post_shape(V, &db, &dsp, &dw);
+        }
     }
     r.relax_variant = best_c + (best_w ? 8 : 0);
     r.relax_ms = best_r;
-    r.post_block = best_b ? best_b : db;
-    r.post_sites_per_thread = best_b ? best_sp : dsp;
-    r.post_ms = best_b ? best_p : pm;
+    r.post_block = db;
+    r.post_sites_per_thread = dsp;
+    r.post_ms = pm;
     if (out) *out = r;
     return GC_OK;
 }
