@@ -224,6 +224,17 @@ gc_status gc_orbit_angles(gc_ctx *ctx, gc_orbit orbit, double *phi_out);
  * flight).  params NULL: defaults. */
 gc_status gc_launch(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_solve_params *params);
 
+/* gc_launch from the caller's gauge transformations instead of random
+ * starts: theta [n_starts][V] (host, radians, finite) is start s's angles
+ * theta_i, relaxed (at least one sweep) and filtered like a random start.
+ * A state that is already stationary stays there after its first sweep, so
+ * this also classifies given states: F, key and the first-region flags, e.g.
+ * of the trivial orbit's twisted states and singular families (Sec. II).
+ * Start ids are first_start .. first_start + n_starts - 1 as usual.  Errors
+ * as gc_launch, GC_EINVAL for NULL or non-finite theta. */
+gc_status gc_launch_from(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const double *theta,
+                         const gc_solve_params *params);
+
 /* Launch several orbits as one batch, captured once into a HIP graph: the
  * orbits are grouped by relax kernel (dimension, layout, slots per lane) and
  * each group is one chain of persistent kernel launches (relax, post,
@@ -301,6 +312,25 @@ gc_status gc_kernel_time_ms(gc_ctx *ctx, gc_orbit orbit, double *solve_ms);
  * GC_ESTATE (no completed launch). */
 gc_status gc_saturation(gc_ctx *ctx, gc_orbit orbit, int32_t n_points, const uint64_t *sample_sizes,
                         int32_t in_region_only, uint64_t *distinct_out);
+
+/* Histogram quantities and weights of gc_histogram. */
+enum { GC_HIST_X = 0,        /* x = F / (d V) of each copy */
+       GC_HIST_REL = 1 };    /* (F - F_g) / F_g, F_g the lowest F among the orbit's counted copies */
+enum { GC_HIST_COPIES = 0,   /* each distinct copy counts once */
+       GC_HIST_STARTS = 1 }; /* each copy counts its hits: the starts that reached it */
+
+/* Distributions of the minima (Sec. IV.B: the normalised distribution of the
+ * functional at the minima over orbits and samples, and the distribution of
+ * (F_i - F_g)/F_g relative to each orbit's global minimum).  For each of the
+ * n_orbits completed launches, the copies carrying every flag of
+ * require_flags (e.g. GC_FLAG_IN_REGION) are binned into n_bins equal bins
+ * on [lo, hi); counts [n_orbits][n_bins + 2] receives per orbit the
+ * underflow count, the bins, then the overflow count (caller-owned).
+ * Averages over orbits (e.g. of normalised histograms) are the caller's.
+ * Computed on the device from the compacted tables.  Errors: GC_EINVAL,
+ * GC_ESTATE (an orbit without a completed launch), GC_ENOMEM. */
+gc_status gc_histogram(gc_ctx *ctx, int32_t n_orbits, const gc_orbit *orbits, int32_t quantity, int32_t weight,
+                       uint32_t require_flags, double lo, double hi, int32_t n_bins, uint64_t *counts);
 
 /* The paper's own count of a completed launch (Sec. III): the number of
  * distinct values trunc(x * 1e8) among the converged starts within the first

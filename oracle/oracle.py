@@ -373,3 +373,43 @@ def enumerate_copies(extent, phi, start_ids, params: SolveParams, threads: int =
     conv = rec["status"] == CONVERGED
     paper_count = int(np.unique(rec["paper_X"][conv]).size)
     return dict(records=rec, table=table, paper_count=paper_count, state=g)
+
+
+# --------------------------------------------------------------------------
+# Distributions of the minima over orbits (Sec. IV.B)
+# --------------------------------------------------------------------------
+
+HIST_X, HIST_REL = 0, 1
+HIST_COPIES, HIST_STARTS = 0, 1
+
+
+def histogram(copies, dim: int, V: int, quantity: int, weight: int, require_flags: int,
+              lo: float, hi: float, n_bins: int) -> np.ndarray:
+    """Counts of one orbit's minima in n_bins equal bins of [lo, hi), with an
+    underflow count first and an overflow count last (n_bins + 2 entries).
+
+    copies: iterable of dicts with 'F', 'flags', 'hits' (a copy table's entries).
+    Only copies carrying every flag of require_flags count.  The binned value
+    is x = F / (d V) (quantity HIST_X; the functional per link, eq. (3)) or the
+    deviation from the orbit's global minimum (F - F_g) / F_g with F_g the
+    lowest F among the counted copies (quantity HIST_REL).  A copy adds 1
+    (HIST_COPIES) or its number of hits (HIST_STARTS).  A value v falls in bin
+    1 + floor(((v - lo) / (hi - lo)) * n_bins), evaluated in double precision
+    in that order and capped at the last bin; v < lo (or NaN) underflows and
+    v >= hi overflows."""
+    counted = [e for e in copies if (int(e["flags"]) & require_flags) == require_flags]
+    out = np.zeros(n_bins + 2, dtype=np.uint64)
+    if not counted:
+        return out
+    F_g = min(float(e["F"]) for e in counted)
+    for e in counted:
+        F = float(e["F"])
+        v = F / float(dim * V) if quantity == HIST_X else (F - F_g) / F_g
+        if not v >= lo:
+            b = 0
+        elif not v < hi:
+            b = n_bins + 1
+        else:
+            b = 1 + min(n_bins - 1, int(math.floor(((v - lo) / (hi - lo)) * n_bins)))
+        out[b] += int(e["hits"]) if weight == HIST_STARTS else 1
+    return out

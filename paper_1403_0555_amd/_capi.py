@@ -21,6 +21,8 @@ GC_MEAN_SQ, GC_MAX_ABS = 0, 1
 GC_START_PENDING, GC_START_CONVERGED, GC_START_NONCONVERGED, GC_START_BADNUM = 0, 1, 2, 3
 GC_FLAG_IN_REGION, GC_FLAG_SINGULAR, GC_FLAG_SADDLE, GC_FLAG_COLLISION, GC_FLAG_LANCZOS_CAP = 1, 2, 4, 8, 16
 GC_ORBIT_IDLE, GC_ORBIT_QUEUED, GC_ORBIT_RUNNING, GC_ORBIT_DONE, GC_ORBIT_ERROR = 0, 1, 2, 3, 4
+GC_HIST_X, GC_HIST_REL = 0, 1
+GC_HIST_COPIES, GC_HIST_STARTS = 0, 1
 
 EXPORTED_SYMBOLS = [
     "gc_version", "gc_status_str", "gc_lattice_check", "gc_solve_params_default",
@@ -28,6 +30,7 @@ EXPORTED_SYMBOLS = [
     "gc_launch", "gc_launch_batch", "gc_poll", "gc_wait", "gc_fetch", "gc_fetch_starts",
     "gc_fetch_state", "gc_fetch_start_state", "gc_release", "gc_last_error", "gc_kernel_time_ms", "gc_launch_bytes",
     "gc_memory_info", "gc_autotune", "gc_saturation", "gc_paper_saturation", "gc_launch_static",
+    "gc_launch_from", "gc_histogram",
 ]
 
 
@@ -126,6 +129,9 @@ def lib():
         "gc_saturation": ([vp, u64, i32, P(u64), i32, P(u64)], i32),
         "gc_paper_saturation": ([vp, u64, i32, P(u64), P(u64)], i32),
         "gc_launch_static": ([vp, u64, u64, P(gc_solve_params), vp, vp, u64, vp, vp], i32),
+        "gc_launch_from": ([vp, u64, u64, P(ctypes.c_double), P(gc_solve_params)], i32),
+        "gc_histogram": ([vp, i32, P(u64), i32, i32, ctypes.c_uint32, ctypes.c_double, ctypes.c_double, i32,
+                          P(u64)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -263,6 +269,26 @@ class Context:
     def gc_launch(self, orbit: int, n_starts: int, params: SolveParams | None = None):
         p = (params or SolveParams()).c()
         self._check(self._L.gc_launch(self._h, orbit, n_starts, ctypes.byref(p)), "gc_launch")
+
+    def gc_launch_from(self, orbit: int, theta, params: SolveParams | None = None):
+        """Launch from the caller's start angles theta [n_starts][V] (float64)."""
+        p = (params or SolveParams()).c()
+        t = np.ascontiguousarray(theta, dtype=np.float64)
+        if t.ndim != 2:
+            raise ValueError("theta must be [n_starts][V]")
+        self._check(self._L.gc_launch_from(self._h, orbit, t.shape[0],
+                                           t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(p)),
+                    "gc_launch_from")
+
+    def gc_histogram(self, orbits, lo: float, hi: float, n_bins: int, quantity: int = GC_HIST_X,
+                     weight: int = GC_HIST_COPIES, require_flags: int = 0) -> np.ndarray:
+        """Per-orbit counts [n_orbits][n_bins + 2]: underflow, bins, overflow."""
+        n = len(orbits)
+        o = (ctypes.c_uint64 * n)(*orbits)
+        out = np.zeros((n, n_bins + 2), dtype=np.uint64)
+        self._check(self._L.gc_histogram(self._h, n, o, quantity, weight, require_flags, lo, hi, n_bins,
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))), "gc_histogram")
+        return out
 
     def gc_launch_batch(self, orbits, n_starts, params: SolveParams | None = None):
         p = (params or SolveParams()).c()

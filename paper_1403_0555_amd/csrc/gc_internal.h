@@ -96,6 +96,7 @@ struct GcJobDev {
     double2 *states;                 // [n_starts][V] final g of every start, natural site order
     uint32_t *blk;                   // [(table_mask + 1) / 256] per-block copy counts, then offsets
     uint32_t *fixed_sweeps;          // [n_starts] batch-synchronous sweep counts (sync_batch > 0), else null
+    const double *theta_init;        // [n_starts][V] the caller's start angles, else null (Philox starts)
 };
 
 static_assert(sizeof(GcStartRec) == 64, "record layout");
@@ -135,6 +136,14 @@ hipError_t gc_launch_orbit_random(double *phi, int64_t n_links, uint64_t seed, u
 hipError_t gc_launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
 // Write bytes (host source, copied into kernel arguments) to device memory.
 hipError_t gc_launch_store(void *dst, const void *src, size_t bytes, hipStream_t s);
+// Per-orbit histogram of the copies of one compacted table: x = F/(dV)
+// (quantity 0) or (F - F_g)/F_g against the orbit's lowest F among the
+// counted copies (quantity 1); weight 1 per copy or its hit count; only
+// copies with all of require_flags; counts [n_bins + 2] (underflow, bins,
+// overflow), fmin_bits scratch for F_g.  Enqueued on s.
+hipError_t gc_launch_histogram(const GcCopyRec *copies, const unsigned long long *n_copies, double dV, int quantity,
+                               int weight_hits, uint32_t require_flags, double lo, double hi, int n_bins,
+                               unsigned long long *counts, unsigned long long *fmin_bits, hipStream_t s);
 // Batch-synchronous stop: per batch of sync_batch starts, the largest
 // first-pass sweep count, written per start to fixed_sweeps; relax counters
 // cleared for the second pass.

@@ -1048,6 +1048,36 @@ __global__ void sync_kernel(GcJobDev J)
     }
 }
 
+// Histograms of the minima (the distribution studies of Sec. IV.B): first the
+// lowest F among the counted copies (IEEE bits of F >= 0 order like the
+// values), then one atomic add per counted copy into its bin.
+__global__ void hist_min_kernel(const GcCopyRec *__restrict__ copies, const unsigned long long *n_copies,
+                                uint32_t require_flags, unsigned long long *fmin_bits)
+{
+    const uint64_t n = *n_copies;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (uint64_t)gridDim.x * blockDim.x)
+        if ((copies[c].flags & require_flags) == require_flags)
+            atomicMin(fmin_bits, (unsigned long long)__double_as_longlong(copies[c].F));
+}
+
+__global__ void hist_kernel(const GcCopyRec *__restrict__ copies, const unsigned long long *n_copies, double dV,
+                            int quantity, int weight_hits, uint32_t require_flags, double lo, double hi, int n_bins,
+                            unsigned long long *counts, const unsigned long long *fmin_bits)
+{
+    const uint64_t n = *n_copies;
+    const double Fg = __longlong_as_double((long long)*fmin_bits);
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (uint64_t)gridDim.x * blockDim.x) {
+        const GcCopyRec r = copies[c];
+        if ((r.flags & require_flags) != require_flags) continue;
+        const double v = quantity == 0 ? r.F / dV : (r.F - Fg) / Fg;
+        int b;
+        if (!(v >= lo)) b = 0;
+        else if (!(v < hi)) b = n_bins + 1;
+        else b = 1 + min(n_bins - 1, (int)((v - lo) / (hi - lo) * (double)n_bins));
+        atomicAdd(&counts[b], weight_hits ? (unsigned long long)r.hits : 1ULL);
+    }
+}
+
 // Bytes carried in a kernel argument and written to device memory: lets a
 // caller enqueue descriptors without host staging memory.
 constexpr size_t kStoreMax = 2048;
@@ -1327,6 +1357,18 @@ hipError_t gc_launch_store(void *dst, const void *src, size_t bytes, hipStream_t
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t gc_launch_histogram(const GcCopyRec *copies, const unsigned long long *n_copies, double dV, int quantity,
+                               int weight_hits, uint32_t require_flags, double lo, double hi, int n_bins,
+                               unsigned long long *counts, unsigned long long *fmin_bits, hipStream_t s)
+{
+    hipLaunchKernelGGL(hist_min_kernel, dim3(256), dim3(256), 0, s, copies, n_copies, require_flags, fmin_bits);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(hist_kernel, dim3(256), dim3(256), 0, s, copies, n_copies, dV, quantity, weight_hits,
+                       require_flags, lo, hi, n_bins, counts, fmin_bits);
+    return hipGetLastError();
 }
 
 hipError_t gc_launch_zero_u64(unsigned long long *p, int n, hipStream_t s)

@@ -155,13 +155,14 @@ __global__ __launch_bounds__(B) void relax_wg_kernel(const GcJobDev *__restrict_
 
         for (int b = tid; 4 * b < V; b += B) {
             uint64_t c[4];
-            start_block(J.start_seed, sid, O.orbit_index, (uint64_t)b, c);
+            // the caller's start angles, else Philox (the block is skipped then)
+            if (!J.theta_init) start_block(J.start_seed, sid, O.orbit_index, (uint64_t)b, c);
 #pragma unroll 1
             for (int k = 0; k < 4; ++k) {
                 const int i = 4 * b + k;
                 if (i < V) {
                     double sn, cs;
-                    sincos(angle_of(c[k]), &sn, &cs);
+                    sincos(J.theta_init ? J.theta_init[local * (uint64_t)V + i] : angle_of(c[k]), &sn, &cs);
                     if (J.precision == 1) st32[i] = flt2{(float)cs, (float)sn};
                     else st64[i] = dbl2{cs, sn};
                 }

@@ -239,7 +239,7 @@ struct FilterGroup {
 
 // Device memory of one job.
 struct JobLayout {
-    std::vector<size_t> o_rec, o_table, o_cnt, o_copies, o_ncopies, o_states, o_blk, o_sync;
+    std::vector<size_t> o_rec, o_table, o_cnt, o_copies, o_ncopies, o_states, o_blk, o_sync, o_theta;
     std::vector<uint64_t> table_cap;
     std::vector<Group> groups;
     std::vector<PostGroup> posts;
@@ -272,6 +272,7 @@ struct Job {
     uint64_t total = 0;
     // kernel variants forced for this job (gc_autotune trials), -1 / 0: none
     int force_creg = -1, force_wps = -1;
+    std::vector<double> theta;       // the caller's start angles [n][V] (gc_launch_from), else empty
 };
 
 struct Orbit {
@@ -624,6 +625,7 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         L.o_blk.push_back(place(sizeof(uint32_t) * ((cap + 255) / 256)));
         L.o_states.push_back(place(sizeof(double2) * n * (uint64_t)o->V));
         L.o_sync.push_back(job->p.sync_batch ? place(sizeof(uint32_t) * n) : 0);
+        L.o_theta.push_back(job->theta.empty() ? 0 : place(sizeof(double) * n * (uint64_t)o->V));
         // two colours: one wavefront per start (GC_WAVES states per
         // workgroup in LDS) up to 128 slots per colour, a workgroup of wps
         // wavefronts per start above; other colourings take the generic
@@ -880,6 +882,7 @@ void fill_job_devs(Job *job, unsigned char *base)
         J.blk = (uint32_t *)(base + L.o_blk[j]);
         J.sync_batch = job->p.sync_batch;
         J.fixed_sweeps = job->p.sync_batch ? (uint32_t *)(base + L.o_sync[j]) : nullptr;
+        J.theta_init = job->theta.empty() ? nullptr : (const double *)(base + L.o_theta[j]);
     }
 }
 
@@ -898,6 +901,7 @@ std::vector<Blob> job_blobs(Job *job)
     auto add_blob = [&](size_t dst, const void *src, size_t bytes) {
         blobs.push_back(Blob{dst, std::vector<unsigned char>((const unsigned char *)src, (const unsigned char *)src + bytes)});
     };
+    if (!job->theta.empty()) add_blob(L.o_theta[0], job->theta.data(), sizeof(double) * job->theta.size());
     for (const FilterGroup &fg : L.filters) {
         std::vector<GcJobDev> fj;
         for (int j : fg.jobs) fj.push_back(job->jobs[j]);
@@ -1765,6 +1769,71 @@ gc_status gc_launch(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_sol
     Orbit *o = find_orbit(ctx, orbit);
     if (!o) return GC_EINVAL;
     return launch_locked(ctx, {o}, {n_starts}, p, false, nullptr);
+}
+
+gc_status gc_launch_from(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const double *theta,
+                         const gc_solve_params *params)
+{
+    gc_solve_params p;
+    if (params) p = *params; else fill_defaults(&p);
+    gc_status st = check_params(&p);
+    if (st != GC_OK) return st;
+    if (n_starts == 0 || n_starts > (1ull << 32) || !theta) return GC_EINVAL;
+    GC_ENTER(ctx);
+    Orbit *o = find_orbit(ctx, orbit);
+    if (!o) return GC_EINVAL;
+    const size_t n = (size_t)n_starts * (size_t)o->V;
+    for (size_t k = 0; k < n; ++k)
+        if (!std::isfinite(theta[k])) return GC_EINVAL;
+    for (Orbit *x : {o})
+        if (x->job && (x->job->state == GC_ORBIT_QUEUED || x->job->state == GC_ORBIT_RUNNING)) return GC_EBUSY;
+    Job *job = new Job;
+    job->orbits.push_back(o);
+    job->n_starts.push_back(n_starts);
+    job->p = p;
+    job->theta.assign(theta, theta + n);
+    st = enqueue_locked(ctx, job);
+    if (st != GC_OK) delete job;
+    return st;
+}
+
+gc_status gc_histogram(gc_ctx *ctx, int32_t n_orbits, const gc_orbit *orbits, int32_t quantity, int32_t weight,
+                       uint32_t require_flags, double lo, double hi, int32_t n_bins, uint64_t *counts)
+{
+    if (n_orbits < 1 || !orbits || !counts || n_bins < 1 || n_bins > (1 << 24) || !(hi > lo) ||
+        !std::isfinite(lo) || !std::isfinite(hi) || (quantity != GC_HIST_X && quantity != GC_HIST_REL) ||
+        (weight != GC_HIST_COPIES && weight != GC_HIST_STARTS))
+        return GC_EINVAL;
+    GC_ENTER(ctx);
+    std::vector<Orbit *> os;
+    for (int32_t k = 0; k < n_orbits; ++k) {
+        Orbit *o = find_orbit(ctx, orbits[k]);
+        if (!o) return GC_EINVAL;
+        if (!o->job || o->job->state != GC_ORBIT_DONE) return GC_ESTATE;
+        os.push_back(o);
+    }
+    const size_t per = (size_t)n_bins + 2;
+    void *blk = nullptr;
+    size_t got = 0;
+    gc_status st = pool_get(ctx, sizeof(unsigned long long) * (per * n_orbits + n_orbits), &blk, &got);
+    if (st != GC_OK) return st;
+    unsigned long long *cnt = (unsigned long long *)blk, *fmin = cnt + per * n_orbits;
+    hipStream_t s = ctx->util;
+    hipError_t e = gc_launch_zero_u64(cnt, (int)(per * n_orbits), s);
+    const unsigned long long inf_bits = ~0ULL;
+    for (int32_t k = 0; k < n_orbits && e == hipSuccess; ++k) {
+        e = gc_launch_store(fmin + k, &inf_bits, sizeof inf_bits, s);
+        if (e != hipSuccess) break;
+        const Orbit *o = os[k];
+        e = gc_launch_histogram(o->res.copies, o->res.n_copies, (double)o->d * (double)o->V, quantity,
+                                weight == GC_HIST_STARTS, require_flags, lo, hi, n_bins, cnt + per * k, fmin + k, s);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(counts, cnt, sizeof(unsigned long long) * per * n_orbits, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    ctx->pool.put(blk, got);
+    if (e != hipSuccess) return fail(ctx, e, "gc_histogram");
+    return GC_OK;
 }
 
 gc_status gc_launch_batch(gc_ctx *ctx, int32_t n_orbits, const gc_orbit *orbits, const uint64_t *n_starts,

@@ -298,13 +298,14 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 
     // random start, written at its colour-split position loc[i]
     for (int b = lane; 4 * b < V; b += T) {
         uint64_t c[4];
-        start_block(J.start_seed, sid, O.orbit_index, (uint64_t)b, c);
+        // the caller's start angles, else Philox (the block is skipped then)
+        if (!J.theta_init) start_block(J.start_seed, sid, O.orbit_index, (uint64_t)b, c);
 #pragma unroll 1
         for (int k = 0; k < 4; ++k) {
             const int i = 4 * b + k;
             if (i < V) {
                 double sn, cs;
-                sincos(angle_of(c[k]), &sn, &cs);
+                sincos(J.theta_init ? J.theta_init[local * (uint64_t)V + i] : angle_of(c[k]), &sn, &cs);
                 const int p = WO.loc[i];
                 if (J.precision == 1) st32[p] = flt2{(float)cs, (float)sn};
                 else st64[p] = dbl2{cs, sn};

@@ -14,7 +14,9 @@ import sys
 import numpy as np
 import pytest
 
+import gribov_inputs as GI
 import paper_1403_0555_amd as gc
+from oracle import oracle as O
 
 pytestmark = pytest.mark.gpu
 
@@ -83,3 +85,66 @@ def test_distinct_minima_match_table_i_at_plateau():
     ok, info = _agrees(counts, row)
     note(f"  ours {info[0]:.1f} +- {info[1]:.1f}, paper {info[2]} +- {info[3]}, bound {info[4]:.1f}")
     assert ok, info
+
+
+# ---------------------------------------------------------------------------
+# Distributions of the minima (Sec. IV.B) computed on the device
+# ---------------------------------------------------------------------------
+
+def _copy_dicts(c):
+    return [dict(F=float(r["F"]), flags=int(r["flags"]), hits=int(r["hits"])) for r in c]
+
+
+HIST_CASES = [(gc.GC_HIST_X, gc.GC_HIST_COPIES, 0, 0.0, 0.5, 50),
+              (gc.GC_HIST_X, gc.GC_HIST_STARTS, gc.GC_FLAG_IN_REGION, 0.1, 0.4, 300),
+              (gc.GC_HIST_REL, gc.GC_HIST_COPIES, gc.GC_FLAG_IN_REGION, 0.0, 0.6, 60),
+              (gc.GC_HIST_REL, gc.GC_HIST_STARTS, 0, 0.01, 0.3, 7)]
+
+
+@pytest.mark.parametrize("extent,n_orbits,n_starts", [((4, 4), 120, 3000), ((6, 6), 100, 20000),
+                                                      ((4, 4, 4), 100, 20000)])
+def test_histograms_of_many_orbits(extent, n_orbits, n_starts):
+    """gc_histogram over >= 100 orbits of one batch equals the oracle's
+    histogram definition applied to each orbit's fetched copies (same values,
+    same bins: exact counts), and on the smallest lattice equals it applied to
+    the oracle's own copy tables of the same orbits."""
+    note(f"histograms {extent}: {n_orbits} orbits x {n_starts} starts")
+    d, V = len(extent), int(np.prod(extent))
+    params = gc.SolveParams(omega=1.0)
+    with gc.Context(0) as ctx:
+        hs = [ctx.gc_orbit_random(extent, ORBIT_SEED, oi) for oi in range(n_orbits)]
+        ctx.gc_launch_batch(hs, [n_starts] * n_orbits, params)
+        for h in hs:
+            assert ctx.gc_wait(h) == gc.GC_OK
+        fetched = [_copy_dicts(ctx.gc_fetch(h)) for h in hs]
+        for q, w, req, lo, hi, nb in HIST_CASES:
+            got = ctx.gc_histogram(hs, lo, hi, nb, quantity=q, weight=w, require_flags=req)
+            want = np.stack([O.histogram(c, d, V, q, w, req, lo, hi, nb) for c in fetched])
+            assert np.array_equal(got, want), (q, w, req)
+            n_counted = [sum((e["flags"] & req) == req for e in c) for c in fetched]
+            if w == gc.GC_HIST_COPIES:
+                assert np.array_equal(got.sum(axis=1), n_counted)
+        if extent == (4, 4):
+            # the oracle's own tables: same copies, F within 1e-10 per site, so
+            # a count may move only where a value lies that close to a bin edge
+            for oi in range(10):
+                phi = GI.orbit_angles(extent, ORBIT_SEED, oi)
+                tab = O.enumerate_copies(extent, phi, np.arange(n_starts),
+                                         O.SolveParams(omega=1.0, orbit_index=oi))["table"]
+                for q, w, req, lo, hi, nb in HIST_CASES:
+                    want = O.histogram(tab.values(), d, V, q, w, req, lo, hi, nb)
+                    got = ctx.gc_histogram([hs[oi]], lo, hi, nb, quantity=q, weight=w, require_flags=req)[0]
+                    if not np.array_equal(got, want):
+                        width = (hi - lo) / nb
+                        Fg = min(e["F"] for e in tab.values() if (e["flags"] & req) == req)
+                        vals = [e["F"] / (d * V) if q == gc.GC_HIST_X else (e["F"] - Fg) / Fg
+                                for e in tab.values()]
+                        near = [v for v in vals if abs((v - lo) / width - round((v - lo) / width)) < 1e-8]
+                        assert near, (oi, q, w, got, want)
+        # errors
+        with pytest.raises(gc.GcError):
+            ctx.gc_histogram(hs[:1], 1.0, 0.0, 10)
+        h_new = ctx.gc_orbit_random(extent, ORBIT_SEED, 999)
+        with pytest.raises(gc.GcError) as e:
+            ctx.gc_histogram([h_new], 0.0, 1.0, 10)
+        assert e.value.status == gc.GC_ESTATE

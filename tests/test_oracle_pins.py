@@ -567,3 +567,25 @@ def test_sync_batch_runs_each_batch_to_its_slowest_start():
     assert np.max(np.abs(rs["F"] - own["F"])) < 1e-10
     longer = rs["sweeps64"] > own["sweeps64"]
     assert longer.any() and np.all(rs["D"][longer] <= own["D"][longer])
+
+
+def test_histogram_definition_by_hand():
+    """Sec. IV.B distributions on a four-copy table worked by hand: x = F/(dV)
+    with d = 2, V = 1 gives 0.5, 1.0, 1.75, 5.0; the relative deviation against
+    the lowest counted F."""
+    tab = [dict(F=1.0, flags=1, hits=5), dict(F=2.0, flags=1, hits=1),
+           dict(F=3.5, flags=0, hits=2), dict(F=10.0, flags=1, hits=3)]
+    H = lambda q, w, req, lo, hi, nb: list(O.histogram(tab, 2, 1, q, w, req, lo, hi, nb))
+    X, REL, CP, ST = O.HIST_X, O.HIST_REL, O.HIST_COPIES, O.HIST_STARTS
+    # bins of width 0.5 on [0, 2): 0.5 -> second bin, 1.0 -> third, 1.75 -> fourth, 5.0 over
+    assert H(X, CP, 0, 0.0, 2.0, 4) == [0, 0, 1, 1, 1, 1]
+    assert H(X, CP, 1, 0.0, 2.0, 4) == [0, 0, 1, 1, 0, 1]
+    assert H(X, ST, 1, 0.0, 2.0, 4) == [0, 0, 5, 1, 0, 3]
+    # underflow below lo
+    assert H(X, CP, 0, 0.6, 2.0, 2) == [1, 1, 1, 1]
+    # relative: F_g = 1 gives 0, 1, (2.5), 9
+    assert H(REL, CP, 1, 0.0, 2.0, 2) == [0, 1, 1, 1]
+    assert H(REL, CP, 0, 0.0, 2.0, 2) == [0, 1, 1, 2]
+    assert H(REL, ST, 0, 0.0, 4.0, 2) == [0, 6, 2, 3]
+    # the lowest counted copy defines F_g: require a flag nobody has -> empty
+    assert H(REL, CP, 2, 0.0, 1.0, 3) == [0, 0, 0, 0, 0]
