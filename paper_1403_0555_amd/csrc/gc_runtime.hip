@@ -494,26 +494,25 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
             site[(size_t)col[i] * half + (i >> 1)] = i;
         }
         std::vector<uint16_t> nb((size_t)2 * half * 8, 0);
-        std::vector<uint32_t> desc((size_t)2 * half, 0);
         std::vector<double2> c64((size_t)2 * 2 * d * half);
         std::vector<float2> c32((size_t)2 * 2 * d * half);
+        const bool scaled = 16 * (size_t)half <= 0xFFFF;
+        std::vector<uint16_t> nbo(scaled ? (size_t)2 * half * 8 : 0, 0);
+        std::vector<double2> l64((size_t)2 * d * half);
+        std::vector<float2> l32((size_t)2 * d * half);
         for (int c = 0; c < 2; ++c)
             for (int h = 0; h < half; ++h) {
                 const int i = site[(size_t)c * half + h];
-                uint32_t dw = (uint32_t)i;
-                for (int mu = 0; mu < d; ++mu) {
-                    const int x = coord[(size_t)i * d + mu];
-                    if (x == n[mu] - 1) dw |= 1u << (12 + mu);
-                    if (x == 0) dw |= 1u << (16 + mu);
-                }
-                desc[(size_t)c * half + h] = dw;
                 for (int k = 0; k < 2 * d; ++k) {
                     const int mu = k < d ? k : k - d;
                     const int nsite = k < d ? nbr[(size_t)mu * V + i] : nbr[(size_t)(d + mu) * V + i];
                     nb[((size_t)c * half + h) * 8 + k] = (uint16_t)(nsite >> 1);
+                    if (scaled) nbo[((size_t)c * half + h) * 8 + k] = (uint16_t)(16 * (nsite >> 1));
                     double2 u;
                     if (k < d) {
                         u = U64[(size_t)mu * V + i];
+                        l64[((size_t)c * d + mu) * half + h] = u;
+                        l32[((size_t)c * d + mu) * half + h] = make_float2((float)u.x, (float)u.y);
                     } else {
                         u = U64[(size_t)mu * V + nsite];
                         u.y = -u.y;
@@ -525,13 +524,16 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
         size_t woff = 0;
         auto wplace = [&](size_t bytes) { size_t at = woff; woff = align_up(woff + bytes, 256); return at; };
         const size_t w_loc = wplace(loc.size() * 2), w_nb = wplace(nb.size() * 2), w_c64 = wplace(c64.size() * 16),
-                     w_c32 = wplace(c32.size() * 8), w_desc = wplace(desc.size() * 4);
+                     w_c32 = wplace(c32.size() * 8),
+                     w_nbo = wplace(nbo.size() * 2), w_l64 = wplace(l64.size() * 16), w_l32 = wplace(l32.size() * 8);
         std::vector<unsigned char> wh(woff, 0);
         memcpy(&wh[w_loc], loc.data(), loc.size() * 2);
         memcpy(&wh[w_nb], nb.data(), nb.size() * 2);
         memcpy(&wh[w_c64], c64.data(), c64.size() * 16);
         memcpy(&wh[w_c32], c32.data(), c32.size() * 8);
-        memcpy(&wh[w_desc], desc.data(), desc.size() * 4);
+        if (scaled) memcpy(&wh[w_nbo], nbo.data(), nbo.size() * 2);
+        memcpy(&wh[w_l64], l64.data(), l64.size() * 16);
+        memcpy(&wh[w_l32], l32.data(), l32.size() * 8);
         void *wdevmem = nullptr;
         GC_HIP(ctx->pool.get(woff, &wdevmem, &got));
         o->wave_tables = wdevmem;
@@ -543,7 +545,9 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
         o->wdev.nb = (const uint4 *)(wb + w_nb);
         o->wdev.coef64 = (const double2 *)(wb + w_c64);
         o->wdev.coef32 = (const float2 *)(wb + w_c32);
-        o->wdev.desc = (const uint32_t *)(wb + w_desc);
+        o->wdev.nbo = scaled ? (const uint4 *)(wb + w_nbo) : nullptr;
+        o->wdev.link64 = (const double2 *)(wb + w_l64);
+        o->wdev.link32 = (const float2 *)(wb + w_l32);
     }
     return GC_OK;
 }
@@ -591,12 +595,12 @@ void give_event(gc_ctx *ctx, hipEvent_t &e, bool timing)
 // lane (orbits of one bucket share a kernel).
 int ns_bucket(int d, int ns)
 {
-    static const int b1[] = {1, 4, 12, 32}, b2[] = {1, 2, 4, 12, 32}, b3[] = {2, 4, 8, 32}, b4[] = {1, 2, 4, 11, 32};
+    static const int b1[] = {1, 4, 12, 16}, b2[] = {1, 2, 4, 12, 16}, b3[] = {2, 4, 8, 16}, b4[] = {1, 2, 4, 11, 16};
     const int *b = d == 1 ? b1 : d == 2 ? b2 : d == 3 ? b3 : b4;
     const int nb = d == 1 ? 4 : d == 2 ? 5 : d == 3 ? 4 : 5;
     for (int k = 0; k < nb; ++k)
         if (ns <= b[k]) return b[k];
-    return 32;
+    return 16;
 }
 
 // Layout of a job's device block and its launch groups.  Each orbit runs the
@@ -680,8 +684,11 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
                 const Orbit *o = job->orbits[j];
                 coef_bytes = std::max(coef_bytes, (size_t)2 * o->d * o->V * (mixed ? 24 : 16));
             }
-            const size_t states = (size_t)GC_WAVES * 16 * gV + (g.ns <= 2 ? 16 * (size_t)gV : 0);   // + neighbour table
-            g.coef_lds = (coef_bytes + states <= 64 * 1024) ? 1 : 0;
+            // states + neighbour table + links staged in LDS
+            const size_t states = (size_t)(GC_WAVES + 1 + gc_links_in_lds(g.d, ns_bucket(g.d, g.ns))) * 16 * gV;
+            // a staged coefficient table only where a lane has at most two
+            // slots; above, the links are read through buffer loads
+            g.coef_lds = (g.ns <= 2 && coef_bytes + states <= 64 * 1024) ? 1 : 0;
             g.lds = states + (g.coef_lds ? coef_bytes : 0);
             if (g.lds > ctx->lds_max) return GC_EUNSUPPORTED;
             // colour-0 coefficients in registers where a lane has at most two

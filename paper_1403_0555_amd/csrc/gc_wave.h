@@ -8,14 +8,35 @@ struct GcWaveOrbit {
     int32_t half, pad;              // V / 2
     const uint16_t *loc;            // [V] site -> c * half + h
     const uint4 *nb;                // [2][half] neighbour half indices, 8 x u16 (forward mu, then backward)
-    const uint32_t *desc;           // [2][half] site i | forward-wrap bits << 12 | backward-wrap bits << 16
     const double2 *coef64;          // [2][2d][half] U_{i,k} (forward) / conj(U_{i-k,k}) (backward)
     const float2 *coef32;           // same, rounded to single precision
+    // Lattices with more than two slots per lane and colour: the neighbour
+    // table with each half index scaled to a byte offset (16 h, the
+    // double2 stride; null when 16 half > 65535) and the links once each,
+    // U_{i,mu} of the site (c, h) at [c][mu][half]: the backward
+    // coefficient of a site is the conjugate of its backward neighbour's
+    // forward link.
+    const uint4 *nbo;               // [2][half] 8 x u16 byte offsets 16 h (forward mu, then backward)
+    const double2 *link64;          // [2][d][half]
+    const float2 *link32;           // same, rounded to single precision
 };
 
 // Wavefronts per workgroup of the wave kernel; each needs V float2 of
 // private scratch for the single-to-double promotion.
 constexpr int GC_WAVES = 4;
+
+// Kernels with more than two slots per lane (ns > 2) stage the links of
+// their first gc_links_in_lds(d, ns) directions (both colours, double
+// precision, 16 V bytes per direction) in LDS beside the neighbour table and
+// the GC_WAVES states: as many as fit in 160 KiB for the largest lattice of
+// the instantiated slot count (half <= 64 ns).
+constexpr int gc_links_in_lds(int d, int ns)
+{
+    const long V = 128L * ns;
+    const long room = 160L * 1024 - (long)(GC_WAVES + 1) * 16 * V;
+    const long dl = (ns > 2 && room > 0) ? room / (16 * V) : 0;
+    return dl < d ? (int)dl : d;
+}
 
 // variant = coef_lds | creg << 1: coefficient table staged in LDS (else
 // read from global memory) and the number of colours (0..2) whose

@@ -42,24 +42,29 @@ struct NbWords {
     }
 };
 
-// ... or from its descriptor (site index | forward-wrap bits << 12 |
-// backward-wrap bits << 16) and the lattice strides s_mu, wraps N_mu s_mu.
-template <int D> struct Strides {
-    int s[D], w[D];
-};
-template <int D> struct NbDesc {
-    uint32_t dsc;
-    const Strides<D> &L;
-    __device__ __forceinline__ uint32_t operator()(int k) const
-    {
-        const int i = (int)(dsc & 0xFFFu);
-        const int mu = k < D ? k : k - D;
-        int j;
-        if (k < D) j = i + L.s[mu] - (((dsc >> (12 + mu)) & 1u) ? L.w[mu] : 0);
-        else j = i - L.s[mu] + (((dsc >> (16 + mu)) & 1u) ? L.w[mu] : 0);
-        return (uint32_t)(j >> 1);
-    }
-};
+// Raw buffer access to a link table: the per-lane byte offset in a VGPR,
+// the wave-uniform plane offset in an SGPR, no address arithmetic on the
+// vector unit.  Reads past the table's end return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename C> __device__ __forceinline__ C buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ dbl2 buffer_load<dbl2>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ flt2 buffer_load<flt2>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(flt2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+// Byte offset of neighbour k in a scaled table entry (16 h per neighbour).
+__device__ __forceinline__ uint32_t nb_off(const u32x4 &w, int k)
+{
+    const uint32_t word = (k >> 1) == 0 ? w.x : (k >> 1) == 1 ? w.y : (k >> 1) == 2 ? w.z : w.w;
+    return (k & 1) ? (word >> 16) : (word & 0xFFFFu);
+}
 
 // S = sum_k coef_k g_{n_k}, forward mu = 0..d-1 then backward, as in the
 // coefficient table, each complex product accumulated by four FMAs.  The
@@ -126,19 +131,27 @@ template <int WPS> __device__ __forceinline__ double start_max(double v, double 
 // Sweeps of one precision on the wave's state st[2][half].  Returns status.
 // Lane l owns slots h = l + 64k, k < NS, of each colour; slots beyond the
 // half volume are computed on a clamped index and discarded, so the passes
-// have no divergent branches.  For NS <= 2 the packed neighbour entries of
-// the lane's slots are held in registers (from the LDS copy nbt of the
-// table); otherwise they are recomputed from the slot descriptors.  CREG
-// colours (0, 1 or 2, starting with colour 0) keep the coefficients of the
-// lane's slots in registers for the whole phase.
+// have no divergent branches.  Two variants share the sweep schedule below:
+//
+// * NS <= 2 (relax_wave_t): the packed neighbour entries and the lane's own
+//   values are held in registers, and CREG colours (0, 1 or 2, starting with
+//   colour 0) keep the coefficients of the lane's slots in registers for the
+//   whole phase;
+// * NS > 2 (relax_wave_big): each slot reads its scaled neighbour entry from
+//   the LDS table nbt, and its 2d coefficients from the link table through
+//   buffer loads (forward: its own links; backward: the conjugated forward
+//   links of its backward neighbours, at the neighbour's table offset).
+//
+// Colour 0 of sweep t + 1 first reads the colour-0 staples of the state
+// after sweep t; at a check point they complete the norm of sweep t.
 template <int D, typename R, int NS, bool RELAX, int CREG, int WPS, typename CP>
 __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<const u32x4> nbt,
                             lds_ptr<typename cx<R>::T> st, double eps, uint64_t cap, bool fixed, uint64_t &sweeps,
                             double &D_out, double *red)
 {
+    static_assert(NS <= 2, "register-held neighbour entries");
     const int half = WO.half;
     using C = typename cx<R>::T;
-    constexpr bool NB_REG = NS <= 2;
     // thread index within the start: the lane, or the workgroup thread when
     // WPS wavefronts share the start
     const int lane = WPS > 1 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
@@ -156,31 +169,14 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
         valid[k] = h < half;
         hs[k] = valid[k] ? h : half - 1;
     }
-    u32x4 nr[NB_REG ? 2 : 1][NB_REG ? NS : 1];
-    C own[NB_REG ? 2 : 1][NB_REG ? NS : 1];   // the lane's own sites (NB_REG): LDS is only written
-    uint32_t d0[NB_REG ? 1 : NS], d1[NB_REG ? 1 : NS];
-    Strides<D> L;
-    if constexpr (NB_REG) {
+    u32x4 nr[2][NS];
+    C own[2][NS];   // the lane's own sites: LDS is only written
 #pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            nr[0][k] = nbt[hs[k]];
-            nr[1][k] = nbt[half + hs[k]];
-            own[0][k] = st0[hs[k]];
-            own[1][k] = st1[hs[k]];
-        }
-    } else {
-        int str = 1;
-#pragma unroll
-        for (int mu = 0; mu < D; ++mu) {
-            L.s[mu] = str;
-            L.w[mu] = str * J.orb.ext[mu];
-            str *= J.orb.ext[mu];
-        }
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            d0[k] = WO.desc[hs[k]];
-            d1[k] = WO.desc[half + hs[k]];
-        }
+    for (int k = 0; k < NS; ++k) {
+        nr[0][k] = nbt[hs[k]];
+        nr[1][k] = nbt[half + hs[k]];
+        own[0][k] = st0[hs[k]];
+        own[1][k] = st1[hs[k]];
     }
     constexpr int NCR = CREG > 0 ? CREG : 1;
     C cr[NCR][NS][2 * D];
@@ -200,8 +196,6 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
     int status = GC_ST_NONCONVERGED;
     D_out = INFINITY;
     for (;;) {
-        // sweep t + 1 first reads the colour-0 staples of the state after
-        // sweep t; at a check point they complete the norm of sweep t
         const bool pending = (t > 0) && ckpt;
         const bool last = (t == cap);
         // an opaque offset keeps per-slot index arithmetic inside the sweep
@@ -211,12 +205,8 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             const int h = hs[k] + z;
-            C s;
-            if constexpr (NB_REG) s = staple<D, R, (CREG >= 1)>(cr[0][k], coef, st1, NbWords{nr[0][k]}, 0, h, half);
-            else s = staple<D, R, (CREG >= 1)>(cr[0][k], coef, st1, NbDesc<D>{d0[k] + (uint32_t)z, L}, 0, h, half);
-            C g0;
-            if constexpr (NB_REG) g0 = own[0][k];
-            else g0 = st0[h];
+            const C s = staple<D, R, (CREG >= 1)>(cr[0][k], coef, st1, NbWords{nr[0][k]}, 0, h, half);
+            const C g0 = own[0][k];
             const double dv = (double)(g0.x * s.y - g0.y * s.x);
             const double a = maxabs ? fmax(acc0, fabs(dv)) : acc0 + dv * dv;
             acc0 = valid[k] ? a : acc0;
@@ -237,7 +227,7 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
         if (last) break;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            if constexpr (NB_REG) own[0][k] = gnew[k];
+            own[0][k] = gnew[k];
             if (valid[k]) st0[hs[k]] = gnew[k];
         }
         start_sync<WPS>();
@@ -251,17 +241,149 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             const int h = hs[k] + z;
-            C s;
-            if constexpr (NB_REG)
-                s = staple<D, R, (CREG >= 2)>(cr[NCR - 1][k], coef, st0, NbWords{nr[NB_REG ? 1 : 0][k]}, 1, h, half);
-            else
-                s = staple<D, R, (CREG >= 2)>(cr[NCR - 1][k], coef, st0, NbDesc<D>{d1[k] + (uint32_t)z, L}, 1, h,
-                                              half);
-            C g1;
-            if constexpr (NB_REG) g1 = own[NB_REG ? 1 : 0][k];
-            else g1 = st1[h];
-            const C g = local_update<RELAX, R>(g1, s, omega);
-            if constexpr (NB_REG) own[NB_REG ? 1 : 0][k] = g;
+            const C s = staple<D, R, (CREG >= 2)>(cr[NCR - 1][k], coef, st0, NbWords{nr[1][k]}, 1, h, half);
+            const C g = local_update<RELAX, R>(own[1][k], s, omega);
+            own[1][k] = g;
+            if (valid[k]) st1[hs[k]] = g;
+            const double dv = (double)(g.x * s.y - g.y * s.x);
+            const double a = maxabs ? fmax(a1, fabs(dv)) : a1 + dv * dv;
+            a1 = valid[k] ? a : a1;
+        }
+        if (chk) part1 = a1;
+        start_sync<WPS>();
+    }
+    sweeps = t;
+    return status;
+}
+
+template <int D, int NS> constexpr int links_in_lds() { return gc_links_in_lds(D, NS); }
+
+// Staple of slot h of colour COL from the scaled table entry w: forward
+// mu = 0..d-1 then backward, each complex product by four FMAs in the order
+// of staple() (a backward coefficient is conj(U), negated exactly).  Table
+// offsets are byte offsets of 16-byte sites; the state and the global links
+// of single precision have 8-byte sites, hence the shift.  Links of
+// directions mu < DL come from LDS (lnk, double precision, rounded to
+// single precision in the single-precision phase: the same values as the
+// single-precision table), the others through buffer loads.
+template <int D, int DL, typename R, int COL>
+__device__ __forceinline__ typename cx<R>::T staple_big(const u32x4 w, lds_ptr<const unsigned char> other,
+                                                        lds_ptr<const unsigned char> lnk, uint32_t hb,
+                                                        __amdgpu_buffer_rsrc_t links, uint32_t vo, uint32_t plane,
+                                                        uint32_t lplane)
+{
+    using C = typename cx<R>::T;
+    constexpr int SH = sizeof(C) == 16 ? 0 : 1;
+    R ax = 0, ay = 0;
+#pragma unroll
+    for (int k = 0; k < 2 * D; ++k) {
+        const int mu = k < D ? k : k - D;
+        const uint32_t raw = nb_off(w, k);
+        const uint32_t off = raw >> SH;
+        const C g = *(lds_ptr<const C>)(other + off);
+        C u;
+        if (mu < DL) {
+            // [c][mu][half] planes of lplane bytes: own slot (hb = 16 h) or
+            // the backward neighbour (raw = 16 h')
+            const int c = k < D ? COL : 1 - COL;
+            const dbl2 v = *(lds_ptr<const dbl2>)(lnk + (uint32_t)(c * DL + mu) * lplane + (k < D ? hb : raw));
+            u.x = (R)v.x;
+            u.y = (R)v.y;
+        } else if (k < D) {
+            u = buffer_load<C>(links, vo, (uint32_t)(COL * D + mu) * plane);
+        } else {
+            u = buffer_load<C>(links, off, (uint32_t)((1 - COL) * D + mu) * plane);
+        }
+        if (k >= D) u.y = -u.y;
+        ax = fma(u.x, g.x, ax);
+        ax = fma(-u.y, g.y, ax);
+        ay = fma(u.x, g.y, ay);
+        ay = fma(u.y, g.x, ay);
+    }
+    C s;
+    s.x = ax;
+    s.y = ay;
+    return s;
+}
+
+template <int D, typename R, int NS, bool RELAX, int WPS>
+__device__ int relax_wave_big(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t links, lds_ptr<const dbl2> lnk,
+                              lds_ptr<const u32x4> nbt, lds_ptr<typename cx<R>::T> st, double eps, uint64_t cap,
+                              bool fixed, uint64_t &sweeps, double &D_out, double *red)
+{
+    constexpr int DL = links_in_lds<D, NS>();
+    lds_ptr<const unsigned char> lb = (lds_ptr<const unsigned char>)lnk;
+    const uint32_t lplane = (uint32_t)half * 16u;
+    using C = typename cx<R>::T;
+    const int lane = WPS > 1 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+    lds_ptr<C> st0 = st;
+    lds_ptr<C> st1 = st + half;
+    lds_ptr<const unsigned char> b0 = (lds_ptr<const unsigned char>)st0;
+    lds_ptr<const unsigned char> b1 = (lds_ptr<const unsigned char>)st1;
+    const uint32_t plane = (uint32_t)half * (uint32_t)sizeof(C);   // bytes of one (colour, mu) link plane
+    const R omega = (R)J.omega;
+    const uint64_t check = fixed ? cap : J.check_every > 0 ? (uint64_t)J.check_every : 1;
+    const bool maxabs = J.stop_norm != 0;
+    int hs[NS];
+    bool valid[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const int h = lane + 64 * WPS * k;
+        valid[k] = h < half;
+        hs[k] = valid[k] ? h : half - 1;
+    }
+
+    uint64_t t = 0;
+    uint64_t until = check;
+    bool ckpt = false;
+    double part1 = 0.0;
+    int status = GC_ST_NONCONVERGED;
+    D_out = INFINITY;
+    for (;;) {
+        const bool pending = (t > 0) && ckpt;
+        const bool last = (t == cap);
+        const int z = opaque_zero();
+        C gnew[NS];
+        double acc0 = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const int h = hs[k] + z;
+            const C s = staple_big<D, DL, R, 0>(nbt[h], b1, lb, (uint32_t)h * 16u, links,
+                                                (uint32_t)h * (uint32_t)sizeof(C), plane, lplane);
+            const C g0 = st0[h];
+            const double dv = (double)(g0.x * s.y - g0.y * s.x);
+            const double a = maxabs ? fmax(acc0, fabs(dv)) : acc0 + dv * dv;
+            acc0 = valid[k] ? a : acc0;
+            gnew[k] = local_update<RELAX, R>(g0, s, omega);
+        }
+        if (pending) {
+            double Dn;
+            if (maxabs) Dn = start_max<WPS>(fmax(acc0, part1), red);
+            else Dn = start_sum<WPS>(acc0 + part1, red) / (double)(2 * half);
+            D_out = Dn;
+            if (!(Dn == Dn)) { status = GC_ST_BADNUM; break; }
+            if (Dn < eps) {
+                status = GC_ST_CONVERGED;
+                if (!fixed) break;
+            }
+        }
+        if (last) break;
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+            if (valid[k]) st0[hs[k]] = gnew[k];
+        start_sync<WPS>();
+        ++t;
+        --until;
+        ckpt = (until == 0) || (t == cap);
+        if (until == 0) until = check;
+        const bool chk = ckpt;
+        double a1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const int h = hs[k] + z;
+            const C s = staple_big<D, DL, R, 1>(nbt[half + h], b0, lb, (uint32_t)h * 16u, links,
+                                                (uint32_t)h * (uint32_t)sizeof(C), plane, lplane);
+            const C g = local_update<RELAX, R>(st1[h], s, omega);
             if (valid[k]) st1[hs[k]] = g;
             const double dv = (double)(g.x * s.y - g.y * s.x);
             const double a = maxabs ? fmax(a1, fabs(dv)) : a1 + dv * dv;
@@ -275,17 +397,29 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
 }
 
 template <int D, typename R, int NS, int CREG, int WPS, typename CP>
-__device__ int relax_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<const u32x4> nbt,
-                          lds_ptr<typename cx<R>::T> st, double eps, uint64_t cap, bool fixed, uint64_t &sweeps,
-                          double &D_out, double *red)
+__device__ int relax_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<const dbl2> lnk,
+                          lds_ptr<const u32x4> nbt, lds_ptr<typename cx<R>::T> st, double eps, uint64_t cap,
+                          bool fixed, uint64_t &sweeps, double &D_out, double *red)
 {
-    if ((R)J.omega == (R)1)
-        return relax_wave_t<D, R, NS, true, CREG, WPS>(J, WO, coef, nbt, st, eps, cap, fixed, sweeps, D_out, red);
-    return relax_wave_t<D, R, NS, false, CREG, WPS>(J, WO, coef, nbt, st, eps, cap, fixed, sweeps, D_out, red);
+    if constexpr (NS > 2) {
+        const uint32_t bytes = (uint32_t)(2 * D * WO.half * sizeof(typename cx<R>::T));
+        const __amdgpu_buffer_rsrc_t links =
+            buffer_rsrc(sizeof(R) == 8 ? (const void *)WO.link64 : (const void *)WO.link32, bytes);
+        if ((R)J.omega == (R)1)
+            return relax_wave_big<D, R, NS, true, WPS>(J, WO.half, links, lnk, nbt, st, eps, cap, fixed, sweeps,
+                                                       D_out, red);
+        return relax_wave_big<D, R, NS, false, WPS>(J, WO.half, links, lnk, nbt, st, eps, cap, fixed, sweeps, D_out,
+                                                    red);
+    } else {
+        if ((R)J.omega == (R)1)
+            return relax_wave_t<D, R, NS, true, CREG, WPS>(J, WO, coef, nbt, st, eps, cap, fixed, sweeps, D_out,
+                                                           red);
+        return relax_wave_t<D, R, NS, false, CREG, WPS>(J, WO, coef, nbt, st, eps, cap, fixed, sweeps, D_out, red);
+    }
 }
 
 template <int D, int NS, int CREG, int WPS, typename CP64, typename CP32>
-__device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 coef64, CP32 coef32,
+__device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 coef64, CP32 coef32, lds_ptr<const dbl2> lnk,
                                  lds_ptr<const u32x4> nbt, lds_ptr<dbl2> st64, lds_ptr<flt2> st32,
                                  glb_ptr<flt2> bounce, uint64_t local, double *red)
 {
@@ -321,7 +455,7 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 
     const bool fixed = (J.flags & GC_JOB_SYNC2) != 0;
     const uint64_t cap = fixed ? (uint64_t)J.fixed_sweeps[local] : J.max_sweeps;
     if (J.precision == 1) {
-        status = relax_wave<D, float, NS, CREG, WPS>(J, WO, coef32, nbt, st32, J.eps32, J.max_sweeps, false, sw32, Dn,
+        status = relax_wave<D, float, NS, CREG, WPS>(J, WO, coef32, lnk, nbt, st32, J.eps32, J.max_sweeps, false, sw32, Dn,
                                                      red);
         if (status == GC_ST_CONVERGED) {
             // promotion g64 = normalise((double) g32): both states share the
@@ -337,11 +471,11 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 
                 st64[p] = dbl2{xr * r, xi * r};
             }
             start_sync<WPS>();
-            status = relax_wave<D, double, NS, CREG, WPS>(J, WO, coef64, nbt, st64, J.eps64, J.max_sweeps, false,
+            status = relax_wave<D, double, NS, CREG, WPS>(J, WO, coef64, lnk, nbt, st64, J.eps64, J.max_sweeps, false,
                                                           sw64, Dn, red);
         }
     } else {
-        status = relax_wave<D, double, NS, CREG, WPS>(J, WO, coef64, nbt, st64, J.eps64, cap, fixed, sw64, Dn, red);
+        status = relax_wave<D, double, NS, CREG, WPS>(J, WO, coef64, lnk, nbt, st64, J.eps64, cap, fixed, sw64, Dn, red);
     }
     // final state in natural site order
     glb_ptr<dbl2> out = as_global(reinterpret_cast<dbl2 *>(J.states + local * (uint64_t)V));
@@ -353,9 +487,10 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 
     start_sync<WPS>();
 }
 
-// WG = WAVES wavefronts.  LDS: [neighbour table 16V when NS <= 2 | coef64 |
-// coef32 when COEF_LDS] then per wave a 16V-byte state region (double2[V],
-// or float2[V] in the single-precision phase).
+// WG = WAVES wavefronts.  LDS: [neighbour table 16V | coef64 | coef32 when
+// COEF_LDS (NS <= 2 only) | links of DL directions 16 DL V (NS > 2)] then
+// per wave a 16V-byte state region (double2[V], or float2[V] in the
+// single-precision phase).
 template <int D, int NS, int WAVES, bool COEF_LDS, int CREG>
 __global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__restrict__ jobs,
                                                           const GcWaveOrbit *__restrict__ worbs, int n_jobs,
@@ -386,15 +521,15 @@ __global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__rest
         const GcWaveOrbit &WO = worbs[jn];
         const int V = J.orb.V;
         const int ncoef = 2 * D * V;      // complex entries per precision
-        // neighbour table (16 bytes per slot, 16V in all, when NS <= 2),
-        // then the coefficients when staged, then the wavefronts' states
+        // neighbour table (16 bytes per slot, 16V in all; half indices when
+        // NS <= 2, byte offsets above), then the coefficients when staged,
+        // then the wavefronts' states
         lds_ptr<u32x4> nbt = as_lds(reinterpret_cast<u32x4 *>(smem));
-        size_t off = 0;
-        if constexpr (NS <= 2) {
-            glb_ptr<const u32x4> nbg = as_global(reinterpret_cast<const u32x4 *>(WO.nb));
+        {
+            glb_ptr<const u32x4> nbg = as_global(reinterpret_cast<const u32x4 *>(NS <= 2 ? WO.nb : WO.nbo));
             for (int t = threadIdx.x; t < V; t += 64 * WAVES) nbt[t] = nbg[t];
-            off = 16 * (size_t)V;
         }
+        size_t off = 16 * (size_t)V;
         const dbl2 *g64 = reinterpret_cast<const dbl2 *>(WO.coef64);
         const flt2 *g32 = reinterpret_cast<const flt2 *>(WO.coef32);
         lds_ptr<dbl2> c64 = as_lds(reinterpret_cast<dbl2 *>(smem + off));
@@ -406,6 +541,20 @@ __global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__rest
                 for (int t = threadIdx.x; t < ncoef; t += 64 * WAVES) c32[t] = g32[t];
                 off += 8 * (size_t)ncoef;
             }
+        }
+        // NS > 2: the links of the first DL directions, planes (c, mu < DL)
+        // of the [c][mu][half] table
+        constexpr int DL = NS > 2 ? links_in_lds<D, NS>() : 0;
+        lds_ptr<dbl2> lnk = c64;
+        if constexpr (DL > 0) {
+            const int half = WO.half;
+            glb_ptr<const dbl2> lg = as_global(reinterpret_cast<const dbl2 *>(WO.link64));
+            for (int t = threadIdx.x; t < 2 * DL * half; t += 64 * WAVES) {
+                const int pl = t / half, h = t - pl * half;   // plane c * DL + mu
+                const int c = pl / DL, mu = pl - c * DL;
+                lnk[t] = lg[(c * D + mu) * half + h];
+            }
+            off += 16 * (size_t)DL * V;
         }
         __syncthreads();
         lds_ptr<dbl2> st64 = as_lds(reinterpret_cast<dbl2 *>(smem + off + (size_t)wave * 16 * V));
@@ -419,10 +568,10 @@ __global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__rest
             if (s >= J.n_starts) break;
             lds_ptr<const u32x4> nbc = nbt;
             if (COEF_LDS)
-                relax_start_wave<D, NS, CREG, 1>(J, WO, c64, c32, nbc, st64, st32, bounce, s, nullptr);
+                relax_start_wave<D, NS, CREG, 1>(J, WO, c64, c32, lnk, nbc, st64, st32, bounce, s, nullptr);
             else
-                relax_start_wave<D, NS, CREG, 1>(J, WO, as_global(g64), as_global(g32), nbc, st64, st32, bounce, s,
-                                                 nullptr);
+                relax_start_wave<D, NS, CREG, 1>(J, WO, as_global(g64), as_global(g32), lnk, nbc, st64, st32, bounce,
+                                                 s, nullptr);
         }
         __syncthreads();
         j0 = jn;
@@ -478,7 +627,8 @@ __global__ __launch_bounds__(64 * WPS) void wps_kernel(const GcJobDev *__restric
             const uint64_t s = uniform((uint64_t)claim);
             __syncthreads();
             if (s >= J.n_starts) break;
-            relax_start_wave<D, 2, 0, WPS>(J, WO, as_global(g64), as_global(g32), nbc, st64, st32, bounce, s, red);
+            relax_start_wave<D, 2, 0, WPS>(J, WO, as_global(g64), as_global(g32), lds_ptr<const dbl2>(nullptr), nbc,
+                                           st64, st32, bounce, s, red);
         }
         __syncthreads();
         j0 = jn;
@@ -534,8 +684,14 @@ hipError_t launch_t(const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, 
                       : launch_v<D, NS, WAVES, false, 2>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s);
     }
     if (creg != 0) return hipErrorInvalidValue;
-    return cl ? launch_v<D, NS, WAVES, true, 0>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s)
-              : launch_v<D, NS, WAVES, false, 0>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s);
+    if constexpr (NS > 2) {
+        // links through buffer loads: no staged coefficient table
+        if (cl) return hipErrorInvalidValue;
+        return launch_v<D, NS, WAVES, false, 0>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s);
+    } else {
+        return cl ? launch_v<D, NS, WAVES, true, 0>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s)
+                  : launch_v<D, NS, WAVES, false, 0>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s);
+    }
 }
 
 template <int D, int NS, int WAVES>
@@ -548,7 +704,12 @@ hipError_t occ_t(int variant, size_t lds, int *per_cu)
         if (creg == 2) return cl ? occ_v<D, NS, WAVES, true, 2>(lds, per_cu) : occ_v<D, NS, WAVES, false, 2>(lds, per_cu);
     }
     if (creg != 0) return hipErrorInvalidValue;
-    return cl ? occ_v<D, NS, WAVES, true, 0>(lds, per_cu) : occ_v<D, NS, WAVES, false, 0>(lds, per_cu);
+    if constexpr (NS > 2) {
+        if (cl) return hipErrorInvalidValue;
+        return occ_v<D, NS, WAVES, false, 0>(lds, per_cu);
+    } else {
+        return cl ? occ_v<D, NS, WAVES, true, 0>(lds, per_cu) : occ_v<D, NS, WAVES, false, 0>(lds, per_cu);
+    }
 }
 
 
@@ -556,7 +717,8 @@ hipError_t occ_t(int variant, size_t lds, int *per_cu)
 
 // Entry points of one lattice dimension D: each gc_waveD.hip instantiates
 // the kernels of its D only (NS = slots per lane per colour =
-// ceil(half / 64), instantiated for half-volumes up to 2048 sites).
+// ceil(half / 64), instantiated for half-volumes up to 1024 sites, the
+// largest whose states and table fit in LDS).
 #define GC_WAVE_DEFINE_DIM(D, NS_LIST)                                                                    \
     hipError_t gc_wave_occupancy_d##D(int ns, int variant, size_t lds, int *per_cu)                        \
     {                                                                                                     \
