@@ -206,6 +206,7 @@ struct Group {
     int d = 0;
     std::vector<int> jobs;           // indices into Job::orbits
     int block = 64, grid = 1, ns = 1, coef_lds = 0, creg = 0, wps = 0;
+    int rm = 0;                      // relax mode of the exchange-region kernel (ns > 2)
     size_t lds = 0;
     size_t o_jobs = 0, o_worbs = 0, o_next = 0, o_prefix = 0, o_bounce = 0;
     size_t o_jobs1 = 0;              // first-pass descriptors of a batch-synchronous launch
@@ -678,14 +679,19 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             if (e != hipSuccess) return fail(ctx, e, "occupancy");
         } else if (g.wave) {
             g.ns = (gV / 2 + 63) / 64;
-            g.block = 64 * GC_WAVES;
+            g.block = 64 * gc_wave_starts_per_wg(g.ns);
+            g.rm = g.ns > 2 ? gc_wave_relax_mode(job->p.omega) : 0;
             size_t coef_bytes = 0;
             for (int j : g.jobs) {
                 const Orbit *o = job->orbits[j];
                 coef_bytes = std::max(coef_bytes, (size_t)2 * o->d * o->V * (mixed ? 24 : 16));
             }
-            // states + neighbour table + links staged in LDS
-            const size_t states = (size_t)(GC_WAVES + 1 + gc_links_in_lds(g.d, ns_bucket(g.d, g.ns))) * 16 * gV;
+            // neighbour table + states (two-colour regions of 16V, or 8V
+            // exchange regions of the register-resident kernel) + links
+            // staged in LDS
+            const size_t states =
+                g.ns > 2 ? (size_t)(1 + gc_links_in_lds(g.d, ns_bucket(g.d, g.ns))) * 16 * gV + (size_t)GC_WAVES_RR * 8 * gV
+                         : (size_t)(GC_WAVES + 1) * 16 * gV;
             // a staged coefficient table only where a lane has at most two
             // slots; above, the links are read through buffer loads
             g.coef_lds = (g.ns <= 2 && coef_bytes + states <= 64 * 1024) ? 1 : 0;
@@ -699,7 +705,7 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             if (tc != ctx->tune_creg.end()) g.creg = std::min(tc->second, gc_wave_creg_max(g.d, g.ns));
             if (ctx->creg_override >= 0) g.creg = std::min(ctx->creg_override, gc_wave_creg_max(g.d, g.ns));
             if (job->force_creg >= 0) g.creg = std::min(job->force_creg, gc_wave_creg_max(g.d, g.ns));
-            hipError_t e = gc_wave_occupancy(g.d, g.ns, g.coef_lds | (g.creg << 1), g.lds, &per_cu);
+            hipError_t e = gc_wave_occupancy(g.d, g.ns, g.coef_lds | (g.creg << 1) | (g.rm << 3), g.lds, &per_cu);
             if (e != hipSuccess) return fail(ctx, e, "occupancy");
         } else {
             g.block = block_for(gV);
@@ -709,7 +715,7 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             if (e != hipSuccess) return fail(ctx, e, "occupancy");
         }
         per_cu = std::max(per_cu, 1);
-        const uint64_t per_wg = (g.wave && g.wps == 0) ? GC_WAVES : 1;
+        const uint64_t per_wg = (g.wave && g.wps == 0) ? (uint64_t)gc_wave_starts_per_wg(g.ns) : 1;
         uint64_t grid = (uint64_t)per_cu * (uint64_t)ctx->n_cu;
         grid = std::min<uint64_t>(grid, std::max<uint64_t>((g.total + per_wg - 1) / per_wg, 1));
         g.grid = (int)grid;
@@ -718,7 +724,9 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         g.o_worbs = place(sizeof(GcWaveOrbit) * g.jobs.size());
         g.o_next = place(sizeof(unsigned long long) * g.jobs.size());
         g.o_prefix = place(sizeof(uint64_t) * (g.jobs.size() + 1));
-        g.o_bounce = g.wave ? place(sizeof(float2) * (size_t)gV * per_wg * g.grid) : 0;
+        // promotion scratch of the two-region kernels (the register-resident
+        // kernel promotes in registers)
+        g.o_bounce = (g.wave && (g.wps > 0 || g.ns <= 2)) ? place(sizeof(float2) * (size_t)gV * per_wg * g.grid) : 0;
     }
     // key pass: one workgroup per start, one launch per workgroup shape
     // within each relax group's chain; filter pass: one workgroup per copy,
@@ -979,7 +987,7 @@ hipError_t enqueue_chain(Job *job, unsigned char *base, int gi, hipStream_t qs, 
         if (g.wave)
             return gc_launch_wave(g.d, g.ns, (const GcJobDev *)(base + o_jobs),
                                   (const GcWaveOrbit *)(base + g.o_worbs), (int)g.jobs.size(),
-                                  (unsigned long long *)(base + g.o_next), g.coef_lds | (g.creg << 1),
+                                  (unsigned long long *)(base + g.o_next), g.coef_lds | (g.creg << 1) | (g.rm << 3),
                                   (float2 *)(base + g.o_bounce), g.grid, g.lds, qs);
         return gc_launch_relax_wg(g.block, (const GcJobDev *)(base + o_jobs), (int)g.jobs.size(),
                                   (const uint64_t *)(base + g.o_prefix), (unsigned long long *)(base + g.o_next),

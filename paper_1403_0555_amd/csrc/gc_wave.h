@@ -25,27 +25,40 @@ struct GcWaveOrbit {
 // private scratch for the single-to-double promotion.
 constexpr int GC_WAVES = 4;
 
+// Wavefronts (starts) per workgroup of the register-resident kernel used
+// above two slots per lane; each start takes 8V bytes of LDS.
+constexpr int GC_WAVES_RR = 8;
+inline int gc_wave_starts_per_wg(int ns) { return ns > 2 ? GC_WAVES_RR : GC_WAVES; }
+
 // Kernels with more than two slots per lane (ns > 2) stage the links of
 // their first gc_links_in_lds(d, ns) directions (both colours, double
 // precision, 16 V bytes per direction) in LDS beside the neighbour table and
-// the GC_WAVES states: as many as fit in 160 KiB for the largest lattice of
-// the instantiated slot count (half <= 64 ns).
+// the GC_WAVES_RR exchange regions: as many as fit in 160 KiB for the
+// largest lattice of the instantiated slot count (half <= 64 ns).
 constexpr int gc_links_in_lds(int d, int ns)
 {
     const long V = 128L * ns;
-    const long room = 160L * 1024 - (long)(GC_WAVES + 1) * 16 * V;
+    const long room = 160L * 1024 - 16 * V - (long)GC_WAVES_RR * 8 * V;
     const long dl = (ns > 2 && room > 0) ? room / (16 * V) : 0;
     return dl < d ? (int)dl : d;
 }
 
-// variant = coef_lds | creg << 1: coefficient table staged in LDS (else
-// read from global memory) and the number of colours (0..2) whose
-// coefficients a lane keeps in registers (gc_wave_creg_max(d, ns) at most).
+// variant = coef_lds | creg << 1 | rm << 3: coefficient table staged in LDS
+// (else read from global memory) and the number of colours (0..2) whose
+// coefficients a lane keeps in registers (gc_wave_creg_max(d, ns) at most),
+// both for ns <= 2; rm, for ns > 2, the relax mode gc_wave_relax_mode(omega).
 hipError_t gc_wave_occupancy(int d, int ns, int variant, size_t lds, int *per_cu);
 hipError_t gc_launch_wave(int d, int ns, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs,
                           unsigned long long *job_next, int variant, float2 *bounce, int grid, size_t lds,
                           hipStream_t s);
 int gc_wave_creg_max(int d, int ns);
+// Relax mode of the exchange-region kernel: 1 plain relaxation (omega = 1),
+// 2 plain relaxation in the single-precision phase only (omega rounds to 1
+// in single precision), 0 over-relaxation.
+inline int gc_wave_relax_mode(double omega)
+{
+    return omega == 1.0 ? 1 : (float)omega == 1.0f ? 2 : 0;
+}
 
 // Workgroup-per-start variant (lattices with more than 128 slots per
 // colour): wps wavefronts share a start, at most two slots per thread.

@@ -128,22 +128,15 @@ template <int WPS> __device__ __forceinline__ double start_max(double v, double 
     return v;
 }
 
-// Sweeps of one precision on the wave's state st[2][half].  Returns status.
-// Lane l owns slots h = l + 64k, k < NS, of each colour; slots beyond the
-// half volume are computed on a clamped index and discarded, so the passes
-// have no divergent branches.  Two variants share the sweep schedule below:
-//
-// * NS <= 2 (relax_wave_t): the packed neighbour entries and the lane's own
-//   values are held in registers, and CREG colours (0, 1 or 2, starting with
-//   colour 0) keep the coefficients of the lane's slots in registers for the
-//   whole phase;
-// * NS > 2 (relax_wave_big): each slot reads its scaled neighbour entry from
-//   the LDS table nbt, and its 2d coefficients from the link table through
-//   buffer loads (forward: its own links; backward: the conjugated forward
-//   links of its backward neighbours, at the neighbour's table offset).
-//
-// Colour 0 of sweep t + 1 first reads the colour-0 staples of the state
-// after sweep t; at a check point they complete the norm of sweep t.
+// Sweeps of one precision on the wave's state st[2][half], at most two slots
+// per lane (NS <= 2).  Returns status.  Lane l owns slots h = l + 64k, k < NS,
+// of each colour; slots beyond the half volume are computed on a clamped
+// index and discarded, so the passes have no divergent branches.  The packed
+// neighbour entries and the lane's own values are held in registers, and
+// CREG colours (0, 1 or 2, starting with colour 0) keep the coefficients of
+// the lane's slots in registers for the whole phase.  Colour 0 of sweep
+// t + 1 first reads the colour-0 staples of the state after sweep t; at a
+// check point they complete the norm of sweep t.
 template <int D, typename R, int NS, bool RELAX, int CREG, int WPS, typename CP>
 __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<const u32x4> nbt,
                             lds_ptr<typename cx<R>::T> st, double eps, uint64_t cap, bool fixed, uint64_t &sweeps,
@@ -306,120 +299,18 @@ __device__ __forceinline__ typename cx<R>::T staple_big(const u32x4 w, lds_ptr<c
     return s;
 }
 
-template <int D, typename R, int NS, bool RELAX, int WPS>
-__device__ int relax_wave_big(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t links, lds_ptr<const dbl2> lnk,
-                              lds_ptr<const u32x4> nbt, lds_ptr<typename cx<R>::T> st, double eps, uint64_t cap,
-                              bool fixed, uint64_t &sweeps, double &D_out, double *red)
-{
-    constexpr int DL = links_in_lds<D, NS>();
-    lds_ptr<const unsigned char> lb = (lds_ptr<const unsigned char>)lnk;
-    const uint32_t lplane = (uint32_t)half * 16u;
-    using C = typename cx<R>::T;
-    const int lane = WPS > 1 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
-    lds_ptr<C> st0 = st;
-    lds_ptr<C> st1 = st + half;
-    lds_ptr<const unsigned char> b0 = (lds_ptr<const unsigned char>)st0;
-    lds_ptr<const unsigned char> b1 = (lds_ptr<const unsigned char>)st1;
-    const uint32_t plane = (uint32_t)half * (uint32_t)sizeof(C);   // bytes of one (colour, mu) link plane
-    const R omega = (R)J.omega;
-    const uint64_t check = fixed ? cap : J.check_every > 0 ? (uint64_t)J.check_every : 1;
-    const bool maxabs = J.stop_norm != 0;
-    int hs[NS];
-    bool valid[NS];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        const int h = lane + 64 * WPS * k;
-        valid[k] = h < half;
-        hs[k] = valid[k] ? h : half - 1;
-    }
-
-    uint64_t t = 0;
-    uint64_t until = check;
-    bool ckpt = false;
-    double part1 = 0.0;
-    int status = GC_ST_NONCONVERGED;
-    D_out = INFINITY;
-    for (;;) {
-        const bool pending = (t > 0) && ckpt;
-        const bool last = (t == cap);
-        const int z = opaque_zero();
-        C gnew[NS];
-        double acc0 = 0.0;
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            const int h = hs[k] + z;
-            const C s = staple_big<D, DL, R, 0>(nbt[h], b1, lb, (uint32_t)h * 16u, links,
-                                                (uint32_t)h * (uint32_t)sizeof(C), plane, lplane);
-            const C g0 = st0[h];
-            const double dv = (double)(g0.x * s.y - g0.y * s.x);
-            const double a = maxabs ? fmax(acc0, fabs(dv)) : acc0 + dv * dv;
-            acc0 = valid[k] ? a : acc0;
-            gnew[k] = local_update<RELAX, R>(g0, s, omega);
-        }
-        if (pending) {
-            double Dn;
-            if (maxabs) Dn = start_max<WPS>(fmax(acc0, part1), red);
-            else Dn = start_sum<WPS>(acc0 + part1, red) / (double)(2 * half);
-            D_out = Dn;
-            if (!(Dn == Dn)) { status = GC_ST_BADNUM; break; }
-            if (Dn < eps) {
-                status = GC_ST_CONVERGED;
-                if (!fixed) break;
-            }
-        }
-        if (last) break;
-#pragma unroll
-        for (int k = 0; k < NS; ++k)
-            if (valid[k]) st0[hs[k]] = gnew[k];
-        start_sync<WPS>();
-        ++t;
-        --until;
-        ckpt = (until == 0) || (t == cap);
-        if (until == 0) until = check;
-        const bool chk = ckpt;
-        double a1 = 0.0;
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            const int h = hs[k] + z;
-            const C s = staple_big<D, DL, R, 1>(nbt[half + h], b0, lb, (uint32_t)h * 16u, links,
-                                                (uint32_t)h * (uint32_t)sizeof(C), plane, lplane);
-            const C g = local_update<RELAX, R>(st1[h], s, omega);
-            if (valid[k]) st1[hs[k]] = g;
-            const double dv = (double)(g.x * s.y - g.y * s.x);
-            const double a = maxabs ? fmax(a1, fabs(dv)) : a1 + dv * dv;
-            a1 = valid[k] ? a : a1;
-        }
-        if (chk) part1 = a1;
-        start_sync<WPS>();
-    }
-    sweeps = t;
-    return status;
-}
-
 template <int D, typename R, int NS, int CREG, int WPS, typename CP>
-__device__ int relax_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<const dbl2> lnk,
-                          lds_ptr<const u32x4> nbt, lds_ptr<typename cx<R>::T> st, double eps, uint64_t cap,
-                          bool fixed, uint64_t &sweeps, double &D_out, double *red)
+__device__ int relax_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<const u32x4> nbt,
+                          lds_ptr<typename cx<R>::T> st, double eps, uint64_t cap, bool fixed, uint64_t &sweeps,
+                          double &D_out, double *red)
 {
-    if constexpr (NS > 2) {
-        const uint32_t bytes = (uint32_t)(2 * D * WO.half * sizeof(typename cx<R>::T));
-        const __amdgpu_buffer_rsrc_t links =
-            buffer_rsrc(sizeof(R) == 8 ? (const void *)WO.link64 : (const void *)WO.link32, bytes);
-        if ((R)J.omega == (R)1)
-            return relax_wave_big<D, R, NS, true, WPS>(J, WO.half, links, lnk, nbt, st, eps, cap, fixed, sweeps,
-                                                       D_out, red);
-        return relax_wave_big<D, R, NS, false, WPS>(J, WO.half, links, lnk, nbt, st, eps, cap, fixed, sweeps, D_out,
-                                                    red);
-    } else {
-        if ((R)J.omega == (R)1)
-            return relax_wave_t<D, R, NS, true, CREG, WPS>(J, WO, coef, nbt, st, eps, cap, fixed, sweeps, D_out,
-                                                           red);
-        return relax_wave_t<D, R, NS, false, CREG, WPS>(J, WO, coef, nbt, st, eps, cap, fixed, sweeps, D_out, red);
-    }
+    if ((R)J.omega == (R)1)
+        return relax_wave_t<D, R, NS, true, CREG, WPS>(J, WO, coef, nbt, st, eps, cap, fixed, sweeps, D_out, red);
+    return relax_wave_t<D, R, NS, false, CREG, WPS>(J, WO, coef, nbt, st, eps, cap, fixed, sweeps, D_out, red);
 }
 
 template <int D, int NS, int CREG, int WPS, typename CP64, typename CP32>
-__device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 coef64, CP32 coef32, lds_ptr<const dbl2> lnk,
+__device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 coef64, CP32 coef32,
                                  lds_ptr<const u32x4> nbt, lds_ptr<dbl2> st64, lds_ptr<flt2> st32,
                                  glb_ptr<flt2> bounce, uint64_t local, double *red)
 {
@@ -455,7 +346,7 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 
     const bool fixed = (J.flags & GC_JOB_SYNC2) != 0;
     const uint64_t cap = fixed ? (uint64_t)J.fixed_sweeps[local] : J.max_sweeps;
     if (J.precision == 1) {
-        status = relax_wave<D, float, NS, CREG, WPS>(J, WO, coef32, lnk, nbt, st32, J.eps32, J.max_sweeps, false, sw32, Dn,
+        status = relax_wave<D, float, NS, CREG, WPS>(J, WO, coef32, nbt, st32, J.eps32, J.max_sweeps, false, sw32, Dn,
                                                      red);
         if (status == GC_ST_CONVERGED) {
             // promotion g64 = normalise((double) g32): both states share the
@@ -471,11 +362,11 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 
                 st64[p] = dbl2{xr * r, xi * r};
             }
             start_sync<WPS>();
-            status = relax_wave<D, double, NS, CREG, WPS>(J, WO, coef64, lnk, nbt, st64, J.eps64, J.max_sweeps, false,
+            status = relax_wave<D, double, NS, CREG, WPS>(J, WO, coef64, nbt, st64, J.eps64, J.max_sweeps, false,
                                                           sw64, Dn, red);
         }
     } else {
-        status = relax_wave<D, double, NS, CREG, WPS>(J, WO, coef64, lnk, nbt, st64, J.eps64, cap, fixed, sw64, Dn, red);
+        status = relax_wave<D, double, NS, CREG, WPS>(J, WO, coef64, nbt, st64, J.eps64, cap, fixed, sw64, Dn, red);
     }
     // final state in natural site order
     glb_ptr<dbl2> out = as_global(reinterpret_cast<dbl2 *>(J.states + local * (uint64_t)V));
@@ -487,10 +378,268 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 
     start_sync<WPS>();
 }
 
-// WG = WAVES wavefronts.  LDS: [neighbour table 16V | coef64 | coef32 when
-// COEF_LDS (NS <= 2 only) | links of DL directions 16 DL V (NS > 2)] then
-// per wave a 16V-byte state region (double2[V], or float2[V] in the
-// single-precision phase).
+// Exchange-region variant for more than two slots per lane (NS > 2).  A
+// start keeps one region X[half] in LDS, holding the colour that the next
+// pass reads; the lane holds the values of its own slots of the colour being
+// updated in registers.  Colour-0 pass: staples from X (colour 1), new
+// values into registers (kept until the stopping norm of the previous sweep
+// has been decided); then every lane takes its colour-1 values back from X
+// and writes its new colour-0 values in their place.  Colour-1 pass:
+// staples from X (colour 0), values updated in registers; then the lanes
+// swap colour 0 back out of X and colour 1 in.  One wavefront runs a start
+// alone, so the LDS instructions of a pass (all reads, then the swap) are
+// ordered by program order; the fences keep the compiler from moving them.
+// Half the LDS of a two-region state lets twice the starts share a compute
+// unit.  The sweep schedule, the stopping norm and the arithmetic are those
+// of relax_wave_t.  own: the start's values on entry and on return.
+template <int D, typename R, int NS, bool RELAX>
+__device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t links, lds_ptr<const dbl2> lnk,
+                        lds_ptr<const u32x4> nbt, lds_ptr<typename cx<R>::T> X, typename cx<R>::T (&own)[2][NS],
+                        double eps, uint64_t cap, bool fixed, uint64_t &sweeps, double &D_out)
+{
+    using C = typename cx<R>::T;
+    constexpr int DL = links_in_lds<D, NS>();
+    const int lane = (int)(threadIdx.x & 63);
+    lds_ptr<const unsigned char> xb = (lds_ptr<const unsigned char>)X;
+    lds_ptr<const unsigned char> lb = (lds_ptr<const unsigned char>)lnk;
+    const uint32_t lplane = (uint32_t)half * 16u;
+    const uint32_t plane = (uint32_t)half * (uint32_t)sizeof(C);
+    const R omega = (R)J.omega;
+    const uint64_t check = fixed ? cap : J.check_every > 0 ? (uint64_t)J.check_every : 1;
+    const bool maxabs = J.stop_norm != 0;
+    // slot k of the lane: h = lane + 64 k, computed on a clamped index and
+    // discarded beyond the half volume (recomputed where used: no
+    // registers held for it)
+#define GC_RR_SLOT(k) const int hk = lane + 64 * (k); const bool vk = hk < half; const int hc = vk ? hk : half - 1
+    // the first pass reads colour 1
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        GC_RR_SLOT(k);
+        (void)hc;
+        if (vk) X[hk] = own[1][k];
+    }
+    wave_sync();
+    C g0r[NS], g1r[NS];   // colour-0 values (colour-0 pass), colour-1 values (colour-1 pass)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) g0r[k] = own[0][k];
+
+    uint64_t t = 0;
+    uint64_t until = check;
+    bool ckpt = false;
+    double part1 = 0.0;
+    int status = GC_ST_NONCONVERGED;
+    D_out = INFINITY;
+    for (;;) {
+        const bool pending = (t > 0) && ckpt;
+        const bool last = (t == cap);
+        const int z = opaque_zero();
+        C gnew[NS];
+        double acc0 = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            GC_RR_SLOT(k);
+            const int h = hc + z;
+            const C s = staple_big<D, DL, R, 0>(nbt[h], xb, lb, (uint32_t)h * 16u, links,
+                                                (uint32_t)h * (uint32_t)sizeof(C), plane, lplane);
+            const C g0 = g0r[k];
+            const double dv = (double)(g0.x * s.y - g0.y * s.x);
+            const double a = maxabs ? fmax(acc0, fabs(dv)) : acc0 + dv * dv;
+            acc0 = vk ? a : acc0;
+            gnew[k] = local_update<RELAX, R>(g0, s, omega);
+        }
+        if (pending) {
+            double Dn;
+            if (maxabs) Dn = wave_max(fmax(acc0, part1));
+            else Dn = wave_sum(acc0 + part1) / (double)(2 * half);
+            D_out = Dn;
+            if (!(Dn == Dn)) { status = GC_ST_BADNUM; break; }
+            if (Dn < eps) {
+                status = GC_ST_CONVERGED;
+                if (!fixed) break;
+            }
+        }
+        if (last) break;
+        // swap: colour 1 out of X, the new colour 0 in
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            GC_RR_SLOT(k);
+            g1r[k] = X[hc];
+            if (vk) X[hk] = gnew[k];
+        }
+        wave_sync();
+        ++t;
+        --until;
+        ckpt = (until == 0) || (t == cap);
+        if (until == 0) until = check;
+        const bool chk = ckpt;
+        double a1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            GC_RR_SLOT(k);
+            const int h = hc + z;
+            const C s = staple_big<D, DL, R, 1>(nbt[half + h], xb, lb, (uint32_t)h * 16u, links,
+                                                (uint32_t)h * (uint32_t)sizeof(C), plane, lplane);
+            const C g = local_update<RELAX, R>(g1r[k], s, omega);
+            g1r[k] = g;
+            const double dv = (double)(g.x * s.y - g.y * s.x);
+            const double a = maxabs ? fmax(a1, fabs(dv)) : a1 + dv * dv;
+            a1 = vk ? a : a1;
+        }
+        if (chk) part1 = a1;
+        // swap: colour 0 out of X, the new colour 1 in
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            GC_RR_SLOT(k);
+            g0r[k] = X[hc];
+            if (vk) X[hk] = g1r[k];
+        }
+        wave_sync();
+    }
+    // X holds colour 1
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        GC_RR_SLOT(k);
+        (void)vk;
+        own[0][k] = g0r[k];
+        own[1][k] = X[hc];
+    }
+    wave_sync();
+#undef GC_RR_SLOT
+    sweeps = t;
+    return status;
+}
+
+// Relax modes of the exchange-region kernel, fixed per launch from omega:
+// over-relaxation in both precisions, plain relaxation in both (omega = 1),
+// or plain relaxation in the single-precision phase only (omega rounds to 1
+// in single precision but differs from 1).
+enum { GC_RM_OR = 0, GC_RM_RELAX = 1, GC_RM_RELAX32 = 2 };
+
+template <int D, typename R, int NS, bool RELAX>
+__device__ __forceinline__ int relax_rr_links(const GcJobDev &J, const GcWaveOrbit &WO, lds_ptr<const dbl2> lnk,
+                                              lds_ptr<const u32x4> nbt, lds_ptr<typename cx<R>::T> X,
+                                              typename cx<R>::T (&own)[2][NS], double eps, uint64_t cap, bool fixed,
+                                              uint64_t &sweeps, double &D_out)
+{
+    const uint32_t bytes = (uint32_t)(2 * D * WO.half * sizeof(typename cx<R>::T));
+    const __amdgpu_buffer_rsrc_t links =
+        buffer_rsrc(sizeof(R) == 8 ? (const void *)WO.link64 : (const void *)WO.link32, bytes);
+    return relax_rr<D, R, NS, RELAX>(J, WO.half, links, lnk, nbt, X, own, eps, cap, fixed, sweeps, D_out);
+}
+
+// Values of colour c of a start, exchanged through X: slot h of the lane's
+// own list, from the sites i with loc[i] = c half + h.
+template <typename C, int NS>
+__device__ __forceinline__ void rr_gather(lds_ptr<C> X, C (&dst)[NS], int half)
+{
+    const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const int h = lane + 64 * k;
+        dst[k] = X[h < half ? h : half - 1];
+    }
+}
+
+template <int D, int NS, typename C>
+__device__ __forceinline__ void rr_init(const GcJobDev &J, const GcWaveOrbit &WO, lds_ptr<C> X, uint64_t local,
+                                        C (&own)[2][NS])
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const GcOrbitDev &O = J.orb;
+    const int V = O.V;
+    const int half = WO.half;
+    const uint64_t sid = J.first_start + local;
+    // random start (or the caller's angles), one colour per round: the sites
+    // of colour c go to X at their half index, then to the lanes' slots
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        wave_sync();
+        for (int b = lane; 4 * b < V; b += 64) {
+            uint64_t w[4];
+            if (!J.theta_init) start_block(J.start_seed, sid, O.orbit_index, (uint64_t)b, w);
+#pragma unroll 1
+            for (int q = 0; q < 4; ++q) {
+                const int i = 4 * b + q;
+                if (i < V) {
+                    const int p = WO.loc[i] - c * half;
+                    if (p >= 0 && p < half) {
+                        double sn, cs;
+                        sincos(J.theta_init ? J.theta_init[local * (uint64_t)V + i] : angle_of(w[q]), &sn, &cs);
+                        if constexpr (sizeof(C) == 8) X[p] = flt2{(float)cs, (float)sn};
+                        else X[p] = dbl2{cs, sn};
+                    }
+                }
+            }
+        }
+        wave_sync();
+        rr_gather<C, NS>(X, own[c], half);
+    }
+}
+
+template <int D, int NS, int RM>
+__device__ void relax_start_rr(const GcJobDev &J, const GcWaveOrbit &WO, lds_ptr<const dbl2> lnk,
+                               lds_ptr<const u32x4> nbt, lds_ptr<unsigned char> xr, uint64_t local)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int V = J.orb.V;
+    const int half = WO.half;
+    lds_ptr<dbl2> X64 = (lds_ptr<dbl2>)xr;
+    const bool single = J.precision == 1;
+    dbl2 own64[2][NS];
+    uint64_t sw32 = 0, sw64 = 0;
+    double Dn = INFINITY;
+    int status = GC_ST_CONVERGED;
+    if (single) {
+        flt2 own32[2][NS];
+        rr_init<D, NS, flt2>(J, WO, (lds_ptr<flt2>)xr, local, own32);
+        status = relax_rr_links<D, float, NS, RM != GC_RM_OR>(J, WO, lnk, nbt, (lds_ptr<flt2>)xr, own32, J.eps32,
+                                                               J.max_sweeps, false, sw32, Dn);
+        // promotion g64 = normalise((double) g32) after convergence, else the
+        // single-precision values reported as they are
+        const bool conv = status == GC_ST_CONVERGED;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                const double xr_ = (double)own32[c][k].x, xi = (double)own32[c][k].y;
+                const double r = conv ? rsqrt(xr_ * xr_ + xi * xi) : 1.0;
+                own64[c][k] = dbl2{xr_ * r, xi * r};
+            }
+    } else {
+        rr_init<D, NS, dbl2>(J, WO, X64, local, own64);
+    }
+    if (status == GC_ST_CONVERGED) {
+        const bool fixed = !single && (J.flags & GC_JOB_SYNC2) != 0;
+        const uint64_t cap = fixed ? (uint64_t)J.fixed_sweeps[local] : J.max_sweeps;
+        status = relax_rr_links<D, double, NS, RM == GC_RM_RELAX>(J, WO, lnk, nbt, X64, own64, J.eps64, cap, fixed,
+                                                                  sw64, Dn);
+    }
+    // final state in natural site order, one colour per round through X
+    glb_ptr<dbl2> out = as_global(reinterpret_cast<dbl2 *>(J.states + local * (uint64_t)V));
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const int h = lane + 64 * k;
+            if (h < half) X64[h] = own64[c][k];
+        }
+        wave_sync();
+        for (int i = lane; i < V; i += 64) {
+            const int p = WO.loc[i] - c * half;
+            if (p >= 0 && p < half) out[i] = X64[p];
+        }
+    }
+    if (lane == 0) record_relax(J, local, status, sw32, sw64, Dn);
+    wave_sync();
+}
+
+// WG = WAVES wavefronts, at most two slots per lane.  LDS: [neighbour table
+// 16V | coef64 | coef32 when COEF_LDS] then per wave a 16V-byte state region
+// (double2[V], or float2[V] in the single-precision phase).
 template <int D, int NS, int WAVES, bool COEF_LDS, int CREG>
 __global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__restrict__ jobs,
                                                           const GcWaveOrbit *__restrict__ worbs, int n_jobs,
@@ -521,12 +670,11 @@ __global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__rest
         const GcWaveOrbit &WO = worbs[jn];
         const int V = J.orb.V;
         const int ncoef = 2 * D * V;      // complex entries per precision
-        // neighbour table (16 bytes per slot, 16V in all; half indices when
-        // NS <= 2, byte offsets above), then the coefficients when staged,
-        // then the wavefronts' states
+        // neighbour table (16 bytes per slot, 16V in all), then the
+        // coefficients when staged, then the wavefronts' states
         lds_ptr<u32x4> nbt = as_lds(reinterpret_cast<u32x4 *>(smem));
         {
-            glb_ptr<const u32x4> nbg = as_global(reinterpret_cast<const u32x4 *>(NS <= 2 ? WO.nb : WO.nbo));
+            glb_ptr<const u32x4> nbg = as_global(reinterpret_cast<const u32x4 *>(WO.nb));
             for (int t = threadIdx.x; t < V; t += 64 * WAVES) nbt[t] = nbg[t];
         }
         size_t off = 16 * (size_t)V;
@@ -542,20 +690,6 @@ __global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__rest
                 off += 8 * (size_t)ncoef;
             }
         }
-        // NS > 2: the links of the first DL directions, planes (c, mu < DL)
-        // of the [c][mu][half] table
-        constexpr int DL = NS > 2 ? links_in_lds<D, NS>() : 0;
-        lds_ptr<dbl2> lnk = c64;
-        if constexpr (DL > 0) {
-            const int half = WO.half;
-            glb_ptr<const dbl2> lg = as_global(reinterpret_cast<const dbl2 *>(WO.link64));
-            for (int t = threadIdx.x; t < 2 * DL * half; t += 64 * WAVES) {
-                const int pl = t / half, h = t - pl * half;   // plane c * DL + mu
-                const int c = pl / DL, mu = pl - c * DL;
-                lnk[t] = lg[(c * D + mu) * half + h];
-            }
-            off += 16 * (size_t)DL * V;
-        }
         __syncthreads();
         lds_ptr<dbl2> st64 = as_lds(reinterpret_cast<dbl2 *>(smem + off + (size_t)wave * 16 * V));
         lds_ptr<flt2> st32 = as_lds(reinterpret_cast<flt2 *>(smem + off + (size_t)wave * 16 * V));
@@ -568,10 +702,73 @@ __global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__rest
             if (s >= J.n_starts) break;
             lds_ptr<const u32x4> nbc = nbt;
             if (COEF_LDS)
-                relax_start_wave<D, NS, CREG, 1>(J, WO, c64, c32, lnk, nbc, st64, st32, bounce, s, nullptr);
+                relax_start_wave<D, NS, CREG, 1>(J, WO, c64, c32, nbc, st64, st32, bounce, s, nullptr);
             else
-                relax_start_wave<D, NS, CREG, 1>(J, WO, as_global(g64), as_global(g32), lnk, nbc, st64, st32, bounce,
-                                                 s, nullptr);
+                relax_start_wave<D, NS, CREG, 1>(J, WO, as_global(g64), as_global(g32), nbc, st64, st32, bounce, s,
+                                                 nullptr);
+        }
+        __syncthreads();
+        j0 = jn;
+    }
+}
+
+// WG = GC_WAVES_RR wavefronts, one start each, for lattices with more than
+// two slots per lane.  LDS: [neighbour table 16V (byte offsets) | links of
+// DL directions 16 DL V] then per wave an 8V-byte exchange region
+// (double2[half], or float2[half] in the single-precision phase).
+template <int D, int NS, int RM>
+__global__ __launch_bounds__(64 * GC_WAVES_RR) void wave_rr_kernel(const GcJobDev *__restrict__ jobs,
+                                                                    const GcWaveOrbit *__restrict__ worbs,
+                                                                    int n_jobs, unsigned long long *job_next)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int cur_job;
+    constexpr int DL = links_in_lds<D, NS>();
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    int j0 = (int)(blockIdx.x % (unsigned)n_jobs);
+    for (int round = 0; round < n_jobs; ++round) {
+        if (threadIdx.x == 0) {
+            int pick = -1;
+            for (int k = 0; k < n_jobs; ++k) {
+                const int j = (j0 + k) % n_jobs;
+                if (__hip_atomic_load(&job_next[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < jobs[j].n_starts) {
+                    pick = j;
+                    break;
+                }
+            }
+            cur_job = pick;
+        }
+        __syncthreads();
+        const int jn = uniform(cur_job);
+        __syncthreads();
+        if (jn < 0) break;
+        const GcJobDev &J = jobs[jn];
+        const GcWaveOrbit &WO = worbs[jn];
+        const int V = J.orb.V;
+        const int half = WO.half;
+        lds_ptr<u32x4> nbt = as_lds(reinterpret_cast<u32x4 *>(smem));
+        glb_ptr<const u32x4> nbg = as_global(reinterpret_cast<const u32x4 *>(WO.nbo));
+        for (int t = threadIdx.x; t < V; t += 64 * GC_WAVES_RR) nbt[t] = nbg[t];
+        size_t off = 16 * (size_t)V;
+        lds_ptr<dbl2> lnk = as_lds(reinterpret_cast<dbl2 *>(smem + off));
+        if constexpr (DL > 0) {
+            glb_ptr<const dbl2> lg = as_global(reinterpret_cast<const dbl2 *>(WO.link64));
+            for (int t = threadIdx.x; t < 2 * DL * half; t += 64 * GC_WAVES_RR) {
+                const int pl = t / half, h = t - pl * half;   // plane c * DL + mu
+                const int c = pl / DL, mu = pl - c * DL;
+                lnk[t] = lg[(c * D + mu) * half + h];
+            }
+            off += 16 * (size_t)DL * V;
+        }
+        __syncthreads();
+        lds_ptr<unsigned char> xr = as_lds(smem + off + (size_t)wave * 8 * V);
+        for (;;) {
+            unsigned long long s = 0;
+            if (lane == 0) s = atomicAdd(&job_next[jn], 1ULL);
+            s = uniform((uint64_t)s);
+            if (s >= J.n_starts) break;
+            relax_start_rr<D, NS, RM>(J, WO, lnk, nbt, xr, s);
         }
         __syncthreads();
         j0 = jn;
@@ -627,8 +824,7 @@ __global__ __launch_bounds__(64 * WPS) void wps_kernel(const GcJobDev *__restric
             const uint64_t s = uniform((uint64_t)claim);
             __syncthreads();
             if (s >= J.n_starts) break;
-            relax_start_wave<D, 2, 0, WPS>(J, WO, as_global(g64), as_global(g32), lds_ptr<const dbl2>(nullptr), nbc,
-                                           st64, st32, bounce, s, red);
+            relax_start_wave<D, 2, 0, WPS>(J, WO, as_global(g64), as_global(g32), nbc, st64, st32, bounce, s, red);
         }
         __syncthreads();
         j0 = jn;
@@ -674,7 +870,7 @@ hipError_t launch_t(const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, 
                     int variant, float2 *bounce, int grid, size_t lds, hipStream_t s)
 {
     const bool cl = (variant & 1) != 0;
-    const int creg = variant >> 1;
+    const int creg = (variant >> 1) & 3;
     if constexpr (creg_ok<D, NS>()) {
         if (creg == 1)
             return cl ? launch_v<D, NS, WAVES, true, 1>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s)
@@ -685,9 +881,22 @@ hipError_t launch_t(const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, 
     }
     if (creg != 0) return hipErrorInvalidValue;
     if constexpr (NS > 2) {
-        // links through buffer loads: no staged coefficient table
+        // register-resident kernel: no staged coefficient table
         if (cl) return hipErrorInvalidValue;
-        return launch_v<D, NS, WAVES, false, 0>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s);
+        (void)bounce;
+        const int rm = (variant >> 3) & 3;
+        if (rm == GC_RM_OR)
+            hipLaunchKernelGGL((wave_rr_kernel<D, NS, GC_RM_OR>), dim3(grid), dim3(64 * GC_WAVES_RR), lds, s, jobs,
+                               worbs, n_jobs, job_next);
+        else if (rm == GC_RM_RELAX)
+            hipLaunchKernelGGL((wave_rr_kernel<D, NS, GC_RM_RELAX>), dim3(grid), dim3(64 * GC_WAVES_RR), lds, s, jobs,
+                               worbs, n_jobs, job_next);
+        else if (rm == GC_RM_RELAX32)
+            hipLaunchKernelGGL((wave_rr_kernel<D, NS, GC_RM_RELAX32>), dim3(grid), dim3(64 * GC_WAVES_RR), lds, s,
+                               jobs, worbs, n_jobs, job_next);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
     } else {
         return cl ? launch_v<D, NS, WAVES, true, 0>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s)
                   : launch_v<D, NS, WAVES, false, 0>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s);
@@ -698,7 +907,7 @@ template <int D, int NS, int WAVES>
 hipError_t occ_t(int variant, size_t lds, int *per_cu)
 {
     const bool cl = (variant & 1) != 0;
-    const int creg = variant >> 1;
+    const int creg = (variant >> 1) & 3;
     if constexpr (creg_ok<D, NS>()) {
         if (creg == 1) return cl ? occ_v<D, NS, WAVES, true, 1>(lds, per_cu) : occ_v<D, NS, WAVES, false, 1>(lds, per_cu);
         if (creg == 2) return cl ? occ_v<D, NS, WAVES, true, 2>(lds, per_cu) : occ_v<D, NS, WAVES, false, 2>(lds, per_cu);
@@ -706,7 +915,10 @@ hipError_t occ_t(int variant, size_t lds, int *per_cu)
     if (creg != 0) return hipErrorInvalidValue;
     if constexpr (NS > 2) {
         if (cl) return hipErrorInvalidValue;
-        return occ_v<D, NS, WAVES, false, 0>(lds, per_cu);
+        // the three relax modes share their resource use; the
+        // over-relaxation instantiation stands for them
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, wave_rr_kernel<D, NS, GC_RM_OR>, 64 * GC_WAVES_RR,
+                                                            lds);
     } else {
         return cl ? occ_v<D, NS, WAVES, true, 0>(lds, per_cu) : occ_v<D, NS, WAVES, false, 0>(lds, per_cu);
     }
