@@ -122,12 +122,14 @@ hipError_t gc_launch_post(int block, int sp, int wreg, int keys, const GcJobDev 
                           const uint64_t *prefix, unsigned long long *next, uint64_t total, double *wbuf,
                           uint64_t wstride, int grid, size_t lds_bytes, hipStream_t s);
 // Filter pass in the line-segment layout (seg sites per thread along
-// direction 0): gc_lanczos_shape returns 0 when no instantiated shape fits.
+// direction 0), one kernel per lattice dimension d (every job of a launch
+// has dimension d): gc_lanczos_shape returns 0 when no instantiated shape
+// fits.
 int gc_lanczos_shape(int d, const int *ext, int V, int *block, int *seg);
 size_t gc_lanczos_lds_bytes(int d, int N0, int seg, int V, int lmax);
-hipError_t gc_lanczos_occupancy(int block, int seg, size_t lds_bytes, int *blocks_per_cu);
-hipError_t gc_launch_lanczos(int block, int seg, const GcJobDev *jobs, int n_jobs, unsigned long long *next, int grid,
-                             size_t lds_bytes, hipStream_t s);
+hipError_t gc_lanczos_occupancy(int d, int block, int seg, size_t lds_bytes, int *blocks_per_cu);
+hipError_t gc_launch_lanczos(int d, int block, int seg, const GcJobDev *jobs, int n_jobs, unsigned long long *next,
+                             int grid, size_t lds_bytes, hipStream_t s);
 
 // Table and bookkeeping kernels.
 hipError_t gc_launch_reset(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);

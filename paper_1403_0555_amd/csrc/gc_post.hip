@@ -14,7 +14,7 @@
 //                region test).
 // Also the table bookkeeping kernels: reset, representatives, compaction,
 // and the patch of re-filtered representatives.
-#include "gc_common.h"
+#include "gc_filter.h"
 
 #include <algorithm>
 #include <cstdio>
@@ -94,223 +94,6 @@ __device__ GcEntry *table_find(const GcJobDev &J, uint64_t key_hi, uint64_t key_
         idx = (idx + 1) & mask;
     }
     return nullptr;
-}
-
-// Workgroup reductions over B threads: wave reductions, then the waves'
-// partials combined in a fixed order.  Every thread returns the result.
-// Successive calls on one scratch array alternate between its two halves
-// (ph toggles), so a call needs a single barrier: a half is rewritten only
-// after every wave has passed the barrier of the call in between, and so has
-// finished reading it.
-template <int B, int N>
-__device__ __forceinline__ void wg_sum_n(double (&v)[N], double *red, int &ph)
-{
-#pragma unroll
-    for (int n = 0; n < N; ++n) v[n] = wave_sum(v[n]);
-    if (B > 64) {
-        double *r = red + ph * (4 * (B / 64));
-        ph ^= 1;
-        if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-            for (int n = 0; n < N; ++n) r[n * (B / 64) + (threadIdx.x >> 6)] = v[n];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int n = 0; n < N; ++n) {
-            double t = r[n * (B / 64)];
-#pragma unroll
-            for (int w = 1; w < B / 64; ++w) t += r[n * (B / 64) + w];
-            v[n] = t;
-        }
-    }
-}
-
-template <int B>
-__device__ __forceinline__ uint64_t wg_sum_u64(uint64_t v, uint64_t *red, int &ph)
-{
-    v = wave_sum_u64(v);
-    if (B > 64) {
-        uint64_t *r = red + ph * (B / 64);
-        ph ^= 1;
-        if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = v;
-        __syncthreads();
-        uint64_t t = r[0];
-#pragma unroll
-        for (int w = 1; w < B / 64; ++w) t += r[w];
-        v = t;
-    }
-    return v;
-}
-
-template <int B>
-__device__ __forceinline__ int wg_min_int(int v, int *red, int &ph)
-{
-    v = wave_min_int(v);
-    if (B > 64) {
-        int *r = red + ph * (B / 64);
-        ph ^= 1;
-        if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = v;
-        __syncthreads();
-        int t = r[0];
-#pragma unroll
-        for (int w = 1; w < B / 64; ++w) t = min(t, r[w]);
-        v = t;
-    }
-    return v;
-}
-
-typedef __attribute__((address_space(3))) const double lds_cdouble;
-
-// Number of eigenvalues of the k x k tridiagonal below x: the sign changes
-// of the Sturm sequence p_0 = 1, p_j = det(T_j - x) = (alpha_j - x) p_{j-1}
-// - beta_{j-1}^2 p_{j-2}.  An exact zero is replaced by the smallest normal
-// number of the sign opposite to its predecessor (the usual convention for
-// a vanishing term; the next term then takes that sign too).  Division- and
-// branch-free: one dependent FMA and a select per step, sign changes counted
-// from the sign bits.  The diagonal and off-diagonal are fetched from LDS
-// four rows ahead of the recurrence, and the pair (p_{j-1}, p_j) is rescaled
-// by a power of two after every four rows, which keeps it in range and
-// leaves every sign unchanged.
-__device__ __forceinline__ double sturm_nonzero(double p, double prev)
-{
-    return (p == 0.0) ? -copysign(0x1.0p-1022, prev) : p;
-}
-
-__device__ __forceinline__ int sign_change(double a, double b)
-{
-    return (int)(((uint64_t)__double_as_longlong(a) ^ (uint64_t)__double_as_longlong(b)) >> 63);
-}
-
-__device__ __forceinline__ void sturm_step(double a, double b2, double x, double &p0, double &p1, int &cnt)
-{
-    const double p2 = sturm_nonzero(fma(a - x, p1, -b2 * p0), p1);
-    cnt += sign_change(p2, p1);
-    p0 = p1;
-    p1 = p2;
-}
-
-__device__ int sturm_count(lds_cdouble *alpha, lds_cdouble *beta2, int k, double x)
-{
-    double p0 = 1.0, p1 = sturm_nonzero(alpha[0] - x, 1.0);
-    int cnt = sign_change(p1, 1.0);
-    int j = 1;
-    for (; j + 4 <= k; j += 4) {
-        double a[4], b[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            a[u] = alpha[j + u];
-            b[u] = beta2[j + u - 1];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) sturm_step(a[u], b[u], x, p0, p1, cnt);
-        int e;
-        (void)frexp(p1, &e);
-        p0 = ldexp(p0, -e);
-        p1 = ldexp(p1, -e);
-    }
-    for (; j < k; ++j) sturm_step(alpha[j], beta2[j - 1], x, p0, p1, cnt);
-    return cnt;
-}
-
-// Smallest eigenvalue of the tridiagonal by (B+1)-section inside [lo, hi]
-// (count(lo) = 0, count(hi) >= 1), to a bracket of 1e-15 max(1, |theta|)
-// when final, else of tol_rel / 100 of that (the convergence test compares
-// values at tol_rel, and the value it accepts is this one, so its bracket
-// error stays a hundredth of the test's tolerance).  Unless final (or the workgroup is a
-// single wave, whose rounds are cheap), the search stops early when the
-// eigenvalue lies more than 1e6 tol_rel max(1, |theta|) below prev
-// (the previous check's upper bound) and the bracket is small against that
-// distance: the convergence test then fails whatever the remaining digits
-// are.  hi_out receives the final upper end, a guaranteed upper bound.
-template <int B>
-__device__ double tridiag_min_eig(lds_cdouble *alpha, lds_cdouble *beta2, int k, double lo, double hi, int *ired,
-                                  int &iph, double prev, double tol_rel, bool final, double &hi_out)
-{
-    const double width = final ? 1e-15 : 1e-2 * tol_rel;
-    for (int round = 0; round < 24; ++round) {
-        if (hi - lo <= width * fmax(1.0, fabs(hi))) break;
-        if (!final && B > 64) {   // a round costs barriers only for several waves
-            const double gap = prev - hi, scale = fmax(1.0, fabs(hi));
-            const bool fails = gap > 1e6 * tol_rel * scale;   // far from converging
-            const double need = (prev < INFINITY) ? 0.05 * gap : 1e-4 * scale;
-            if (fails && hi - lo <= need) break;
-        }
-        const double step = (hi - lo) / (double)(B + 1);
-        const double x = lo + step * (double)(threadIdx.x + 1);
-        const int first = wg_min_int<B>(sturm_count(alpha, beta2, k, x) >= 1 ? (int)threadIdx.x : B, ired, iph);
-        const double nlo = (first == 0) ? lo : lo + step * (double)first;
-        const double nhi = (first == B) ? hi : lo + step * (double)(first + 1);
-        lo = nlo;
-        hi = nhi;
-    }
-    hi_out = hi;
-    return 0.5 * (lo + hi);
-}
-
-// Smallest Ritz value of the k x k tridiagonal, inside the Gershgorin
-// interval [glo, ghi].  By interlacing it never increases as k grows, so the
-// previous check's upper bound prev bounds it above; a window below it is
-// tried first.
-template <int B>
-__device__ double ritz_min(lds_cdouble *alpha, lds_cdouble *beta2, int k, double glo, double ghi, double prev,
-                           double prev_step, int *ired, int &iph, double tol_rel, bool final, double &hi_out)
-{
-    double lo = glo - 1e-12 * (1.0 + fabs(glo));
-    double hi = ghi + 1e-12 * (1.0 + fabs(ghi));
-    if (prev < hi) {
-        const double top = prev + 1e-12 * (1.0 + fabs(prev));
-        const double bot = top - fmax(4.0 * prev_step, 1e-9 * (1.0 + fabs(prev)));
-        const bool top_ok = sturm_count(alpha, beta2, k, top) >= 1;
-        if (top_ok && bot > lo && sturm_count(alpha, beta2, k, bot) == 0)
-            return tridiag_min_eig<B>(alpha, beta2, k, bot, top, ired, iph, prev, tol_rel, final, hi_out);
-        if (top_ok) hi = top;
-    }
-    return tridiag_min_eig<B>(alpha, beta2, k, lo, hi, ired, iph, prev, tol_rel, final, hi_out);
-}
-
-// Lanczos stops when the lowest Ritz value moved by at most this relative
-// amount since the previous check (at least 8 iterations earlier).  Its
-// error is then of the same order, some 1e-11 in absolute terms for these
-// operators, far below the region threshold (1e-6).
-constexpr double kRitzTol = 1e-10;
-
-__device__ uint32_t region_flags(double lam2, double tol)
-{
-    if (lam2 > tol) return GC_F_IN_REGION;
-    if (lam2 < -tol) return GC_F_SADDLE;
-    return GC_F_SINGULAR;
-}
-
-constexpr uint32_t kFilterFlags = GC_F_IN_REGION | GC_F_SINGULAR | GC_F_SADDLE | GC_F_LANCZOS_CAP;
-
-// The filter's results: into the copy and its representative's start record.
-__device__ void write_filter(const GcJobDev &J, uint64_t c, uint64_t local, double lam2, uint32_t flags, uint32_t lit)
-{
-    GcCopyRec &cp = J.copies[c];
-    cp.lambda2 = lam2;
-    cp.flags |= flags & kFilterFlags;
-    cp.lanczos_iters = lit;
-    GcStartRec &r = J.rec[local];
-    r.lambda2 = lam2;
-    r.flags = (r.flags & ~kFilterFlags) | (flags & kFilterFlags);
-    r.lanczos_iters = lit;
-}
-
-// The item of a filter pass: copy s of the concatenated copy lists of the
-// jobs (job order), or jn = -1 past the end.
-__device__ __forceinline__ void copy_item(const GcJobDev *jobs, int n_jobs, uint64_t s, int &jn, uint64_t &c)
-{
-    uint64_t base = 0;
-    jn = -1;
-    for (int j = 0; j < n_jobs; ++j) {
-        const uint64_t nc = *jobs[j].n_copies;
-        if (s < base + nc) {
-            jn = j;
-            break;
-        }
-        base += nc;
-    }
-    c = s - base;
 }
 
 // Values at a thread's own sites i = tid + B k: registers, or a strided
@@ -678,220 +461,6 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
     }
 }
 
-// FP filter in the line-segment layout, one workgroup of B threads per copy
-// of the compacted tables (at the copy's representative start): thread t
-// owns S consecutive sites along direction 0 (x_0 runs fastest, so they are
-// consecutive site indices), segment t % (N_0/S) of line t / (N_0/S).  The
-// Lanczos vector u of the own sites, q_{j-1} and M u stay in registers, and
-// so do the direction-0 link weights; direction-0 neighbours inside the
-// segment are the thread's own entries.  LDS holds u (8V bytes) for the
-// other threads, the forward link weights of directions 1..d-1 (and of
-// direction 0 when a line has several segments), V doubles each, and the
-// tridiagonal; the state g is staged over the weights at the start.  The
-// iteration is post_kernel's: one reduction per iteration, the same formulas
-// per site.
-template <int B, int S>
-__global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__ jobs, int n_jobs,
-                                                    unsigned long long *next)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[2 * 4 * (B / 64)];
-    __shared__ int ired[2 * (B / 64)];
-    __shared__ unsigned long long claim;
-    int rph = 0, iph = 0;   // halves of the reduction scratch in use
-    for (;;) {
-        const int tid = (int)threadIdx.x + opaque_zero();
-        if (tid == 0) claim = atomicAdd(next, 1ULL);
-        __syncthreads();
-        const uint64_t s = uniform((uint64_t)claim);
-        __syncthreads();
-        int jn;
-        uint64_t c;
-        copy_item(jobs, n_jobs, s, jn, c);
-        jn = uniform(jn);
-        if (jn < 0) break;
-        const GcJobDev &J = jobs[jn];
-        const GcOrbitDev &O = J.orb;
-        const int V = O.V, d = O.d, N0 = O.ext[0];
-        const uint64_t local = J.copies[c].rep_start - J.first_start;
-        const int nseg = N0 / S;
-        const bool act = tid < V / S;
-        const int line = act ? tid / nseg : 0, o = act ? (tid % nseg) * S : 0;
-        const int i0 = line * N0 + o;
-        const bool whole = (S == N0);   // the segment is a whole line
-        const int nw = whole ? d - 1 : d;   // weight arrays in LDS
-        const int w0off = whole ? -1 : 0;   // LDS array of direction mu: mu + w0off
-        lds_ptr<double> u = as_lds(reinterpret_cast<double *>(smem));
-        lds_ptr<double> wl = u + V;
-        const int lmax = min(min(J.lanczos_max, GC_LMAX), V);
-        lds_ptr<double> alpha = wl + (size_t)nw * V;
-        lds_ptr<double> beta2 = alpha + lmax;
-
-        // own link weights w = Re(conj(g_i) U_{i,mu} g_{i+mu}) from the
-        // representative's state in global memory: direction 0 into
-        // registers, the others into LDS
-        glb_ptr<const dbl2> src = as_global(reinterpret_cast<const dbl2 *>(J.states + local * (uint64_t)V));
-        glb_ptr<const dbl2> Ug = as_global(reinterpret_cast<const dbl2 *>(O.U64));
-        double w0[S];
-        int df[GC_MAXD], db[GC_MAXD];   // neighbour offsets of directions >= 1 (the same for every own site)
-#pragma unroll
-        for (int mu = 0; mu < GC_MAXD; ++mu) {
-            df[mu] = 0;
-            db[mu] = 0;
-            if (act && mu > 0 && mu < d) {
-                df[mu] = (int)O.nbr[mu * V + i0] - i0;
-                db[mu] = (int)O.nbr[(d + mu) * V + i0] - i0;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
-            const int i = i0 + k;
-            w0[k] = 0.0;
-            if (act) {
-                const dbl2 gi = src[i];
-#pragma unroll
-                for (int mu = 0; mu < GC_MAXD; ++mu) {
-                    if (mu < d) {
-                        const dbl2 gf = src[O.nbr[mu * V + i]];
-                        const dbl2 uu = Ug[mu * V + i];
-                        const double tr = uu.x * gf.x - uu.y * gf.y, ti = uu.x * gf.y + uu.y * gf.x;
-                        const double ur = gi.x * tr + gi.y * ti;
-                        if (mu == 0) w0[k] = ur;
-                        if (mu + w0off >= 0) wl[(mu + w0off) * V + i] = ur;
-                    }
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        double uo[S], qp[S], mv[S];
-        double sums[1] = {0.0};
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
-            const int i = i0 + k;
-            qp[k] = 0.0;
-            uo[k] = 0.0;
-            mv[k] = 0.0;
-            if (act) {
-                const double x = (double)(mix64((uint64_t)i + 0x5851F42D4C957F2DULL) >> 11) * 0x1.0p-53 - 0.5;
-                uo[k] = x;
-                sums[0] += x;
-            }
-        }
-        wg_sum_n<B, 1>(sums, red, rph);
-        const double mean = sums[0] / (double)V;
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
-            if (act) {
-                uo[k] -= mean;
-                u[i0 + k] = uo[k];
-            }
-        }
-        const double sigma = 4.0 * d + 1.0;
-        double theta = INFINITY, theta_old = INFINITY, theta_step = 1.0;
-        double rows_lo = INFINITY, rows_hi = -INFINITY;   // Gershgorin bounds of the complete rows
-        double a_prev = 0.0, b_prev2 = 0.0;                // alpha_{j-1}, beta_{j-2}
-        int next_check = 24;                               // iteration count of the next Ritz check
-        int it = 0;
-        bool conv = false;
-        // the neighbours across the ends of a segment that is not a whole line
-        const int ia = line * N0 + (o + S) % N0, ib = line * N0 + (o + N0 - 1) % N0;
-        for (it = 0; it < lmax; ++it) {
-            if (B > 64) __syncthreads();   // u and the weights complete in LDS
-            else wave_sync();
-            double s4[4] = {0.0, 0.0, 0.0, 0.0};
-            if (act) {
-                const double ua = whole ? uo[0] : u[ia];
-                const double ub = whole ? uo[S - 1] : u[ib];
-                const double wbe = whole ? w0[S - 1] : wl[ib];
-#pragma unroll
-                for (int k = 0; k < S; ++k) {
-                    const int i = i0 + k + opaque_zero();
-                    const double ui = uo[k];
-                    // direction 0: neighbours and weights of the own segment
-                    const double uf = (k + 1 < S) ? uo[k + 1] : ua;
-                    const double ubk = (k > 0) ? uo[k - 1] : ub;
-                    const double wb0 = (k > 0) ? w0[k - 1] : wbe;
-                    double m = w0[k] * (ui - uf) + wb0 * (ui - ubk);
-#pragma unroll
-                    for (int mu = 1; mu < GC_MAXD; ++mu)
-                        if (mu < d) {
-                            const int a = (mu + w0off) * V;
-                            m += wl[a + i] * (ui - u[i + df[mu]]) + wl[a + i + db[mu]] * (ui - u[i + db[mu]]);
-                        }
-                    mv[k] = m;
-                    s4[0] += ui * ui;
-                    s4[1] += ui * m;
-                    s4[2] += ui;
-                    s4[3] += ui * qp[k];
-                    // one site at a time: bounds the loads in flight
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-            wg_sum_n<B, 4>(s4, red, rph);
-            const double bt = sqrt(s4[0]);
-            const double bp = it > 0 ? bt : 0.0;      // beta_{j-1} (the start vector's norm is not in T)
-            if (it > 0) {
-                if (tid == 0) beta2[it - 1] = s4[0];
-                rows_lo = fmin(rows_lo, a_prev - b_prev2 - bt);
-                rows_hi = fmax(rows_hi, a_prev + b_prev2 + bt);
-                if (bt <= 1e-13 * sigma) {
-                    // the Krylov space is exhausted: T of it rows is exact
-                    if (B > 64) __syncthreads();
-                    else wave_sync();
-                    double theta_hi;
-                    theta = ritz_min<B>(alpha, beta2, it, rows_lo, rows_hi, theta_old, theta_step, ired, iph,
-                                        kRitzTol, true, theta_hi);
-                    conv = true;
-                    break;
-                }
-            }
-            const double inv = 1.0 / bt;
-            const double sq = s4[2] * inv;
-            const double shift = sigma * sq / (double)V;
-            const double a_j = s4[1] * inv * inv + shift * sq - bp * (s4[3] * inv);
-            if (tid == 0) alpha[it] = a_j;
-            if (act) {
-#pragma unroll
-                for (int k = 0; k < S; ++k) {
-                    const double q = uo[k] * inv;
-                    const double r = mv[k] * inv + shift - bp * qp[k] - a_j * q;
-                    qp[k] = q;
-                    uo[k] = r;
-                    u[i0 + k] = r;
-                }
-            }
-            if (it + 1 >= next_check || it + 1 == lmax) {
-                if (B > 64) __syncthreads();   // the tridiagonal is complete in LDS
-                else wave_sync();
-                const bool final = it + 1 == lmax;
-                double theta_hi;
-                theta = ritz_min<B>(alpha, beta2, it + 1, fmin(rows_lo, a_j - bp), fmax(rows_hi, a_j + bp),
-                                    theta_old, theta_step, ired, iph, kRitzTol, final, theta_hi);
-                const double tol = kRitzTol * fmax(1.0, fabs(theta));
-                const double change = theta_old - theta;
-                if (fabs(change) <= tol) {
-                    conv = true;
-                    ++it;
-                    break;
-                }
-                const int gap = !(change <= 1e6 * tol) ? 24 : !(change <= 1e3 * tol) ? 16 : 8;
-                next_check = it + 1 + gap;
-                if (theta_old < INFINITY) theta_step = change;
-                theta_old = theta_hi;
-            }
-            b_prev2 = bp;
-            a_prev = a_j;
-        }
-        uint32_t flags = region_flags(theta, J.lambda_tol);
-        if (!conv) flags |= GC_F_LANCZOS_CAP;
-        if (tid == 0) {
-            write_filter(J, c, local, theta, flags, (uint32_t)it);
-            atomicAdd(&J.cnt->lanczos_runs, 1ULL);
-        }
-        __syncthreads();
-    }
-}
-
 __global__ void reset_kernel(GcJobDev J)
 {
     const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1208,51 +777,36 @@ size_t gc_lanczos_lds_bytes(int d, int N0, int S, int V, int lmax)
     return 8 * (size_t)V + 8 * (size_t)nw * V + 16 * l;
 }
 
-#define GC_LANCZOS_SEG(FN, B, ...)                                                                        \
-    switch (seg) {                                                                                        \
-    case 1: return FN<B, 1>(__VA_ARGS__);                                                                 \
-    case 2: return FN<B, 2>(__VA_ARGS__);                                                                 \
-    case 3: return FN<B, 3>(__VA_ARGS__);                                                                 \
-    case 4: return FN<B, 4>(__VA_ARGS__);                                                                 \
-    case 5: return FN<B, 5>(__VA_ARGS__);                                                                 \
-    case 6: return FN<B, 6>(__VA_ARGS__);                                                                 \
-    case 7: return FN<B, 7>(__VA_ARGS__);                                                                 \
-    case 8: return FN<B, 8>(__VA_ARGS__);                                                                 \
-    case 10: return FN<B, 10>(__VA_ARGS__);                                                               \
-    default: return hipErrorInvalidValue;                                                                 \
+#define GC_LANCZOS_DECLARE_DIM(D)                                                                         \
+    hipError_t gc_lanczos_occupancy_d##D(int block, int seg, size_t lds_bytes, int *blocks_per_cu);       \
+    hipError_t gc_launch_lanczos_d##D(int block, int seg, const GcJobDev *jobs, int n_jobs,               \
+                                      unsigned long long *next, int grid, size_t lds_bytes, hipStream_t s);
+GC_LANCZOS_DECLARE_DIM(1)
+GC_LANCZOS_DECLARE_DIM(2)
+GC_LANCZOS_DECLARE_DIM(3)
+GC_LANCZOS_DECLARE_DIM(4)
+
+hipError_t gc_lanczos_occupancy(int d, int block, int seg, size_t lds_bytes, int *blocks_per_cu)
+{
+    switch (d) {
+    case 1: return gc_lanczos_occupancy_d1(block, seg, lds_bytes, blocks_per_cu);
+    case 2: return gc_lanczos_occupancy_d2(block, seg, lds_bytes, blocks_per_cu);
+    case 3: return gc_lanczos_occupancy_d3(block, seg, lds_bytes, blocks_per_cu);
+    case 4: return gc_lanczos_occupancy_d4(block, seg, lds_bytes, blocks_per_cu);
+    default: return hipErrorInvalidValue;
     }
-#define GC_LANCZOS_DISPATCH(FN, ...)                                                                      \
-    switch (block) {                                                                                      \
-    case 64: GC_LANCZOS_SEG(FN, 64, __VA_ARGS__)                                                          \
-    case 128: GC_LANCZOS_SEG(FN, 128, __VA_ARGS__)                                                        \
-    case 256: GC_LANCZOS_SEG(FN, 256, __VA_ARGS__)                                                        \
-    case 512: GC_LANCZOS_SEG(FN, 512, __VA_ARGS__)                                                        \
-    default: return hipErrorInvalidValue;                                                                 \
+}
+
+hipError_t gc_launch_lanczos(int d, int block, int seg, const GcJobDev *jobs, int n_jobs, unsigned long long *next,
+                             int grid, size_t lds_bytes, hipStream_t s)
+{
+    switch (d) {
+    case 1: return gc_launch_lanczos_d1(block, seg, jobs, n_jobs, next, grid, lds_bytes, s);
+    case 2: return gc_launch_lanczos_d2(block, seg, jobs, n_jobs, next, grid, lds_bytes, s);
+    case 3: return gc_launch_lanczos_d3(block, seg, jobs, n_jobs, next, grid, lds_bytes, s);
+    case 4: return gc_launch_lanczos_d4(block, seg, jobs, n_jobs, next, grid, lds_bytes, s);
+    default: return hipErrorInvalidValue;
     }
-
-template <int B, int S>
-static hipError_t lanczos_occ_t(size_t lds, int *per_cu)
-{
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, lanczos_kernel<B, S>, B, lds);
-}
-
-template <int B, int S>
-static hipError_t lanczos_launch_t(const GcJobDev *jobs, int n_jobs, unsigned long long *next, int grid, size_t lds,
-                                   hipStream_t s)
-{
-    hipLaunchKernelGGL((lanczos_kernel<B, S>), dim3(grid), dim3(B), lds, s, jobs, n_jobs, next);
-    return hipGetLastError();
-}
-
-hipError_t gc_lanczos_occupancy(int block, int seg, size_t lds_bytes, int *blocks_per_cu)
-{
-    GC_LANCZOS_DISPATCH(lanczos_occ_t, lds_bytes, blocks_per_cu)
-}
-
-hipError_t gc_launch_lanczos(int block, int seg, const GcJobDev *jobs, int n_jobs, unsigned long long *next, int grid,
-                             size_t lds_bytes, hipStream_t s)
-{
-    GC_LANCZOS_DISPATCH(lanczos_launch_t, jobs, n_jobs, next, grid, lds_bytes, s)
 }
 
 hipError_t gc_launch_reset(const GcJobDev *jobs_host, int n_jobs, hipStream_t s)
