@@ -489,8 +489,10 @@ def main():
     }
     out.update(extra)
     if not args.no_cpu:
-        n_sample = args.cpu_sample or (5000 if V <= 256 else 16)
-        out["cpu_baseline"] = cpu_baseline(w, r["phi"], min(n_sample, n), 2 if V > 256 else 200)
+        # about 10-20 s of oracle work on the machine's host threads, a few
+        # seconds on one core
+        n_sample = args.cpu_sample or (5000 if V <= 256 else 144)
+        out["cpu_baseline"] = cpu_baseline(w, r["phi"], min(n_sample, n), 16 if V > 256 else 200)
     print(json.dumps(out), flush=True)
 
 
