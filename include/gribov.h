@@ -371,27 +371,27 @@ gc_status gc_launch_static(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const
 
 /* Result of gc_autotune. */
 typedef struct {
-    int32_t relax_variant;          /* colours whose coefficients a lane keeps in registers (0..2), plus 8
-                                       when a workgroup of several wavefronts shares each start */
+    int32_t relax_variant;          /* colours whose coefficients a lane keeps in registers (0..2); 0 for
+                                       lattices with more than two slots per lane (nothing to tune there) */
     int32_t post_block;             /* FP filter kernel of this lattice: threads per workgroup */
     int32_t post_sites_per_thread;  /* and sites per thread (not tuned: the shape follows from the lattice) */
     int32_t pad;
     double relax_ms, post_ms;       /* best measured times of the chosen variants */
 } gc_tune_result;
 
-/* Kernel-variant autotuner for the shape of this orbit (Sec. III sweeps and
- * the first-region filter; the variants compute the same quantities).  Runs
- * timed launches of n_starts starts with params on the orbit, synchronously:
- * a warm-up, then each relax variant (for lattices with more than two slots
- * per lane: one wavefront or a workgroup per start; coefficients of 0, 1 or
- * 2 colours held in registers where a lane has at most two slots) and each
- * post-kernel
- * workgroup shape that covers V, two launches each, timed with HIP events.
- * The fastest choices are stored in the context and used by every later
- * launch of an orbit with the same dimension, slots per lane and precision
- * (relax) or volume (post).  The orbit's results afterwards are those of the
- * last trial launch.  out may be NULL.  Errors: GC_EINVAL (no orbit,
- * n_starts = 0), GC_EBUSY (orbit running), launch errors. */
+/* Kernel-variant autotuner for the shape of this orbit (Sec. III sweeps).
+ * Runs timed launches of n_starts starts with params on the orbit,
+ * synchronously: a warm-up, then, where a lane holds at most two slots per
+ * colour, the relax variants that keep the coefficients of 0, 1 or 2 colours
+ * in registers, two launches each, timed with HIP events.  The variants
+ * compute the same products in the same order, so results are bitwise the
+ * same whatever is chosen.  The fastest choice is stored in the context (and
+ * in the tuning cache) and used by every later launch of an orbit with the
+ * same dimension, slots per lane and precision.  The filter's shape follows
+ * from the lattice and is reported, not tuned.  The orbit's results
+ * afterwards are those of the last trial launch.  out may be NULL.  Errors:
+ * GC_EINVAL (no orbit, n_starts = 0), GC_EBUSY (orbit running), launch
+ * errors. */
 gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_solve_params *params,
                       gc_tune_result *out);
 

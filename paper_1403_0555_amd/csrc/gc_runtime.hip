@@ -273,7 +273,7 @@ struct Job {
     double solve_ms = 0.0, post_ms = 0.0, filter_ms = 0.0;
     uint64_t total = 0;
     // kernel variants forced for this job (gc_autotune trials), -1 / 0: none
-    int force_creg = -1, force_wps = -1;
+    int force_creg = -1;
     std::vector<double> theta;       // the caller's start angles [n][V] (gc_launch_from), else empty
 };
 
@@ -312,7 +312,6 @@ struct gc_ctx {
     // kernel variants chosen by gc_autotune: relax coefficient colours and
     // layout per (d, slots per lane, precision), post workgroup shape per V
     std::map<uint64_t, int> tune_creg;
-    std::map<uint64_t, int> tune_wps;   // workgroup-per-start layout on (1) or off (0)
     std::string tune_cache;             // file the choices persist in ("" none)
     uint64_t budget = 0, used = 0;
     std::vector<hipStream_t> streams;   // launch streams (the caller's one when given)
@@ -639,13 +638,11 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         const int o_ns = (o->V / 2 + 63) / 64;
         int wps = (o->K == 2) ? gc_wps_for(o_ns) : -1;
         if (wps > 0 && (size_t)(GC_WAVES + 1) * 16 * o->V <= ctx->lds_max) {
-            // both layouts fit: one wavefront per start unless tuned otherwise
-            int on = 0;
-            const auto tw = ctx->tune_wps.find(creg_key(o->d, o_ns, mixed));
-            if (tw != ctx->tune_wps.end()) on = tw->second;
-            if (ctx->wps_override >= 0) on = ctx->wps_override;
-            if (job->force_wps >= 0) on = job->force_wps;
-            if (!on) wps = 0;
+            // both layouts fit: one wavefront per start (the exchange-region
+            // kernel measured several times faster than a workgroup per
+            // start, and it keeps one reduction order for a shape), unless
+            // the context forces the workgroup layout
+            if (ctx->wps_override <= 0) wps = 0;
         }
         if (wps > 0 && 32 * (size_t)o->V > ctx->lds_max) wps = -1;
         const bool wave = (o->K == 2) && wps >= 0 && (wps > 0 || (size_t)(GC_WAVES + 1) * 16 * o->V <= ctx->lds_max);
@@ -1541,17 +1538,13 @@ gc_status launch_locked(gc_ctx *ctx, const std::vector<Orbit *> &orbits, const s
     job->n_starts = n_starts;
     job->p = p;
     job->graph = graph;
-    if (force) {
-        job->force_creg = force->force_creg;
-        job->force_wps = force->force_wps;
-    }
+    if (force) job->force_creg = force->force_creg;
     gc_status st = enqueue_locked(ctx, job);
     if (st != GC_OK) delete job;
     return st;
 }
 
-// Tuning cache: one line per choice, "creg <key> <value>" or "wps <key>
-// <value>".
+// Tuning cache: one line per choice, "creg <key> <value>".
 void load_tune_cache(gc_ctx *ctx)
 {
     FILE *f = fopen(ctx->tune_cache.c_str(), "r");
@@ -1561,8 +1554,7 @@ void load_tune_cache(gc_ctx *ctx)
     int a = 0;
     while (fscanf(f, "%15s %llu %d", kind, &k, &a) == 3) {
         if (!strcmp(kind, "creg")) ctx->tune_creg[(uint64_t)k] = a;
-        else if (!strcmp(kind, "wps")) ctx->tune_wps[(uint64_t)k] = a;
-        else break;
+        else if (strcmp(kind, "wps")) break;   // layout choices of older caches: no longer tuned
     }
     fclose(f);
 }
@@ -1574,7 +1566,6 @@ void save_tune_cache(gc_ctx *ctx)
     FILE *f = fopen(tmp.c_str(), "w");
     if (!f) return;
     for (auto &kv : ctx->tune_creg) fprintf(f, "creg %llu %d\n", (unsigned long long)kv.first, kv.second);
-    for (auto &kv : ctx->tune_wps) fprintf(f, "wps %llu %d\n", (unsigned long long)kv.first, kv.second);
     fclose(f);
     (void)rename(tmp.c_str(), ctx->tune_cache.c_str());
 }
@@ -2115,10 +2106,9 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
     const bool mixed = p.precision == GC_MIXED;
     // one measured launch with the given variant forced on that launch only
     // (launches of other orbits meanwhile use the context's choices)
-    auto trial = [&](int creg, int wps, double *relax_ms, double *post_ms) -> gc_status {
+    auto trial = [&](int creg, double *relax_ms, double *post_ms) -> gc_status {
         Job force;
         force.force_creg = creg;
-        force.force_wps = wps;
         gc_status s2;
         {
             std::unique_lock<std::mutex> lk(ctx->mu);
@@ -2139,34 +2129,18 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
     const int ns = (V / 2 + 63) / 64;
     const int cmax = wave ? gc_wave_creg_max(d, ns) : 0;
     double rm = 0, pm = 0;
-    st = trial(-1, -1, &rm, &pm);   // warm-up: code objects, pool
+    st = trial(-1, &rm, &pm);   // warm-up: code objects, pool
     if (st != GC_OK) return st;
-    // relax layout for more than two slots per lane: one wavefront per start
-    // or a workgroup per start, best of two launches each
-    const bool wps_ok = (K == 2) && gc_wps_for(ns) > 0 && 32 * (size_t)V <= ctx->lds_max &&
-                        (size_t)(GC_WAVES + 1) * 16 * V <= ctx->lds_max;
-    int best_w = 0;
     double best_r = INFINITY;
-    if (wps_ok) {
-        double tw[2] = {INFINITY, INFINITY};
-        for (int w = 0; w < 2; ++w)
-            for (int rep = 0; rep < 2; ++rep) {
-                st = trial(0, w, &rm, &pm);
-                if (st != GC_OK) return st;
-                tw[w] = std::min(tw[w], rm);
-            }
-        best_w = tw[1] < tw[0] ? 1 : 0;
-        best_r = tw[best_w];
-    }
     // relax: register-coefficient colours 0..cmax of the one-wavefront
     // layout (the workgroup layout has no such variants), best of two each
     int best_c = 0;
-    if (!best_w) {
+    {
         double bc = INFINITY;
         for (int c = 0; c <= cmax; ++c) {
             double t = INFINITY;
             for (int rep = 0; rep < 2; ++rep) {
-                st = trial(c, 0, &rm, &pm);
+                st = trial(c, &rm, &pm);
                 if (st != GC_OK) return st;
                 t = std::min(t, rm);
             }
@@ -2176,8 +2150,7 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
     }
     {
         std::lock_guard<std::mutex> g(ctx->mu);
-        if (wps_ok) ctx->tune_wps[creg_key(d, ns, mixed)] = best_w;
-        if (wave && !best_w) ctx->tune_creg[creg_key(d, ns, mixed)] = best_c;
+        if (wave) ctx->tune_creg[creg_key(d, ns, mixed)] = best_c;
         save_tune_cache(ctx);
     }
     // the filter's shape depends on the lattice only: reported, not tuned
@@ -2192,7 +2165,7 @@ gc_status gc_autotune(gc_ctx *ctx, gc_orbit orbit, uint64_t n_starts, const gc_s
             gc_post_shape(V, &db, &dsp, &dw);
         }
     }
-    r.relax_variant = best_c + (best_w ? 8 : 0);
+    r.relax_variant = best_c;
     r.relax_ms = best_r;
     r.post_block = db;
     r.post_sites_per_thread = dsp;

@@ -120,9 +120,9 @@ def test_launch_while_busy_is_refused():
 
 @pytest.mark.parametrize("extent,precision,n", [((4, 4, 4, 4), "fp64", 3000), ((8, 8, 8), "mixed", 2000)])
 def test_autotune_keeps_results(extent, precision, n):
-    """Tuned kernel variants compute the same copies: keys, hits and first
-    starts identical, F and lambda2 within rounding of a different
-    reduction order."""
+    """Tuned kernel variants compute the same copies bit for bit: the
+    variants differ in where coefficients live, not in the arithmetic or its
+    order."""
     params = gc.SolveParams(omega=1.7 if precision == "mixed" else 1.0, precision=precision)
     phi = GI.orbit_angles(extent, 2, 9)
     V = int(np.prod(extent))
@@ -133,16 +133,15 @@ def test_autotune_keeps_results(extent, precision, n):
         ref = ctx.gc_fetch(h)
         note("autotune %s %s" % (extent, precision))
         r = ctx.gc_autotune(h, n, params)
-        assert r["relax_variant"] % 8 in (0, 1, 2) and r["relax_variant"] in (0, 1, 2, 8, 9, 10)
+        assert r["relax_variant"] in (0, 1, 2)
         assert r["post_block"] * r["post_sites_per_thread"] >= V
         assert r["relax_ms"] > 0 and r["post_ms"] > 0
         ctx.gc_launch(h, n, params)
         assert ctx.gc_wait(h) == gc.GC_OK
         got = ctx.gc_fetch(h)
-        for f in ("key_hi", "key_lo", "hits", "first_start"):
+        for f in ("key_hi", "key_lo", "hits", "first_start", "rep_start", "flags", "F", "lambda2",
+                  "lanczos_iters"):
             assert np.array_equal(got[f], ref[f]), f
-        assert np.max(np.abs(got["F"] - ref["F"])) / V < 1e-12
-        assert np.max(np.abs(got["lambda2"] - ref["lambda2"])) < 1e-10
         ctx.gc_release(h)
 
 
