@@ -41,8 +41,9 @@ def relax_flops_per_site_update(d: int, omega: float) -> int:
     """Algorithmic floating-point operations of one site update: the staple
     S_i (2d complex multiply-adds, 16 d), its normalisation (8) and the
     divergence Im(conj(g_i) S_i) with its share of the stopping norm (5);
-    over-relaxation (omega != 1) adds the rotation towards S_i (24)."""
-    return 16 * d + 13 + (0 if omega == 1.0 else 24)
+    over-relaxation (omega != 1) adds the interpolation (1 - omega) g +
+    omega S/|S| (4) and its normalisation (7)."""
+    return 16 * d + 13 + (0 if omega == 1.0 else 11)
 
 
 def lanczos_flops_per_site(d: int) -> int:

@@ -97,7 +97,7 @@ typedef struct {
 } gc_lattice;
 
 typedef struct {
-    double omega;               /* 1: relaxation (eqs. (4)-(5)); (0,2): over-relaxation g <- g N(1 + omega (z - 1)) */
+    double omega;               /* 1: relaxation (eqs. (4)-(5)); (0,2): over-relaxation g <- N((1 - omega) g + omega S/|S|) */
     double eps32;               /* stop of the single-precision phase (GC_MIXED) */
     double eps64;               /* stop of the double-precision phase */
     double lambda_tol;          /* region threshold tau on lambda2 */

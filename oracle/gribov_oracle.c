@@ -27,7 +27,9 @@
  *     g_i = S_i/|S_i| with S_i = sum_mu [U_{i,mu} g_{i+mu} + conj(U_{i-mu,mu}) g_{i-mu}],
  *     which is the paper's "phase of K_i^*" rule with theta -> -theta;
  *   - over-relaxation (the paper uses none; the workloads ask for omega=1.7):
- *     z = conj(g) S/|S|, w = 1 + omega (z - 1), g <- g w/|w|;
+ *     g <- v/|v| with v = (1 - omega) g + omega S/|S|, the step from g towards
+ *     the local optimum S/|S| stretched by omega and put back on the unit
+ *     circle (for |g| = 1 this is g w/|w| with w = 1 + omega (conj(g) S/|S| - 1));
  *   - stopping: D = (1/V) sum_i div_i^2 < eps with div_i = Im(conj(g_i) S_i),
  *     evaluated on the post-sweep state, per start (never across starts);
  *     the paper's max |div| < eps rule is available as stop_norm = 1;
@@ -272,17 +274,11 @@ static void or_sweep64(const or_lattice *L, const double *Ur, const double *Ui,
                 gr[i] = hr;
                 gi[i] = hi;
             } else {
-                double zr = gr[i] * hr + gi[i] * hi;   /* conj(g) * h */
-                double zi = gr[i] * hi - gi[i] * hr;
-                double wr = 1.0 + omega * (zr - 1.0);
-                double wi = omega * zi;
-                double wn = sqrt(wr * wr + wi * wi);
-                wr = wr / wn;
-                wi = wi / wn;
-                double nr = gr[i] * wr - gi[i] * wi;
-                double ni = gr[i] * wi + gi[i] * wr;
-                gr[i] = nr;
-                gi[i] = ni;
+                double vr = (1.0 - omega) * gr[i] + omega * hr;
+                double vi = (1.0 - omega) * gi[i] + omega * hi;
+                double vn = sqrt(vr * vr + vi * vi);
+                gr[i] = vr / vn;
+                gi[i] = vi / vn;
             }
         }
     }
@@ -304,17 +300,11 @@ static void or_sweep32(const or_lattice *L, const float *Ur, const float *Ui,
                 gr[i] = hr;
                 gi[i] = hi;
             } else {
-                float zr = gr[i] * hr + gi[i] * hi;
-                float zi = gr[i] * hi - gi[i] * hr;
-                float wr = 1.0f + omega * (zr - 1.0f);
-                float wi = omega * zi;
-                float wn = sqrtf(wr * wr + wi * wi);
-                wr = wr / wn;
-                wi = wi / wn;
-                float nr = gr[i] * wr - gi[i] * wi;
-                float ni = gr[i] * wi + gi[i] * wr;
-                gr[i] = nr;
-                gi[i] = ni;
+                float vr = (1.0f - omega) * gr[i] + omega * hr;
+                float vi = (1.0f - omega) * gi[i] + omega * hi;
+                float vn = sqrtf(vr * vr + vi * vi);
+                gr[i] = vr / vn;
+                gi[i] = vi / vn;
             }
         }
     }

@@ -194,9 +194,10 @@ __device__ __forceinline__ double rsq(double x)
 
 // Local maximisation of eqs. (4)-(5) in the eq. (3) convention: from the
 // staple S, g <- S/|S| (RELAX, omega = 1) or the over-relaxed
-// g <- g N(1 + omega (z - 1)), z = conj(g) S/|S|, N(w) = w/|w|.  |S| = 0
-// leaves g unchanged.  Written without branches so that the compiler can
-// schedule a whole colour pass as one block.
+// g <- N((1 - omega) g + omega S/|S|), N(v) = v/|v| (for |g| = 1 the same
+// map as g N(1 + omega (conj(g) S/|S| - 1))).  |S| = 0 leaves g unchanged.
+// Written without branches so that the compiler can schedule a whole colour
+// pass as one block.
 template <bool RELAX, typename R>
 __device__ __forceinline__ typename cx<R>::T local_update(typename cx<R>::T g0, typename cx<R>::T s, R omega)
 {
@@ -204,21 +205,18 @@ __device__ __forceinline__ typename cx<R>::T local_update(typename cx<R>::T g0, 
     const R n2 = s.x * s.x + s.y * s.y;
     const bool ok = n2 > (R)0;
     const R r = rsq(ok ? n2 : (R)1);
-    const R hx = s.x * r, hy = s.y * r;
     C g;
     if (RELAX) {
-        g.x = hx;
-        g.y = hy;
+        g.x = s.x * r;
+        g.y = s.y * r;
     } else {
-        const R zx = g0.x * hx + g0.y * hy;
-        const R zy = g0.x * hy - g0.y * hx;
-        R wx = (R)1 + omega * (zx - (R)1);
-        R wy = omega * zy;
-        const R rw = rsq(wx * wx + wy * wy);
-        wx *= rw;
-        wy *= rw;
-        g.x = g0.x * wx - g0.y * wy;
-        g.y = g0.x * wy + g0.y * wx;
+        const R a = (R)1 - omega;
+        const R b = omega * r;
+        const R vx = fma(s.x, b, a * g0.x);
+        const R vy = fma(s.y, b, a * g0.y);
+        const R rv = rsq(vx * vx + vy * vy);
+        g.x = vx * rv;
+        g.y = vy * rv;
     }
     g.x = ok ? g.x : g0.x;
     g.y = ok ? g.y : g0.y;
