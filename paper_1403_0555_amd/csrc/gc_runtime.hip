@@ -678,7 +678,7 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         } else if (g.wave) {
             g.ns = (gV / 2 + 63) / 64;
             g.block = 64 * gc_wave_starts_per_wg(g.ns);
-            g.rm = g.ns > 2 ? gc_wave_relax_mode(job->p.omega) : 0;
+            g.rm = g.ns > 2 ? gc_wave_relax_mode(job->p.omega, job->p.stop_norm) : 0;
             size_t coef_bytes = 0;
             for (int j : g.jobs) {
                 const Orbit *o = job->orbits[j];
@@ -687,9 +687,8 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             // neighbour table + states (two-colour regions of 16V, or 8V
             // exchange regions of the register-resident kernel) + links
             // staged in LDS
-            const size_t states =
-                g.ns > 2 ? (size_t)(1 + gc_links_in_lds(g.d, ns_bucket(g.d, g.ns))) * 16 * gV + (size_t)GC_WAVES_RR * 8 * gV
-                         : (size_t)(GC_WAVES + 1) * 16 * gV;
+            const size_t states = g.ns > 2 ? gc_rr_lds_bytes(g.d, ns_bucket(g.d, g.ns), gV)
+                                           : (size_t)(GC_WAVES + 1) * 16 * gV;
             // a staged coefficient table only where a lane has at most two
             // slots; above, the links are read through buffer loads
             g.coef_lds = (g.ns <= 2 && coef_bytes + states <= 64 * 1024) ? 1 : 0;

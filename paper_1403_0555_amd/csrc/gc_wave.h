@@ -43,10 +43,21 @@ constexpr int gc_links_in_lds(int d, int ns)
     return dl < d ? (int)dl : d;
 }
 
+// LDS of the exchange-region kernel for ns (the instantiated slot count) and
+// V sites: the staged link planes first (2 d_l planes of 64 ns double2, a
+// size fixed at compile time, so that their addresses are immediates), then
+// the neighbour table (16V) and one exchange region per start (8V).
+constexpr size_t gc_rr_links_bytes(int d, int ns) { return (size_t)2 * gc_links_in_lds(d, ns) * 64 * ns * 16; }
+constexpr size_t gc_rr_lds_bytes(int d, int ns, int V)
+{
+    return gc_rr_links_bytes(d, ns) + 16 * (size_t)V + (size_t)GC_WAVES_RR * 8 * V;
+}
+
 // variant = coef_lds | creg << 1 | rm << 3: coefficient table staged in LDS
 // (else read from global memory) and the number of colours (0..2) whose
 // coefficients a lane keeps in registers (gc_wave_creg_max(d, ns) at most),
-// both for ns <= 2; rm, for ns > 2, the relax mode gc_wave_relax_mode(omega).
+// both for ns <= 2; rm, for ns > 2, the relax mode gc_wave_relax_mode(omega,
+// stop_norm).
 hipError_t gc_wave_occupancy(int d, int ns, int variant, size_t lds, int *per_cu);
 hipError_t gc_launch_wave(int d, int ns, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs,
                           unsigned long long *job_next, int variant, float2 *bounce, int grid, size_t lds,
@@ -54,10 +65,11 @@ hipError_t gc_launch_wave(int d, int ns, const GcJobDev *jobs, const GcWaveOrbit
 int gc_wave_creg_max(int d, int ns);
 // Relax mode of the exchange-region kernel: 1 plain relaxation (omega = 1),
 // 2 plain relaxation in the single-precision phase only (omega rounds to 1
-// in single precision), 0 over-relaxation.
-inline int gc_wave_relax_mode(double omega)
+// in single precision), 0 over-relaxation; plus 4 for the max |div| stopping
+// norm (stop_norm != 0).
+inline int gc_wave_relax_mode(double omega, int stop_norm)
 {
-    return omega == 1.0 ? 1 : (float)omega == 1.0f ? 2 : 0;
+    return (omega == 1.0 ? 1 : (float)omega == 1.0f ? 2 : 0) | (stop_norm ? 4 : 0);
 }
 
 // Workgroup-per-start variant (lattices with more than 128 slots per

@@ -392,7 +392,7 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 
 // Half the LDS of a two-region state lets twice the starts share a compute
 // unit.  The sweep schedule, the stopping norm and the arithmetic are those
 // of relax_wave_t.  own: the start's values on entry and on return.
-template <int D, typename R, int NS, bool RELAX>
+template <int D, typename R, int NS, bool RELAX, bool MAXABS>
 __device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t links, lds_ptr<const dbl2> lnk,
                         lds_ptr<const u32x4> nbt, lds_ptr<typename cx<R>::T> X, typename cx<R>::T (&own)[2][NS],
                         double eps, uint64_t cap, bool fixed, uint64_t &sweeps, double &D_out)
@@ -402,11 +402,11 @@ __device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t link
     const int lane = (int)(threadIdx.x & 63);
     lds_ptr<const unsigned char> xb = (lds_ptr<const unsigned char>)X;
     lds_ptr<const unsigned char> lb = (lds_ptr<const unsigned char>)lnk;
-    const uint32_t lplane = (uint32_t)half * 16u;
+    constexpr uint32_t lplane = 64u * NS * 16u;   // staged link planes: 64 NS sites each
     const uint32_t plane = (uint32_t)half * (uint32_t)sizeof(C);
     const R omega = (R)J.omega;
     const uint64_t check = fixed ? cap : J.check_every > 0 ? (uint64_t)J.check_every : 1;
-    const bool maxabs = J.stop_norm != 0;
+    constexpr bool maxabs = MAXABS;
     // slot k of the lane: h = lane + 64 k, computed on a clamped index and
     // discarded beyond the half volume (recomputed where used: no
     // registers held for it)
@@ -515,10 +515,11 @@ __device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t link
 // Relax modes of the exchange-region kernel, fixed per launch from omega:
 // over-relaxation in both precisions, plain relaxation in both (omega = 1),
 // or plain relaxation in the single-precision phase only (omega rounds to 1
-// in single precision but differs from 1).
-enum { GC_RM_OR = 0, GC_RM_RELAX = 1, GC_RM_RELAX32 = 2 };
+// in single precision but differs from 1); GC_RM_MAXABS added for the
+// max |div| stopping norm.
+enum { GC_RM_OR = 0, GC_RM_RELAX = 1, GC_RM_RELAX32 = 2, GC_RM_MAXABS = 4 };
 
-template <int D, typename R, int NS, bool RELAX>
+template <int D, typename R, int NS, bool RELAX, bool MAXABS>
 __device__ __forceinline__ int relax_rr_links(const GcJobDev &J, const GcWaveOrbit &WO, lds_ptr<const dbl2> lnk,
                                               lds_ptr<const u32x4> nbt, lds_ptr<typename cx<R>::T> X,
                                               typename cx<R>::T (&own)[2][NS], double eps, uint64_t cap, bool fixed,
@@ -527,7 +528,7 @@ __device__ __forceinline__ int relax_rr_links(const GcJobDev &J, const GcWaveOrb
     const uint32_t bytes = (uint32_t)(2 * D * WO.half * sizeof(typename cx<R>::T));
     const __amdgpu_buffer_rsrc_t links =
         buffer_rsrc(sizeof(R) == 8 ? (const void *)WO.link64 : (const void *)WO.link32, bytes);
-    return relax_rr<D, R, NS, RELAX>(J, WO.half, links, lnk, nbt, X, own, eps, cap, fixed, sweeps, D_out);
+    return relax_rr<D, R, NS, RELAX, MAXABS>(J, WO.half, links, lnk, nbt, X, own, eps, cap, fixed, sweeps, D_out);
 }
 
 // Values of colour c of a start, exchanged through X: slot h of the lane's
@@ -595,8 +596,8 @@ __device__ void relax_start_rr(const GcJobDev &J, const GcWaveOrbit &WO, lds_ptr
     if (single) {
         flt2 own32[2][NS];
         rr_init<D, NS, flt2>(J, WO, (lds_ptr<flt2>)xr, local, own32);
-        status = relax_rr_links<D, float, NS, RM != GC_RM_OR>(J, WO, lnk, nbt, (lds_ptr<flt2>)xr, own32, J.eps32,
-                                                               J.max_sweeps, false, sw32, Dn);
+        status = relax_rr_links<D, float, NS, (RM & 3) != GC_RM_OR, (RM & GC_RM_MAXABS) != 0>(
+            J, WO, lnk, nbt, (lds_ptr<flt2>)xr, own32, J.eps32, J.max_sweeps, false, sw32, Dn);
         // promotion g64 = normalise((double) g32) after convergence, else the
         // single-precision values reported as they are
         const bool conv = status == GC_ST_CONVERGED;
@@ -614,8 +615,8 @@ __device__ void relax_start_rr(const GcJobDev &J, const GcWaveOrbit &WO, lds_ptr
     if (status == GC_ST_CONVERGED) {
         const bool fixed = !single && (J.flags & GC_JOB_SYNC2) != 0;
         const uint64_t cap = fixed ? (uint64_t)J.fixed_sweeps[local] : J.max_sweeps;
-        status = relax_rr_links<D, double, NS, RM == GC_RM_RELAX>(J, WO, lnk, nbt, X64, own64, J.eps64, cap, fixed,
-                                                                  sw64, Dn);
+        status = relax_rr_links<D, double, NS, (RM & 3) == GC_RM_RELAX, (RM & GC_RM_MAXABS) != 0>(
+            J, WO, lnk, nbt, X64, own64, J.eps64, cap, fixed, sw64, Dn);
     }
     // final state in natural site order, one colour per round through X
     glb_ptr<dbl2> out = as_global(reinterpret_cast<dbl2 *>(J.states + local * (uint64_t)V));
@@ -713,9 +714,10 @@ __global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__rest
 }
 
 // WG = GC_WAVES_RR wavefronts, one start each, for lattices with more than
-// two slots per lane.  LDS: [neighbour table 16V (byte offsets) | links of
-// DL directions 16 DL V] then per wave an 8V-byte exchange region
-// (double2[half], or float2[half] in the single-precision phase).
+// two slots per lane.  LDS (gc_rr_lds_bytes): [links of DL directions, planes
+// of 64 NS double2 | neighbour table 16V (byte offsets)] then per wave an
+// 8V-byte exchange region (double2[half], or float2[half] in the
+// single-precision phase).
 template <int D, int NS, int RM>
 __global__ __launch_bounds__(64 * GC_WAVES_RR) void wave_rr_kernel(const GcJobDev *__restrict__ jobs,
                                                                     const GcWaveOrbit *__restrict__ worbs,
@@ -747,22 +749,21 @@ __global__ __launch_bounds__(64 * GC_WAVES_RR) void wave_rr_kernel(const GcJobDe
         const GcWaveOrbit &WO = worbs[jn];
         const int V = J.orb.V;
         const int half = WO.half;
-        lds_ptr<u32x4> nbt = as_lds(reinterpret_cast<u32x4 *>(smem));
-        glb_ptr<const u32x4> nbg = as_global(reinterpret_cast<const u32x4 *>(WO.nbo));
-        for (int t = threadIdx.x; t < V; t += 64 * GC_WAVES_RR) nbt[t] = nbg[t];
-        size_t off = 16 * (size_t)V;
-        lds_ptr<dbl2> lnk = as_lds(reinterpret_cast<dbl2 *>(smem + off));
+        constexpr size_t LB = gc_rr_links_bytes(D, NS);
+        lds_ptr<dbl2> lnk = as_lds(reinterpret_cast<dbl2 *>(smem));
         if constexpr (DL > 0) {
             glb_ptr<const dbl2> lg = as_global(reinterpret_cast<const dbl2 *>(WO.link64));
             for (int t = threadIdx.x; t < 2 * DL * half; t += 64 * GC_WAVES_RR) {
                 const int pl = t / half, h = t - pl * half;   // plane c * DL + mu
                 const int c = pl / DL, mu = pl - c * DL;
-                lnk[t] = lg[(c * D + mu) * half + h];
+                lnk[pl * 64 * NS + h] = lg[(c * D + mu) * half + h];
             }
-            off += 16 * (size_t)DL * V;
         }
+        lds_ptr<u32x4> nbt = as_lds(reinterpret_cast<u32x4 *>(smem + LB));
+        glb_ptr<const u32x4> nbg = as_global(reinterpret_cast<const u32x4 *>(WO.nbo));
+        for (int t = threadIdx.x; t < V; t += 64 * GC_WAVES_RR) nbt[t] = nbg[t];
         __syncthreads();
-        lds_ptr<unsigned char> xr = as_lds(smem + off + (size_t)wave * 8 * V);
+        lds_ptr<unsigned char> xr = as_lds(smem + LB + 16 * (size_t)V + (size_t)wave * 8 * V);
         for (;;) {
             unsigned long long s = 0;
             if (lane == 0) s = atomicAdd(&job_next[jn], 1ULL);
@@ -884,18 +885,21 @@ hipError_t launch_t(const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, 
         // register-resident kernel: no staged coefficient table
         if (cl) return hipErrorInvalidValue;
         (void)bounce;
-        const int rm = (variant >> 3) & 3;
-        if (rm == GC_RM_OR)
-            hipLaunchKernelGGL((wave_rr_kernel<D, NS, GC_RM_OR>), dim3(grid), dim3(64 * GC_WAVES_RR), lds, s, jobs,
-                               worbs, n_jobs, job_next);
-        else if (rm == GC_RM_RELAX)
-            hipLaunchKernelGGL((wave_rr_kernel<D, NS, GC_RM_RELAX>), dim3(grid), dim3(64 * GC_WAVES_RR), lds, s, jobs,
-                               worbs, n_jobs, job_next);
-        else if (rm == GC_RM_RELAX32)
-            hipLaunchKernelGGL((wave_rr_kernel<D, NS, GC_RM_RELAX32>), dim3(grid), dim3(64 * GC_WAVES_RR), lds, s,
-                               jobs, worbs, n_jobs, job_next);
-        else
-            return hipErrorInvalidValue;
+        switch ((variant >> 3) & 7) {
+#define GC_RR_LAUNCH(RM)                                                                                  \
+    case RM:                                                                                              \
+        hipLaunchKernelGGL((wave_rr_kernel<D, NS, RM>), dim3(grid), dim3(64 * GC_WAVES_RR), lds, s, jobs, worbs, \
+                           n_jobs, job_next);                                                             \
+        break;
+            GC_RR_LAUNCH(0)
+            GC_RR_LAUNCH(1)
+            GC_RR_LAUNCH(2)
+            GC_RR_LAUNCH(4)
+            GC_RR_LAUNCH(5)
+            GC_RR_LAUNCH(6)
+#undef GC_RR_LAUNCH
+        default: return hipErrorInvalidValue;
+        }
         return hipGetLastError();
     } else {
         return cl ? launch_v<D, NS, WAVES, true, 0>(jobs, worbs, n_jobs, job_next, bounce, grid, lds, s)
