@@ -85,7 +85,9 @@ __device__ __forceinline__ void wave_sync_global()
 // (r0 + r1) + (r2 + r3).
 template <int CTRL> __device__ __forceinline__ int dpp32(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+    // every row and bank enabled: no lane keeps an old value, so none is
+    // initialised
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
 }
 template <int CTRL> __device__ __forceinline__ double dpp64(double v)
 {
@@ -111,6 +113,23 @@ __device__ __forceinline__ double wave_sum(double v)
     v += dpp64<kDppHalfMirror>(v);
     v += dpp64<kDppRowMirror>(v);
     return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+// N sums at once, step by step across the values: the DPP moves of one
+// value fill the waits the others' additions need.  Same association order
+// as wave_sum for each value.
+template <int N> __device__ __forceinline__ void wave_sum_n(double (&v)[N])
+{
+#pragma unroll
+    for (int n = 0; n < N; ++n) v[n] += dpp64<kDppQuadSwap1>(v[n]);
+#pragma unroll
+    for (int n = 0; n < N; ++n) v[n] += dpp64<kDppQuadSwap2>(v[n]);
+#pragma unroll
+    for (int n = 0; n < N; ++n) v[n] += dpp64<kDppHalfMirror>(v[n]);
+#pragma unroll
+    for (int n = 0; n < N; ++n) v[n] += dpp64<kDppRowMirror>(v[n]);
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+        v[n] = (lane_value(v[n], 0) + lane_value(v[n], 16)) + (lane_value(v[n], 32) + lane_value(v[n], 48));
 }
 __device__ __forceinline__ double wave_max(double v)
 {

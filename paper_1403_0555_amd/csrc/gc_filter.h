@@ -19,8 +19,7 @@ using namespace gc;
 template <int B, int N>
 __device__ __forceinline__ void wg_sum_n(double (&v)[N], double *red, int &ph)
 {
-#pragma unroll
-    for (int n = 0; n < N; ++n) v[n] = wave_sum(v[n]);
+    wave_sum_n<N>(v);
     if (B > 64) {
         double *r = red + ph * (4 * (B / 64));
         ph ^= 1;

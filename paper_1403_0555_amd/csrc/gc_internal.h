@@ -127,9 +127,10 @@ hipError_t gc_launch_post(int block, int sp, int wreg, int keys, const GcJobDev 
 // fits.
 int gc_lanczos_shape(int d, const int *ext, int V, int *block, int *seg);
 size_t gc_lanczos_lds_bytes(int d, int N0, int seg, int V, int lmax);
-hipError_t gc_lanczos_occupancy(int d, int block, int seg, size_t lds_bytes, int *blocks_per_cu);
-hipError_t gc_launch_lanczos(int d, int block, int seg, const GcJobDev *jobs, int n_jobs, unsigned long long *next,
-                             int grid, size_t lds_bytes, hipStream_t s);
+// whole: the segments are whole lines (seg == N0) for every job of the launch.
+hipError_t gc_lanczos_occupancy(int d, int block, int seg, int whole, size_t lds_bytes, int *blocks_per_cu);
+hipError_t gc_launch_lanczos(int d, int block, int seg, int whole, const GcJobDev *jobs, int n_jobs,
+                             unsigned long long *next, int grid, size_t lds_bytes, hipStream_t s);
 
 // Table and bookkeeping kernels.
 hipError_t gc_launch_reset(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);

@@ -49,7 +49,7 @@ __device__ double ritz_wave0(lds_cdouble *alpha, lds_cdouble *beta2, int k, doub
 // touch consecutive doubles, and a neighbour in direction mu >= 1 (the same
 // k of another segment) at a constant thread offset.  The iteration is
 // post_kernel's: one reduction per iteration, the same formulas per site.
-template <int B, int S, int D>
+template <int B, int S, int D, bool WHOLE>
 __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__ jobs, int n_jobs,
                                                     unsigned long long *next)
 {
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
         const bool act = tid < V / S;
         const int line = act ? tid / nseg : 0, o = act ? (tid % nseg) * S : 0;
         const int i0 = line * N0 + o;
-        const bool whole = (S == N0);   // the segment is a whole line
+        constexpr bool whole = WHOLE;   // the segment is a whole line (S == N0, the launch's choice)
         const int T = V / S;              // active threads, the stride of the segment-major arrays
         const int nw = whole ? d - 1 : d;   // weight arrays in LDS
         const int w0off = whole ? -1 : 0;   // LDS array of direction mu: mu + w0off
@@ -161,19 +161,38 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
         // line: the first site of the next segment, the last of the previous
         const int ia = line * nseg + ((o + S) % N0) / S;
         const int ib = (S - 1) * T + line * nseg + ((o + N0 - 1) % N0) / S;
+        // byte offsets within an LDS array of the own site and of the
+        // neighbours in directions >= 1 (fixed for the copy); the k-th site
+        // adds k T 8, kept in a scalar register
+        lds_ptr<const unsigned char> ubase = (lds_ptr<const unsigned char>)u;
+        const uint32_t t8 = 8u * (uint32_t)tid;
+        uint32_t of8[GC_MAXD], ob8[GC_MAXD];
+#pragma unroll
+        for (int mu = 0; mu < GC_MAXD; ++mu) {
+            of8[mu] = 8u * (uint32_t)(tid + df[mu]);
+            ob8[mu] = 8u * (uint32_t)(tid + db[mu]);
+        }
         for (it = 0; it < lmax; ++it) {
             if (B > 64) __syncthreads();   // u and the weights complete in LDS
             else wave_sync();
             double s4[4] = {0.0, 0.0, 0.0, 0.0};
             if (act) {
-                // read in both cases (valid indices), selected without a branch
-                const double ua_l = u[ia], ub_l = u[ib], wbe_l = wl[ib];
-                const double ua = whole ? uo[0] : ua_l;
-                const double ub = whole ? uo[S - 1] : ub_l;
-                const double wbe = whole ? w0[S - 1] : wbe_l;
+                double ua, ub, wbe;
+                if constexpr (whole) {
+                    ua = uo[0];
+                    ub = uo[S - 1];
+                    wbe = w0[S - 1];
+                } else {
+                    ua = u[ia];
+                    ub = u[ib];
+                    wbe = wl[ib];
+                }
 #pragma unroll
                 for (int k = 0; k < S; ++k) {
-                    const int i = k * T + tid + opaque_zero();
+                    uint32_t kb = 8u * (uint32_t)(k * T);
+                    // opaque: the site addresses are formed per site, not
+                    // held in registers across the iteration
+                    asm volatile("" : "+s"(kb));
                     const double ui = uo[k];
                     // direction 0: neighbours and weights of the own segment
                     const double uf = (k + 1 < S) ? uo[k + 1] : ua;
@@ -183,8 +202,14 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
 #pragma unroll
                     for (int mu = 1; mu < GC_MAXD; ++mu)
                         if (mu < d) {
-                            const int a = (mu + w0off) * V;
-                            m += wl[a + i] * (ui - u[i + df[mu]]) + wl[a + i + db[mu]] * (ui - u[i + db[mu]]);
+                            lds_ptr<const unsigned char> ub8 = ubase + kb;
+                            lds_ptr<const unsigned char> wb8 =
+                                (lds_ptr<const unsigned char>)(wl + (mu + w0off) * V) + kb;
+                            const double wf_ = *(lds_ptr<const double>)(wb8 + t8);
+                            const double uf_ = *(lds_ptr<const double>)(ub8 + of8[mu]);
+                            const double wb_ = *(lds_ptr<const double>)(wb8 + ob8[mu]);
+                            const double ub_ = *(lds_ptr<const double>)(ub8 + ob8[mu]);
+                            m += wf_ * (ui - uf_) + wb_ * (ui - ub_);
                         }
                     mv[k] = m;
                     s4[0] += ui * ui;
@@ -260,17 +285,19 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
 
 // Entry points of one lattice dimension D (gc_lanczosD.hip): occupancy and
 // launch of lanczos_kernel<B, S, D> for the shapes gc_lanczos_shape picks.
+#define GC_LANCZOS_W(FN, B, S, D, ...)                                                                    \
+    return whole ? FN<B, S, D, true>(__VA_ARGS__) : FN<B, S, D, false>(__VA_ARGS__);
 #define GC_LANCZOS_SEG(FN, B, D, ...)                                                                     \
     switch (seg) {                                                                                        \
-    case 1: return FN<B, 1, D>(__VA_ARGS__);                                                              \
-    case 2: return FN<B, 2, D>(__VA_ARGS__);                                                              \
-    case 3: return FN<B, 3, D>(__VA_ARGS__);                                                              \
-    case 4: return FN<B, 4, D>(__VA_ARGS__);                                                              \
-    case 5: return FN<B, 5, D>(__VA_ARGS__);                                                              \
-    case 6: return FN<B, 6, D>(__VA_ARGS__);                                                              \
-    case 7: return FN<B, 7, D>(__VA_ARGS__);                                                              \
-    case 8: return FN<B, 8, D>(__VA_ARGS__);                                                              \
-    case 10: return FN<B, 10, D>(__VA_ARGS__);                                                            \
+    case 1: GC_LANCZOS_W(FN, B, 1, D, __VA_ARGS__)                                                        \
+    case 2: GC_LANCZOS_W(FN, B, 2, D, __VA_ARGS__)                                                        \
+    case 3: GC_LANCZOS_W(FN, B, 3, D, __VA_ARGS__)                                                        \
+    case 4: GC_LANCZOS_W(FN, B, 4, D, __VA_ARGS__)                                                        \
+    case 5: GC_LANCZOS_W(FN, B, 5, D, __VA_ARGS__)                                                        \
+    case 6: GC_LANCZOS_W(FN, B, 6, D, __VA_ARGS__)                                                        \
+    case 7: GC_LANCZOS_W(FN, B, 7, D, __VA_ARGS__)                                                        \
+    case 8: GC_LANCZOS_W(FN, B, 8, D, __VA_ARGS__)                                                        \
+    case 10: GC_LANCZOS_W(FN, B, 10, D, __VA_ARGS__)                                                      \
     default: return hipErrorInvalidValue;                                                                 \
     }
 #define GC_LANCZOS_DISPATCH(FN, D, ...)                                                                   \
@@ -282,26 +309,28 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
     default: return hipErrorInvalidValue;                                                                 \
     }
 
-template <int B, int S, int D>
+template <int B, int S, int D, bool WHOLE>
 static hipError_t lanczos_occ_t(size_t lds, int *per_cu)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, lanczos_kernel<B, S, D>, B, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, lanczos_kernel<B, S, D, WHOLE>, B, lds);
 }
 
-template <int B, int S, int D>
+template <int B, int S, int D, bool WHOLE>
 static hipError_t lanczos_launch_t(const GcJobDev *jobs, int n_jobs, unsigned long long *next, int grid, size_t lds,
                                    hipStream_t s)
 {
-    hipLaunchKernelGGL((lanczos_kernel<B, S, D>), dim3(grid), dim3(B), lds, s, jobs, n_jobs, next);
+    hipLaunchKernelGGL((lanczos_kernel<B, S, D, WHOLE>), dim3(grid), dim3(B), lds, s, jobs, n_jobs, next);
     return hipGetLastError();
 }
 
+// whole: the segments are whole lines (S == N0) for every job of the launch
 #define GC_LANCZOS_DEFINE_DIM(D)                                                                          \
-    hipError_t gc_lanczos_occupancy_d##D(int block, int seg, size_t lds_bytes, int *blocks_per_cu)        \
+    hipError_t gc_lanczos_occupancy_d##D(int block, int seg, int whole, size_t lds_bytes,                 \
+                                         int *blocks_per_cu)                                              \
     {                                                                                                     \
         GC_LANCZOS_DISPATCH(lanczos_occ_t, D, lds_bytes, blocks_per_cu)                                   \
     }                                                                                                     \
-    hipError_t gc_launch_lanczos_d##D(int block, int seg, const GcJobDev *jobs, int n_jobs,               \
+    hipError_t gc_launch_lanczos_d##D(int block, int seg, int whole, const GcJobDev *jobs, int n_jobs,    \
                                       unsigned long long *next, int grid, size_t lds_bytes, hipStream_t s)  \
     {                                                                                                     \
         GC_LANCZOS_DISPATCH(lanczos_launch_t, D, jobs, n_jobs, next, grid, lds_bytes, s)                  \

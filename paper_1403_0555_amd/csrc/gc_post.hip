@@ -778,33 +778,34 @@ size_t gc_lanczos_lds_bytes(int d, int N0, int S, int V, int lmax)
 }
 
 #define GC_LANCZOS_DECLARE_DIM(D)                                                                         \
-    hipError_t gc_lanczos_occupancy_d##D(int block, int seg, size_t lds_bytes, int *blocks_per_cu);       \
-    hipError_t gc_launch_lanczos_d##D(int block, int seg, const GcJobDev *jobs, int n_jobs,               \
+    hipError_t gc_lanczos_occupancy_d##D(int block, int seg, int whole, size_t lds_bytes,                 \
+                                         int *blocks_per_cu);                                             \
+    hipError_t gc_launch_lanczos_d##D(int block, int seg, int whole, const GcJobDev *jobs, int n_jobs,    \
                                       unsigned long long *next, int grid, size_t lds_bytes, hipStream_t s);
 GC_LANCZOS_DECLARE_DIM(1)
 GC_LANCZOS_DECLARE_DIM(2)
 GC_LANCZOS_DECLARE_DIM(3)
 GC_LANCZOS_DECLARE_DIM(4)
 
-hipError_t gc_lanczos_occupancy(int d, int block, int seg, size_t lds_bytes, int *blocks_per_cu)
+hipError_t gc_lanczos_occupancy(int d, int block, int seg, int whole, size_t lds_bytes, int *blocks_per_cu)
 {
     switch (d) {
-    case 1: return gc_lanczos_occupancy_d1(block, seg, lds_bytes, blocks_per_cu);
-    case 2: return gc_lanczos_occupancy_d2(block, seg, lds_bytes, blocks_per_cu);
-    case 3: return gc_lanczos_occupancy_d3(block, seg, lds_bytes, blocks_per_cu);
-    case 4: return gc_lanczos_occupancy_d4(block, seg, lds_bytes, blocks_per_cu);
+    case 1: return gc_lanczos_occupancy_d1(block, seg, whole, lds_bytes, blocks_per_cu);
+    case 2: return gc_lanczos_occupancy_d2(block, seg, whole, lds_bytes, blocks_per_cu);
+    case 3: return gc_lanczos_occupancy_d3(block, seg, whole, lds_bytes, blocks_per_cu);
+    case 4: return gc_lanczos_occupancy_d4(block, seg, whole, lds_bytes, blocks_per_cu);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t gc_launch_lanczos(int d, int block, int seg, const GcJobDev *jobs, int n_jobs, unsigned long long *next,
-                             int grid, size_t lds_bytes, hipStream_t s)
+hipError_t gc_launch_lanczos(int d, int block, int seg, int whole, const GcJobDev *jobs, int n_jobs,
+                             unsigned long long *next, int grid, size_t lds_bytes, hipStream_t s)
 {
     switch (d) {
-    case 1: return gc_launch_lanczos_d1(block, seg, jobs, n_jobs, next, grid, lds_bytes, s);
-    case 2: return gc_launch_lanczos_d2(block, seg, jobs, n_jobs, next, grid, lds_bytes, s);
-    case 3: return gc_launch_lanczos_d3(block, seg, jobs, n_jobs, next, grid, lds_bytes, s);
-    case 4: return gc_launch_lanczos_d4(block, seg, jobs, n_jobs, next, grid, lds_bytes, s);
+    case 1: return gc_launch_lanczos_d1(block, seg, whole, jobs, n_jobs, next, grid, lds_bytes, s);
+    case 2: return gc_launch_lanczos_d2(block, seg, whole, jobs, n_jobs, next, grid, lds_bytes, s);
+    case 3: return gc_launch_lanczos_d3(block, seg, whole, jobs, n_jobs, next, grid, lds_bytes, s);
+    case 4: return gc_launch_lanczos_d4(block, seg, whole, jobs, n_jobs, next, grid, lds_bytes, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -231,6 +231,7 @@ struct PostGroup {
 struct FilterGroup {
     bool fast = false;
     int d = 0;                        // lattice dimension (fast kernel: one per dimension)
+    int whole = 0;                    // fast kernel: segments are whole lines (seg == N0)
     int block = 64, seg = 1, sp = 1, wreg = 1, grid = 1;
     size_t lds = 0;
     uint64_t total = 0, wstride = 0;   // total: an upper bound of the copies (the starts)
@@ -759,6 +760,7 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
                 gc_lanczos_lds_bytes(o->d, o->lat.extent[0], fs, o->V, lmax) <= ctx->lds_max) {
                 f.fast = true;
                 f.d = o->d;
+                f.whole = fs == o->lat.extent[0] ? 1 : 0;
                 f.block = fb;
                 f.seg = fs;
             } else {
@@ -769,6 +771,7 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             int m = 0;
             while (m < (int)L.filters.size() &&
                    !(L.filters[m].chain == f.chain && L.filters[m].fast == f.fast && L.filters[m].d == f.d &&
+                     L.filters[m].whole == f.whole &&
                      L.filters[m].block == f.block && L.filters[m].seg == f.seg && L.filters[m].sp == f.sp &&
                      L.filters[m].wreg == f.wreg))
                 ++m;
@@ -807,7 +810,7 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
         if (lds > ctx->lds_max) return GC_EUNSUPPORTED;
         fg.lds = lds;
         int per_cu = 0;
-        hipError_t e = fg.fast ? gc_lanczos_occupancy(fg.d, fg.block, fg.seg, lds, &per_cu)
+        hipError_t e = fg.fast ? gc_lanczos_occupancy(fg.d, fg.block, fg.seg, fg.whole, lds, &per_cu)
                                : gc_post_occupancy(fg.block, fg.sp, fg.wreg, 0, lds, &per_cu);
         if (e != hipSuccess) return fail(ctx, e, "occupancy");
         per_cu = std::max(per_cu, 1);
@@ -1020,7 +1023,8 @@ hipError_t enqueue_chain(Job *job, unsigned char *base, int gi, hipStream_t qs, 
     for (const FilterGroup &fg : L.filters) {
         if (fg.chain != gi) continue;
         if (fg.fast)
-            e = gc_launch_lanczos(fg.d, fg.block, fg.seg, (const GcJobDev *)(base + fg.o_jobs), (int)fg.jobs.size(),
+            e = gc_launch_lanczos(fg.d, fg.block, fg.seg, fg.whole, (const GcJobDev *)(base + fg.o_jobs),
+                                  (int)fg.jobs.size(),
                                   (unsigned long long *)(base + fg.o_next), fg.grid, fg.lds, qs);
         else
             e = gc_launch_post(fg.block, fg.sp, fg.wreg, 0, (const GcJobDev *)(base + fg.o_jobs), (int)fg.jobs.size(),
