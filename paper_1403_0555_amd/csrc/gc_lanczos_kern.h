@@ -172,6 +172,25 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
             of8[mu] = 8u * (uint32_t)(tid + df[mu]);
             ob8[mu] = 8u * (uint32_t)(tid + db[mu]);
         }
+        // the diagonal of M at the own sites, the sum of their 2d link
+        // weights, once per copy (M u)_i = diag_i u_i - sum_nb w u_nb
+        if (B > 64) __syncthreads();   // the weights complete in LDS
+        else wave_sync();
+        double dg[S];
+        {
+            const double wbe0 = whole ? w0[S - 1] : wl[ib];
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                double a = w0[k] + ((k > 0) ? w0[k - 1] : wbe0);
+#pragma unroll
+                for (int mu = 1; mu < GC_MAXD; ++mu)
+                    if (mu < d) {
+                        lds_ptr<const double> wm = wl + (mu + w0off) * V + k * T;
+                        a += wm[tid] + wm[tid + db[mu]];
+                    }
+                dg[k] = act ? a : 0.0;
+            }
+        }
         for (it = 0; it < lmax; ++it) {
             if (B > 64) __syncthreads();   // u and the weights complete in LDS
             else wave_sync();
@@ -198,7 +217,9 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
                     const double uf = (k + 1 < S) ? uo[k + 1] : ua;
                     const double ubk = (k > 0) ? uo[k - 1] : ub;
                     const double wb0 = (k > 0) ? w0[k - 1] : wbe;
-                    double m = w0[k] * (ui - uf) + wb0 * (ui - ubk);
+                    double m = dg[k] * ui;
+                    m = fma(-w0[k], uf, m);
+                    m = fma(-wb0, ubk, m);
 #pragma unroll
                     for (int mu = 1; mu < GC_MAXD; ++mu)
                         if (mu < d) {
@@ -209,7 +230,8 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
                             const double uf_ = *(lds_ptr<const double>)(ub8 + of8[mu]);
                             const double wb_ = *(lds_ptr<const double>)(wb8 + ob8[mu]);
                             const double ub_ = *(lds_ptr<const double>)(ub8 + ob8[mu]);
-                            m += wf_ * (ui - uf_) + wb_ * (ui - ub_);
+                            m = fma(-wf_, uf_, m);
+                            m = fma(-wb_, ub_, m);
                         }
                     mv[k] = m;
                     s4[0] += ui * ui;
