@@ -65,11 +65,11 @@ KERNEL_SOURCES = {
 }
 TRAFFIC = {
     # wave_rr_kernel<4, 11, 0>, 10^6 starts of the 6^4 FP64 workload (one dispatch):
-    # FETCH_SIZE 691344.0 KiB x 2.0000 (a 2 GiB copy reads 1048587.6 KiB) and
-    # WRITE_SIZE 20538666.5 KiB x 1.0 (the copy writes 2097152.0 KiB)
-    "sources_sha256": "a3df94808040f855b5fddc67a3b8243db2295ce9009c13efbb0bebe6eb36f8ea",
+    # FETCH_SIZE 942096.7 KiB x 2.0000 (a 2 GiB copy reads 1048587.6 KiB) and
+    # WRITE_SIZE 20541119.1 KiB x 1.0 (the copy writes 2097152.0 KiB)
+    "sources_sha256": "b5db327b9cfd6390fc6497ef70cb0652518a9ae179af01ceb712fe954689a779",
     "kernel": "relax",
-    "bytes_per_launch": 1415856849 + 21031594496,
+    "bytes_per_launch": 1929392697 + 21034105958,
 }
 
 
