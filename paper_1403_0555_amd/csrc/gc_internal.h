@@ -14,6 +14,9 @@
 #define GC_ST_CONVERGED 1
 #define GC_ST_NONCONVERGED 2
 #define GC_ST_BADNUM 3
+// Internal: converged in single precision, state promoted to double precision
+// in HBM, its double-precision phase pending (never left in a finished launch).
+#define GC_ST_PROMOTED 0x50
 
 // Copy flags (mirror GC_FLAG_*).
 #define GC_F_IN_REGION 1u
@@ -25,6 +28,7 @@
 
 // Job flags.
 #define GC_JOB_SYNC2 4u        // batch-synchronous second pass: start s runs exactly fixed_sweeps[s] sweeps
+#define GC_JOB_FROM32 8u       // double-precision pass over the states a single-precision kernel promoted
 
 // Relative spread of F (per site) above which one key is flagged as reached
 // by different stationary points.

@@ -208,6 +208,10 @@ struct Group {
     int block = 64, grid = 1, ns = 1, coef_lds = 0, creg = 0, wps = 0;
     int rm = 0;                      // relax mode of the exchange-region kernel (ns > 2)
     size_t lds = 0;
+    // mixed precision above two slots per lane: the single-precision phase
+    // in its own kernel, before the double-precision one
+    int split = 0, grid32 = 1;
+    size_t lds32 = 0;
     size_t o_jobs = 0, o_worbs = 0, o_next = 0, o_prefix = 0, o_bounce = 0;
     size_t o_jobs1 = 0;              // first-pass descriptors of a batch-synchronous launch
     uint64_t total = 0;
@@ -499,7 +503,7 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
         std::vector<double2> c64((size_t)2 * 2 * d * half);
         std::vector<float2> c32((size_t)2 * 2 * d * half);
         const bool scaled = 16 * (size_t)half <= 0xFFFF;
-        std::vector<uint16_t> nbo(scaled ? (size_t)2 * half * 8 : 0, 0);
+        std::vector<uint16_t> nbo(scaled ? (size_t)2 * half * 8 : 0, 0), nbo32(scaled ? (size_t)2 * half * 8 : 0, 0);
         std::vector<double2> l64((size_t)2 * d * half);
         std::vector<float2> l32((size_t)2 * d * half);
         for (int c = 0; c < 2; ++c)
@@ -509,7 +513,10 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
                     const int mu = k < d ? k : k - d;
                     const int nsite = k < d ? nbr[(size_t)mu * V + i] : nbr[(size_t)(d + mu) * V + i];
                     nb[((size_t)c * half + h) * 8 + k] = (uint16_t)(nsite >> 1);
-                    if (scaled) nbo[((size_t)c * half + h) * 8 + k] = (uint16_t)(16 * (nsite >> 1));
+                    if (scaled) {
+                        nbo[((size_t)c * half + h) * 8 + k] = (uint16_t)(16 * (nsite >> 1));
+                        nbo32[((size_t)c * half + h) * 8 + k] = (uint16_t)(8 * (nsite >> 1));
+                    }
                     double2 u;
                     if (k < d) {
                         u = U64[(size_t)mu * V + i];
@@ -527,13 +534,16 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
         auto wplace = [&](size_t bytes) { size_t at = woff; woff = align_up(woff + bytes, 256); return at; };
         const size_t w_loc = wplace(loc.size() * 2), w_nb = wplace(nb.size() * 2), w_c64 = wplace(c64.size() * 16),
                      w_c32 = wplace(c32.size() * 8),
-                     w_nbo = wplace(nbo.size() * 2), w_l64 = wplace(l64.size() * 16), w_l32 = wplace(l32.size() * 8);
+                     w_nbo = wplace(nbo.size() * 2), w_nbo32 = wplace(nbo32.size() * 2), w_l64 = wplace(l64.size() * 16), w_l32 = wplace(l32.size() * 8);
         std::vector<unsigned char> wh(woff, 0);
         memcpy(&wh[w_loc], loc.data(), loc.size() * 2);
         memcpy(&wh[w_nb], nb.data(), nb.size() * 2);
         memcpy(&wh[w_c64], c64.data(), c64.size() * 16);
         memcpy(&wh[w_c32], c32.data(), c32.size() * 8);
-        if (scaled) memcpy(&wh[w_nbo], nbo.data(), nbo.size() * 2);
+        if (scaled) {
+            memcpy(&wh[w_nbo], nbo.data(), nbo.size() * 2);
+            memcpy(&wh[w_nbo32], nbo32.data(), nbo32.size() * 2);
+        }
         memcpy(&wh[w_l64], l64.data(), l64.size() * 16);
         memcpy(&wh[w_l32], l32.data(), l32.size() * 8);
         void *wdevmem = nullptr;
@@ -548,6 +558,7 @@ gc_status build_orbit(gc_ctx *ctx, Orbit *o)
         o->wdev.coef64 = (const double2 *)(wb + w_c64);
         o->wdev.coef32 = (const float2 *)(wb + w_c32);
         o->wdev.nbo = scaled ? (const uint4 *)(wb + w_nbo) : nullptr;
+        o->wdev.nbo32 = scaled ? (const uint4 *)(wb + w_nbo32) : nullptr;
         o->wdev.link64 = (const double2 *)(wb + w_l64);
         o->wdev.link32 = (const float2 *)(wb + w_l32);
     }
@@ -705,6 +716,17 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             if (job->force_creg >= 0) g.creg = std::min(job->force_creg, gc_wave_creg_max(g.d, g.ns));
             hipError_t e = gc_wave_occupancy(g.d, g.ns, g.coef_lds | (g.creg << 1) | (g.rm << 3), g.lds, &per_cu);
             if (e != hipSuccess) return fail(ctx, e, "occupancy");
+            if (g.ns > 2 && mixed) {
+                g.split = 1;
+                g.lds32 = gc_rr32_lds_bytes(g.d, ns_bucket(g.d, g.ns), gV);
+                if (g.lds32 > ctx->lds_max) return GC_EUNSUPPORTED;
+                int pc32 = 0;
+                e = gc_wave32_occupancy(g.d, g.ns, g.rm, g.lds32, &pc32);
+                if (e != hipSuccess) return fail(ctx, e, "occupancy");
+                pc32 = std::max(pc32, 1);
+                g.grid32 = (int)std::min<uint64_t>((uint64_t)pc32 * ctx->n_cu,
+                                                   std::max<uint64_t>((g.total + GC_WAVES_RR32 - 1) / GC_WAVES_RR32, 1));
+            }
         } else {
             g.block = block_for(gV);
             g.lds = gc_relax_wg_lds_bytes(gV);
@@ -948,6 +970,10 @@ std::vector<Blob> job_blobs(Job *job)
             add_blob(g.o_jobs1, gj.data(), sizeof(GcJobDev) * gj.size());
             for (GcJobDev &J : gj) J.flags |= GC_JOB_SYNC2;
         }
+        // split mixed launch: the double-precision kernel resumes the
+        // promoted states
+        if (g.split)
+            for (GcJobDev &J : gj) J.flags |= GC_JOB_FROM32;
         add_blob(g.o_jobs, gj.data(), sizeof(GcJobDev) * gj.size());
         add_blob(g.o_worbs, gw.data(), sizeof(GcWaveOrbit) * gw.size());
         add_blob(g.o_prefix, gp.data(), sizeof(uint64_t) * gp.size());
@@ -986,6 +1012,15 @@ hipError_t enqueue_chain(Job *job, unsigned char *base, int gi, hipStream_t qs, 
                                  (const GcWaveOrbit *)(base + g.o_worbs), (int)g.jobs.size(),
                                  (unsigned long long *)(base + g.o_next), (float2 *)(base + g.o_bounce), g.grid,
                                  g.lds, qs);
+        if (g.wave && g.split) {
+            // single precision, then double precision from the promoted states
+            hipError_t e2 = gc_launch_wave32(g.d, g.ns, (const GcJobDev *)(base + o_jobs),
+                                             (const GcWaveOrbit *)(base + g.o_worbs), (int)g.jobs.size(),
+                                             (unsigned long long *)(base + g.o_next), g.rm, g.grid32, g.lds32, qs);
+            if (e2 == hipSuccess)
+                e2 = gc_launch_zero_u64((unsigned long long *)(base + g.o_next), (int)g.jobs.size(), qs);
+            if (e2 != hipSuccess) return e2;
+        }
         if (g.wave)
             return gc_launch_wave(g.d, g.ns, (const GcJobDev *)(base + o_jobs),
                                   (const GcWaveOrbit *)(base + g.o_worbs), (int)g.jobs.size(),

@@ -17,6 +17,7 @@ struct GcWaveOrbit {
     // coefficient of a site is the conjugate of its backward neighbour's
     // forward link.
     const uint4 *nbo;               // [2][half] 8 x u16 byte offsets 16 h (forward mu, then backward)
+    const uint4 *nbo32;             // the same scaled for 8-byte sites, 8 h (single-precision kernel)
     const double2 *link64;          // [2][d][half]
     const float2 *link32;           // same, rounded to single precision
 };
@@ -43,6 +44,26 @@ constexpr int gc_links_in_lds(int d, int ns)
     return dl < d ? (int)dl : d;
 }
 
+// The single-precision phase of mixed launches above two slots per lane
+// runs in its own kernel: GC_WAVES_RR32 starts per workgroup (three
+// wavefronts per SIMD), exchange regions of 4V bytes, the links of
+// gc_links_in_lds32(d, ns) directions in single precision in LDS (8 bytes
+// per site and colour); converged states go to HBM promoted to double
+// precision for the double-precision kernel.
+constexpr int GC_WAVES_RR32 = 12;
+constexpr int gc_links_in_lds32(int d, int ns)
+{
+    const long V = 128L * ns;
+    const long room = 160L * 1024 - 16 * V - (long)GC_WAVES_RR32 * 4 * V;
+    const long dl = (ns > 2 && room > 0) ? room / (8 * V) : 0;
+    return dl < d ? (int)dl : d;
+}
+constexpr size_t gc_rr32_links_bytes(int d, int ns) { return (size_t)2 * gc_links_in_lds32(d, ns) * 64 * ns * 8; }
+constexpr size_t gc_rr32_lds_bytes(int d, int ns, int V)
+{
+    return gc_rr32_links_bytes(d, ns) + 16 * (size_t)V + (size_t)GC_WAVES_RR32 * 4 * V;
+}
+
 // LDS of the exchange-region kernel for ns (the instantiated slot count) and
 // V sites: the staged link planes first (2 d_l planes of 64 ns double2, a
 // size fixed at compile time, so that their addresses are immediates), then
@@ -63,6 +84,11 @@ hipError_t gc_launch_wave(int d, int ns, const GcJobDev *jobs, const GcWaveOrbit
                           unsigned long long *job_next, int variant, float2 *bounce, int grid, size_t lds,
                           hipStream_t s);
 int gc_wave_creg_max(int d, int ns);
+// The single-precision kernel of mixed launches (ns > 2): relax mode rm as
+// for gc_launch_wave.
+hipError_t gc_wave32_occupancy(int d, int ns, int rm, size_t lds, int *per_cu);
+hipError_t gc_launch_wave32(int d, int ns, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs,
+                            unsigned long long *job_next, int rm, int grid, size_t lds, hipStream_t s);
 // Relax mode of the exchange-region kernel: 1 plain relaxation (omega = 1),
 // 2 plain relaxation in the single-precision phase only (omega rounds to 1
 // in single precision), 0 over-relaxation; plus 4 for the max |div| stopping

@@ -12,6 +12,14 @@
     hipError_t gc_launch_wps_d##D(int wps, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs,      \
                                   unsigned long long *job_next, float2 *bounce, int grid, size_t lds,        \
                                   hipStream_t s);
+#define GC_WAVE32_DECLARE_DIM(D)                                                                            \
+    hipError_t gc_wave32_occupancy_d##D(int ns, int rm, size_t lds, int *per_cu);                            \
+    hipError_t gc_launch_wave32_d##D(int ns, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs,    \
+                                     unsigned long long *job_next, int rm, int grid, size_t lds, hipStream_t s);
+GC_WAVE32_DECLARE_DIM(1)
+GC_WAVE32_DECLARE_DIM(2)
+GC_WAVE32_DECLARE_DIM(3)
+GC_WAVE32_DECLARE_DIM(4)
 GC_WAVE_DECLARE_DIM(1)
 GC_WAVE_DECLARE_DIM(2)
 GC_WAVE_DECLARE_DIM(3)
@@ -37,6 +45,29 @@ hipError_t gc_launch_wave(int d, int ns, const GcJobDev *jobs, const GcWaveOrbit
     case 2: return gc_launch_wave_d2(ns, jobs, worbs, n_jobs, job_next, variant, bounce, grid, lds, s);
     case 3: return gc_launch_wave_d3(ns, jobs, worbs, n_jobs, job_next, variant, bounce, grid, lds, s);
     case 4: return gc_launch_wave_d4(ns, jobs, worbs, n_jobs, job_next, variant, bounce, grid, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t gc_wave32_occupancy(int d, int ns, int rm, size_t lds, int *per_cu)
+{
+    switch (d) {
+    case 1: return gc_wave32_occupancy_d1(ns, rm, lds, per_cu);
+    case 2: return gc_wave32_occupancy_d2(ns, rm, lds, per_cu);
+    case 3: return gc_wave32_occupancy_d3(ns, rm, lds, per_cu);
+    case 4: return gc_wave32_occupancy_d4(ns, rm, lds, per_cu);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t gc_launch_wave32(int d, int ns, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs,
+                            unsigned long long *job_next, int rm, int grid, size_t lds, hipStream_t s)
+{
+    switch (d) {
+    case 1: return gc_launch_wave32_d1(ns, jobs, worbs, n_jobs, job_next, rm, grid, lds, s);
+    case 2: return gc_launch_wave32_d2(ns, jobs, worbs, n_jobs, job_next, rm, grid, lds, s);
+    case 3: return gc_launch_wave32_d3(ns, jobs, worbs, n_jobs, job_next, rm, grid, lds, s);
+    case 4: return gc_launch_wave32_d4(ns, jobs, worbs, n_jobs, job_next, rm, grid, lds, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -249,24 +249,28 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
     return status;
 }
 
-template <int D, int NS> constexpr int links_in_lds() { return gc_links_in_lds(D, NS); }
-
 // Staple of slot h of colour COL from the scaled table entry w: forward
 // mu = 0..d-1 then backward, each complex product by four FMAs in the order
 // of staple() (a backward coefficient is conj(U), negated exactly).  Table
 // offsets are byte offsets of 16-byte sites; the state and the global links
 // of single precision have 8-byte sites, hence the shift.  Links of
-// directions mu < DL come from LDS (lnk, double precision, rounded to
-// single precision in the single-precision phase: the same values as the
-// single-precision table), the others through buffer loads.
-template <int D, int DL, typename R, int COL>
+// directions mu < DL come from LDS planes of lplane bytes holding LT (double
+// precision for the double-precision kernel, single precision for the
+// single-precision one: the values of the single-precision table), the
+// others through buffer loads.  hb: h sizeof(LT).
+template <int D, int DL, typename R, typename LT, int COL>
 __device__ __forceinline__ typename cx<R>::T staple_big(const u32x4 w, lds_ptr<const unsigned char> other,
                                                         lds_ptr<const unsigned char> lnk, uint32_t hb,
                                                         __amdgpu_buffer_rsrc_t links, uint32_t vo, uint32_t plane,
                                                         uint32_t lplane)
 {
+    // w holds byte offsets scaled for sites of sizeof(LT) bytes (the
+    // single-precision kernel stages the 8-byte table), so offsets of the
+    // state and of LDS links need no shift when both are of that size
     using C = typename cx<R>::T;
-    constexpr int SH = sizeof(C) == 16 ? 0 : 1;
+    constexpr int SH = sizeof(C) == sizeof(LT) ? 0 : (sizeof(C) < sizeof(LT) ? 1 : -1);
+    static_assert(SH >= 0, "state sites no larger than link sites");
+    constexpr int SHL = 0;
     R ax = 0, ay = 0;
 #pragma unroll
     for (int k = 0; k < 2 * D; ++k) {
@@ -276,10 +280,10 @@ __device__ __forceinline__ typename cx<R>::T staple_big(const u32x4 w, lds_ptr<c
         const C g = *(lds_ptr<const C>)(other + off);
         C u;
         if (mu < DL) {
-            // [c][mu][half] planes of lplane bytes: own slot (hb = 16 h) or
-            // the backward neighbour (raw = 16 h')
+            // [c][mu][slot] planes: own slot or the backward neighbour
             const int c = k < D ? COL : 1 - COL;
-            const dbl2 v = *(lds_ptr<const dbl2>)(lnk + (uint32_t)(c * DL + mu) * lplane + (k < D ? hb : raw));
+            const LT v =
+                *(lds_ptr<const LT>)(lnk + (uint32_t)(c * DL + mu) * lplane + (k < D ? hb : (raw >> SHL)));
             u.x = (R)v.x;
             u.y = (R)v.y;
         } else if (k < D) {
@@ -392,17 +396,15 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 
 // Half the LDS of a two-region state lets twice the starts share a compute
 // unit.  The sweep schedule, the stopping norm and the arithmetic are those
 // of relax_wave_t.  own: the start's values on entry and on return.
-template <int D, typename R, int NS, bool RELAX, bool MAXABS>
-__device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t links, lds_ptr<const dbl2> lnk,
+template <int D, typename R, int NS, bool RELAX, bool MAXABS, int DL, typename LT>
+__device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t links, lds_ptr<const unsigned char> lb,
                         lds_ptr<const u32x4> nbt, lds_ptr<typename cx<R>::T> X, typename cx<R>::T (&own)[2][NS],
                         double eps, uint64_t cap, bool fixed, uint64_t &sweeps, double &D_out)
 {
     using C = typename cx<R>::T;
-    constexpr int DL = links_in_lds<D, NS>();
     const int lane = (int)(threadIdx.x & 63);
     lds_ptr<const unsigned char> xb = (lds_ptr<const unsigned char>)X;
-    lds_ptr<const unsigned char> lb = (lds_ptr<const unsigned char>)lnk;
-    constexpr uint32_t lplane = 64u * NS * 16u;   // staged link planes: 64 NS sites each
+    constexpr uint32_t lplane = 64u * NS * (uint32_t)sizeof(LT);   // staged link planes: 64 NS sites each
     const uint32_t plane = (uint32_t)half * (uint32_t)sizeof(C);
     const R omega = (R)J.omega;
     const uint64_t check = fixed ? cap : J.check_every > 0 ? (uint64_t)J.check_every : 1;
@@ -440,7 +442,7 @@ __device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t link
         for (int k = 0; k < NS; ++k) {
             GC_RR_SLOT(k);
             const int h = hc + z;
-            const C s = staple_big<D, DL, R, 0>(nbt[h], xb, lb, (uint32_t)h * 16u, links,
+            const C s = staple_big<D, DL, R, LT, 0>(nbt[h], xb, lb, (uint32_t)h * (uint32_t)sizeof(LT), links,
                                                 (uint32_t)h * (uint32_t)sizeof(C), plane, lplane);
             const C g0 = g0r[k];
             const double dv = (double)(g0.x * s.y - g0.y * s.x);
@@ -479,7 +481,7 @@ __device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t link
         for (int k = 0; k < NS; ++k) {
             GC_RR_SLOT(k);
             const int h = hc + z;
-            const C s = staple_big<D, DL, R, 1>(nbt[half + h], xb, lb, (uint32_t)h * 16u, links,
+            const C s = staple_big<D, DL, R, LT, 1>(nbt[half + h], xb, lb, (uint32_t)h * (uint32_t)sizeof(LT), links,
                                                 (uint32_t)h * (uint32_t)sizeof(C), plane, lplane);
             const C g = local_update<RELAX, R>(g1r[k], s, omega);
             g1r[k] = g;
@@ -519,16 +521,57 @@ __device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t link
 // max |div| stopping norm.
 enum { GC_RM_OR = 0, GC_RM_RELAX = 1, GC_RM_RELAX32 = 2, GC_RM_MAXABS = 4 };
 
-template <int D, typename R, int NS, bool RELAX, bool MAXABS>
-__device__ __forceinline__ int relax_rr_links(const GcJobDev &J, const GcWaveOrbit &WO, lds_ptr<const dbl2> lnk,
-                                              lds_ptr<const u32x4> nbt, lds_ptr<typename cx<R>::T> X,
-                                              typename cx<R>::T (&own)[2][NS], double eps, uint64_t cap, bool fixed,
-                                              uint64_t &sweeps, double &D_out)
+template <int D, typename R, int NS, bool RELAX, bool MAXABS, int DL, typename LT>
+__device__ __forceinline__ int relax_rr_links(const GcJobDev &J, const GcWaveOrbit &WO,
+                                              lds_ptr<const unsigned char> lnk, lds_ptr<const u32x4> nbt,
+                                              lds_ptr<typename cx<R>::T> X, typename cx<R>::T (&own)[2][NS],
+                                              double eps, uint64_t cap, bool fixed, uint64_t &sweeps, double &D_out)
 {
     const uint32_t bytes = (uint32_t)(2 * D * WO.half * sizeof(typename cx<R>::T));
     const __amdgpu_buffer_rsrc_t links =
         buffer_rsrc(sizeof(R) == 8 ? (const void *)WO.link64 : (const void *)WO.link32, bytes);
-    return relax_rr<D, R, NS, RELAX, MAXABS>(J, WO.half, links, lnk, nbt, X, own, eps, cap, fixed, sweeps, D_out);
+    return relax_rr<D, R, NS, RELAX, MAXABS, DL, LT>(J, WO.half, links, lnk, nbt, X, own, eps, cap, fixed, sweeps,
+                                                     D_out);
+}
+
+// The links of the first DL directions, both colours, into LDS planes of
+// 64 NS sites (plane c DL + mu) from the [c][mu][half] table src.
+template <int D, int NS, int DL, typename LT>
+__device__ __forceinline__ void rr_stage_links(lds_ptr<LT> lnk, const LT *src, int half, int nthreads)
+{
+    if constexpr (DL > 0) {
+        glb_ptr<const LT> lg = as_global(src);
+        for (int t = threadIdx.x; t < 2 * DL * half; t += nthreads) {
+            const int pl = t / half, h = t - pl * half;
+            const int c = pl / DL, mu = pl - c * DL;
+            lnk[pl * 64 * NS + h] = lg[(c * D + mu) * half + h];
+        }
+    }
+}
+
+// Final state in natural site order, one colour per round through X.
+template <int NS>
+__device__ __forceinline__ void rr_store(const GcJobDev &J, const GcWaveOrbit &WO, lds_ptr<dbl2> X64, uint64_t local,
+                                         const dbl2 (&own64)[2][NS])
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int V = J.orb.V, half = WO.half;
+    glb_ptr<dbl2> out = as_global(reinterpret_cast<dbl2 *>(J.states + local * (uint64_t)V));
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const int h = lane + 64 * k;
+            if (h < half) X64[h] = own64[c][k];
+        }
+        wave_sync();
+        for (int i = lane; i < V; i += 64) {
+            const int p = WO.loc[i] - c * half;
+            if (p >= 0 && p < half) out[i] = X64[p];
+        }
+    }
+    wave_sync();
 }
 
 // Values of colour c of a start, exchanged through X: slot h of the lane's
@@ -580,45 +623,72 @@ __device__ __forceinline__ void rr_init(const GcJobDev &J, const GcWaveOrbit &WO
     }
 }
 
+// One start on the double-precision exchange-region kernel: from the random
+// (or given) angles, or, for a mixed launch (GC_JOB_FROM32), from the state
+// the single-precision kernel promoted to HBM; starts that the
+// single-precision kernel finished (not converged) are skipped.
 template <int D, int NS, int RM>
-__device__ void relax_start_rr(const GcJobDev &J, const GcWaveOrbit &WO, lds_ptr<const dbl2> lnk,
+__device__ void relax_start_rr(const GcJobDev &J, const GcWaveOrbit &WO, lds_ptr<const unsigned char> lnk,
                                lds_ptr<const u32x4> nbt, lds_ptr<unsigned char> xr, uint64_t local)
 {
     const int lane = (int)(threadIdx.x & 63);
     const int V = J.orb.V;
     const int half = WO.half;
     lds_ptr<dbl2> X64 = (lds_ptr<dbl2>)xr;
-    const bool single = J.precision == 1;
     dbl2 own64[2][NS];
     uint64_t sw32 = 0, sw64 = 0;
     double Dn = INFINITY;
-    int status = GC_ST_CONVERGED;
-    if (single) {
-        flt2 own32[2][NS];
-        rr_init<D, NS, flt2>(J, WO, (lds_ptr<flt2>)xr, local, own32);
-        status = relax_rr_links<D, float, NS, (RM & 3) != GC_RM_OR, (RM & GC_RM_MAXABS) != 0>(
-            J, WO, lnk, nbt, (lds_ptr<flt2>)xr, own32, J.eps32, J.max_sweeps, false, sw32, Dn);
-        // promotion g64 = normalise((double) g32) after convergence, else the
-        // single-precision values reported as they are
-        const bool conv = status == GC_ST_CONVERGED;
+    const bool from32 = (J.flags & GC_JOB_FROM32) != 0;
+    if (from32) {
+        const GcStartRec r = J.rec[local];
+        if (r.status != GC_ST_PROMOTED) return;   // finished in single precision
+        sw32 = r.sweeps32;
+        // the promoted state, natural site order, one colour per round
+        glb_ptr<const dbl2> in = as_global(reinterpret_cast<const dbl2 *>(J.states + local * (uint64_t)V));
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int k = 0; k < NS; ++k) {
-                const double xr_ = (double)own32[c][k].x, xi = (double)own32[c][k].y;
-                const double r = conv ? rsqrt(xr_ * xr_ + xi * xi) : 1.0;
-                own64[c][k] = dbl2{xr_ * r, xi * r};
+        for (int c = 0; c < 2; ++c) {
+            wave_sync();
+            for (int i = lane; i < V; i += 64) {
+                const int p = WO.loc[i] - c * half;
+                if (p >= 0 && p < half) X64[p] = in[i];
             }
+            wave_sync();
+            rr_gather<dbl2, NS>(X64, own64[c], half);
+        }
     } else {
         rr_init<D, NS, dbl2>(J, WO, X64, local, own64);
     }
-    if (status == GC_ST_CONVERGED) {
-        const bool fixed = !single && (J.flags & GC_JOB_SYNC2) != 0;
-        const uint64_t cap = fixed ? (uint64_t)J.fixed_sweeps[local] : J.max_sweeps;
-        status = relax_rr_links<D, double, NS, (RM & 3) == GC_RM_RELAX, (RM & GC_RM_MAXABS) != 0>(
+    const bool fixed = !from32 && (J.flags & GC_JOB_SYNC2) != 0;
+    const uint64_t cap = fixed ? (uint64_t)J.fixed_sweeps[local] : J.max_sweeps;
+    const int status =
+        relax_rr_links<D, double, NS, (RM & 3) == GC_RM_RELAX, (RM & GC_RM_MAXABS) != 0, gc_links_in_lds(D, NS), dbl2>(
             J, WO, lnk, nbt, X64, own64, J.eps64, cap, fixed, sw64, Dn);
-    }
-    // final state in natural site order, one colour per round through X
+    rr_store<NS>(J, WO, X64, local, own64);
+    if (lane == 0) record_relax(J, local, status, sw32, sw64, Dn);
+    wave_sync();
+}
+
+// One start on the single-precision kernel of a mixed launch: relaxed to
+// eps32, then either promoted (g64 = normalise((double) g32)) into HBM for
+// the double-precision kernel, or, not converged, finished here with its
+// single-precision values widened.
+template <int D, int NS, int RM>
+__device__ void relax_start_rr32(const GcJobDev &J, const GcWaveOrbit &WO, lds_ptr<const unsigned char> lnk,
+                                 lds_ptr<const u32x4> nbt, lds_ptr<unsigned char> xr, uint64_t local)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int V = J.orb.V;
+    const int half = WO.half;
+    lds_ptr<flt2> X32 = (lds_ptr<flt2>)xr;
+    flt2 own32[2][NS];
+    uint64_t sw32 = 0;
+    double Dn = INFINITY;
+    rr_init<D, NS, flt2>(J, WO, X32, local, own32);
+    const int status =
+        relax_rr_links<D, float, NS, (RM & 3) != GC_RM_OR, (RM & GC_RM_MAXABS) != 0, gc_links_in_lds32(D, NS), flt2>(
+            J, WO, lnk, nbt, X32, own32, J.eps32, J.max_sweeps, false, sw32, Dn);
+    const bool conv = status == GC_ST_CONVERGED;
+    // natural site order, one colour per round through X (single precision)
     glb_ptr<dbl2> out = as_global(reinterpret_cast<dbl2 *>(J.states + local * (uint64_t)V));
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -626,15 +696,32 @@ __device__ void relax_start_rr(const GcJobDev &J, const GcWaveOrbit &WO, lds_ptr
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             const int h = lane + 64 * k;
-            if (h < half) X64[h] = own64[c][k];
+            if (h < half) X32[h] = own32[c][k];
         }
         wave_sync();
         for (int i = lane; i < V; i += 64) {
             const int p = WO.loc[i] - c * half;
-            if (p >= 0 && p < half) out[i] = X64[p];
+            if (p >= 0 && p < half) {
+                const flt2 g = X32[p];
+                const double xr_ = (double)g.x, xi = (double)g.y;
+                const double r = conv ? rsqrt(xr_ * xr_ + xi * xi) : 1.0;
+                out[i] = dbl2{xr_ * r, xi * r};
+            }
         }
     }
-    if (lane == 0) record_relax(J, local, status, sw32, sw64, Dn);
+    wave_sync();
+    if (lane == 0) {
+        if (conv) {
+            GcStartRec r = {};
+            r.status = GC_ST_PROMOTED;
+            r.sweeps32 = (uint32_t)sw32;
+            r.D = Dn;
+            r.lambda2 = NAN;
+            J.rec[local] = r;
+        } else {
+            record_relax(J, local, status, sw32, 0, Dn);
+        }
+    }
     wave_sync();
 }
 
@@ -714,10 +801,9 @@ __global__ __launch_bounds__(64 * WAVES) void wave_kernel(const GcJobDev *__rest
 }
 
 // WG = GC_WAVES_RR wavefronts, one start each, for lattices with more than
-// two slots per lane.  LDS (gc_rr_lds_bytes): [links of DL directions, planes
-// of 64 NS double2 | neighbour table 16V (byte offsets)] then per wave an
-// 8V-byte exchange region (double2[half], or float2[half] in the
-// single-precision phase).
+// two slots per lane, double precision.  LDS (gc_rr_lds_bytes): [links of DL
+// directions, planes of 64 NS double2 | neighbour table 16V (byte offsets)]
+// then per wave an 8V-byte exchange region (double2[half]).
 template <int D, int NS, int RM>
 __global__ __launch_bounds__(64 * GC_WAVES_RR) void wave_rr_kernel(const GcJobDev *__restrict__ jobs,
                                                                     const GcWaveOrbit *__restrict__ worbs,
@@ -725,7 +811,7 @@ __global__ __launch_bounds__(64 * GC_WAVES_RR) void wave_rr_kernel(const GcJobDe
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int cur_job;
-    constexpr int DL = links_in_lds<D, NS>();
+    constexpr int DL = gc_links_in_lds(D, NS);
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     int j0 = (int)(blockIdx.x % (unsigned)n_jobs);
@@ -750,15 +836,9 @@ __global__ __launch_bounds__(64 * GC_WAVES_RR) void wave_rr_kernel(const GcJobDe
         const int V = J.orb.V;
         const int half = WO.half;
         constexpr size_t LB = gc_rr_links_bytes(D, NS);
-        lds_ptr<dbl2> lnk = as_lds(reinterpret_cast<dbl2 *>(smem));
-        if constexpr (DL > 0) {
-            glb_ptr<const dbl2> lg = as_global(reinterpret_cast<const dbl2 *>(WO.link64));
-            for (int t = threadIdx.x; t < 2 * DL * half; t += 64 * GC_WAVES_RR) {
-                const int pl = t / half, h = t - pl * half;   // plane c * DL + mu
-                const int c = pl / DL, mu = pl - c * DL;
-                lnk[pl * 64 * NS + h] = lg[(c * D + mu) * half + h];
-            }
-        }
+        rr_stage_links<D, NS, DL, dbl2>(as_lds(reinterpret_cast<dbl2 *>(smem)),
+                                        reinterpret_cast<const dbl2 *>(WO.link64), half, 64 * GC_WAVES_RR);
+        lds_ptr<const unsigned char> lnk = as_lds(reinterpret_cast<const unsigned char *>(smem));
         lds_ptr<u32x4> nbt = as_lds(reinterpret_cast<u32x4 *>(smem + LB));
         glb_ptr<const u32x4> nbg = as_global(reinterpret_cast<const u32x4 *>(WO.nbo));
         for (int t = threadIdx.x; t < V; t += 64 * GC_WAVES_RR) nbt[t] = nbg[t];
@@ -774,6 +854,99 @@ __global__ __launch_bounds__(64 * GC_WAVES_RR) void wave_rr_kernel(const GcJobDe
         __syncthreads();
         j0 = jn;
     }
+}
+
+// WG = GC_WAVES_RR32 wavefronts, one start each: the single-precision phase
+// of mixed launches with more than two slots per lane.  LDS
+// (gc_rr32_lds_bytes): [links of DL directions, planes of 64 NS float2 |
+// neighbour table 16V] then per wave a 4V-byte exchange region (float2[half]).
+template <int D, int NS, int RM>
+__global__ __launch_bounds__(64 * GC_WAVES_RR32) void wave_rr32_kernel(const GcJobDev *__restrict__ jobs,
+                                                                        const GcWaveOrbit *__restrict__ worbs,
+                                                                        int n_jobs, unsigned long long *job_next)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int cur_job;
+    constexpr int DL = gc_links_in_lds32(D, NS);
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    int j0 = (int)(blockIdx.x % (unsigned)n_jobs);
+    for (int round = 0; round < n_jobs; ++round) {
+        if (threadIdx.x == 0) {
+            int pick = -1;
+            for (int k = 0; k < n_jobs; ++k) {
+                const int j = (j0 + k) % n_jobs;
+                if (__hip_atomic_load(&job_next[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < jobs[j].n_starts) {
+                    pick = j;
+                    break;
+                }
+            }
+            cur_job = pick;
+        }
+        __syncthreads();
+        const int jn = uniform(cur_job);
+        __syncthreads();
+        if (jn < 0) break;
+        const GcJobDev &J = jobs[jn];
+        const GcWaveOrbit &WO = worbs[jn];
+        const int V = J.orb.V;
+        const int half = WO.half;
+        constexpr size_t LB = gc_rr32_links_bytes(D, NS);
+        rr_stage_links<D, NS, DL, flt2>(as_lds(reinterpret_cast<flt2 *>(smem)),
+                                        reinterpret_cast<const flt2 *>(WO.link32), half, 64 * GC_WAVES_RR32);
+        lds_ptr<const unsigned char> lnk = as_lds(reinterpret_cast<const unsigned char *>(smem));
+        lds_ptr<u32x4> nbt = as_lds(reinterpret_cast<u32x4 *>(smem + LB));
+        glb_ptr<const u32x4> nbg = as_global(reinterpret_cast<const u32x4 *>(WO.nbo32));
+        for (int t = threadIdx.x; t < V; t += 64 * GC_WAVES_RR32) nbt[t] = nbg[t];
+        __syncthreads();
+        lds_ptr<unsigned char> xr = as_lds(smem + LB + 16 * (size_t)V + (size_t)wave * 4 * V);
+        for (;;) {
+            unsigned long long s = 0;
+            if (lane == 0) s = atomicAdd(&job_next[jn], 1ULL);
+            s = uniform((uint64_t)s);
+            if (s >= J.n_starts) break;
+            relax_start_rr32<D, NS, RM>(J, WO, lnk, nbt, xr, s);
+        }
+        __syncthreads();
+        j0 = jn;
+    }
+}
+
+template <int D, int NS, int WAVES>
+hipError_t launch32_t(const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, unsigned long long *job_next,
+                      int rm, int grid, size_t lds, hipStream_t s)
+{
+    if constexpr (NS > 2) {
+        switch (rm) {
+#define GC_RR32_LAUNCH(RM)                                                                                \
+    case RM:                                                                                              \
+        hipLaunchKernelGGL((wave_rr32_kernel<D, NS, RM>), dim3(grid), dim3(64 * GC_WAVES_RR32), lds, s, jobs,  \
+                           worbs, n_jobs, job_next);                                                      \
+        break;
+            GC_RR32_LAUNCH(0)
+            GC_RR32_LAUNCH(1)
+            GC_RR32_LAUNCH(2)
+            GC_RR32_LAUNCH(4)
+            GC_RR32_LAUNCH(5)
+            GC_RR32_LAUNCH(6)
+#undef GC_RR32_LAUNCH
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int D, int NS, int WAVES>
+hipError_t occ32_t(int rm, size_t lds, int *per_cu)
+{
+    (void)rm;
+    if constexpr (NS > 2)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, wave_rr32_kernel<D, NS, GC_RM_OR>,
+                                                            64 * GC_WAVES_RR32, lds);
+    else
+        return hipErrorInvalidValue;
 }
 
 // One start per workgroup of WPS wavefronts, for lattices with more than 128
@@ -945,6 +1118,16 @@ hipError_t occ_t(int variant, size_t lds, int *per_cu)
                                    size_t lds, hipStream_t s)                                             \
     {                                                                                                     \
         NS_LIST(launch_t, D, jobs, worbs, n_jobs, job_next, variant, bounce, grid, lds, s)               \
+    }                                                                                                     \
+    hipError_t gc_wave32_occupancy_d##D(int ns, int rm, size_t lds, int *per_cu)                          \
+    {                                                                                                     \
+        NS_LIST(occ32_t, D, rm, lds, per_cu)                                                              \
+    }                                                                                                     \
+    hipError_t gc_launch_wave32_d##D(int ns, const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, \
+                                     unsigned long long *job_next, int rm, int grid, size_t lds,          \
+                                     hipStream_t s)                                                       \
+    {                                                                                                     \
+        NS_LIST(launch32_t, D, jobs, worbs, n_jobs, job_next, rm, grid, lds, s)                           \
     }                                                                                                     \
     hipError_t gc_wps_occupancy_d##D(int wps, size_t lds, int *per_cu)                                    \
     {                                                                                                     \
