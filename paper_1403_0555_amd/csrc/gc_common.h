@@ -80,9 +80,10 @@ __device__ __forceinline__ void wave_sync_global()
 // Reductions over the 64 lanes of a wavefront; every lane ends with the same
 // value and the association order is fixed.  Within each row of 16 lanes
 // the values are combined through DPP lane permutations (quad swaps, then
-// the half-row and row mirrors), so they never touch LDS; the four row
-// results are then read into scalar registers and combined as
-// (r0 + r1) + (r2 + r3).
+// the half-row and row mirrors); the four row results are then combined as
+// (r0 + r1) + (r2 + r3) through the cross-row swaps of gfx950
+// (v_permlane16_swap, v_permlane32_swap), so nothing touches LDS or scalar
+// registers until the wave-uniform result is read from the first lane.
 template <int CTRL> __device__ __forceinline__ int dpp32(int v)
 {
     // every row and bank enabled: no lane keeps an old value, so none is
@@ -95,10 +96,10 @@ template <int CTRL> __device__ __forceinline__ double dpp64(double v)
     const int lo = dpp32<CTRL>((int)b), hi = dpp32<CTRL>((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
-__device__ __forceinline__ double lane_value(double v, int lane)
+__device__ __forceinline__ double first_lane(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, lane), hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    const int lo = __builtin_amdgcn_readfirstlane((int)b), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 constexpr int kDppQuadSwap1 = 0xB1;   // quad_perm [1, 0, 3, 2]
@@ -106,17 +107,47 @@ constexpr int kDppQuadSwap2 = 0x4E;   // quad_perm [2, 3, 0, 1]
 constexpr int kDppHalfMirror = 0x141; // row_half_mirror
 constexpr int kDppRowMirror = 0x140;  // row_mirror
 
+// Cross-row pairs.  With both operands holding v, permlane16_swap leaves in
+// every lane the value of its even row (first result) and of its odd row
+// (second result) of the same row pair; permlane32_swap does the same for
+// the lower and upper half-waves.  The two halves of a double take the same
+// swap.
+struct RowPair {
+    double lo, hi;   // the even (lower) and the odd (upper) member of the pair
+};
+template <int W> __device__ __forceinline__ RowPair row_pair(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned l = (unsigned)b, h = (unsigned)(b >> 32);
+    const auto sl = W == 16 ? __builtin_amdgcn_permlane16_swap(l, l, false, false)
+                            : __builtin_amdgcn_permlane32_swap(l, l, false, false);
+    const auto sh = W == 16 ? __builtin_amdgcn_permlane16_swap(h, h, false, false)
+                            : __builtin_amdgcn_permlane32_swap(h, h, false, false);
+    return {__longlong_as_double(((long long)sh[0] << 32) | (long long)sl[0]),
+            __longlong_as_double(((long long)sh[1] << 32) | (long long)sl[1])};
+}
+template <int W> __device__ __forceinline__ int row_pair_min(int v)
+{
+    const auto s = W == 16 ? __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false)
+                           : __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    return min((int)s[0], (int)s[1]);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
     v += dpp64<kDppQuadSwap1>(v);
     v += dpp64<kDppQuadSwap2>(v);
     v += dpp64<kDppHalfMirror>(v);
     v += dpp64<kDppRowMirror>(v);
-    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+    RowPair p = row_pair<16>(v);
+    v = p.lo + p.hi;
+    p = row_pair<32>(v);
+    return first_lane(p.lo + p.hi);
 }
-// N sums at once, step by step across the values: the DPP moves of one
+// N sums at once, step by step across the values: the lane moves of one
 // value fill the waits the others' additions need.  Same association order
-// as wave_sum for each value.
+// as wave_sum for each value; the results stay in vector registers (equal
+// in every lane).
 template <int N> __device__ __forceinline__ void wave_sum_n(double (&v)[N])
 {
 #pragma unroll
@@ -128,8 +159,15 @@ template <int N> __device__ __forceinline__ void wave_sum_n(double (&v)[N])
 #pragma unroll
     for (int n = 0; n < N; ++n) v[n] += dpp64<kDppRowMirror>(v[n]);
 #pragma unroll
-    for (int n = 0; n < N; ++n)
-        v[n] = (lane_value(v[n], 0) + lane_value(v[n], 16)) + (lane_value(v[n], 32) + lane_value(v[n], 48));
+    for (int n = 0; n < N; ++n) {
+        const RowPair p = row_pair<16>(v[n]);
+        v[n] = p.lo + p.hi;
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const RowPair p = row_pair<32>(v[n]);
+        v[n] = p.lo + p.hi;
+    }
 }
 __device__ __forceinline__ double wave_max(double v)
 {
@@ -137,7 +175,10 @@ __device__ __forceinline__ double wave_max(double v)
     v = fmax(v, dpp64<kDppQuadSwap2>(v));
     v = fmax(v, dpp64<kDppHalfMirror>(v));
     v = fmax(v, dpp64<kDppRowMirror>(v));
-    return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
+    RowPair p = row_pair<16>(v);
+    v = fmax(p.lo, p.hi);
+    p = row_pair<32>(v);
+    return first_lane(fmax(p.lo, p.hi));
 }
 __device__ __forceinline__ double wave_min(double v)
 {
@@ -145,7 +186,10 @@ __device__ __forceinline__ double wave_min(double v)
     v = fmin(v, dpp64<kDppQuadSwap2>(v));
     v = fmin(v, dpp64<kDppHalfMirror>(v));
     v = fmin(v, dpp64<kDppRowMirror>(v));
-    return fmin(fmin(lane_value(v, 0), lane_value(v, 16)), fmin(lane_value(v, 32), lane_value(v, 48)));
+    RowPair p = row_pair<16>(v);
+    v = fmin(p.lo, p.hi);
+    p = row_pair<32>(v);
+    return first_lane(fmin(p.lo, p.hi));
 }
 __device__ __forceinline__ int wave_min_int(int v)
 {
@@ -153,8 +197,9 @@ __device__ __forceinline__ int wave_min_int(int v)
     v = min(v, dpp32<kDppQuadSwap2>(v));
     v = min(v, dpp32<kDppHalfMirror>(v));
     v = min(v, dpp32<kDppRowMirror>(v));
-    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+    v = row_pair_min<16>(v);
+    v = row_pair_min<32>(v);
+    return __builtin_amdgcn_readfirstlane(v);
 }
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
 {

@@ -128,12 +128,17 @@ hipError_t gc_launch_post(int block, int sp, int wreg, int keys, const GcJobDev 
 // Filter pass in the line-segment layout (seg sites per thread along
 // direction 0), one kernel per lattice dimension d (every job of a launch
 // has dimension d): gc_lanczos_shape returns 0 when no instantiated shape
-// fits.
+// fits.  gc_lanczos_form: bit 0 when the segments are whole lines
+// (seg == N0), bit 1 when the V/seg threads fit a stride of 7 block / 8
+// doubles in the segment-major LDS arrays (else the stride is block); every
+// job of a launch has the same form.
 int gc_lanczos_shape(int d, const int *ext, int V, int *block, int *seg);
-size_t gc_lanczos_lds_bytes(int d, int N0, int seg, int V, int lmax);
-// whole: the segments are whole lines (seg == N0) for every job of the launch.
-hipError_t gc_lanczos_occupancy(int d, int block, int seg, int whole, size_t lds_bytes, int *blocks_per_cu);
-hipError_t gc_launch_lanczos(int d, int block, int seg, int whole, const GcJobDev *jobs, int n_jobs,
+int gc_lanczos_form(int N0, int seg, int V, int block);
+// LDS bytes: u and the weight arrays, seg x stride doubles each, then the
+// tridiagonal.
+size_t gc_lanczos_lds_bytes(int d, int N0, int seg, int V, int lmax, int block);
+hipError_t gc_lanczos_occupancy(int d, int block, int seg, int form, size_t lds_bytes, int *blocks_per_cu);
+hipError_t gc_launch_lanczos(int d, int block, int seg, int form, const GcJobDev *jobs, int n_jobs,
                              unsigned long long *next, int grid, size_t lds_bytes, hipStream_t s);
 
 // Table and bookkeeping kernels.

@@ -41,15 +41,18 @@ __device__ double ritz_wave0(lds_cdouble *alpha, lds_cdouble *beta2, int k, doub
 // consecutive site indices), segment t % (N_0/S) of line t / (N_0/S).  The
 // Lanczos vector u of the own sites, q_{j-1} and M u stay in registers, and
 // so do the direction-0 link weights; direction-0 neighbours inside the
-// segment are the thread's own entries.  LDS holds u (8V bytes) for the
-// other threads, the forward link weights of directions 1..d-1 (and of
-// direction 0 when a line has several segments), V doubles each, and the
-// tridiagonal.  LDS arrays are segment-major: the k-th site of thread t's
-// segment sits at k T + t (T = V/S threads), so the threads of a wavefront
-// touch consecutive doubles, and a neighbour in direction mu >= 1 (the same
-// k of another segment) at a constant thread offset.  The iteration is
+// segment are the thread's own entries.  LDS holds u for the other
+// threads, the forward link weights of directions 1..d-1 (and of direction
+// 0 when a line has several segments), S B doubles each, and the
+// tridiagonal.  LDS arrays are segment-major with a compile-time stride P
+// (B, or 7B/8 when the launch's T = V/S threads fit in it): the k-th site
+// of thread t's segment sits at k P + t, so the threads of a wavefront
+// touch consecutive doubles, a neighbour in direction mu >= 1 (the same k
+// of another segment) sits at a constant thread offset, and every site's
+// address is a per-thread base plus a compile-time offset.  FORM bit 0:
+// the segments are whole lines (S == N0); bit 1: P = 7B/8.  The iteration is
 // post_kernel's: one reduction per iteration, the same formulas per site.
-template <int B, int S, int D, bool WHOLE>
+template <int B, int S, int D, int FORM>
 __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__ jobs, int n_jobs,
                                                     unsigned long long *next)
 {
@@ -79,14 +82,15 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
         const bool act = tid < V / S;
         const int line = act ? tid / nseg : 0, o = act ? (tid % nseg) * S : 0;
         const int i0 = line * N0 + o;
-        constexpr bool whole = WHOLE;   // the segment is a whole line (S == N0, the launch's choice)
-        const int T = V / S;              // active threads, the stride of the segment-major arrays
+        constexpr bool whole = (FORM & 1) != 0;   // the segment is a whole line (S == N0)
+        constexpr int P = (FORM & 2) ? 7 * B / 8 : B;   // stride of the segment-major arrays (>= V/S)
         const int nw = whole ? d - 1 : d;   // weight arrays in LDS
         const int w0off = whole ? -1 : 0;   // LDS array of direction mu: mu + w0off
+        constexpr int A = S * P;            // doubles per LDS array
         lds_ptr<double> u = as_lds(reinterpret_cast<double *>(smem));
-        lds_ptr<double> wl = u + V;
+        lds_ptr<double> wl = u + A;
         const int lmax = min(min(J.lanczos_max, GC_LMAX), V);
-        lds_ptr<double> alpha = wl + (size_t)nw * V;
+        lds_ptr<double> alpha = wl + (size_t)nw * A;
         lds_ptr<double> beta2 = alpha + lmax;
 
         // own link weights w = Re(conj(g_i) U_{i,mu} g_{i+mu}) from the
@@ -121,7 +125,7 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
                         const double tr = uu.x * gf.x - uu.y * gf.y, ti = uu.x * gf.y + uu.y * gf.x;
                         const double ur = gi.x * tr + gi.y * ti;
                         if (mu == 0) w0[k] = ur;
-                        if (mu + w0off >= 0) wl[(mu + w0off) * V + k * T + tid] = ur;
+                        if (mu + w0off >= 0) wl[(mu + w0off) * A + k * P + tid] = ur;
                     }
                 }
             }
@@ -147,7 +151,7 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
         for (int k = 0; k < S; ++k) {
             if (act) {
                 uo[k] -= mean;
-                u[k * T + tid] = uo[k];
+                u[k * P + tid] = uo[k];
             }
         }
         const double sigma = 4.0 * d + 1.0;
@@ -160,17 +164,24 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
         // the neighbours across the ends of a segment that is not a whole
         // line: the first site of the next segment, the last of the previous
         const int ia = line * nseg + ((o + S) % N0) / S;
-        const int ib = (S - 1) * T + line * nseg + ((o + N0 - 1) % N0) / S;
-        // byte offsets within an LDS array of the own site and of the
-        // neighbours in directions >= 1 (fixed for the copy); the k-th site
-        // adds k T 8, kept in a scalar register
+        const int ib = (S - 1) * P + line * nseg + ((o + N0 - 1) % N0) / S;
+        // byte offsets from u of the four values a site reads per direction
+        // mu >= 1 (fixed for the copy): the own forward weight (aw), the
+        // forward neighbour's u (af), the backward neighbour's weight (bw)
+        // and u (bu); the k-th site adds a compile-time offset.  Each is its
+        // own register, opaque to the compiler: two loads from one register
+        // would be paired into a ds_read2st64, whose two addresses, a
+        // multiple of 512 bytes apart, fall in the same LDS bank.
         lds_ptr<const unsigned char> ubase = (lds_ptr<const unsigned char>)u;
-        const uint32_t t8 = 8u * (uint32_t)tid;
-        uint32_t of8[GC_MAXD], ob8[GC_MAXD];
+        uint32_t aw[GC_MAXD], af[GC_MAXD], bw[GC_MAXD], bu[GC_MAXD];
 #pragma unroll
         for (int mu = 0; mu < GC_MAXD; ++mu) {
-            of8[mu] = 8u * (uint32_t)(tid + df[mu]);
-            ob8[mu] = 8u * (uint32_t)(tid + db[mu]);
+            const uint32_t warr = 8u * (uint32_t)((1 + mu + w0off) * A);   // the weight array of mu
+            aw[mu] = warr + 8u * (uint32_t)tid;
+            af[mu] = 8u * (uint32_t)(tid + df[mu]);
+            bw[mu] = warr + 8u * (uint32_t)(tid + db[mu]);
+            bu[mu] = 8u * (uint32_t)(tid + db[mu]);
+            if (mu > 0 && mu < d) asm volatile("" : "+v"(aw[mu]), "+v"(af[mu]), "+v"(bw[mu]), "+v"(bu[mu]));
         }
         // the diagonal of M at the own sites, the sum of their 2d link
         // weights, once per copy (M u)_i = diag_i u_i - sum_nb w u_nb
@@ -185,7 +196,7 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
 #pragma unroll
                 for (int mu = 1; mu < GC_MAXD; ++mu)
                     if (mu < d) {
-                        lds_ptr<const double> wm = wl + (mu + w0off) * V + k * T;
+                        lds_ptr<const double> wm = wl + (mu + w0off) * A + k * P;
                         a += wm[tid] + wm[tid + db[mu]];
                     }
                 dg[k] = act ? a : 0.0;
@@ -208,10 +219,7 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
                 }
 #pragma unroll
                 for (int k = 0; k < S; ++k) {
-                    uint32_t kb = 8u * (uint32_t)(k * T);
-                    // opaque: the site addresses are formed per site, not
-                    // held in registers across the iteration
-                    asm volatile("" : "+s"(kb));
+                    const uint32_t kb = 8u * (uint32_t)(k * P);
                     const double ui = uo[k];
                     // direction 0: neighbours and weights of the own segment
                     const double uf = (k + 1 < S) ? uo[k + 1] : ua;
@@ -223,13 +231,11 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
 #pragma unroll
                     for (int mu = 1; mu < GC_MAXD; ++mu)
                         if (mu < d) {
-                            lds_ptr<const unsigned char> ub8 = ubase + kb;
-                            lds_ptr<const unsigned char> wb8 =
-                                (lds_ptr<const unsigned char>)(wl + (mu + w0off) * V) + kb;
-                            const double wf_ = *(lds_ptr<const double>)(wb8 + t8);
-                            const double uf_ = *(lds_ptr<const double>)(ub8 + of8[mu]);
-                            const double wb_ = *(lds_ptr<const double>)(wb8 + ob8[mu]);
-                            const double ub_ = *(lds_ptr<const double>)(ub8 + ob8[mu]);
+                            lds_ptr<const unsigned char> b8 = ubase + kb;
+                            const double wf_ = *(lds_ptr<const double>)(b8 + aw[mu]);
+                            const double uf_ = *(lds_ptr<const double>)(b8 + af[mu]);
+                            const double wb_ = *(lds_ptr<const double>)(b8 + bw[mu]);
+                            const double ub_ = *(lds_ptr<const double>)(b8 + bu[mu]);
                             m = fma(-wf_, uf_, m);
                             m = fma(-wb_, ub_, m);
                         }
@@ -270,7 +276,7 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
                     const double r = mv[k] * inv + shift - bp * qp[k] - a_j * q;
                     qp[k] = q;
                     uo[k] = r;
-                    u[k * T + tid] = r;
+                    u[k * P + tid] = r;
                 }
             }
             if (it + 1 >= next_check || it + 1 == lmax) {
@@ -306,20 +312,27 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
 }  // namespace
 
 // Entry points of one lattice dimension D (gc_lanczosD.hip): occupancy and
-// launch of lanczos_kernel<B, S, D> for the shapes gc_lanczos_shape picks.
-#define GC_LANCZOS_W(FN, B, S, D, ...)                                                                    \
-    return whole ? FN<B, S, D, true>(__VA_ARGS__) : FN<B, S, D, false>(__VA_ARGS__);
+// launch of lanczos_kernel<B, S, D, FORM> for the shapes gc_lanczos_shape
+// and gc_lanczos_form pick.
+#define GC_LANCZOS_F(FN, B, S, D, ...)                                                                    \
+    switch (form) {                                                                                       \
+    case 0: return FN<B, S, D, 0>(__VA_ARGS__);                                                           \
+    case 1: return FN<B, S, D, 1>(__VA_ARGS__);                                                           \
+    case 2: return FN<B, S, D, 2>(__VA_ARGS__);                                                           \
+    case 3: return FN<B, S, D, 3>(__VA_ARGS__);                                                           \
+    default: return hipErrorInvalidValue;                                                                 \
+    }
 #define GC_LANCZOS_SEG(FN, B, D, ...)                                                                     \
     switch (seg) {                                                                                        \
-    case 1: GC_LANCZOS_W(FN, B, 1, D, __VA_ARGS__)                                                        \
-    case 2: GC_LANCZOS_W(FN, B, 2, D, __VA_ARGS__)                                                        \
-    case 3: GC_LANCZOS_W(FN, B, 3, D, __VA_ARGS__)                                                        \
-    case 4: GC_LANCZOS_W(FN, B, 4, D, __VA_ARGS__)                                                        \
-    case 5: GC_LANCZOS_W(FN, B, 5, D, __VA_ARGS__)                                                        \
-    case 6: GC_LANCZOS_W(FN, B, 6, D, __VA_ARGS__)                                                        \
-    case 7: GC_LANCZOS_W(FN, B, 7, D, __VA_ARGS__)                                                        \
-    case 8: GC_LANCZOS_W(FN, B, 8, D, __VA_ARGS__)                                                        \
-    case 10: GC_LANCZOS_W(FN, B, 10, D, __VA_ARGS__)                                                      \
+    case 1: GC_LANCZOS_F(FN, B, 1, D, __VA_ARGS__)                                                        \
+    case 2: GC_LANCZOS_F(FN, B, 2, D, __VA_ARGS__)                                                        \
+    case 3: GC_LANCZOS_F(FN, B, 3, D, __VA_ARGS__)                                                        \
+    case 4: GC_LANCZOS_F(FN, B, 4, D, __VA_ARGS__)                                                        \
+    case 5: GC_LANCZOS_F(FN, B, 5, D, __VA_ARGS__)                                                        \
+    case 6: GC_LANCZOS_F(FN, B, 6, D, __VA_ARGS__)                                                        \
+    case 7: GC_LANCZOS_F(FN, B, 7, D, __VA_ARGS__)                                                        \
+    case 8: GC_LANCZOS_F(FN, B, 8, D, __VA_ARGS__)                                                        \
+    case 10: GC_LANCZOS_F(FN, B, 10, D, __VA_ARGS__)                                                      \
     default: return hipErrorInvalidValue;                                                                 \
     }
 #define GC_LANCZOS_DISPATCH(FN, D, ...)                                                                   \
@@ -331,28 +344,28 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
     default: return hipErrorInvalidValue;                                                                 \
     }
 
-template <int B, int S, int D, bool WHOLE>
+template <int B, int S, int D, int FORM>
 static hipError_t lanczos_occ_t(size_t lds, int *per_cu)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, lanczos_kernel<B, S, D, WHOLE>, B, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, lanczos_kernel<B, S, D, FORM>, B, lds);
 }
 
-template <int B, int S, int D, bool WHOLE>
+template <int B, int S, int D, int FORM>
 static hipError_t lanczos_launch_t(const GcJobDev *jobs, int n_jobs, unsigned long long *next, int grid, size_t lds,
                                    hipStream_t s)
 {
-    hipLaunchKernelGGL((lanczos_kernel<B, S, D, WHOLE>), dim3(grid), dim3(B), lds, s, jobs, n_jobs, next);
+    hipLaunchKernelGGL((lanczos_kernel<B, S, D, FORM>), dim3(grid), dim3(B), lds, s, jobs, n_jobs, next);
     return hipGetLastError();
 }
 
-// whole: the segments are whole lines (S == N0) for every job of the launch
+// form: gc_lanczos_form's value, the same for every job of the launch
 #define GC_LANCZOS_DEFINE_DIM(D)                                                                          \
-    hipError_t gc_lanczos_occupancy_d##D(int block, int seg, int whole, size_t lds_bytes,                 \
+    hipError_t gc_lanczos_occupancy_d##D(int block, int seg, int form, size_t lds_bytes,                  \
                                          int *blocks_per_cu)                                              \
     {                                                                                                     \
         GC_LANCZOS_DISPATCH(lanczos_occ_t, D, lds_bytes, blocks_per_cu)                                   \
     }                                                                                                     \
-    hipError_t gc_launch_lanczos_d##D(int block, int seg, int whole, const GcJobDev *jobs, int n_jobs,    \
+    hipError_t gc_launch_lanczos_d##D(int block, int seg, int form, const GcJobDev *jobs, int n_jobs,     \
                                       unsigned long long *next, int grid, size_t lds_bytes, hipStream_t s)  \
     {                                                                                                     \
         GC_LANCZOS_DISPATCH(lanczos_launch_t, D, jobs, n_jobs, next, grid, lds_bytes, s)                  \

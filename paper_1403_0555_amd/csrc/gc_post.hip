@@ -770,42 +770,48 @@ int gc_lanczos_shape(int d, const int *ext, int V, int *block, int *seg)
     return 1;
 }
 
-size_t gc_lanczos_lds_bytes(int d, int N0, int S, int V, int lmax)
+int gc_lanczos_form(int N0, int S, int V, int block)
+{
+    return (S == N0 ? 1 : 0) | (V / S <= 7 * block / 8 ? 2 : 0);
+}
+
+size_t gc_lanczos_lds_bytes(int d, int N0, int S, int V, int lmax, int block)
 {
     const int nw = (S == N0) ? d - 1 : d;
+    const int P = (gc_lanczos_form(N0, S, V, block) & 2) ? 7 * block / 8 : block;
     const size_t l = (size_t)std::min(std::min(lmax, GC_LMAX), V);
-    return 8 * (size_t)V + 8 * (size_t)nw * V + 16 * l;
+    return 8 * (size_t)(1 + nw) * S * P + 16 * l;
 }
 
 #define GC_LANCZOS_DECLARE_DIM(D)                                                                         \
-    hipError_t gc_lanczos_occupancy_d##D(int block, int seg, int whole, size_t lds_bytes,                 \
+    hipError_t gc_lanczos_occupancy_d##D(int block, int seg, int form, size_t lds_bytes,                  \
                                          int *blocks_per_cu);                                             \
-    hipError_t gc_launch_lanczos_d##D(int block, int seg, int whole, const GcJobDev *jobs, int n_jobs,    \
+    hipError_t gc_launch_lanczos_d##D(int block, int seg, int form, const GcJobDev *jobs, int n_jobs,     \
                                       unsigned long long *next, int grid, size_t lds_bytes, hipStream_t s);
 GC_LANCZOS_DECLARE_DIM(1)
 GC_LANCZOS_DECLARE_DIM(2)
 GC_LANCZOS_DECLARE_DIM(3)
 GC_LANCZOS_DECLARE_DIM(4)
 
-hipError_t gc_lanczos_occupancy(int d, int block, int seg, int whole, size_t lds_bytes, int *blocks_per_cu)
+hipError_t gc_lanczos_occupancy(int d, int block, int seg, int form, size_t lds_bytes, int *blocks_per_cu)
 {
     switch (d) {
-    case 1: return gc_lanczos_occupancy_d1(block, seg, whole, lds_bytes, blocks_per_cu);
-    case 2: return gc_lanczos_occupancy_d2(block, seg, whole, lds_bytes, blocks_per_cu);
-    case 3: return gc_lanczos_occupancy_d3(block, seg, whole, lds_bytes, blocks_per_cu);
-    case 4: return gc_lanczos_occupancy_d4(block, seg, whole, lds_bytes, blocks_per_cu);
+    case 1: return gc_lanczos_occupancy_d1(block, seg, form, lds_bytes, blocks_per_cu);
+    case 2: return gc_lanczos_occupancy_d2(block, seg, form, lds_bytes, blocks_per_cu);
+    case 3: return gc_lanczos_occupancy_d3(block, seg, form, lds_bytes, blocks_per_cu);
+    case 4: return gc_lanczos_occupancy_d4(block, seg, form, lds_bytes, blocks_per_cu);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t gc_launch_lanczos(int d, int block, int seg, int whole, const GcJobDev *jobs, int n_jobs,
+hipError_t gc_launch_lanczos(int d, int block, int seg, int form, const GcJobDev *jobs, int n_jobs,
                              unsigned long long *next, int grid, size_t lds_bytes, hipStream_t s)
 {
     switch (d) {
-    case 1: return gc_launch_lanczos_d1(block, seg, whole, jobs, n_jobs, next, grid, lds_bytes, s);
-    case 2: return gc_launch_lanczos_d2(block, seg, whole, jobs, n_jobs, next, grid, lds_bytes, s);
-    case 3: return gc_launch_lanczos_d3(block, seg, whole, jobs, n_jobs, next, grid, lds_bytes, s);
-    case 4: return gc_launch_lanczos_d4(block, seg, whole, jobs, n_jobs, next, grid, lds_bytes, s);
+    case 1: return gc_launch_lanczos_d1(block, seg, form, jobs, n_jobs, next, grid, lds_bytes, s);
+    case 2: return gc_launch_lanczos_d2(block, seg, form, jobs, n_jobs, next, grid, lds_bytes, s);
+    case 3: return gc_launch_lanczos_d3(block, seg, form, jobs, n_jobs, next, grid, lds_bytes, s);
+    case 4: return gc_launch_lanczos_d4(block, seg, form, jobs, n_jobs, next, grid, lds_bytes, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -235,7 +235,7 @@ struct PostGroup {
 struct FilterGroup {
     bool fast = false;
     int d = 0;                        // lattice dimension (fast kernel: one per dimension)
-    int whole = 0;                    // fast kernel: segments are whole lines (seg == N0)
+    int form = 0;                     // fast kernel: gc_lanczos_form (whole lines, array stride)
     int block = 64, seg = 1, sp = 1, wreg = 1, grid = 1;
     size_t lds = 0;
     uint64_t total = 0, wstride = 0;   // total: an upper bound of the copies (the starts)
@@ -779,10 +779,10 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             f.chain = (int)gi;
             int fb = 0, fs = 0;
             if (gc_lanczos_shape(o->d, o->lat.extent, o->V, &fb, &fs) &&
-                gc_lanczos_lds_bytes(o->d, o->lat.extent[0], fs, o->V, lmax) <= ctx->lds_max) {
+                gc_lanczos_lds_bytes(o->d, o->lat.extent[0], fs, o->V, lmax, fb) <= ctx->lds_max) {
                 f.fast = true;
                 f.d = o->d;
-                f.whole = fs == o->lat.extent[0] ? 1 : 0;
+                f.form = gc_lanczos_form(o->lat.extent[0], fs, o->V, fb);
                 f.block = fb;
                 f.seg = fs;
             } else {
@@ -793,7 +793,7 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             int m = 0;
             while (m < (int)L.filters.size() &&
                    !(L.filters[m].chain == f.chain && L.filters[m].fast == f.fast && L.filters[m].d == f.d &&
-                     L.filters[m].whole == f.whole &&
+                     L.filters[m].form == f.form &&
                      L.filters[m].block == f.block && L.filters[m].seg == f.seg && L.filters[m].sp == f.sp &&
                      L.filters[m].wreg == f.wreg))
                 ++m;
@@ -826,13 +826,13 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             const Orbit *o = job->orbits[j];
             fV = std::max(fV, o->V);
             fd = std::max(fd, o->d);
-            lds = std::max(lds, fg.fast ? gc_lanczos_lds_bytes(o->d, o->lat.extent[0], fg.seg, o->V, lmax)
+            lds = std::max(lds, fg.fast ? gc_lanczos_lds_bytes(o->d, o->lat.extent[0], fg.seg, o->V, lmax, fg.block)
                                         : gc_post_lds_bytes(o->d, o->V, 0, lmax));
         }
         if (lds > ctx->lds_max) return GC_EUNSUPPORTED;
         fg.lds = lds;
         int per_cu = 0;
-        hipError_t e = fg.fast ? gc_lanczos_occupancy(fg.d, fg.block, fg.seg, fg.whole, lds, &per_cu)
+        hipError_t e = fg.fast ? gc_lanczos_occupancy(fg.d, fg.block, fg.seg, fg.form, lds, &per_cu)
                                : gc_post_occupancy(fg.block, fg.sp, fg.wreg, 0, lds, &per_cu);
         if (e != hipSuccess) return fail(ctx, e, "occupancy");
         per_cu = std::max(per_cu, 1);
@@ -1058,7 +1058,7 @@ hipError_t enqueue_chain(Job *job, unsigned char *base, int gi, hipStream_t qs, 
     for (const FilterGroup &fg : L.filters) {
         if (fg.chain != gi) continue;
         if (fg.fast)
-            e = gc_launch_lanczos(fg.d, fg.block, fg.seg, fg.whole, (const GcJobDev *)(base + fg.o_jobs),
+            e = gc_launch_lanczos(fg.d, fg.block, fg.seg, fg.form, (const GcJobDev *)(base + fg.o_jobs),
                                   (int)fg.jobs.size(),
                                   (unsigned long long *)(base + fg.o_next), fg.grid, fg.lds, qs);
         else
