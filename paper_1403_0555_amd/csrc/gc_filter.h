@@ -76,19 +76,15 @@ typedef __attribute__((address_space(3))) const double lds_cdouble;
 
 // Number of eigenvalues of the k x k tridiagonal below x: the sign changes
 // of the Sturm sequence p_0 = 1, p_j = det(T_j - x) = (alpha_j - x) p_{j-1}
-// - beta_{j-1}^2 p_{j-2}.  An exact zero is replaced by the smallest normal
-// number of the sign opposite to its predecessor (the usual convention for
-// a vanishing term; the next term then takes that sign too).  Division- and
-// branch-free: one dependent FMA and a select per step, sign changes counted
-// from the sign bits.  The diagonal and off-diagonal are fetched from LDS
-// four rows ahead of the recurrence, and the pair (p_{j-1}, p_j) is rescaled
-// by a power of two after every four rows, which keeps it in range and
-// leaves every sign unchanged.
-__device__ __forceinline__ double sturm_nonzero(double p, double prev)
-{
-    return (p == 0.0) ? -copysign(0x1.0p-1022, prev) : p;
-}
-
+// - beta_{j-1}^2 p_{j-2}, counted from the sign bits.  An exact zero p_j
+// counts as positive: the next term is then -beta_j^2 p_{j-1}, of the sign
+// opposite to p_{j-1}, so the two steps around the zero hold exactly one
+// sign change, as under the usual convention (a vanishing term takes the
+// sign opposite to its predecessor); every beta_j of the run is positive
+// (it stops before a vanishing one).  Division- and branch-free: one
+// dependent FMA per step.  The pair (p_{j-1}, p_j) is rescaled by a power of
+// two after every four rows, which keeps it in range and leaves every sign
+// unchanged.
 __device__ __forceinline__ int sign_change(double a, double b)
 {
     return (int)(((uint64_t)__double_as_longlong(a) ^ (uint64_t)__double_as_longlong(b)) >> 63);
@@ -96,7 +92,7 @@ __device__ __forceinline__ int sign_change(double a, double b)
 
 __device__ __forceinline__ void sturm_step(double a, double b2, double x, double &p0, double &p1, int &cnt)
 {
-    const double p2 = sturm_nonzero(fma(a - x, p1, -b2 * p0), p1);
+    const double p2 = fma(a - x, p1, -b2 * p0);
     cnt += sign_change(p2, p1);
     p0 = p1;
     p1 = p2;
@@ -104,7 +100,7 @@ __device__ __forceinline__ void sturm_step(double a, double b2, double x, double
 
 __device__ int sturm_count(lds_cdouble *alpha, lds_cdouble *beta2, int k, double x)
 {
-    double p0 = 1.0, p1 = sturm_nonzero(alpha[0] - x, 1.0);
+    double p0 = 1.0, p1 = alpha[0] - x;
     int cnt = sign_change(p1, 1.0);
     int j = 1;
     for (; j + 4 <= k; j += 4) {
@@ -162,8 +158,10 @@ __device__ double tridiag_min_eig(lds_cdouble *alpha, lds_cdouble *beta2, int k,
 
 // Smallest Ritz value of the k x k tridiagonal, inside the Gershgorin
 // interval [glo, ghi].  By interlacing it never increases as k grows, so the
-// previous check's upper bound prev bounds it above; a window below it is
-// tried first.
+// previous check's upper bound prev bounds it above, and a window [bot, top]
+// just below it is tried first: one round over B points that include both
+// ends (x_t = bot + (top - bot) t / (B - 1)) tells at once whether the
+// window holds the value (count(bot) = 0 and count(top) >= 1) and where.
 template <int B>
 __device__ double ritz_min(lds_cdouble *alpha, lds_cdouble *beta2, int k, double glo, double ghi, double prev,
                            double prev_step, int *ired, int &iph, double tol_rel, bool final, double &hi_out)
@@ -173,10 +171,19 @@ __device__ double ritz_min(lds_cdouble *alpha, lds_cdouble *beta2, int k, double
     if (prev < hi) {
         const double top = prev + 1e-12 * (1.0 + fabs(prev));
         const double bot = top - fmax(4.0 * prev_step, 1e-9 * (1.0 + fabs(prev)));
-        const bool top_ok = sturm_count(alpha, beta2, k, top) >= 1;
-        if (top_ok && bot > lo && sturm_count(alpha, beta2, k, bot) == 0)
-            return tridiag_min_eig<B>(alpha, beta2, k, bot, top, ired, iph, prev, tol_rel, final, hi_out);
-        if (top_ok) hi = top;
+        if (bot > lo) {
+            const double step = (top - bot) / (double)(B - 1);
+            const double x = ((int)threadIdx.x == B - 1) ? top : bot + step * (double)threadIdx.x;
+            const int first =
+                wg_min_int<B>(sturm_count(alpha, beta2, k, x) >= 1 ? (int)threadIdx.x : B, ired, iph);
+            if (first > 0 && first < B)
+                return tridiag_min_eig<B>(alpha, beta2, k, bot + step * (double)(first - 1),
+                                          (first == B - 1) ? top : bot + step * (double)first, ired, iph, prev,
+                                          tol_rel, final, hi_out);
+            if (first == 0) hi = bot;   // below the window: bot bounds it above
+        } else if (sturm_count(alpha, beta2, k, top) >= 1) {
+            hi = top;
+        }
     }
     return tridiag_min_eig<B>(alpha, beta2, k, lo, hi, ired, iph, prev, tol_rel, final, hi_out);
 }
