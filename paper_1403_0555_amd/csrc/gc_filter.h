@@ -194,6 +194,16 @@ __device__ double ritz_min(lds_cdouble *alpha, lds_cdouble *beta2, int k, double
 // operators, far below the region threshold (1e-6).
 constexpr double kRitzTol = 1e-10;
 
+// The checks' schedule: the first after kFirstCheck iterations, then every
+// 24 while the lowest Ritz value still moves by more than 1e6 times the
+// tolerance, every 16 while it moves by more than 1e3 times, else every 8
+// (the value settles by about a decade per 8 iterations near the end).
+constexpr int kFirstCheck = 24;
+__device__ __forceinline__ int check_gap(double change, double tol)
+{
+    return !(change <= 1e6 * tol) ? 24 : !(change <= 1e3 * tol) ? 16 : 8;
+}
+
 __device__ uint32_t region_flags(double lam2, double tol)
 {
     if (lam2 > tol) return GC_F_IN_REGION;

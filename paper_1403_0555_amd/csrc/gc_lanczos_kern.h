@@ -155,10 +155,11 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
             }
         }
         const double sigma = 4.0 * d + 1.0;
+        const double sigma_v = sigma / (double)V;   // the weight of the projector on the constant vector
         double theta = INFINITY, theta_old = INFINITY, theta_step = 1.0;
         double rows_lo = INFINITY, rows_hi = -INFINITY;   // Gershgorin bounds of the complete rows
         double a_prev = 0.0, b_prev2 = 0.0;                // alpha_{j-1}, beta_{j-2}
-        int next_check = 24;                               // iteration count of the next Ritz check
+        int next_check = kFirstCheck;                      // iteration count of the next Ritz check
         int it = 0;
         bool conv = false;
         // the neighbours across the ends of a segment that is not a whole
@@ -249,7 +250,10 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
                 }
             }
             wg_sum_n<B, 4>(s4, red, rph);
-            const double bt = sqrt(s4[0]);
+            // 1/|u| from the reciprocal square root, no division on the
+            // iteration's dependency chain (a vanishing |u| gives bt = 0)
+            const double inv = rsq(fmax(s4[0], 1e-300));
+            const double bt = s4[0] * inv;
             const double bp = it > 0 ? bt : 0.0;      // beta_{j-1} (the start vector's norm is not in T)
             if (it > 0) {
                 if (tid == 0) beta2[it - 1] = s4[0];
@@ -264,9 +268,8 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
                     break;
                 }
             }
-            const double inv = 1.0 / bt;
             const double sq = s4[2] * inv;
-            const double shift = sigma * sq / (double)V;
+            const double shift = sigma_v * sq;
             const double a_j = s4[1] * inv * inv + shift * sq - bp * (s4[3] * inv);
             if (tid == 0) alpha[it] = a_j;
             if (act) {
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(B) void lanczos_kernel(const GcJobDev *__restrict__
                     ++it;
                     break;
                 }
-                const int gap = !(change <= 1e6 * tol) ? 24 : !(change <= 1e3 * tol) ? 16 : 8;
+                const int gap = check_gap(change, tol);
                 next_check = it + 1 + gap;
                 if (theta_old < INFINITY) theta_step = change;
                 theta_old = theta_hi;

@@ -343,7 +343,7 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
             double theta = INFINITY, theta_old = INFINITY, theta_step = 1.0;
             double rows_lo = INFINITY, rows_hi = -INFINITY;   // Gershgorin bounds of the complete rows
             double a_prev = 0.0, b_prev2 = 0.0;                // alpha_{j-1}, beta_{j-2}
-            int next_check = 24;                               // iteration count of the next Ritz check
+            int next_check = kFirstCheck;                      // iteration count of the next Ritz check
             int it = 0;
             bool conv = false;
             for (it = 0; it < lmax; ++it) {
@@ -442,7 +442,7 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                     }
                     // far from converged: look again later (the change is then
                     // measured over the longer gap, a test at least as strict)
-                    const int gap = !(change <= 1e6 * tol) ? 24 : !(change <= 1e3 * tol) ? 16 : 8;
+                    const int gap = check_gap(change, tol);
                     next_check = it + 1 + gap;
                     if (theta_old < INFINITY) theta_step = change;
                     theta_old = theta_hi;
