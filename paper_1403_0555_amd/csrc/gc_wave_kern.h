@@ -438,11 +438,14 @@ __device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t link
         const int z = opaque_zero();
         C gnew[NS];
         double acc0 = 0.0;
+        u32x4 wnext = nbt[min(lane, half - 1) + z];
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             GC_RR_SLOT(k);
             const int h = hc + z;
-            const C s = staple_big<D, DL, R, LT, 0>(nbt[h], xb, lb, (uint32_t)h * (uint32_t)sizeof(LT), links,
+            const u32x4 wcur = wnext;
+            if (k + 1 < NS) wnext = nbt[min(lane + 64 * (k + 1), half - 1) + z];
+            const C s = staple_big<D, DL, R, LT, 0>(wcur, xb, lb, (uint32_t)h * (uint32_t)sizeof(LT), links,
                                                 (uint32_t)h * (uint32_t)sizeof(C), plane, lplane);
             const C g0 = g0r[k];
             const double dv = (double)(g0.x * s.y - g0.y * s.x);
@@ -477,11 +480,14 @@ __device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t link
         if (until == 0) until = check;
         const bool chk = ckpt;
         double a1 = 0.0;
+        u32x4 wnext1 = nbt[half + min(lane, half - 1) + z];
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             GC_RR_SLOT(k);
             const int h = hc + z;
-            const C s = staple_big<D, DL, R, LT, 1>(nbt[half + h], xb, lb, (uint32_t)h * (uint32_t)sizeof(LT), links,
+            const u32x4 wcur = wnext1;
+            if (k + 1 < NS) wnext1 = nbt[half + min(lane + 64 * (k + 1), half - 1) + z];
+            const C s = staple_big<D, DL, R, LT, 1>(wcur, xb, lb, (uint32_t)h * (uint32_t)sizeof(LT), links,
                                                 (uint32_t)h * (uint32_t)sizeof(C), plane, lplane);
             const C g = local_update<RELAX, R>(g1r[k], s, omega);
             g1r[k] = g;
