@@ -65,11 +65,11 @@ KERNEL_SOURCES = {
 }
 TRAFFIC = {
     # wave_rr_kernel<4, 11, 0>, 10^6 starts of the 6^4 FP64 workload (one dispatch):
-    # FETCH_SIZE 1037830.6 KiB x 2.0000 (a 2 GiB copy reads 1048587.6 KiB) and
-    # WRITE_SIZE 20541516.3 KiB x 1.0 (the copy writes 2097152.0 KiB)
-    "sources_sha256": "7e84ffe80c7e2892acd6a2a0734e2423136c239a9cc8b44c99e1a9437cea863e",
+    # FETCH_SIZE 1018660.8 KiB x 2.0000 (a 2 GiB copy reads 1048587.5 KiB) and
+    # WRITE_SIZE 20541473.0 KiB x 1.0 (the copy writes 2097152.0 KiB)
+    "sources_sha256": "7538527a02144b9e6a0686ef5c7c91928aadd73c59da44b11659fba646e927aa",
     "kernel": "relax",
-    "bytes_per_launch": 2125477069 + 21034512691,
+    "bytes_per_launch": 2086217318 + 21034468352,
 }
 
 
