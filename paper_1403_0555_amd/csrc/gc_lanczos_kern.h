@@ -43,7 +43,7 @@ __device__ double ritz_wave0(lds_cdouble *alpha, lds_cdouble *beta2, int k, doub
 // so do the direction-0 link weights; direction-0 neighbours inside the
 // segment are the thread's own entries.  LDS holds u for the other
 // threads, the forward link weights of directions 1..d-1 (and of direction
-// 0 when a line has several segments), S B doubles each, and the
+// 0 when a line has several segments), S P doubles each, and the
 // tridiagonal.  LDS arrays are segment-major with a compile-time stride P
 // (B, or 7B/8 when the launch's T = V/S threads fit in it): the k-th site
 // of thread t's segment sits at k P + t, so the threads of a wavefront

@@ -313,6 +313,7 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
             // r_j = A q_j - beta_{j-1} q_{j-1} - alpha_j q_j follow site by site.
             // q_{j-1} and M u of the own sites stay in registers.
             const double sigma = 4.0 * d + 1.0;
+            const double sigma_v = sigma / (double)V;   // the weight of the projector on the constant vector
             lds_ptr<double> vu = as_lds(reinterpret_cast<double *>(smem));
             OwnVec<WREG, SP> qp, mu;
             if constexpr (!WREG) {
@@ -389,7 +390,10 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                     __builtin_amdgcn_sched_barrier(0);
                 }
                 wg_sum_n<B, 4>(s4, red, rph);
-                const double bt = sqrt(s4[0]);
+                // 1/|u| through the reciprocal square root (a vanishing |u|
+                // gives bt = 0), as in the line-segment kernel
+                const double inv = rsq(fmax(s4[0], 1e-300));
+                const double bt = s4[0] * inv;
                 const double bp = it > 0 ? bt : 0.0;      // beta_{j-1} (the start vector's norm is not in T)
                 if (it > 0) {
                     if (tid == 0) beta2[it - 1] = s4[0];
@@ -407,9 +411,8 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                         break;
                     }
                 }
-                const double inv = 1.0 / bt;
                 const double sq = s4[2] * inv;
-                const double shift = sigma * sq / (double)V;
+                const double shift = sigma_v * sq;
                 const double a_j = s4[1] * inv * inv + shift * sq - bp * (s4[3] * inv);
                 if (tid == 0) alpha[it] = a_j;
                 // the residual over u: every thread finished reading u in the
