@@ -182,15 +182,20 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
         const GcStartRec rec0 = J.rec[local];
         if (KEYS && rec0.status != GC_ST_CONVERGED) continue;   // uniform across the workgroup
 
+        // the filter stages the state in LDS, followed by the tridiagonal;
+        // the key pass reads it from global memory (once per link end, the
+        // start's few kilobytes staying in cache) and keeps only the link
+        // angles in LDS, so that more workgroups share a CU
         lds_ptr<dbl2> g = as_lds(reinterpret_cast<dbl2 *>(smem));
-        // the link angles (key phase) and the tridiagonal (Lanczos) share LDS
-        lds_ptr<float> a32 = as_lds(reinterpret_cast<float *>(smem + 16 * (size_t)V));
+        lds_ptr<float> a32 = as_lds(reinterpret_cast<float *>(smem));
         lds_ptr<double> alpha = as_lds(reinterpret_cast<double *>(smem + 16 * (size_t)V));
         const int lmax = min(min(J.lanczos_max, GC_LMAX), V);
         lds_ptr<double> beta2 = alpha + lmax;
         glb_ptr<const dbl2> src = as_global(reinterpret_cast<const dbl2 *>(J.states + local * (uint64_t)V));
-        for (int i = tid; i < V; i += B) g[i] = src[i];
-        __syncthreads();
+        if constexpr (!KEYS) {
+            for (int i = tid; i < V; i += B) g[i] = src[i];
+            __syncthreads();
+        }
 
         // ---- own sites: forward links (F, angles) for the key, or the FP
         // weights w = Re u of every link touching the site for the filter
@@ -210,7 +215,7 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                 }
                 if (i < V && mu < d) {
                     const int f = O.nbr[mu * V + i], b = O.nbr[(d + mu) * V + i];
-                    const dbl2 gi = g[i], gf = g[f];
+                    const dbl2 gi = KEYS ? src[i] : g[i], gf = KEYS ? src[f] : g[f];
                     const dbl2 u = U[mu * V + i];
                     const double tr = u.x * gf.x - u.y * gf.y, ti = u.x * gf.y + u.y * gf.x;
                     const double ur = gi.x * tr + gi.y * ti, ui = gi.x * ti - gi.y * tr;
@@ -680,8 +685,8 @@ int grid_for(uint64_t work)
 
 size_t gc_post_lds_bytes(int d, int V, int keys, int lmax)
 {
-    // the state, then the link angles (key pass) or the tridiagonal (filter)
-    if (keys) return 16 * (size_t)V + 4 * (size_t)d * V;
+    // the link angles (key pass), or the state and the tridiagonal (filter)
+    if (keys) return 4 * (size_t)d * V;
     const size_t l = (size_t)std::min(std::min(lmax, GC_LMAX), V);
     return 16 * (size_t)V + 16 * l;
 }
