@@ -266,17 +266,20 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                     fold(k, rint((A - O.phi_plaq[k]) / kTwoPi));
                 }
             }
-            // line windings: lines of direction mu in order
+            // line windings: lines of direction mu in order; a line starts
+            // at its site with x_mu = 0 and steps by the site stride of mu
+            int st = 1;
             for (int mu = 0; mu < d; ++mu) {
                 for (int q = O.line_off[mu] + tid; q < O.line_off[mu + 1]; q += B) {
                     int i = O.line_site[q];
                     double acc = 0.0;
                     for (int t = 0; t < O.ext[mu]; ++t) {
                         acc += (double)a32[mu * V + i];
-                        i = O.nbr[mu * V + i];
+                        i += st;
                     }
                     fold(O.n_plaq + q, rint((acc - O.phi_line[q]) / kTwoPi));
                 }
+                st *= O.ext[mu];
             }
             h0 = wg_sum_u64<B>(h0, ured, uph);
             h1 = wg_sum_u64<B>(h1, ured, uph);
