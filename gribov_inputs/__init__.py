@@ -70,6 +70,26 @@ def orbit_angles(extent, seed: int = 0, orbit_index: int = 0) -> np.ndarray:
     return uniform_angle(raw).reshape(dim, V)
 
 
+SU2_TAG = 0x55
+
+
+def su2_links(extent, seed: int = 0, orbit_index: int = 0) -> np.ndarray:
+    """Hot SU(2) configuration (beta = 0): every link Haar-random, as a unit
+    quaternion (a0, a1, a2, a3) for U = a0 + i (a1 s1 + a2 s2 + a3 s3);
+    float64, shape (dim, V, 4).  Link l = mu*V + i takes four normal
+    deviates (Box-Muller on the uniforms of counter (0, orbit_index, 0x55, 0)
+    onwards under key (seed, 2), eight uniforms per link) scaled to unit
+    length, which is the uniform distribution on the 3-sphere."""
+    extent = [int(n) for n in extent]
+    dim, V = len(extent), volume(extent)
+    n = dim * V
+    u = uniform01(seed, (0, orbit_index, SU2_TAG, 0), 8 * n).reshape(n, 4, 2)
+    r = np.sqrt(-2.0 * np.log1p(-u[..., 0]))
+    z = np.where(np.arange(4) % 2 == 0, r * np.cos(TWO_PI * u[..., 1]), r * np.sin(TWO_PI * u[..., 1]))
+    z /= np.sqrt((z * z).sum(axis=1, keepdims=True))
+    return z.reshape(dim, V, 4)
+
+
 def cold_orbit(extent) -> np.ndarray:
     """Trivial orbit: every link angle zero (Sec. I)."""
     return np.zeros((len(extent), volume(extent)), dtype=np.float64)

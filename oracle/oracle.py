@@ -413,3 +413,114 @@ def histogram(copies, dim: int, V: int, quantity: int, weight: int, require_flag
             b = 1 + min(n_bins - 1, int(math.floor(((v - lo) / (hi - lo)) * n_bins)))
         out[b] += int(e["hits"]) if weight == HIST_STARTS else 1
     return out
+
+
+# --------------------------------------------------------------------------
+# SU(2) configurations through the maximal Abelian reduction.  Sec. I states
+# the Landau functional for SU(N_c) (eq. (1)) and argues that the Neuberger
+# problem of SU(N_c) lies in the maximal Abelian subgroup U(1)^{N_c-1}, the
+# coset part being free of it; the U(1) copies are the ones enumerated.  An
+# SU(2) configuration is therefore gauge-fixed on the coset SU(2)/U(1) to the
+# maximal Abelian gauge (the reading: maximise R = sum_{x,mu} 1/2 Tr(s3 U' s3
+# U'^dagger), U' = g_x U_{x,mu} g_{x+mu}^dagger, by local maximisation colour
+# by colour), and the diagonal phases of U' form the compact U(1) orbit.
+# Quaternions q = (q0, q1, q2, q3) stand for q0 + i (q1 s1 + q2 s2 + q3 s3).
+# --------------------------------------------------------------------------
+
+def q_mul(p, q):
+    """Product of quaternions (..., 4): (i s_a)(i s_b) = -delta_ab - i eps_abc s_c."""
+    p0, p1, p2, p3 = p[..., 0], p[..., 1], p[..., 2], p[..., 3]
+    r0, r1, r2, r3 = q[..., 0], q[..., 1], q[..., 2], q[..., 3]
+    return np.stack([p0 * r0 - p1 * r1 - p2 * r2 - p3 * r3,
+                     p0 * r1 + r0 * p1 - (p2 * r3 - p3 * r2),
+                     p0 * r2 + r0 * p2 - (p3 * r1 - p1 * r3),
+                     p0 * r3 + r0 * p3 - (p1 * r2 - p2 * r1)], axis=-1)
+
+
+def q_conj(q):
+    """Inverse of a unit quaternion (the Hermitian conjugate)."""
+    return q * np.array([1.0, -1.0, -1.0, -1.0])
+
+
+def q_rot3(q):
+    """b with Q s3 Q^dagger = b . s for Q = q: b3 = |alpha|^2 - |beta|^2 and
+    b1 - i b2 = -2 alpha beta for Q = [[alpha, beta], [-conj(beta), conj(alpha)]],
+    alpha = q0 + i q3, beta = q2 + i q1."""
+    q0, q1, q2, q3 = q[..., 0], q[..., 1], q[..., 2], q[..., 3]
+    return np.stack([-2.0 * (q0 * q2 - q1 * q3), 2.0 * (q0 * q1 + q2 * q3),
+                     q0 * q0 + q3 * q3 - q1 * q1 - q2 * q2], axis=-1)
+
+
+def q_from_axis3(n):
+    """The gauge transformation g with g^dagger s3 g = n . s whose diagonal
+    element is real and non-negative (h = g^dagger: alpha = sqrt((1 + n3)/2),
+    beta = -(n1 - i n2)/(2 alpha); alpha = 0, beta = 1 at n3 = -1)."""
+    a = np.sqrt(0.5 * (1.0 + n[..., 2]))
+    safe = a > 0.0
+    den = np.where(safe, 2.0 * a, 1.0)
+    br = np.where(safe, -n[..., 0] / den, 1.0)
+    bi = np.where(safe, n[..., 1] / den, 0.0)
+    h = np.stack([a, bi, br, np.zeros_like(a)], axis=-1)   # alpha = h0 + i h3, beta = h2 + i h1
+    return q_conj(h)
+
+
+def mag_transformed(extent, links, g):
+    """U'_{x,mu} = g_x U_{x,mu} g_{x+mu}^dagger, shape (dim, V, 4)."""
+    fwd, _ = neighbours(extent)
+    d = len(extent)
+    return np.stack([q_mul(q_mul(g, links[mu]), q_conj(g[fwd[mu]])) for mu in range(d)])
+
+
+def mag_project(extent, links, eps: float = 1e-20, max_sweeps: int = 100000, want_g: bool = False):
+    """Maximal Abelian gauge by local maximisation and the Abelian projection.
+
+    Sweeps update the sites of colour 0, then of colour 1 (even extents): at
+    site x, R depends on g_x only through n . M, n . s = g_x^dagger s3 g_x and
+    M = sum_mu [w_mu + y_mu] (mu ascending, forward then backward), with
+    W = U_{x,mu} g_{x+mu}^dagger, w . s = W s3 W^dagger, and
+    Y = g_{x-mu} U_{x-mu,mu}, y . s = Y^dagger s3 Y; so n = M/|M| (M = 0
+    leaves g_x unchanged) and g_x = q_from_axis3(n).  D = (1/V) sum_x
+    |n_x - n_x^old|^2 over a sweep; the reduction stops after the first sweep
+    with D < eps.  Returns (phi [dim][V] = arg of the diagonal element q0 +
+    i q3 of U', sweeps, R/(dim V), converged[, g])."""
+    ext = [int(n) for n in extent]
+    d, V = len(ext), volume(ext)
+    if any(n % 2 for n in ext):
+        raise ValueError("the maximal Abelian reduction needs even extents")
+    links = np.asarray(links, dtype=np.float64).reshape(d, V, 4)
+    fwd, bwd = neighbours(ext)
+    coords = np.array(np.unravel_index(np.arange(V), ext[::-1]))[::-1]
+    colour = coords.sum(axis=0) % 2
+    sites = [np.nonzero(colour == c)[0] for c in (0, 1)]
+    g = np.zeros((V, 4))
+    g[:, 0] = 1.0
+    sweeps, converged = 0, False
+    while sweeps < max_sweeps:
+        acc = 0.0
+        for c in (0, 1):
+            x = sites[c]
+            M = np.zeros((x.size, 3))
+            for mu in range(d):
+                W = q_mul(links[mu, x], q_conj(g[fwd[mu, x]]))
+                M = M + q_rot3(W)
+                b = bwd[mu, x]
+                Y = q_mul(g[b], links[mu, b])
+                M = M + q_rot3(q_conj(Y))
+            m2 = (M * M).sum(axis=1)
+            ok = m2 > 0.0
+            n = M / np.sqrt(np.where(ok, m2, 1.0))[:, None]
+            old = q_rot3(q_conj(g[x]))
+            new_g = np.where(ok[:, None], q_from_axis3(n), g[x])
+            new_n = np.where(ok[:, None], n, old)
+            acc += float(((new_n - old) ** 2).sum())
+            g[x] = new_g
+        sweeps += 1
+        if acc / V < eps:
+            converged = True
+            break
+    Up = mag_transformed(ext, links, g)
+    R = float(q_rot3(Up)[..., 2].sum()) / (d * V)
+    phi = np.arctan2(Up[..., 3], Up[..., 0])
+    if want_g:
+        return phi, sweeps, R, converged, g
+    return phi, sweeps, R, converged
