@@ -206,6 +206,40 @@ gc_status gc_orbit_load(gc_ctx *ctx, const gc_lattice *lat, const double *phi,
 gc_status gc_orbit_random(gc_ctx *ctx, const gc_lattice *lat, uint64_t seed,
                           uint64_t orbit_index, gc_orbit *out);
 
+/* SU(2) configurations through the maximal Abelian reduction (Sec. I: eq. (1)
+ * states the Landau functional for SU(N_c); the Neuberger problem of SU(N_c)
+ * lies in its maximal Abelian subgroup U(1)^{N_c-1}, so its copies are those
+ * of a compact U(1) field).  The configuration is gauge-fixed on the coset
+ * SU(2)/U(1) to the maximal Abelian gauge, R = sum 1/2 Tr(s3 U' s3 U'^dagger)
+ * with U'_{x,mu} = g_x U_{x,mu} g_{x+mu}^dagger maximised site by site
+ * (sweeps over colour 0, then colour 1, from g = 1; at each site g_x is the
+ * transformation with g_x^dagger s3 g_x along the sum of the rotated s3 of
+ * its 2d links, its diagonal element real and non-negative), until the mean
+ * over sites of |n_x - n_x^old|^2 in a sweep falls below eps; the phases
+ * phi = arg (U')_{11} then load as an ordinary orbit (gc_orbit_load).
+ * links: host [dim][V][4] float64 unit quaternions (a0, a1, a2, a3) for
+ * U = a0 + i (a1 s1 + a2 s2 + a3 s3); non-finite or |a|^2 off 1 by more than
+ * 1e-10 -> GC_EINVAL.  Even extents, periodic transformations
+ * (lat->antiperiodic = 0) and V <= 4096 only, else GC_EUNSUPPORTED.  params
+ * NULL: eps 1e-20, max_sweeps 100000.  info (may be NULL): sweeps, R/(dim V)
+ * and whether the threshold was reached.  Runs on the device, one workgroup,
+ * and returns when the orbit is loaded. */
+typedef struct gc_mag_params {
+    double eps;           /* threshold on the sweep's mean |n - n_old|^2 (>= 0) */
+    uint64_t max_sweeps;  /* >= 1 */
+} gc_mag_params;
+
+typedef struct gc_mag_info {
+    uint64_t sweeps;
+    double R;             /* R/(dim V), in [-1, 1]; 1 for an Abelian field */
+    int32_t converged;
+    int32_t reserved;
+} gc_mag_info;
+
+gc_status gc_orbit_load_su2(gc_ctx *ctx, const gc_lattice *lat, const double *links,
+                            uint64_t orbit_index, const gc_mag_params *params,
+                            gc_mag_info *info, gc_orbit *out);
+
 /* Copy the orbit's angles back (host [dim][V]). */
 gc_status gc_orbit_angles(gc_ctx *ctx, gc_orbit orbit, double *phi_out);
 

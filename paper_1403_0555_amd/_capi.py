@@ -30,7 +30,7 @@ EXPORTED_SYMBOLS = [
     "gc_launch", "gc_launch_batch", "gc_poll", "gc_wait", "gc_fetch", "gc_fetch_starts",
     "gc_fetch_state", "gc_fetch_start_state", "gc_release", "gc_last_error", "gc_kernel_time_ms", "gc_launch_bytes",
     "gc_memory_info", "gc_autotune", "gc_saturation", "gc_paper_saturation", "gc_launch_static",
-    "gc_launch_from", "gc_histogram",
+    "gc_launch_from", "gc_histogram", "gc_orbit_load_su2",
 ]
 
 
@@ -38,6 +38,15 @@ class gc_tune_result(ctypes.Structure):
     _fields_ = [("relax_variant", ctypes.c_int32), ("post_block", ctypes.c_int32),
                 ("post_sites_per_thread", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("relax_ms", ctypes.c_double), ("post_ms", ctypes.c_double)]
+
+
+class gc_mag_params(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("max_sweeps", ctypes.c_uint64)]
+
+
+class gc_mag_info(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_uint64), ("R", ctypes.c_double), ("converged", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class gc_ctx_params(ctypes.Structure):
@@ -111,6 +120,8 @@ def lib():
         "gc_destroy": ([vp], i32),
         "gc_orbit_load": ([vp, P(gc_lattice), P(ctypes.c_double), u64, P(u64)], i32),
         "gc_orbit_random": ([vp, P(gc_lattice), u64, u64, P(u64)], i32),
+        "gc_orbit_load_su2": ([vp, P(gc_lattice), P(ctypes.c_double), u64, P(gc_mag_params), P(gc_mag_info),
+                               P(u64)], i32),
         "gc_orbit_angles": ([vp, u64, P(ctypes.c_double)], i32),
         "gc_launch": ([vp, u64, u64, P(gc_solve_params)], i32),
         "gc_launch_batch": ([vp, i32, P(u64), P(u64), P(gc_solve_params)], i32),
@@ -249,6 +260,24 @@ class Context:
         self._check(st, "gc_orbit_load")
         self.extent[out.value] = tuple(int(n) for n in extent)
         return out.value
+
+    def gc_orbit_load_su2(self, extent, links, orbit_index: int = 0, eps: float = 1e-20,
+                          max_sweeps: int = 100000):
+        """SU(2) links [dim][V][4] (unit quaternions) through the maximal
+        Abelian reduction; returns (orbit handle, {sweeps, R, converged})."""
+        lat = _lattice(extent, 0)
+        links = np.ascontiguousarray(links, dtype=np.float64)
+        d, V = len(extent), int(np.prod(extent))
+        if links.size != 4 * d * V:
+            raise ValueError("links must hold dim x V quaternions")
+        prm = gc_mag_params(eps, max_sweeps)
+        info = gc_mag_info()
+        out = ctypes.c_uint64()
+        st = self._L.gc_orbit_load_su2(self._h, ctypes.byref(lat), links.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       orbit_index, ctypes.byref(prm), ctypes.byref(info), ctypes.byref(out))
+        self._check(st, "gc_orbit_load_su2")
+        self.extent[out.value] = tuple(int(n) for n in extent)
+        return out.value, {"sweeps": int(info.sweeps), "R": float(info.R), "converged": bool(info.converged)}
 
     def gc_orbit_random(self, extent, seed: int = 0, orbit_index: int = 0, antiperiodic: int = 0) -> int:
         lat = _lattice(extent, antiperiodic)

@@ -145,6 +145,19 @@ hipError_t gc_launch_lanczos(int d, int block, int seg, int form, const GcJobDev
 hipError_t gc_launch_reset(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);
 hipError_t gc_launch_finalize(const GcJobDev *jobs_host, int n_jobs, hipStream_t s);   // representatives + compaction
 hipError_t gc_launch_orbit_random(double *phi, int64_t n_links, uint64_t seed, uint64_t orbit_index, hipStream_t s);
+
+// Maximal Abelian reduction of an SU(2) configuration (gc_su2.hip): one
+// workgroup; links [d][V] quaternions, nbr [2d][V], csite [V] (colour-0
+// sites, then colour-1), phi [d][V] out.  LDS: gc_mag_lds_bytes(V).
+struct GcMagOut {
+    uint64_t sweeps;
+    double R;
+    int32_t converged;
+    int32_t pad;
+};
+size_t gc_mag_lds_bytes(int V);
+hipError_t gc_launch_mag(const double *links, const int *nbr, const int *csite, int d, int V, double eps,
+                         uint64_t max_sweeps, double *phi, GcMagOut *out, hipStream_t s);
 hipError_t gc_launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
 // Write bytes (host source, copied into kernel arguments) to device memory.
 hipError_t gc_launch_store(void *dst, const void *src, size_t bytes, hipStream_t s);

@@ -1795,6 +1795,77 @@ gc_status gc_orbit_random(gc_ctx *ctx, const gc_lattice *lat, uint64_t seed, uin
     return new_orbit(ctx, lat, std::move(v), orbit_index, out);
 }
 
+gc_status gc_orbit_load_su2(gc_ctx *ctx, const gc_lattice *lat, const double *links, uint64_t orbit_index,
+                            const gc_mag_params *mp, gc_mag_info *info, gc_orbit *out)
+{
+    if (!lat || !links || !out) return GC_EINVAL;
+    int K = 0, V = 0;
+    gc_status st = check_lattice(lat, &K, &V);
+    if (st != GC_OK) return st;
+    const int d = lat->dim;
+    // the checkerboard of even extents, periodic gauge transformations, and
+    // the transformations of a configuration held in LDS (32 V bytes)
+    for (int mu = 0; mu < d; ++mu)
+        if (lat->extent[mu] % 2) return GC_EUNSUPPORTED;
+    if (lat->antiperiodic || V > 4096) return GC_EUNSUPPORTED;
+    const double eps = mp ? mp->eps : 1e-20;
+    const uint64_t cap = mp ? mp->max_sweeps : 100000;
+    if (!(eps >= 0.0) || !std::isfinite(eps) || cap < 1) return GC_EINVAL;
+    const size_t nl = (size_t)d * V;
+    for (size_t l = 0; l < nl; ++l) {
+        const double *q = links + 4 * l;
+        if (!std::isfinite(q[0]) || !std::isfinite(q[1]) || !std::isfinite(q[2]) || !std::isfinite(q[3]))
+            return GC_EINVAL;
+        if (std::fabs(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3] - 1.0) > 1e-10) return GC_EINVAL;
+    }
+    // periodic neighbours (x_0 fastest) and the sites of each colour
+    std::vector<int> nbr((size_t)2 * d * V), csite;
+    csite.reserve(V);
+    int stride[4] = {1, 1, 1, 1};
+    for (int mu = 1; mu < d; ++mu) stride[mu] = stride[mu - 1] * lat->extent[mu - 1];
+    for (int c = 0; c < 2; ++c)
+        for (int i = 0; i < V; ++i) {
+            int par = 0;
+            for (int mu = 0; mu < d; ++mu) par += (i / stride[mu]) % lat->extent[mu];
+            if (par % 2 == c) csite.push_back(i);
+        }
+    for (int mu = 0; mu < d; ++mu)
+        for (int i = 0; i < V; ++i) {
+            const int n = lat->extent[mu], x = (i / stride[mu]) % n;
+            nbr[(size_t)mu * V + i] = i + (((x + 1) % n) - x) * stride[mu];
+            nbr[(size_t)(d + mu) * V + i] = i + (((x + n - 1) % n) - x) * stride[mu];
+        }
+    GC_ENTER(ctx);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_links = 0, o_nbr = al(o_links + 32 * nl), o_cs = al(o_nbr + 4 * nbr.size()),
+                 o_phi = al(o_cs + 4 * csite.size()), o_out = al(o_phi + 8 * nl), total = al(o_out + sizeof(GcMagOut));
+    void *blk = nullptr;
+    size_t got = 0;
+    st = pool_get(ctx, total, &blk, &got);
+    if (st != GC_OK) return st;
+    unsigned char *b = (unsigned char *)blk;
+    hipStream_t s = ctx->util;
+    std::vector<double> phi(nl);
+    GcMagOut mo{};
+    hipError_t e = hipMemcpyAsync(b + o_links, links, 32 * nl, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b + o_nbr, nbr.data(), 4 * nbr.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b + o_cs, csite.data(), 4 * csite.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = gc_launch_mag((const double *)(b + o_links), (const int *)(b + o_nbr), (const int *)(b + o_cs), d, V, eps,
+                          cap, (double *)(b + o_phi), (GcMagOut *)(b + o_out), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(phi.data(), b + o_phi, 8 * nl, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&mo, b + o_out, sizeof mo, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    ctx->pool.put(blk, got);
+    if (e != hipSuccess) return fail(ctx, e, "maximal Abelian reduction");
+    if (info) {
+        info->sweeps = mo.sweeps;
+        info->R = mo.R;
+        info->converged = mo.converged;
+    }
+    return new_orbit(ctx, lat, std::move(phi), orbit_index, out);
+}
+
 gc_status gc_orbit_angles(gc_ctx *ctx, gc_orbit orbit, double *phi_out)
 {
     if (!phi_out) return GC_EINVAL;

@@ -1,0 +1,142 @@
+"""GPU: SU(2) configurations through the maximal Abelian reduction
+(gc_orbit_load_su2; Sec. I: the Neuberger problem of SU(N_c) lies in its
+maximal Abelian subgroup, so the copies enumerated are those of a compact
+U(1) field).
+
+* The device reduction against the oracle's on Haar-random configurations:
+  same sweep count, R, and projected angles.
+* An Abelian configuration loads as its own angles after one sweep; the same
+  field after a smooth SU(2) gauge transformation comes back with R = 1 and
+  its plaquette angles.
+* Copies enumerated on a reduced SU(2) orbit equal the oracle's relaxation of
+  the same orbit start by start.
+* Arguments outside the supported set are refused before any device work.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import gribov_inputs as GI
+import paper_1403_0555_amd as gc
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print("[gpu-su2] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = gc.Context(0)
+    yield c
+    c.close()
+
+
+def wrapped(a):
+    return np.angle(np.exp(1j * a))
+
+
+@pytest.mark.parametrize("extent,seed", [((4, 4), 0), ((6, 6), 1), ((4, 4, 4), 2), ((4, 4, 4, 4), 3),
+                                         ((6, 6, 6, 6), 4)])
+def test_reduction_matches_oracle(ctx, extent, seed):
+    note(f"reduction {extent} seed {seed}")
+    U = GI.su2_links(extent, seed, 0)
+    h, info = ctx.gc_orbit_load_su2(extent, U)
+    phi = ctx.gc_orbit_angles(h)
+    o_phi, o_sweeps, o_R, o_conv = O.mag_project(extent, U)
+    note(f"  sweeps {info['sweeps']} (oracle {o_sweeps}), R {info['R']:.15f} (oracle {o_R:.15f})")
+    assert info["converged"] and o_conv
+    assert abs(info["sweeps"] - o_sweeps) <= 1
+    assert abs(info["R"] - o_R) < 1e-12
+    assert np.max(np.abs(wrapped(phi - o_phi))) < 1e-9
+    ctx.gc_release(h)
+
+
+def abelian_links(phi):
+    return np.stack([np.cos(phi), np.zeros_like(phi), np.zeros_like(phi), np.sin(phi)], axis=-1)
+
+
+@pytest.mark.parametrize("extent", [(8, 8), (4, 4, 4), (6, 6, 6, 6)])
+def test_abelian_configuration_loads_as_its_angles(ctx, extent):
+    phi = GI.orbit_angles(extent, 11, 0)
+    h, info = ctx.gc_orbit_load_su2(extent, abelian_links(phi))
+    assert info["converged"] and info["sweeps"] == 1
+    assert abs(info["R"] - 1.0) < 1e-15
+    assert np.max(np.abs(wrapped(ctx.gc_orbit_angles(h) - phi))) < 1e-15
+    ctx.gc_release(h)
+
+
+def plaquette_angles(extent, phi):
+    fwd, _ = O.neighbours(extent)
+    d = len(extent)
+    return np.array([phi[mu] + phi[nu][fwd[mu]] - phi[mu][fwd[nu]] - phi[nu]
+                     for mu in range(d) for nu in range(mu + 1, d)])
+
+
+@pytest.mark.parametrize("extent", [(4, 4, 4), (4, 4, 4, 4)])
+def test_gauge_transformed_abelian_field_is_recovered(ctx, extent):
+    d, V = len(extent), int(np.prod(extent))
+    phi = GI.orbit_angles(extent, 7, 2)
+    U = abelian_links(phi)
+    a = 0.2 * (GI.uniform01(3, (0, 0, 0x47, 0), 3 * V).reshape(V, 3) - 0.5) * 2.0
+    t = np.linalg.norm(a, axis=1)
+    Om = np.column_stack([np.cos(t), np.sin(t)[:, None] * a / t[:, None]])
+    fwd, _ = O.neighbours(extent)
+    Ut = np.stack([O.q_mul(O.q_mul(Om, U[mu]), O.q_conj(Om[fwd[mu]])) for mu in range(d)])
+    h, info = ctx.gc_orbit_load_su2(extent, Ut, eps=1e-26)
+    assert info["converged"] and info["R"] > 1.0 - 1e-12
+    dp = plaquette_angles(extent, ctx.gc_orbit_angles(h)) - plaquette_angles(extent, phi)
+    assert np.max(np.abs(wrapped(dp))) < 1e-9
+    ctx.gc_release(h)
+
+
+@pytest.mark.parametrize("extent,n", [((4, 4, 4), 400), ((4, 4, 4, 4), 200)])
+def test_copies_of_a_reduced_orbit_match_oracle(ctx, extent, n):
+    """The reduced orbit is an ordinary U(1) orbit: the device relaxes it
+    exactly as the oracle relaxes the same angles."""
+    V = int(np.prod(extent))
+    U = GI.su2_links(extent, 5, 1)
+    h, info = ctx.gc_orbit_load_su2(extent, U, orbit_index=1)
+    phi = ctx.gc_orbit_angles(h)
+    p = gc.SolveParams(omega=1.7)
+    note(f"copies of a reduced {extent} orbit, {n} starts")
+    ctx.gc_launch(h, n, p)
+    assert ctx.gc_wait(h, 300_000) == gc.GC_OK
+    starts = ctx.gc_fetch_starts(h, n)
+    rec, _, _ = O.solve(extent, phi, np.arange(n), O.SolveParams(omega=1.7, orbit_index=1))
+    assert np.array_equal(starts["status"], rec["status"])
+    conv = rec["status"] == O.CONVERGED
+    assert np.array_equal(starts["key_hi"][conv], rec["key_hi"][conv])
+    assert np.array_equal(starts["key_lo"][conv], rec["key_lo"][conv])
+    assert np.max(np.abs(starts["F"][conv] - rec["F"][conv])) / V < 1e-10
+    copies = ctx.gc_fetch(h)
+    assert int(copies["hits"].sum()) == int(conv.sum())
+    ctx.gc_release(h)
+
+
+def test_unsupported_arguments_are_refused(ctx):
+    U = GI.su2_links((4, 4), 0, 0)
+    bad = U.copy()
+    bad[1, 3, 0] *= 1.001
+    with pytest.raises(gc.GcError) as e:
+        ctx.gc_orbit_load_su2((4, 4), bad)
+    assert e.value.status == gc.GC_EINVAL
+    bad = U.copy()
+    bad[0, 0, 2] = np.nan
+    with pytest.raises(gc.GcError) as e:
+        ctx.gc_orbit_load_su2((4, 4), bad)
+    assert e.value.status == gc.GC_EINVAL
+    with pytest.raises(gc.GcError) as e:
+        ctx.gc_orbit_load_su2((6, 3), GI.su2_links((6, 3), 0, 0))
+    assert e.value.status == gc.GC_EUNSUPPORTED
+    with pytest.raises(gc.GcError) as e:
+        ctx.gc_orbit_load_su2((10, 10, 10, 10), GI.su2_links((10, 10, 10, 10), 0, 0))
+    assert e.value.status == gc.GC_EUNSUPPORTED
+    with pytest.raises(gc.GcError) as e:
+        ctx.gc_orbit_load_su2((4, 4), U, max_sweeps=0)
+    assert e.value.status == gc.GC_EINVAL
