@@ -68,7 +68,7 @@ __device__ __forceinline__ Quat load_q(const double *__restrict__ p, size_t k)
     return Quat{v.x, v.y, v.z, v.w};
 }
 
-constexpr int kMagBlock = 256;
+constexpr int kMagBlock = 1024;
 
 // Sum over the workgroup in a fixed order (wavefront sums, then the waves in
 // order); every thread returns the total.
