@@ -1847,6 +1847,8 @@ gc_status gc_orbit_load_su2(gc_ctx *ctx, const gc_lattice *lat, const double *li
     hipStream_t s = ctx->util;
     std::vector<double> phi(nl);
     GcMagOut mo{};
+    // the reduction takes milliseconds: the context stays available meanwhile
+    lk.unlock();
     hipError_t e = hipMemcpyAsync(b + o_links, links, 32 * nl, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(b + o_nbr, nbr.data(), 4 * nbr.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(b + o_cs, csite.data(), 4 * csite.size(), hipMemcpyHostToDevice, s);
@@ -1856,8 +1858,10 @@ gc_status gc_orbit_load_su2(gc_ctx *ctx, const gc_lattice *lat, const double *li
     if (e == hipSuccess) e = hipMemcpyAsync(phi.data(), b + o_phi, 8 * nl, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&mo, b + o_out, sizeof mo, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    lk.lock();
     ctx->pool.put(blk, got);
     if (e != hipSuccess) return fail(ctx, e, "maximal Abelian reduction");
+    if (ctx->failed) return GC_EDEVICE;
     if (info) {
         info->sweeps = mo.sweeps;
         info->R = mo.R;
