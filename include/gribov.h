@@ -219,14 +219,15 @@ gc_status gc_orbit_random(gc_ctx *ctx, const gc_lattice *lat, uint64_t seed,
  * phi = arg (U')_{11} then load as an ordinary orbit (gc_orbit_load).
  * links: host [dim][V][4] float64 unit quaternions (a0, a1, a2, a3) for
  * U = a0 + i (a1 s1 + a2 s2 + a3 s3); non-finite or |a|^2 off 1 by more than
- * 1e-10 -> GC_EINVAL.  Even extents, periodic transformations
- * (lat->antiperiodic = 0) and V <= 4096 only, else GC_EUNSUPPORTED.  params
+ * 1e-10, eps < 0 or max_sweeps outside 1 .. 10^6 -> GC_EINVAL.  Even
+ * extents, periodic transformations (lat->antiperiodic = 0) and V <= 4096
+ * only, else GC_EUNSUPPORTED.  params
  * NULL: eps 1e-20, max_sweeps 100000.  info (may be NULL): sweeps, R/(dim V)
  * and whether the threshold was reached.  Runs on the device, one workgroup,
  * and returns when the orbit is loaded. */
 typedef struct gc_mag_params {
     double eps;           /* threshold on the sweep's mean |n - n_old|^2 (>= 0) */
-    uint64_t max_sweeps;  /* >= 1 */
+    uint64_t max_sweeps;  /* 1 .. 10^6 */
 } gc_mag_params;
 
 typedef struct gc_mag_info {

@@ -1810,7 +1810,8 @@ gc_status gc_orbit_load_su2(gc_ctx *ctx, const gc_lattice *lat, const double *li
     if (lat->antiperiodic || V > 4096) return GC_EUNSUPPORTED;
     const double eps = mp ? mp->eps : 1e-20;
     const uint64_t cap = mp ? mp->max_sweeps : 100000;
-    if (!(eps >= 0.0) || !std::isfinite(eps) || cap < 1) return GC_EINVAL;
+    // at most 10^6 sweeps: about 20 s for the largest supported lattice
+    if (!(eps >= 0.0) || !std::isfinite(eps) || cap < 1 || cap > 1000000) return GC_EINVAL;
     const size_t nl = (size_t)d * V;
     for (size_t l = 0; l < nl; ++l) {
         const double *q = links + 4 * l;

@@ -12,7 +12,6 @@ U(1) field).
   the same orbit start by start.
 * Arguments outside the supported set are refused before any device work.
 """
-import math
 import sys
 
 import numpy as np
@@ -137,6 +136,7 @@ def test_unsupported_arguments_are_refused(ctx):
     with pytest.raises(gc.GcError) as e:
         ctx.gc_orbit_load_su2((10, 10, 10, 10), GI.su2_links((10, 10, 10, 10), 0, 0))
     assert e.value.status == gc.GC_EUNSUPPORTED
-    with pytest.raises(gc.GcError) as e:
-        ctx.gc_orbit_load_su2((4, 4), U, max_sweeps=0)
-    assert e.value.status == gc.GC_EINVAL
+    for kw in ({"max_sweeps": 0}, {"max_sweeps": 10**6 + 1}, {"eps": -1.0}):
+        with pytest.raises(gc.GcError) as e:
+            ctx.gc_orbit_load_su2((4, 4), U, **kw)
+        assert e.value.status == gc.GC_EINVAL
