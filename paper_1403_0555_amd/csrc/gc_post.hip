@@ -256,14 +256,19 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                 h1 += mix64(c1 ^ word);
             };
             // plaquettes: planes in order (uniform), sites across the threads
+            // (the wrap numbers lie within about 1e-5 of integers, so the
+            // quotient by 2 pi may be a product with its reciprocal; the
+            // hash sums commute, so the order of the elements is free)
+            constexpr double kInvTwoPi = 1.0 / kTwoPi;
             for (int pl = 0; pl < O.n_plaq / V; ++pl) {
                 const int mu = O.plane_mu[pl], nu = O.plane_nu[pl];
+#pragma unroll 2
                 for (int i = tid; i < V; i += B) {
                     const int fm = O.nbr[mu * V + i], fn = O.nbr[nu * V + i];
                     const double A = (double)a32[mu * V + i] + (double)a32[nu * V + fm] - (double)a32[mu * V + fn] -
                                      (double)a32[nu * V + i];
                     const int k = pl * V + i;
-                    fold(k, rint((A - O.phi_plaq[k]) / kTwoPi));
+                    fold(k, rint((A - O.phi_plaq[k]) * kInvTwoPi));
                 }
             }
             // line windings: lines of direction mu in order; a line starts
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(B) void post_kernel(const GcJobDev *__restrict__ jo
                         acc += (double)a32[mu * V + i];
                         i += st;
                     }
-                    fold(O.n_plaq + q, rint((acc - O.phi_line[q]) / kTwoPi));
+                    fold(O.n_plaq + q, rint((acc - O.phi_line[q]) * kInvTwoPi));
                 }
                 st *= O.ext[mu];
             }
