@@ -195,6 +195,19 @@ def run_workload(gc, ctx, w, n, steps, warmup, tune_n, inflight=1, keep_starts=F
             "last": last, "inflight": inflight}
 
 
+def su2_reduction(gc, ctx, extent):
+    """The maximal Abelian reduction of a Haar-random SU(2) configuration on
+    the lattice of the workload (once per configuration, before enumeration):
+    wall time of gc_orbit_load_su2 after a first call, sweeps and R/(dV)."""
+    links = GI.su2_links(extent, 0, 0)
+    ctx.gc_release(ctx.gc_orbit_load_su2(extent, links)[0])
+    t0 = time.perf_counter()
+    h, info = ctx.gc_orbit_load_su2(extent, links)
+    ms = (time.perf_counter() - t0) * 1e3
+    ctx.gc_release(h)
+    return {"load_ms": ms, "sweeps": info["sweeps"], "R": info["R"], "converged": info["converged"]}
+
+
 def compare_precisions(w, r64, rmx):
     """Single-precision error of the mixed result, start by start against the
     double-precision run of the same orbit and starts."""
@@ -450,6 +463,7 @@ def main():
                                          "fp32_error": compare_precisions(w3, a, b),
                                          "mixed_over_fp64": (b["conv_inreg"] / b["wall"]) /
                                                             (a["conv_inreg"] / a["wall"])}
+            extra["su2_maximal_abelian_6x6x6x6"] = su2_reduction(gc, ctx, w.extent)
     ctx.close()
 
     relax, post = rooflines(w, r)
