@@ -40,8 +40,8 @@ def wrapped(a):
     return np.angle(np.exp(1j * a))
 
 
-@pytest.mark.parametrize("extent,seed", [((4, 4), 0), ((6, 6), 1), ((4, 4, 4), 2), ((4, 4, 4, 4), 3),
-                                         ((6, 6, 6, 6), 4)])
+@pytest.mark.parametrize("extent,seed", [((8,), 5), ((2, 2), 6), ((4, 4), 0), ((6, 6), 1), ((4, 4, 4), 2),
+                                         ((4, 4, 4, 4), 3), ((6, 6, 6, 6), 4)])
 def test_reduction_matches_oracle(ctx, extent, seed):
     note(f"reduction {extent} seed {seed}")
     U = GI.su2_links(extent, seed, 0)
