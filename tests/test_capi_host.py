@@ -7,6 +7,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 import paper_1403_0555_amd as gc
@@ -87,3 +88,33 @@ def test_no_device_is_reported(monkeypatch):
         pytest.skip("a GPU is present")
     h = ctypes.c_void_p()
     assert gc.lib().gc_create(None, ctypes.byref(h)) == gc.GC_EDEVICE
+
+
+def test_su2_reduction_arguments_checked_without_device():
+    """gc_orbit_load_su2 validates the lattice, the links and the parameters
+    before it touches the context or the device."""
+    from paper_1403_0555_amd._capi import gc_lattice, gc_mag_params, gc_mag_info
+    import gribov_inputs as GI
+    L = gc.lib()
+    P = ctypes.POINTER(ctypes.c_double)
+    out, info = ctypes.c_uint64(), gc_mag_info()
+
+    def call(extent, links, eps=1e-20, max_sweeps=100000):
+        lat = gc_lattice(len(extent), (ctypes.c_int32 * 4)(*(list(extent) + [1] * (4 - len(extent)))), 0)
+        prm = gc_mag_params(eps, max_sweeps)
+        ptr = links.ctypes.data_as(P) if links is not None else None
+        return L.gc_orbit_load_su2(None, ctypes.byref(lat), ptr, 0, ctypes.byref(prm), ctypes.byref(info),
+                                   ctypes.byref(out))
+
+    good = np.ascontiguousarray(GI.su2_links((4, 4), 0, 0))
+    assert call((4, 4), None) == gc.GC_EINVAL
+    assert call((6, 3), np.ascontiguousarray(GI.su2_links((6, 3), 0, 0))) == gc.GC_EUNSUPPORTED
+    assert call((10, 10, 10, 10), np.zeros((4, 10000, 4))) == gc.GC_EUNSUPPORTED
+    bad = good.copy()
+    bad[0, 5, 1] += 1e-6
+    assert call((4, 4), bad) == gc.GC_EINVAL
+    assert call((4, 4), good, max_sweeps=0) == gc.GC_EINVAL
+    assert call((4, 4), good, max_sweeps=10**6 + 1) == gc.GC_EINVAL
+    assert call((4, 4), good, eps=float("nan")) == gc.GC_EINVAL
+    # valid arguments: the missing context is the only fault left
+    assert call((4, 4), good) == gc.GC_EINVAL
