@@ -261,14 +261,19 @@ __device__ __forceinline__ double rsq(double x)
 // g <- N((1 - omega) g + omega S/|S|), N(v) = v/|v| (for |g| = 1 the same
 // map as g N(1 + omega (conj(g) S/|S| - 1))).  |S| = 0 leaves g unchanged.
 // Written without branches so that the compiler can schedule a whole colour
-// pass as one block.
-template <bool RELAX, typename R>
+// pass as one block.  GUARD keeps the reciprocal square root's argument
+// finite at |S| = 0; unguarded, that case runs through infinities and NaNs
+// that the final select discards, with the same result and two selects
+// fewer (taken where the kernel's register allocation stays spill-free).
+// The squared moduli are written as explicit FMAs so that every kernel
+// variant rounds them alike.
+template <bool RELAX, typename R, bool GUARD = true>
 __device__ __forceinline__ typename cx<R>::T local_update(typename cx<R>::T g0, typename cx<R>::T s, R omega)
 {
     using C = typename cx<R>::T;
-    const R n2 = s.x * s.x + s.y * s.y;
+    const R n2 = fma(s.y, s.y, s.x * s.x);
     const bool ok = n2 > (R)0;
-    const R r = rsq(ok ? n2 : (R)1);
+    const R r = rsq(GUARD ? (ok ? n2 : (R)1) : n2);
     C g;
     if (RELAX) {
         g.x = s.x * r;
@@ -278,7 +283,7 @@ __device__ __forceinline__ typename cx<R>::T local_update(typename cx<R>::T g0, 
         const R b = omega * r;
         const R vx = fma(s.x, b, a * g0.x);
         const R vy = fma(s.y, b, a * g0.y);
-        const R rv = rsq(vx * vx + vy * vy);
+        const R rv = rsq(fma(vy, vy, vx * vx));
         g.x = vx * rv;
         g.y = vy * rv;
     }

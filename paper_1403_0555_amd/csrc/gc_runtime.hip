@@ -207,6 +207,7 @@ struct Group {
     std::vector<int> jobs;           // indices into Job::orbits
     int block = 64, grid = 1, ns = 1, coef_lds = 0, creg = 0, wps = 0;
     int rm = 0;                      // relax mode of the exchange-region kernel (ns > 2)
+    int full = 0;                    // GC_RM_FULL_SLOTS for the double-precision kernel, or 0
     size_t lds = 0;
     // mixed precision above two slots per lane: the single-precision phase
     // in its own kernel, before the double-precision one
@@ -216,6 +217,9 @@ struct Group {
     size_t o_jobs1 = 0;              // first-pass descriptors of a batch-synchronous launch
     uint64_t total = 0;
 };
+
+// Kernel variant word of a wavefront-per-start group (gc_launch_wave).
+int wave_variant(const Group &g) { return g.coef_lds | (g.creg << 1) | ((g.rm | g.full) << 3); }
 
 // Orbits of one relax group sharing one post-kernel shape (workgroup size by
 // V), so that an orbit's per-start arithmetic is the same alone and in a
@@ -691,6 +695,14 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             g.ns = (gV / 2 + 63) / 64;
             g.block = 64 * gc_wave_starts_per_wg(g.ns);
             g.rm = g.ns > 2 ? gc_wave_relax_mode(job->p.omega, job->p.stop_norm) : 0;
+            // every orbit fills all slots of a lane but the last: the
+            // double-precision kernel tests only the last slot (mean-square
+            // norm only)
+            if (g.ns > 2 && (g.rm & 4) == 0) {
+                bool full = true;
+                for (int j : g.jobs) full = full && (job->orbits[j]->V / 2 + 63) / 64 == ns_bucket(g.d, g.ns);
+                g.full = full ? GC_RM_FULL_SLOTS : 0;
+            }
             size_t coef_bytes = 0;
             for (int j : g.jobs) {
                 const Orbit *o = job->orbits[j];
@@ -714,7 +726,7 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             if (tc != ctx->tune_creg.end()) g.creg = std::min(tc->second, gc_wave_creg_max(g.d, g.ns));
             if (ctx->creg_override >= 0) g.creg = std::min(ctx->creg_override, gc_wave_creg_max(g.d, g.ns));
             if (job->force_creg >= 0) g.creg = std::min(job->force_creg, gc_wave_creg_max(g.d, g.ns));
-            hipError_t e = gc_wave_occupancy(g.d, g.ns, g.coef_lds | (g.creg << 1) | (g.rm << 3), g.lds, &per_cu);
+            hipError_t e = gc_wave_occupancy(g.d, g.ns, wave_variant(g), g.lds, &per_cu);
             if (e != hipSuccess) return fail(ctx, e, "occupancy");
             if (g.ns > 2 && mixed) {
                 g.split = 1;
@@ -1024,7 +1036,7 @@ hipError_t enqueue_chain(Job *job, unsigned char *base, int gi, hipStream_t qs, 
         if (g.wave)
             return gc_launch_wave(g.d, g.ns, (const GcJobDev *)(base + o_jobs),
                                   (const GcWaveOrbit *)(base + g.o_worbs), (int)g.jobs.size(),
-                                  (unsigned long long *)(base + g.o_next), g.coef_lds | (g.creg << 1) | (g.rm << 3),
+                                  (unsigned long long *)(base + g.o_next), wave_variant(g),
                                   (float2 *)(base + g.o_bounce), g.grid, g.lds, qs);
         return gc_launch_relax_wg(g.block, (const GcJobDev *)(base + o_jobs), (int)g.jobs.size(),
                                   (const uint64_t *)(base + g.o_prefix), (unsigned long long *)(base + g.o_next),

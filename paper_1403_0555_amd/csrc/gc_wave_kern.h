@@ -396,7 +396,11 @@ __device__ void relax_start_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP64 
 // Half the LDS of a two-region state lets twice the starts share a compute
 // unit.  The sweep schedule, the stopping norm and the arithmetic are those
 // of relax_wave_t.  own: the start's values on entry and on return.
-template <int D, typename R, int NS, bool RELAX, bool MAXABS, int DL, typename LT>
+// Slots beyond the half volume work on the clamped site half - 1 and are
+// neither stored nor counted.  FULL: every slot of a lane but its last lies
+// on the lattice (ceil(half / 64) = NS), so only the last slot is tested;
+// the norm's products are explicit FMAs, so both variants round alike.
+template <int D, typename R, int NS, bool RELAX, bool MAXABS, int DL, typename LT, bool FULL = false>
 __device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t links, lds_ptr<const unsigned char> lb,
                         lds_ptr<const u32x4> nbt, lds_ptr<typename cx<R>::T> X, typename cx<R>::T (&own)[2][NS],
                         double eps, uint64_t cap, bool fixed, uint64_t &sweeps, double &D_out)
@@ -412,7 +416,7 @@ __device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t link
     // slot k of the lane: h = lane + 64 k, computed on a clamped index and
     // discarded beyond the half volume (recomputed where used: no
     // registers held for it)
-#define GC_RR_SLOT(k) const int hk = lane + 64 * (k); const bool vk = hk < half; const int hc = vk ? hk : half - 1
+#define GC_RR_SLOT(k) const int hk = lane + 64 * (k); const bool vk = (FULL && (k) < NS - 1) || hk < half; const int hc = vk ? hk : half - 1
     // the first pass reads colour 1
     wave_sync();
 #pragma unroll
@@ -448,10 +452,10 @@ __device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t link
             const C s = staple_big<D, DL, R, LT, 0>(wcur, xb, lb, (uint32_t)h * (uint32_t)sizeof(LT), links,
                                                 (uint32_t)h * (uint32_t)sizeof(C), plane, lplane);
             const C g0 = g0r[k];
-            const double dv = (double)(g0.x * s.y - g0.y * s.x);
-            const double a = maxabs ? fmax(acc0, fabs(dv)) : acc0 + dv * dv;
+            const double dv = (double)fma(g0.x, s.y, -(g0.y * s.x));
+            const double a = maxabs ? fmax(acc0, fabs(dv)) : fma(dv, dv, acc0);
             acc0 = vk ? a : acc0;
-            gnew[k] = local_update<RELAX, R>(g0, s, omega);
+            gnew[k] = local_update<RELAX, R, !FULL>(g0, s, omega);
         }
         if (pending) {
             double Dn;
@@ -489,10 +493,10 @@ __device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t link
             if (k + 1 < NS) wnext1 = nbt[half + min(lane + 64 * (k + 1), half - 1) + z];
             const C s = staple_big<D, DL, R, LT, 1>(wcur, xb, lb, (uint32_t)h * (uint32_t)sizeof(LT), links,
                                                 (uint32_t)h * (uint32_t)sizeof(C), plane, lplane);
-            const C g = local_update<RELAX, R>(g1r[k], s, omega);
+            const C g = local_update<RELAX, R, !FULL>(g1r[k], s, omega);
             g1r[k] = g;
-            const double dv = (double)(g.x * s.y - g.y * s.x);
-            const double a = maxabs ? fmax(a1, fabs(dv)) : a1 + dv * dv;
+            const double dv = (double)fma(g.x, s.y, -(g.y * s.x));
+            const double a = maxabs ? fmax(a1, fabs(dv)) : fma(dv, dv, a1);
             a1 = vk ? a : a1;
         }
         if (chk) part1 = a1;
@@ -524,10 +528,11 @@ __device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t link
 // over-relaxation in both precisions, plain relaxation in both (omega = 1),
 // or plain relaxation in the single-precision phase only (omega rounds to 1
 // in single precision but differs from 1); GC_RM_MAXABS added for the
-// max |div| stopping norm.
-enum { GC_RM_OR = 0, GC_RM_RELAX = 1, GC_RM_RELAX32 = 2, GC_RM_MAXABS = 4 };
+// max |div| stopping norm; GC_RM_FULL (double-precision kernel, mean-square
+// norm) where every orbit of the launch has ceil(half / 64) = NS.
+enum { GC_RM_OR = 0, GC_RM_RELAX = 1, GC_RM_RELAX32 = 2, GC_RM_MAXABS = 4, GC_RM_FULL = GC_RM_FULL_SLOTS };
 
-template <int D, typename R, int NS, bool RELAX, bool MAXABS, int DL, typename LT>
+template <int D, typename R, int NS, bool RELAX, bool MAXABS, int DL, typename LT, bool FULL = false>
 __device__ __forceinline__ int relax_rr_links(const GcJobDev &J, const GcWaveOrbit &WO,
                                               lds_ptr<const unsigned char> lnk, lds_ptr<const u32x4> nbt,
                                               lds_ptr<typename cx<R>::T> X, typename cx<R>::T (&own)[2][NS],
@@ -536,8 +541,8 @@ __device__ __forceinline__ int relax_rr_links(const GcJobDev &J, const GcWaveOrb
     const uint32_t bytes = (uint32_t)(2 * D * WO.half * sizeof(typename cx<R>::T));
     const __amdgpu_buffer_rsrc_t links =
         buffer_rsrc(sizeof(R) == 8 ? (const void *)WO.link64 : (const void *)WO.link32, bytes);
-    return relax_rr<D, R, NS, RELAX, MAXABS, DL, LT>(J, WO.half, links, lnk, nbt, X, own, eps, cap, fixed, sweeps,
-                                                     D_out);
+    return relax_rr<D, R, NS, RELAX, MAXABS, DL, LT, FULL>(J, WO.half, links, lnk, nbt, X, own, eps, cap, fixed,
+                                                           sweeps, D_out);
 }
 
 // The links of the first DL directions, both colours, into LDS planes of
@@ -667,8 +672,8 @@ __device__ void relax_start_rr(const GcJobDev &J, const GcWaveOrbit &WO, lds_ptr
     const bool fixed = !from32 && (J.flags & GC_JOB_SYNC2) != 0;
     const uint64_t cap = fixed ? (uint64_t)J.fixed_sweeps[local] : J.max_sweeps;
     const int status =
-        relax_rr_links<D, double, NS, (RM & 3) == GC_RM_RELAX, (RM & GC_RM_MAXABS) != 0, gc_links_in_lds(D, NS), dbl2>(
-            J, WO, lnk, nbt, X64, own64, J.eps64, cap, fixed, sw64, Dn);
+        relax_rr_links<D, double, NS, (RM & 3) == GC_RM_RELAX, (RM & GC_RM_MAXABS) != 0, gc_links_in_lds(D, NS), dbl2,
+                       (RM & GC_RM_FULL) != 0>(J, WO, lnk, nbt, X64, own64, J.eps64, cap, fixed, sw64, Dn);
     rr_store<NS>(J, WO, X64, local, own64);
     if (lane == 0) record_relax(J, local, status, sw32, sw64, Dn);
     wave_sync();
@@ -1064,7 +1069,7 @@ hipError_t launch_t(const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, 
         // register-resident kernel: no staged coefficient table
         if (cl) return hipErrorInvalidValue;
         (void)bounce;
-        switch ((variant >> 3) & 7) {
+        switch ((variant >> 3) & 15) {
 #define GC_RR_LAUNCH(RM)                                                                                  \
     case RM:                                                                                              \
         hipLaunchKernelGGL((wave_rr_kernel<D, NS, RM>), dim3(grid), dim3(64 * GC_WAVES_RR), lds, s, jobs, worbs, \
@@ -1076,6 +1081,9 @@ hipError_t launch_t(const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, 
             GC_RR_LAUNCH(4)
             GC_RR_LAUNCH(5)
             GC_RR_LAUNCH(6)
+            GC_RR_LAUNCH(GC_RM_FULL)
+            GC_RR_LAUNCH(GC_RM_FULL | 1)
+            GC_RR_LAUNCH(GC_RM_FULL | 2)
 #undef GC_RR_LAUNCH
         default: return hipErrorInvalidValue;
         }
@@ -1100,6 +1108,9 @@ hipError_t occ_t(int variant, size_t lds, int *per_cu)
         if (cl) return hipErrorInvalidValue;
         // the three relax modes share their resource use; the
         // over-relaxation instantiation stands for them
+        if ((variant >> 3) & GC_RM_FULL)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, wave_rr_kernel<D, NS, GC_RM_FULL>,
+                                                                64 * GC_WAVES_RR, lds);
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, wave_rr_kernel<D, NS, GC_RM_OR>, 64 * GC_WAVES_RR,
                                                             lds);
     } else {

@@ -394,6 +394,38 @@ def test_batch_equals_single_launches(ctx):
         ctx.gc_release(hs[k])
 
 
+def test_full_and_partial_slot_kernels_agree(ctx):
+    """6^4 (half volume 648) fills every slot of a lane but the last of the
+    eleven-slot double-precision kernel: alone it runs the variant that tests
+    only the last slot.  Batched with 6x6x6x4 (half volume 432: seven slots in
+    the same kernel) the group runs the variant that tests every slot.  The
+    6^4 starts come out bit for bit the same, final states included, and the
+    partial orbit matches the oracle."""
+    big, small = (6, 6, 6, 6), (6, 6, 6, 4)
+    n_big, n_small = 300, 40
+    p = gc.SolveParams(omega=1.7)
+    phi_b, phi_s = GI.orbit_angles(big, 2, 0), GI.orbit_angles(small, 2, 1)
+    note("6^4 alone (%d starts), then batched with 6x6x6x4" % n_big)
+    hb = ctx.gc_orbit_load(big, phi_b, 0)
+    ctx.gc_launch(hb, n_big, p)
+    assert ctx.gc_wait(hb, 300_000) == gc.GC_OK
+    alone = ctx.gc_fetch_starts(hb, n_big)
+    alone_states = [ctx.gc_fetch_start_state(hb, s) for s in (0, 17, n_big - 1)]
+    hs = ctx.gc_orbit_load(small, phi_s, 1)
+    ctx.gc_launch_batch([hb, hs], [n_big, n_small], p)
+    assert ctx.gc_wait(hb, 300_000) == gc.GC_OK and ctx.gc_wait(hs, 300_000) == gc.GC_OK
+    both = ctx.gc_fetch_starts(hb, n_big)
+    for f in ("status", "key_hi", "key_lo", "sweeps64", "F", "D"):
+        assert np.array_equal(alone[f], both[f]), f
+    for s, st in zip((0, 17, n_big - 1), alone_states):
+        assert np.array_equal(ctx.gc_fetch_start_state(hb, s), st)
+    o = O.enumerate_copies(small, phi_s, np.arange(n_small), oracle_params(p, 1))
+    compare_starts(small, ctx.gc_fetch_starts(hs, n_small), o["records"])
+    compare_tables(small, phi_s, ctx.gc_fetch(hs), o, p)
+    ctx.gc_release(hb)
+    ctx.gc_release(hs)
+
+
 def test_saturation_curve_matches_oracle(ctx):
     """Distinct copies within the first 2^k starts (the paper's saturation
     curves), from the table's lowest start ids, against the oracle's table."""
