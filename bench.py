@@ -64,14 +64,13 @@ KERNEL_SOURCES = {
     "lanczos_kernel": ("gc_lanczos_kern.h", "gc_filter.h", "gc_lanczos4.hip", "gc_common.h", "gc_internal.h"),
 }
 TRAFFIC = {
-    # wave_rr_kernel<4, 11, 0>, 10^6 starts of the 6^4 FP64 workload (one dispatch):
-    # FETCH_SIZE 1018660.8 KiB x 2.0000 (a 2 GiB copy reads 1048587.5 KiB) and
-    # WRITE_SIZE 20541473.0 KiB x 1.0 (the copy writes 2097152.0 KiB); the
-    # sources have since gained declarations for another kernel only (the
-    # relax kernel's code is unchanged)
-    "sources_sha256": "bcd68ae3400343f4cdbec7bb419e12b63777e25ea08af1abc974c1c54cb38bed",
+    # wave_rr_kernel<4, 11, 8> (exact-slot variant), 10^6 starts of the 6^4
+    # FP64 workload (one dispatch): FETCH_SIZE 665782.7 KiB x 2.0000 (a 2 GiB
+    # copy reads 1048587.5 KiB) and WRITE_SIZE 20538190.2 KiB x 1.0 (the copy
+    # writes 2097152.0 KiB)
+    "sources_sha256": "235660ca87b452bda2ebd669c7abe848450376ed7f2e3ce64d7a044b3a3fc8fd",
     "kernel": "relax",
-    "bytes_per_launch": 2086217318 + 21034468352,
+    "bytes_per_launch": 1363522944 + 21031106752,
 }
 
 
