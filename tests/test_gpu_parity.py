@@ -394,18 +394,19 @@ def test_batch_equals_single_launches(ctx):
         ctx.gc_release(hs[k])
 
 
-def test_full_and_partial_slot_kernels_agree(ctx):
+@pytest.mark.parametrize("omega", [1.7, 1.0])
+def test_full_and_partial_slot_kernels_agree(ctx, omega):
     """6^4 (half volume 648) fills every slot of a lane but the last of the
     eleven-slot double-precision kernel: alone it runs the variant that tests
     only the last slot.  Batched with 6x6x6x4 (half volume 432: seven slots in
     the same kernel) the group runs the variant that tests every slot.  The
     6^4 starts come out bit for bit the same, final states included, and the
-    partial orbit matches the oracle."""
+    partial orbit matches the oracle; over-relaxation and plain relaxation."""
     big, small = (6, 6, 6, 6), (6, 6, 6, 4)
     n_big, n_small = 300, 40
-    p = gc.SolveParams(omega=1.7)
+    p = gc.SolveParams(omega=omega)
     phi_b, phi_s = GI.orbit_angles(big, 2, 0), GI.orbit_angles(small, 2, 1)
-    note("6^4 alone (%d starts), then batched with 6x6x6x4" % n_big)
+    note("6^4 alone (%d starts, omega %s), then batched with 6x6x6x4" % (n_big, omega))
     hb = ctx.gc_orbit_load(big, phi_b, 0)
     ctx.gc_launch(hb, n_big, p)
     assert ctx.gc_wait(hb, 300_000) == gc.GC_OK
