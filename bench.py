@@ -139,6 +139,9 @@ def run_workload(gc, ctx, w, n, steps, warmup, tune_n, inflight=1, keep_starts=F
     params = gc.SolveParams(omega=w.omega, precision=w.precision, eps32=w.eps32, eps64=w.eps64,
                             start_seed=w.start_seed)
     hs = [ctx.gc_orbit_load(w.extent, phi, w.orbit_index) for _ in range(inflight)]
+    # one host buffer per launch in flight, reused by every fetch (at most
+    # one copy per start); the warmup touches its pages
+    bufs = [np.zeros(n, dtype=gc.COPY_DTYPE) for _ in range(inflight)]
     tune = None
     if tune_n:
         tune = ctx.gc_autotune(hs[0], min(n, tune_n), params)
@@ -152,7 +155,7 @@ def run_workload(gc, ctx, w, n, steps, warmup, tune_n, inflight=1, keep_starts=F
     def finish(i):
         if ctx.gc_wait(hs[i], 600_000) != gc.GC_OK:
             raise RuntimeError("launch timed out")
-        return ctx.gc_fetch(hs[i]), ctx.gc_poll(hs[i])
+        return ctx.gc_fetch(hs[i], out=bufs[i]), ctx.gc_poll(hs[i])
 
     for k in range(warmup):
         launch(0)
@@ -168,17 +171,16 @@ def run_workload(gc, ctx, w, n, steps, warmup, tune_n, inflight=1, keep_starts=F
         copies, prog = finish(i)
         lat.append((time.perf_counter() - t_launch[i]) * 1e3)
         if keep_starts and k == steps - 1:
-            last = (copies, i)
+            last = (copies, i)   # a view of bufs[i]: nothing is fetched into it after the last step
         if k + inflight < steps:
             launch(i)
         kms.append(prog["device_ms"])
         pms.append(prog["post_ms"])
         fms.append(prog["filter_ms"])
-        inreg = copies["flags"] & gc.GC_FLAG_IN_REGION != 0
-        conv_inreg += int(copies["hits"][inreg].sum())
+        conv_inreg += int(prog["in_region_hits"])
         upd += int(prog["site_updates"])
         distinct += len(copies)
-        lits += int(copies["lanczos_iters"].sum())
+        lits += int(prog["lanczos_iters"])
         print("%sstep %d: %.1f ms, relax %.1f ms, key pass %.1f ms, filter %.1f ms, %d copies" %
               (label, k, lat[-1], kms[-1], pms[-1], fms[-1], len(copies)), file=sys.stderr, flush=True)
     wall = time.perf_counter() - t0

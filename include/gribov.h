@@ -138,6 +138,8 @@ typedef struct {
     double post_ms;             /* device time of the last launch's key pass and table compaction (single-orbit
                                    launches) */
     double filter_ms;           /* device time of the last launch's FP filter pass (single-orbit launches) */
+    uint64_t in_region_hits;    /* converged starts whose copy has GC_FLAG_IN_REGION (valid when DONE) */
+    uint64_t lanczos_iters;     /* Lanczos iterations summed over the copies' filter runs (valid when DONE) */
 } gc_progress;
 
 /* One distinct copy. */

@@ -72,7 +72,7 @@ class gc_progress(ctypes.Structure):
                                        "in_region", "saddles", "singular", "collisions", "sweeps_total",
                                        "site_updates", "lanczos_runs", "paper_count")] + [
         ("submit_to_done_ms", ctypes.c_double), ("device_ms", ctypes.c_double), ("post_ms", ctypes.c_double),
-        ("filter_ms", ctypes.c_double)]
+        ("filter_ms", ctypes.c_double), ("in_region_hits", ctypes.c_uint64), ("lanczos_iters", ctypes.c_uint64)]
 
 
 COPY_DTYPE = np.dtype([("key_hi", np.uint64), ("key_lo", np.uint64), ("F", np.float64), ("x", np.float64),
@@ -337,9 +337,21 @@ class Context:
             self._check(st, "gc_wait")
         return int(st)
 
-    def gc_fetch(self, orbit: int) -> np.ndarray:
+    def gc_fetch(self, orbit: int, out: np.ndarray | None = None) -> np.ndarray:
+        """The copy table, ascending by key.  out: a caller-owned contiguous
+        COPY_DTYPE array to write into instead of a new one (a caller that
+        fetches every launch keeps one); the result is then its first
+        n_total records.  ValueError if out cannot hold the table."""
         total = ctypes.c_uint64()
         nw = ctypes.c_uint64()
+        if out is not None:
+            if out.dtype != COPY_DTYPE or out.ndim != 1 or not out.flags.c_contiguous or not out.flags.writeable:
+                raise ValueError("out: a writeable contiguous one-dimensional COPY_DTYPE array")
+            self._check(self._L.gc_fetch(self._h, orbit, 0, len(out), out.ctypes.data_as(ctypes.c_void_p),
+                                         ctypes.byref(nw), ctypes.byref(total)), "gc_fetch")
+            if total.value > len(out):
+                raise ValueError("out holds %d records, the table %d" % (len(out), total.value))
+            return out[:nw.value]
         self._check(self._L.gc_fetch(self._h, orbit, 0, 0, None, ctypes.byref(nw), ctypes.byref(total)), "gc_fetch")
         out = np.zeros(total.value, dtype=COPY_DTYPE)
         if total.value:

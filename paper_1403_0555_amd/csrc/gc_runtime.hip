@@ -1543,14 +1543,20 @@ gc_status ensure_copies_locked(gc_ctx *ctx, Orbit *o)
         }
         o->copies[m] = v;
     }
-    uint64_t inr = 0, sad = 0, sng = 0, col = 0;
+    uint64_t inr = 0, sad = 0, sng = 0, col = 0, inr_hits = 0, lits = 0;
     for (const gc_copy &c : o->copies) {
-        if (c.flags & GC_FLAG_IN_REGION) ++inr;
+        if (c.flags & GC_FLAG_IN_REGION) {
+            ++inr;
+            inr_hits += c.hits;
+        }
         if (c.flags & GC_FLAG_SADDLE) ++sad;
         if (c.flags & GC_FLAG_SINGULAR) ++sng;
         if (c.flags & GC_FLAG_COLLISION) ++col;
+        lits += c.lanczos_iters;
     }
     o->last.in_region = inr;
+    o->last.in_region_hits = inr_hits;
+    o->last.lanczos_iters = lits;
     o->last.saddles = sad;
     o->last.singular = sng;
     o->last.collisions = col;

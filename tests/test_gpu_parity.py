@@ -134,6 +134,17 @@ def test_small_2d_workload_full_parity(ctx):
     check_start_filter(copies, starts, o)
     assert prog["distinct"] == len(o["table"]) and prog["converged"] == 1000
     assert prog["in_region"] == len(o["table"])
+    inreg = copies["flags"] & gc.GC_FLAG_IN_REGION != 0
+    assert prog["in_region_hits"] == int(copies["hits"][inreg].sum()) == 1000
+    assert prog["lanczos_iters"] == int(copies["lanczos_iters"].sum()) > 0
+    # into a caller-owned buffer: the same records, a view of its head
+    buf = np.zeros(len(copies) + 5, dtype=gc.COPY_DTYPE)
+    again = ctx.gc_fetch(h, out=buf)
+    assert again.base is buf and np.array_equal(again, copies)
+    with pytest.raises(ValueError):
+        ctx.gc_fetch(h, out=np.zeros(len(copies) - 1, dtype=gc.COPY_DTYPE))
+    with pytest.raises(ValueError):
+        ctx.gc_fetch(h, out=np.zeros(len(copies), dtype=np.float64))
     ctx.gc_release(h)
 
 
