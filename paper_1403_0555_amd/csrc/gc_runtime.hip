@@ -198,6 +198,23 @@ struct PinnedPool {
 
 struct Orbit;
 
+// An orbit's host copy table in a pinned block of the context's pool, so
+// that the device-to-host copy runs at the link's speed: grown on demand,
+// kept across launches of the orbit, handed back to the pool (not freed)
+// when the orbit is released.
+struct HostCopies {
+    gc_copy *p = nullptr;
+    size_t n = 0, cap_bytes = 0;
+    gc_copy *data() { return p; }
+    size_t size() const { return n; }
+    gc_copy &operator[](size_t i) { return p[i]; }
+    gc_copy *begin() { return p; }
+    gc_copy *end() { return p + n; }
+    const gc_copy *begin() const { return p; }
+    const gc_copy *end() const { return p + n; }
+    void clear() { n = 0; }
+};
+
 // Relax launch groups: orbits with odd extents use the workgroup-per-start
 // kernel; orbits with even extents the wavefront-per-start kernel, one launch
 // per dimension, layout and slot count (the kernel is specialised on them).
@@ -303,7 +320,7 @@ struct Orbit {
     int job_index = 0;               // position inside a batch job
     GcJobDev res{};                  // pointers into the job's block
     bool have_copies = false;
-    std::vector<gc_copy> copies;
+    HostCopies copies;
     bool have_starts = false;
     std::vector<gc_start_record> starts;
     uint64_t paper_count = 0;
@@ -1528,7 +1545,20 @@ gc_status ensure_copies_locked(gc_ctx *ctx, Orbit *o)
     // the copies come in table order, which is key_hi order except where
     // linear probing displaced an entry (past its successors, or around the
     // end of the table): an insertion pass finishes the sort by key
-    o->copies.resize(n);
+    if (n * sizeof(gc_copy) > o->copies.cap_bytes) {
+        // a larger pinned block first, then the old one back to the pool
+        void *blk = nullptr;
+        size_t got = 0;
+        if (ctx->pinned.get(n * sizeof(gc_copy), &blk, &got) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->err = "no pinned host memory for the copy table (" + std::to_string(n) + " copies)";
+            return GC_ENOMEM;
+        }
+        ctx->pinned.put(o->copies.p, o->copies.cap_bytes);
+        o->copies.p = (gc_copy *)blk;
+        o->copies.cap_bytes = got;
+    }
+    o->copies.n = n;
     if (n) GC_HIP(hipMemcpy(o->copies.data(), o->res.copies, n * sizeof(gc_copy), hipMemcpyDeviceToHost));
     auto less = [](const gc_copy &a, const gc_copy &b) {
         return a.key_hi != b.key_hi ? a.key_hi < b.key_hi : a.key_lo < b.key_lo;
@@ -1764,6 +1794,8 @@ gc_status gc_destroy(gc_ctx *ctx)
     for (auto &kv : ctx->orbits) {
         ctx->pool.put(kv.second->tables, kv.second->table_bytes);
         ctx->pool.put(kv.second->wave_tables, kv.second->wave_bytes);
+        ctx->pinned.put(kv.second->copies.p, kv.second->copies.cap_bytes);
+        kv.second->copies = HostCopies{};
     }
     ctx->pool.drain();
     ctx->pinned.drain();
@@ -2168,7 +2200,9 @@ gc_status gc_release(gc_ctx *ctx, gc_orbit orbit)
         }
     }
     drop_results_locked(ctx, o);
-    // the tables go back to the pool: no free (which waits for the device)
+    // the tables go back to the pools: no free (which waits for the device)
+    ctx->pinned.put(o->copies.p, o->copies.cap_bytes);
+    o->copies = HostCopies{};
     ctx->pool.put(o->tables, o->table_bytes);
     ctx->pool.put(o->wave_tables, o->wave_bytes);
     ctx->used -= o->table_bytes + o->wave_bytes;
