@@ -137,7 +137,7 @@ template <int WPS> __device__ __forceinline__ double start_max(double v, double 
 // the lane's slots in registers for the whole phase.  Colour 0 of sweep
 // t + 1 first reads the colour-0 staples of the state after sweep t; at a
 // check point they complete the norm of sweep t.
-template <int D, typename R, int NS, bool RELAX, int CREG, int WPS, typename CP>
+template <int D, typename R, int NS, bool RELAX, bool MAXABS, bool FULL, int CREG, int WPS, typename CP>
 __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<const u32x4> nbt,
                             lds_ptr<typename cx<R>::T> st, double eps, uint64_t cap, bool fixed, uint64_t &sweeps,
                             double &D_out, double *red)
@@ -153,13 +153,13 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
     const R omega = (R)J.omega;
     // fixed (batch-synchronous pass): the norm only after the last of cap sweeps
     const uint64_t check = fixed ? cap : J.check_every > 0 ? (uint64_t)J.check_every : 1;
-    const bool maxabs = J.stop_norm != 0;
+    constexpr bool maxabs = MAXABS;
     int hs[NS];
     bool valid[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         const int h = lane + 64 * WPS * k;
-        valid[k] = h < half;
+        valid[k] = FULL || h < half;
         hs[k] = valid[k] ? h : half - 1;
     }
     u32x4 nr[2][NS];
@@ -200,10 +200,10 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
             const int h = hs[k] + z;
             const C s = staple<D, R, (CREG >= 1)>(cr[0][k], coef, st1, NbWords{nr[0][k]}, 0, h, half);
             const C g0 = own[0][k];
-            const double dv = (double)(g0.x * s.y - g0.y * s.x);
-            const double a = maxabs ? fmax(acc0, fabs(dv)) : acc0 + dv * dv;
+            const double dv = (double)fma(g0.x, s.y, -(g0.y * s.x));
+            const double a = maxabs ? fmax(acc0, fabs(dv)) : fma(dv, dv, acc0);
             acc0 = valid[k] ? a : acc0;
-            gnew[k] = local_update<RELAX, R>(g0, s, omega);
+            gnew[k] = local_update<RELAX, R, !FULL>(g0, s, omega);
         }
         if (pending) {
             // one wave reduction per checked sweep, over both colours' lane parts
@@ -235,11 +235,11 @@ __device__ int relax_wave_t(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, l
         for (int k = 0; k < NS; ++k) {
             const int h = hs[k] + z;
             const C s = staple<D, R, (CREG >= 2)>(cr[NCR - 1][k], coef, st0, NbWords{nr[1][k]}, 1, h, half);
-            const C g = local_update<RELAX, R>(own[1][k], s, omega);
+            const C g = local_update<RELAX, R, !FULL>(own[1][k], s, omega);
             own[1][k] = g;
             if (valid[k]) st1[hs[k]] = g;
-            const double dv = (double)(g.x * s.y - g.y * s.x);
-            const double a = maxabs ? fmax(a1, fabs(dv)) : a1 + dv * dv;
+            const double dv = (double)fma(g.x, s.y, -(g.y * s.x));
+            const double a = maxabs ? fmax(a1, fabs(dv)) : fma(dv, dv, a1);
             a1 = valid[k] ? a : a1;
         }
         if (chk) part1 = a1;
@@ -303,14 +303,33 @@ __device__ __forceinline__ typename cx<R>::T staple_big(const u32x4 w, lds_ptr<c
     return s;
 }
 
+// The sweep loop specialised per start (uniform branches): plain relaxation
+// or over-relaxation, the max |div| or the mean-square norm, and, for the
+// double-precision mean-square sweep, whether every slot lies on the lattice
+// (half = 64 WPS NS: no slot is tested and the local update skips the guard
+// on the reciprocal square root's argument; the single-precision sweep
+// measured slower in that form and keeps the general one).  The variants
+// round alike.
 template <int D, typename R, int NS, int CREG, int WPS, typename CP>
 __device__ int relax_wave(const GcJobDev &J, const GcWaveOrbit &WO, CP coef, lds_ptr<const u32x4> nbt,
                           lds_ptr<typename cx<R>::T> st, double eps, uint64_t cap, bool fixed, uint64_t &sweeps,
                           double &D_out, double *red)
 {
-    if ((R)J.omega == (R)1)
-        return relax_wave_t<D, R, NS, true, CREG, WPS>(J, WO, coef, nbt, st, eps, cap, fixed, sweeps, D_out, red);
-    return relax_wave_t<D, R, NS, false, CREG, WPS>(J, WO, coef, nbt, st, eps, cap, fixed, sweeps, D_out, red);
+#define GC_RW(RELAX, MAXABS, FULL)                                                                         \
+    return relax_wave_t<D, R, NS, RELAX, MAXABS, FULL, CREG, WPS>(J, WO, coef, nbt, st, eps, cap, fixed, sweeps, \
+                                                                  D_out, red)
+    const bool relax = (R)J.omega == (R)1;
+    if (J.stop_norm != 0) {
+        if (relax) GC_RW(true, true, false);
+        GC_RW(false, true, false);
+    }
+    if (sizeof(R) == 8 && WO.half == 64 * WPS * NS) {
+        if (relax) GC_RW(true, false, true);
+        GC_RW(false, false, true);
+    }
+    if (relax) GC_RW(true, false, false);
+    GC_RW(false, false, false);
+#undef GC_RW
 }
 
 template <int D, int NS, int CREG, int WPS, typename CP64, typename CP32>
