@@ -735,9 +735,11 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             g.coef_lds = (g.ns <= 2 && coef_bytes + states <= 64 * 1024) ? 1 : 0;
             g.lds = states + (g.coef_lds ? coef_bytes : 0);
             if (g.lds > ctx->lds_max) return GC_EUNSUPPORTED;
-            // colour-0 coefficients in registers where a lane has at most two
-            // slots (measured faster on 4^4 despite two waves per SIMD instead
-            // of three); GC_WAVE_CREG overrides
+            // colour-0 coefficients in registers by default where a lane has
+            // at most two slots: the uneven 32-orbit batch runs 1.4-2.2 %
+            // faster so than with none, though 4^4 alone is faster with none
+            // (44.7 against 49.9 ms per step), which the autotuner finds;
+            // GC_WAVE_CREG overrides
             g.creg = std::min(1, gc_wave_creg_max(g.d, g.ns));
             const auto tc = ctx->tune_creg.find(creg_key(g.d, g.ns, mixed));
             if (tc != ctx->tune_creg.end()) g.creg = std::min(tc->second, gc_wave_creg_max(g.d, g.ns));
