@@ -201,6 +201,24 @@ def test_stopping_variants(ctx):
         ctx.gc_release(h)
 
 
+@pytest.mark.parametrize("extent,omega,n", [
+    ((10, 10, 10), 1.0, 16),       # 500 sites per colour: eight slots per lane
+    ((6, 6, 6, 6), 1.7, 12),       # 648: eleven
+])
+def test_max_abs_stop_on_exchange_region_kernel(ctx, extent, omega, n):
+    """The max |div| stop (the paper's criterion, Sec. III) on lattices of
+    the exchange-region kernel (more than two slots per lane), start by
+    start and copy by copy against the oracle."""
+    phi = GI.orbit_angles(extent, 3, 4)
+    p = gc.SolveParams(omega=omega, stop_norm="max_abs", eps64=1e-12)
+    h, copies, starts, _ = run_gpu(ctx, extent, phi, n, p, orbit_index=4)
+    o = O.enumerate_copies(extent, phi, np.arange(n), oracle_params(p, 4))
+    compare_starts(extent, starts, o["records"])
+    compare_tables(extent, phi, copies, o, p)
+    check_start_filter(copies, starts, o)
+    ctx.gc_release(h)
+
+
 def test_sweep_cap_gives_no_copies(ctx):
     extent = (4, 4)
     phi = GI.orbit_angles(extent, 0, 0)
