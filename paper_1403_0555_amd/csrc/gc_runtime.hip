@@ -713,9 +713,8 @@ gc_status plan_job(gc_ctx *ctx, Job *job, JobLayout &L)
             g.block = 64 * gc_wave_starts_per_wg(g.ns);
             g.rm = g.ns > 2 ? gc_wave_relax_mode(job->p.omega, job->p.stop_norm) : 0;
             // every orbit fills all slots of a lane but the last: the
-            // double-precision kernel tests only the last slot (mean-square
-            // norm only)
-            if (g.ns > 2 && (g.rm & 4) == 0) {
+            // double-precision kernel tests only the last slot
+            if (g.ns > 2) {
                 bool full = true;
                 for (int j : g.jobs) full = full && (job->orbits[j]->V / 2 + 63) / 64 == ns_bucket(g.d, g.ns);
                 g.full = full ? GC_RM_FULL_SLOTS : 0;

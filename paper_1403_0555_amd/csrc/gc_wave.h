@@ -97,10 +97,10 @@ inline int gc_wave_relax_mode(double omega, int stop_norm)
 {
     return (omega == 1.0 ? 1 : (float)omega == 1.0f ? 2 : 0) | (stop_norm ? 4 : 0);
 }
-// Added to a mean-square relax mode (0..2) of gc_launch_wave's variant where
-// every orbit of the launch fills all slots of a lane but the last
-// (ceil(half / 64) equals the instantiated slot count): the double-precision
-// kernel then tests the last slot only.  Not for the single-precision kernel.
+// Added to a relax mode (0..6) of gc_launch_wave's variant where every orbit
+// of the launch fills all slots of a lane but the last (ceil(half / 64)
+// equals the instantiated slot count): the double-precision kernel then
+// tests the last slot only.  Not for the single-precision kernel.
 constexpr int GC_RM_FULL_SLOTS = 8;
 
 // Workgroup-per-start variant (lattices with more than 128 slots per

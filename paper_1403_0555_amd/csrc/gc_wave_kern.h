@@ -547,8 +547,8 @@ __device__ int relax_rr(const GcJobDev &J, int half, __amdgpu_buffer_rsrc_t link
 // over-relaxation in both precisions, plain relaxation in both (omega = 1),
 // or plain relaxation in the single-precision phase only (omega rounds to 1
 // in single precision but differs from 1); GC_RM_MAXABS added for the
-// max |div| stopping norm; GC_RM_FULL (double-precision kernel, mean-square
-// norm) where every orbit of the launch has ceil(half / 64) = NS.
+// max |div| stopping norm; GC_RM_FULL (double-precision kernel) where every
+// orbit of the launch has ceil(half / 64) = NS.
 enum { GC_RM_OR = 0, GC_RM_RELAX = 1, GC_RM_RELAX32 = 2, GC_RM_MAXABS = 4, GC_RM_FULL = GC_RM_FULL_SLOTS };
 
 template <int D, typename R, int NS, bool RELAX, bool MAXABS, int DL, typename LT, bool FULL = false>
@@ -1103,6 +1103,9 @@ hipError_t launch_t(const GcJobDev *jobs, const GcWaveOrbit *worbs, int n_jobs, 
             GC_RR_LAUNCH(GC_RM_FULL)
             GC_RR_LAUNCH(GC_RM_FULL | 1)
             GC_RR_LAUNCH(GC_RM_FULL | 2)
+            GC_RR_LAUNCH(GC_RM_FULL | 4)
+            GC_RR_LAUNCH(GC_RM_FULL | 5)
+            GC_RR_LAUNCH(GC_RM_FULL | 6)
 #undef GC_RR_LAUNCH
         default: return hipErrorInvalidValue;
         }
